@@ -1,0 +1,162 @@
+"""Pins of the oracle's ghost-cell fills (sections 4.2.2 and 4.4) and of the mass identity.
+
+CPU only.  The pins are special cases with known answers (constant and linear
+fields, the exact tanh wedge that satisfies the continuous contact-angle
+condition, the static limit of the dynamic condition, the no-slip and free-slip
+limits of the Navier condition) and the discrete mass identity of the
+semi-implicit step.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle.geometry import build_tables
+from oracle.solver import OracleState, centred_velocity, mirror_value
+
+SQ2 = math.sqrt(2.0)
+
+
+def _state(case, C0=None, faces=None):
+    T = build_tables(case.grid, case.shapes, case.params)
+    if C0 is None:
+        C0, f = case.initial_fields()
+        faces = f if faces is None else faces
+    return OracleState(case.grid, case.params, T, C0, faces), T
+
+
+@pytest.mark.parametrize("kind", ["flat", "sin", "circle"])
+def test_constant_field(kind):
+    case = W.small_case(64, 32, kind=kind, theta_deg=90.0)
+    st, T = _state(case, C0=np.full(case.grid.shape, 0.37))
+    P = np.full(case.grid.shape, 0.37)
+    assert np.max(np.abs(mirror_value(P.reshape(-1), T) - 0.37)) <= 1e-15
+    CG = st.fill_C(P, initial=False)
+    assert np.max(np.abs(CG - 0.37)) <= 1e-12          # 90 degrees: cos(theta) ~ 6e-17
+
+
+def test_linear_field_mirror_value_exact_for_on_centre_interpolation_points():
+    g = W.Grid((32, 16), (0.0, 0.0), (2.0, 1.0))
+    h = g.h
+    prm = W.Params(Cn=0.05, Pe=10.0, d1_cells=1.5, d2_cells=1.0)
+    T = build_tables(g, [W.Shape(W.HALFPLANE, (0.0, 4 * h, 0.0, 0.0, 1.0, 0.0))], prm)
+    y = (np.arange(16) + 0.5) * h
+    x = (np.arange(32) + 0.5) * h
+    P = 0.3 + 1.7 * y[:, None] - 0.4 * x[None, :]
+    CM = mirror_value(P.reshape(-1), T)
+    Mx, My = T.points["M"]
+    assert np.max(np.abs(CM - (0.3 + 1.7 * My - 0.4 * Mx))) <= 1e-14
+
+
+@pytest.mark.parametrize("kind,theta", [("flat", 60.0), ("sin", 45.0), ("circle", 135.0), ("tilted", 120.0)])
+def test_static_condition_holds_at_the_intersect_point(kind, theta):
+    case = W.small_case(64, 32, kind=kind, theta_deg=theta)
+    st, T = _state(case)
+    P = st.C.copy()
+    CG = st.fill_C(P, initial=False)
+    CM = mirror_value(P.reshape(-1), T)
+    g = T.gamma
+    CI = (g * CG + CM) / (g + 1)
+    dCdn = (CM - CG) / ((1 + g) * T.dn)
+    res = (3 / (2 * SQ2)) * case.params.Cn * dCdn + math.cos(math.radians(theta)) * 0.75 * (1 - CI * CI)
+    assert np.max(np.abs(res)) <= 1e-12
+
+
+@pytest.mark.parametrize("theta", [50.0, 120.0])
+def test_tanh_wedge_is_reproduced_under_refinement(theta):
+    """C = tanh(s/(sqrt2 Cn)), s = (x - xc) sin(theta) - (y - yw) cos(theta), meets a flat wall at
+    angle theta and satisfies the continuous static condition; the ghost values converge to it."""
+    errs = []
+    Cn = 0.06
+    th = math.radians(theta)
+    for n in (32, 64, 128):
+        g = W.Grid((2 * n, n), (0.0, 0.0), (2.0, 1.0))
+        h = g.h
+        yw = (int(0.3 * n) + 0.37) * h          # same wall position relative to the cells
+        prm = W.Params(Cn=Cn, Pe=10.0, theta_deg=theta, velocity_fill=False)
+        T = build_tables(g, [W.Shape(W.HALFPLANE, (0.0, yw, 0.0, 0.0, 1.0, 0.0))], prm)
+        x = (np.arange(2 * n) + 0.5) * h
+        y = (np.arange(n) + 0.5) * h
+        s = (x[None, :] - 1.0) * math.sin(th) - (y[:, None] - yw) * math.cos(th)
+        Cex = np.tanh(s / (SQ2 * Cn))
+        st = OracleState(g, prm, T, Cex)
+        CG = st.fill_C(Cex.copy(), initial=False)
+        near = np.abs(T.points["G"][0] - 1.0) < 4 * Cn
+        errs.append(np.max(np.abs(CG - Cex.reshape(-1)[T.gidx])[near]))
+    assert errs[1] < 0.75 * errs[0] and errs[2] < 0.75 * errs[1]
+    assert errs[2] < 0.05
+
+
+def test_dynamic_condition_relaxes_to_the_static_one():
+    """With the fluid frozen, repeated dynamic updates converge to the static ghost values."""
+    case = W.small_case(64, 32, kind="sin", theta_deg=60.0, Vs=2000.0)   # Vs dt = 0.2
+    st, T = _state(case)
+    st.faces = [np.zeros(case.grid.shape) for _ in range(2)]   # no wall advection term
+    P = st.C.copy()
+    Pf = P.reshape(-1)
+    CG_prev = Pf[T.gidx].copy()
+    CG = CG_prev.copy()
+    for _ in range(400):
+        Pf[T.gidx] = 2 * CG - CG_prev
+        new = st.fill_C(P, initial=False)
+        CG_prev, CG = CG, new
+    static = W.small_case(64, 32, kind="sin", theta_deg=60.0, Vs=0.0)
+    st2 = OracleState(static.grid, static.params, T, st.C)
+    Pf[T.gidx] = CG
+    CGs = st2.fill_C(P, initial=False)
+    assert np.max(np.abs(CG - CGs)) <= 1e-10
+
+
+def _random_faces(grid, seed, amp=0.05):
+    rng = np.random.default_rng(seed)
+    return [amp * rng.standard_normal(grid.shape) for _ in range(grid.ndim)]
+
+
+@pytest.mark.parametrize("ls,kind", [(0.0, "sin"), (1e12, "sin"), (0.0, "circle"), (1e12, "tilted")])
+def test_velocity_fill_limits(ls, kind):
+    """No penetration at I always; no slip (ls = 0) gives zero tangential velocity at I;
+    ls -> infinity gives zero normal derivative of the tangential velocity (the capillary
+    bracket vanishes because the static condition holds exactly)."""
+    case = W.small_case(64, 32, kind=kind, theta_deg=70.0, slip_length=ls)
+    st, T = _state(case)
+    st.faces = _random_faces(case.grid, 3)
+    faces_before = [f.copy() for f in st.faces]
+    st.fill_velocity(st.C)
+    uG = st.last_uG
+    n = T.normal
+    g = T.gamma
+    uc = centred_velocity(faces_before, case.grid)
+    uM = np.stack([mirror_value(u.reshape(-1), T) for u in uc])
+    uI = (g * uG + uM) / (g + 1)
+    assert np.max(np.abs((uI * n).sum(0))) <= 1e-13
+    VtM = uM - (uM * n).sum(0) * n
+    VtG = uG - (uG * n).sum(0) * n
+    if ls == 0.0:
+        assert np.max(np.abs(g * VtG + VtM)) <= 1e-13
+    else:
+        assert np.max(np.abs(VtG - VtM)) <= 1e-9
+    # faces touching a ghost hold the mean of the two adjacent centred values; others unchanged
+    ghost = np.zeros(case.grid.cells, bool)
+    ghost[T.gidx] = True
+    ghost = ghost.reshape(case.grid.shape)
+    ux_c = uc[0].reshape(-1).copy()
+    ux_c[T.gidx] = uG[0]
+    ux_c = ux_c.reshape(case.grid.shape)
+    touch = ghost | np.roll(ghost, -1, axis=1)
+    expect = np.where(touch, 0.5 * (ux_c + np.roll(ux_c, -1, axis=1)), faces_before[0])
+    assert np.array_equal(st.faces[0], expect)
+
+
+@pytest.mark.parametrize("kind", ["flat", "sin", "circle"])
+def test_mass_identity_before_ghost_overwrite(kind):
+    """sum C* = (4/3) sum C^n - (1/3) sum C^(n-1): the zero mode of the spectral solve,
+    with the flux-form advection and the reflecting Laplacian summing to zero."""
+    case = W.small_case(64, 32, kind=kind, theta_deg=60.0)
+    st, T = _state(case)
+    st.faces = _random_faces(case.grid, 5, 0.2)
+    for _ in range(5):
+        Cs = st.provisional()
+        ref = (4.0 / 3.0) * st.C.sum() - (1.0 / 3.0) * st.Cp.sum()
+        assert abs(Cs.sum() - ref) <= 1e-11 * np.abs(st.C).sum()
+        st.step(1)
