@@ -1,0 +1,173 @@
+#!/usr/bin/env python3
+"""Benchmark of the CH + ghost-cell IB step on one MI355X.
+
+Workload: the 3D solid sphere (radius 1 at the origin of [-2,2]^3) on a 256^3 grid with a
+spherical droplet of radius 0.5 resting on its top, Cn = 0.015, Pe = 200, Ca = 0.05, static
+90-degree contact angle, slip length 0.01, dt = 1e-4, FP64, velocity fill on.  Inputs are
+synthetic (seeded tanh droplet, fluid at rest) and resident in HBM before timing starts.
+
+Prints ONE JSON line: whole-job cell-updates/s, the roofline of the dominant kernel (its
+algorithmic bytes per launch over its mean HIP-event duration during the timed steps) and
+the FP64 CPU oracle timed on the host on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "CH+IB cell-updates/s at 256³; learned/plain speedup at ≤1° contact-angle err"
+
+
+def algorithmic_bytes(name: str, cells: int, d: int, es: int, G: int, NF: int) -> float:
+    """Bytes the method must move per launch of each kernel of a step.
+
+    Field passes count each array they must read and write once; the ghost kernels count
+    their table entries, gathers and writes per ghost (and per re-interpolated face)."""
+    K = 2 * d + 1
+    if name == "rhs_xdht":
+        return cells * es * (2 + d + 1)              # C^n, C^(n-1), d face arrays in; Q out
+    if name in ("ydht_fwd", "ydht_inv", "neumann_solve", "xdht_out"):
+        return cells * es * 2                        # one read, one write
+    if name == "ghost_fill_C":
+        return G * (4 + 8 * K + es * (7 + 4 * K))
+    if name == "ghost_fill_u":
+        per_ghost = 4 + 8 * K + es * (3 * d + 4 + 2 * K + 2 * K * 4 * d)
+        per_face = 16 + es * 4 + 16 + es * 3
+        return G * per_ghost + NF * per_face
+    return 0.0
+
+
+def cpu_baseline(case, steps: int) -> dict:
+    """The FP64 oracle on the host, on a bounded sample (a few steps) of the same workload."""
+    from oracle.geometry import build_tables
+    from oracle.solver import OracleState, WORKERS
+    T = build_tables(case.grid, case.shapes, case.params)
+    C0, faces = case.initial_fields()
+    orc = OracleState(case.grid, case.params, T, C0, faces)
+    orc.step(1)   # warm-up (FFT plans, page faults)
+    t0 = time.perf_counter()
+    orc.step(steps)
+    dt = time.perf_counter() - t0
+    return {"value": case.grid.cells * steps / dt, "unit": "cell-updates/s", "cores": WORKERS,
+            "kind": "oracle",
+            "sample": f"{steps} steps of the same 256^3 workload after 1 warm-up step "
+                      f"({dt:.1f} s; scipy FFTs on {WORKERS} threads, NumPy stencils single-threaded)"}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--precision", type=int, default=64, choices=(64, 32))
+    ap.add_argument("--n", type=int, default=256, help="cells per axis of the sphere workload")
+    ap.add_argument("--cpu-steps", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="also run one plain device copy of this size (for counter calibration)")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print(json.dumps({"error": "this build runs on exactly one GPU; multi-GPU runs are not part of it"}))
+        return 2
+
+    import torch
+    import workloads as W
+    from paper_2104_00350_amd import chib
+
+    if not torch.cuda.is_available():
+        print(json.dumps({"error": "no GPU visible"}))
+        return 2
+    case = W.config3(args.n)
+    g = case.grid
+    t0 = time.perf_counter()
+    geo = chib.Geometry.build(g.n, g.lo, g.hi, case.shapes, case.params)
+    t_geom = time.perf_counter() - t0
+    st = chib.State(geo, case.params, args.precision)
+    C0, faces = case.initial_fields()
+    st.set_initial(C0, faces)
+    st.step(max(args.warmup, 1))
+    st.sync()
+    print(f"[bench] geometry {t_geom:.1f}s, ghosts {st.G}, warmup done", file=sys.stderr, flush=True)
+
+    if args.copy_calibration_mib:
+        nel = args.copy_calibration_mib * (1 << 20) // 8
+        a = torch.ones(nel, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ms = st.step_timed(args.steps)          # HIP events between kernels on the state's stream
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    dg = st.diagnostics()
+    if dg["status"] != 0:
+        print(json.dumps({"error": "non-finite state after the timed steps"}))
+        return 1
+
+    cells = g.cells
+    es = 8 if args.precision == 64 else 4
+    # faces touching ghosts (the velocity fill's second work list), from the exported tables
+    tabs = geo.export()
+    nx, ny = g.n[0], g.n[1]
+    faces_set = set()
+    for c in tabs["gidx"].tolist():
+        i, j, k = c % nx, (c // nx) % ny, c // (nx * ny)
+        for a_, (di, dj, dk) in enumerate(((1, 0, 0), (0, 1, 0), (0, 0, 1))):
+            cm = ((i - di) % nx) + nx * (((j - dj) % ny) + ny * (k - dk))
+            faces_set.add((a_, cm))
+            faces_set.add((a_, c))
+    NF = len(faces_set)
+
+    kernels = {}
+    for name, t in ms.items():
+        b = algorithmic_bytes(name, cells, 3, es, st.G, NF)
+        kernels[name] = {"ms": round(t, 5), "alg_bytes": int(b), "GB_s": round(b / (t * 1e-3) / 1e9, 1)}
+    dominant = max(ms, key=ms.get)
+    dom = kernels[dominant]
+    gpu_ms = sum(ms.values())
+    value = cells * args.steps / wall
+    achieved = dom["alg_bytes"] / (ms[dominant] * 1e-3) / 1e9
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "cell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * wall / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if args.precision == 64 else "f32",
+        "data": "synthetic",
+        "config": {"workload": f"3D sphere wall r=1 in [-2,2]^3, {args.n}^3 cells, droplet R=0.5 on top, "
+                               "Cn=0.015 Pe=200 Ca=0.05 theta=90 ls=0.01 dt=1e-4, velocity fill on",
+                   "grid": list(g.n), "ghosts": st.G, "faces_touching_ghosts": NF},
+        "roofline": {"bound": "hbm", "kernel": dominant, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None},
+        "gpu_ms_per_step_events": round(gpu_ms, 5),
+        "path_GB_s": round(sum(k["alg_bytes"] for k in kernels.values()) / (gpu_ms * 1e-3) / 1e9, 1),
+        "kernels": kernels,
+    }
+    if not args.no_cpu_baseline:
+        print(f"[bench] GPU done ({value:.3e} cell-updates/s); timing the CPU oracle", file=sys.stderr,
+              flush=True)
+        out["cpu_baseline"] = cpu_baseline(case, args.cpu_steps)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

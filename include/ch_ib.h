@@ -1,0 +1,225 @@
+/*
+ * ch_ib.h -- C ABI of the MI355X library for the hybrid ghost-cell immersed-boundary /
+ * Cahn-Hilliard wetting step of Shahmardi, Rosti, Tammisola & Brandt,
+ * "A fully Eulerian hybrid immersed boundary-phase field model for contact line dynamics
+ * on complex geometries" (arXiv:2104.00350).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Every function that can fail returns an int status: CH_IB_OK (0) or a negative code.
+ *   Nothing aborts or throws.  ch_ib_last_error() returns a thread-local detail string.
+ * - Grids are uniform Cartesian boxes, 2D or 3D, cell centred, axis 0 (x) stored fastest
+ *   (linear cell index = i + n0*(j + n1*k)).  Every axis but the last is periodic; the last
+ *   axis is bounded by two flat box walls (Neumann for the order parameter, no penetration
+ *   for velocity).  This is the box of the end of Appendix A.1 of the paper.  Each n[a] must
+ *   be a power of two between 8 and 2048 and all spacings equal.
+ * - Fields are order parameter C (cell centred) and face velocities on the staggered grid:
+ *   u_a[c] is the velocity normal to the face between cell c and cell c + e_a (section 3.1).
+ *   The face of the last axis above the top cell row is a box wall and always reads as 0.
+ * - Device memory is owned by the caller: the library never allocates or frees device
+ *   memory.  A state lives inside one caller-provided workspace (ch_ib_workspace_bytes)
+ *   and enqueues all its work on one caller-provided HIP stream.  Host objects
+ *   (geometry, state handles) are owned by the library and released by the *_free calls.
+ * - Nothing is re-entrant on the same state; distinct states may be used from distinct
+ *   threads.
+ */
+#ifndef CH_IB_H
+#define CH_IB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---------------------------------------------------------------- */
+enum {
+  CH_IB_OK = 0,
+  CH_IB_EINVAL = -1,       /* invalid argument or parameter set */
+  CH_IB_EGEOM = -2,        /* geometry preprocessing failed (e.g. ghost touching the box wall) */
+  CH_IB_EHIP = -3,         /* a HIP runtime call failed */
+  CH_IB_ENOMEM = -4,       /* workspace or caller buffer too small */
+  CH_IB_ENAN = -5,         /* a non-finite value was found in the state */
+  CH_IB_EUNSUPPORTED = -6  /* valid request this build does not implement (e.g. non power-of-two grid) */
+};
+
+/* ---- wall shapes (solid region; several shapes form a union) --------------------------
+ * HALFPLANE: p[0..2] a point on the wall, p[3..5] wall normal pointing into the fluid;
+ *            solid where (x - p).n < 0.
+ * SINUSOID : p[0] mean height, p[1] amplitude, p[2] wavelength, p[3] phase (radians);
+ *            solid where x_last < p0 + p1 sin(2 pi x_0 / p2 + p3).
+ * SPHERE   : p[0..2] centre, p[3] radius (circle in 2D); solid inside.
+ * BOX      : p[0..2] centre, p[3] half edge, p[4] rotation (radians) in the x-y plane;
+ *            fluid inside the rotated square/cube, solid outside. */
+enum { CH_IB_HALFPLANE = 1, CH_IB_SINUSOID = 2, CH_IB_SPHERE = 3, CH_IB_BOX = 4 };
+
+/* ---- fields addressed by ch_ib_state_set / ch_ib_state_get ------------------------------ */
+enum {
+  CH_IB_FIELD_C = 0,       /* order parameter C^n, all cells (solid included) */
+  CH_IB_FIELD_C_PREV = 1,  /* C^(n-1) (get only; set through ch_ib_state_load) */
+  CH_IB_FIELD_U = 2,       /* face velocity along axis 0 */
+  CH_IB_FIELD_V = 3,       /* face velocity along axis 1 */
+  CH_IB_FIELD_W = 4,       /* face velocity along axis 2 (3D) */
+  CH_IB_FIELD_CI = 5,      /* per-ghost wall value C_I of the dynamic condition (n_ghost values) */
+  CH_IB_FIELD_ALPHA = 6,   /* fluid volume fraction (get only) */
+  CH_IB_FIELD_PHI = 7      /* chemical potential C^3 - C - Cn^2 lap C with mirror ghosts (get only) */
+};
+
+/* ---- params.flags ---------------------------------------------------------------------- */
+enum {
+  CH_IB_FLAG_VELOCITY_FILL = 1  /* refill faces touching ghosts every step (section 4.4) */
+};
+
+typedef struct {
+  int ndim;        /* 2 or 3 */
+  int n[3];        /* cells per axis */
+  double lo[3];    /* box lower corner */
+  double hi[3];    /* box upper corner */
+} ch_ib_grid;
+
+typedef struct {
+  int kind;        /* CH_IB_HALFPLANE ... CH_IB_BOX */
+  double p[10];
+} ch_ib_shape;
+
+/* Dimensionless groups and method options.  Non-dimensional form of the paper's system:
+ * dC/dt + div(uC) = (1/Pe) lap(C^3 - C - Cn^2 lap C), wall condition
+ * DC/Dt = Vs [Cn dC/dn + cos(theta)(1 - C^2)/sqrt2] (Vs = 0: static, Eq. WallBCS with mu_f = 0),
+ * Navier slip with slip length ls and capillary bracket scaled by 1/Ca (Eq. SlipVelocity). */
+typedef struct {
+  double Cn, Pe, Re, Ca, mu;  /* Re is carried but not used by the order-parameter step */
+  double theta_deg;           /* equilibrium contact angle, measured through the C = +1 phase */
+  double Vs;                  /* contact-line relaxation coefficient; 0 selects the static condition */
+  double slip_length;
+  double dt;
+  double S;                   /* stabilisation of Appendix A.1; <= 0 selects Cn sqrt(6 Pe/dt) */
+  double d1_cells;            /* intersect-to-mirror distance in cells; <= 0 selects one cell diagonal */
+  double d2_cells;            /* mirror-to-interpolation-point spacing in cells (0.5 recommended) */
+  int subgrid;                /* subgrid points per direction for the volume fraction; 0: 100 (2D) / 20 (3D) */
+  int precision;              /* 64 (FP64) or 32 (FP32) arithmetic on the device */
+  int flags;                  /* CH_IB_FLAG_* */
+} ch_ib_params;
+
+/* Per-ghost tables (structure of arrays, sorted by ghost cell index), section 4.1.
+ * ap/w are laid out [2][n_ap][n_ghost]: averaging points and weights of IP1 then IP2.
+ * Unused averaging slots carry weight 0 and repeat a used index. */
+typedef struct {
+  int64_t n_ghost;
+  int ndim;
+  int n_ap;          /* 2*ndim + 1 */
+  int64_t *gidx;     /* [n_ghost] linear cell index of the ghost point */
+  double *normal;    /* [ndim][n_ghost] unit wall normal, pointing into the fluid */
+  double *dn;        /* [n_ghost] ghost-to-intersect distance */
+  double *gamma;     /* [n_ghost] d1 / dn */
+  int64_t *ap;       /* [2][n_ap][n_ghost] averaging-point cell indices */
+  double *w;         /* [2][n_ap][n_ghost] normalised inverse-squared-distance weights */
+  double *alpha;     /* [cells] fluid volume fraction, or NULL */
+} ch_ib_ghost_tables;
+
+typedef struct {
+  double mass_box;     /* h^d sum C */
+  double mass_fluid;   /* h^d sum alpha C */
+  double free_energy;  /* bulk + gradient (alpha weighted) + diffuse wall term, u = 0 */
+  double max_abs_C;
+  int64_t step;
+  int status;          /* CH_IB_OK or CH_IB_ENAN */
+  int pad_;
+} ch_ib_diag;
+
+typedef struct ch_ib_geometry ch_ib_geometry;
+typedef struct ch_ib_state ch_ib_state;
+
+/* ---- errors ------------------------------------------------------------------------------ */
+const char *ch_ib_strerror(int status);
+const char *ch_ib_last_error(void);
+int ch_ib_version(void);  /* major*10000 + minor*100 + patch */
+
+/* ---- geometry (one-time host preprocessing, section 4.1) ----------------------------------
+ * ch_ib_geometry_build: volume fraction by subgrid counting (4.1.1), normals from corner
+ *   gradients of the volume fraction (Eqs. NormalVectors_part1/2), ghost points, intersect
+ *   points by marching along the normal and bisecting, mirror points at d1 and interpolation
+ *   points at d2 and 2*d2 beyond it (4.1.2), plus-stencil averaging points with normalised
+ *   1/h^2 weights (Eq. "weright averaged").  Host arrays passed in are copied.
+ *   Returns EGEOM if a ghost touches the bounded axis' box wall or an interpolation point has
+ *   no fluid averaging point within 2h, EINVAL on a bad grid or shape.
+ * ch_ib_geometry_import: tables from the caller (copied), e.g. produced by another
+ *   implementation; alpha may be NULL (then mass_fluid and the free energy use alpha = 1).
+ * ch_ib_geometry_export: copies the tables into caller-allocated arrays sized from
+ *   ch_ib_geometry_count (alpha is copied if non-NULL).
+ * ch_ib_geometry_free: releases the host object (NULL is accepted). */
+int ch_ib_geometry_build(const ch_ib_grid *grid, const ch_ib_shape *shapes, int n_shapes,
+                         const ch_ib_params *params, ch_ib_geometry **out);
+int ch_ib_geometry_import(const ch_ib_grid *grid, const ch_ib_ghost_tables *tables,
+                          ch_ib_geometry **out);
+int ch_ib_geometry_export(const ch_ib_geometry *geom, ch_ib_ghost_tables *dst);
+int ch_ib_geometry_count(const ch_ib_geometry *geom, int64_t *n_ghost, int *n_ap);
+void ch_ib_geometry_free(ch_ib_geometry *geom);
+
+/* ---- state ----------------------------------------------------------------------------------
+ * ch_ib_workspace_bytes: device bytes one state needs (0 on invalid input).
+ * ch_ib_state_create: carves the state out of device_workspace (>= that many bytes, 256-byte
+ *   aligned, caller-owned, must outlive the state), uploads the tables and coefficient tables
+ *   on hip_stream (a hipStream_t; NULL = default stream) and waits for the upload.
+ *   EINVAL if S is below the bound of Appendix A.1 or a parameter is out of range.
+ * ch_ib_state_set: copies a field in (host or device pointer, element type double for
+ *   precision 64 and float for precision 32).  Setting C (or a velocity) marks the state as a
+ *   fresh start: the next ch_ib_step first fills the ghosts of the current fields (initial
+ *   fill) and sets C^(n-1) = C^n.
+ * ch_ib_state_get: copies a field out (same element type rules); synchronous. */
+size_t ch_ib_workspace_bytes(const ch_ib_grid *grid, const ch_ib_geometry *geom,
+                             const ch_ib_params *params);
+int ch_ib_state_create(const ch_ib_grid *grid, const ch_ib_geometry *geom,
+                       const ch_ib_params *params, void *device_workspace, size_t bytes,
+                       void *hip_stream, ch_ib_state **out);
+int ch_ib_state_set(ch_ib_state *st, int field, const void *src, int src_on_device);
+int ch_ib_state_get(ch_ib_state *st, int field, void *dst, int dst_on_device);
+
+/* ---- time stepping (the hot path) -----------------------------------------------------------
+ * ch_ib_step: enqueues n_steps steps on the state's stream and returns without waiting.  One
+ *   step: right-hand side of Eq. Helmholtz1 (history, conservative advection, Laplacian of
+ *   the explicit chemical-potential part), the two Helmholtz solves of Appendix A.1 as one
+ *   spectral division (Hartley transforms on periodic axes, DCT-II on the bounded axis), the
+ *   contact-angle ghost fill of C (section 4.2.2) and, with CH_IB_FLAG_VELOCITY_FILL, the
+ *   no-penetration / Navier-slip fill of the faces touching ghosts (section 4.4).
+ * ch_ib_sync: waits for the stream; reports CH_IB_EHIP on a device error.
+ * ch_ib_diagnostics: mass, free energy, max |C| (deterministic fixed-order reductions);
+ *   synchronous; status CH_IB_ENAN (also returned) if any C is not finite. */
+int ch_ib_step(ch_ib_state *st, int n_steps);
+int ch_ib_sync(ch_ib_state *st);
+int ch_ib_diagnostics(ch_ib_state *st, ch_ib_diag *out);
+
+/* ---- stage entry points (each runs one part of the step on device buffers of the state's
+ * element type, n cells each; used to check each stage on its own) ------------------------------
+ * CH_IB_STAGE_RHS  : out = Q of Eq. Helmholtz1 from the current C^n, C^(n-1), faces (in unused).
+ * CH_IB_STAGE_SOLVE: out = solution C of (lap_h - a)(lap_h + alpha_s) C = in (Eqs. Helmholtz1-2).
+ * CH_IB_STAGE_PHI  : out = chemical potential of the current C (in unused). */
+enum { CH_IB_STAGE_RHS = 1, CH_IB_STAGE_SOLVE = 2, CH_IB_STAGE_PHI = 3 };
+int ch_ib_stage(ch_ib_state *st, int stage, const void *in_device, void *out_device);
+
+/* ---- measurement ------------------------------------------------------------------------------
+ * ch_ib_step_timed: enqueues n_steps (1..4096) steps exactly as ch_ib_step does, with a HIP event
+ *   recorded on the state's stream between consecutive kernels, then waits once.  ms_out[k]
+ *   receives the mean duration (ms per step) of the k-th kernel of a step and names_out[k] its
+ *   name (static string); *n_kernels the number of kernels per step.  At most max_kernels entries
+ *   are written (ENOMEM if a step has more).  Events are created and destroyed inside the call. */
+int ch_ib_step_timed(ch_ib_state *st, int n_steps, int max_kernels, double *ms_out, const char **names_out,
+                     int *n_kernels);
+
+/* ---- checkpoint / resume ---------------------------------------------------------------------
+ * ch_ib_state_save: if buf is NULL, *len receives the size needed; otherwise writes a versioned
+ *   blob (C^n, C^(n-1), faces, per-ghost history, step counter) and sets *len.  Synchronous.
+ * ch_ib_state_load: restores a blob saved from a state with the same grid, tables and precision.
+ * ch_ib_state_free: releases the host handle (the workspace stays the caller's). */
+int ch_ib_state_save(ch_ib_state *st, void *buf, size_t *len);
+int ch_ib_state_load(ch_ib_state *st, const void *buf, size_t len);
+void ch_ib_state_free(ch_ib_state *st);
+
+/* Derived coefficients of Appendix A.1 for a parameter set: S, alpha_s and a = alpha_s + S/Cn^2.
+ * EINVAL if S is below Cn sqrt(6 Pe/dt). */
+int ch_ib_coefficients(const ch_ib_params *params, double *S, double *alpha_s, double *a);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CH_IB_H */

@@ -1,0 +1,663 @@
+// C ABI of the library: state creation inside a caller-owned device workspace, field
+// transfer, the step loop, diagnostics, stage entry points and checkpoints.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+#include "kernels.h"
+
+using chib::fail;
+
+namespace {
+
+constexpr int kVersion = 10000;  // 1.0.0
+constexpr uint32_t kMagic = 0x42494843u;  // "CHIB"
+constexpr int kNred = 1024;
+
+struct FaceList {
+  std::vector<int> cell, axis, gL, gR;
+};
+
+// Faces with a ghost on either side (section 4.4: their velocity is re-interpolated).
+FaceList build_faces(const ch_ib_geometry &g) {
+  FaceList fl;
+  const int d = g.ndim;
+  const int64_t G = g.n_ghost;
+  const int nx = g.n[0], ny = g.n[1];
+  std::vector<std::pair<int, int64_t>> faces;  // (axis, left cell)
+  faces.reserve((size_t)G * 2 * d);
+  auto shift = [&](int64_t c, int a, int s) -> int64_t {
+    int i = (int)(c % nx), j = (int)((c / nx) % ny), k = (int)(c / ((int64_t)nx * ny));
+    int q[3] = {i, j, k};
+    q[a] += s;
+    if (a < d - 1) q[a] = (q[a] + g.n[a]) % g.n[a];
+    return q[0] + (int64_t)nx * (q[1] + (int64_t)ny * q[2]);
+  };
+  for (int64_t gi = 0; gi < G; ++gi) {
+    const int64_t c = g.gidx[gi];
+    for (int a = 0; a < d; ++a) {
+      faces.emplace_back(a, shift(c, a, -1));
+      faces.emplace_back(a, c);
+    }
+  }
+  std::sort(faces.begin(), faces.end());
+  faces.erase(std::unique(faces.begin(), faces.end()), faces.end());
+  auto ghost_of = [&](int64_t c) -> int {
+    auto it = std::lower_bound(g.gidx.begin(), g.gidx.end(), c);
+    return (it != g.gidx.end() && *it == c) ? (int)(it - g.gidx.begin()) : -1;
+  };
+  for (auto &f : faces) {
+    fl.axis.push_back(f.first);
+    fl.cell.push_back((int)f.second);
+    fl.gL.push_back(ghost_of(f.second));
+    fl.gR.push_back(ghost_of(shift(f.second, f.first, 1)));
+  }
+  return fl;
+}
+
+struct Layout {
+  size_t total = 0;
+  size_t off(size_t bytes) {
+    size_t o = total;
+    total += (bytes + 255) & ~(size_t)255;
+    return o;
+  }
+};
+
+struct Offsets {
+  size_t C[2], F[3], W, alpha, gidx, normal, dn, gamma, ap, w, CGn, CGnm1, CMs, CI, CGnew, UG;
+  size_t f_cell, f_axis, f_gL, f_gR, stashL, stashR;
+  size_t twr[3], twi[3], dctc, dcts, lam[3], partial, red_out;
+  size_t total;
+};
+
+Offsets plan_layout(const ch_ib_geometry &g, int es, int64_t NF) {
+  Layout L;
+  Offsets o{};
+  const int64_t N = g.cells, G = g.n_ghost;
+  const int d = g.ndim, K = g.n_ap;
+  o.C[0] = L.off(N * es);
+  o.C[1] = L.off(N * es);
+  for (int a = 0; a < 3; ++a) o.F[a] = a < d ? L.off(N * es) : 0;
+  o.W = L.off(N * es);
+  o.alpha = g.alpha.empty() ? 0 : L.off(N * es);
+  o.gidx = L.off(G * 4);
+  o.normal = L.off(d * G * es);
+  o.dn = L.off(G * es);
+  o.gamma = L.off(G * es);
+  o.ap = L.off(2 * K * G * 4);
+  o.w = L.off(2 * K * G * es);
+  o.CGn = L.off(G * es);
+  o.CGnm1 = L.off(G * es);
+  o.CMs = L.off(G * es);
+  o.CI = L.off(G * es);
+  o.CGnew = L.off(G * es);
+  o.UG = L.off(d * G * es);
+  o.f_cell = L.off(NF * 4);
+  o.f_axis = L.off(NF * 4);
+  o.f_gL = L.off(NF * 4);
+  o.f_gR = L.off(NF * 4);
+  o.stashL = L.off(NF * es);
+  o.stashR = L.off(NF * es);
+  for (int a = 0; a < 3; ++a) {
+    o.twr[a] = a < d ? L.off(g.n[a] * es) : 0;
+    o.twi[a] = a < d ? L.off(g.n[a] * es) : 0;
+    o.lam[a] = a < d ? L.off(g.n[a] * es) : 0;
+  }
+  o.dctc = L.off((g.n[d - 1] / 2 + 1) * es);
+  o.dcts = L.off((g.n[d - 1] / 2 + 1) * es);
+  o.partial = L.off(kNred * 8 * sizeof(double));
+  o.red_out = L.off(8 * sizeof(double));
+  o.total = L.total;
+  return o;
+}
+
+int check_params(const ch_ib_params *p, double *S, double *alpha_s, double *a) {
+  if (!p) return fail(CH_IB_EINVAL, "params is NULL");
+  if (!(p->Cn > 0) || !(p->Pe > 0) || !(p->dt > 0)) return fail(CH_IB_EINVAL, "Cn, Pe and dt must be positive");
+  if (p->precision != 64 && p->precision != 32) return fail(CH_IB_EINVAL, "precision must be 64 or 32");
+  if (p->Vs < 0 || p->slip_length < 0) return fail(CH_IB_EINVAL, "Vs and slip_length must be >= 0");
+  if ((p->flags & CH_IB_FLAG_VELOCITY_FILL) && (!(p->Ca > 0) || !(p->mu > 0)))
+    return fail(CH_IB_EINVAL, "Ca and mu must be positive for the velocity fill");
+  const double Cn = p->Cn, Pe = p->Pe, dt = p->dt;
+  const double Smin = Cn * std::sqrt(6.0 * Pe / dt);
+  const double Sv = p->S > 0 ? p->S : Smin;
+  double disc = 1.0 - 6.0 * Cn * Cn * Pe / (dt * Sv * Sv);
+  if (disc < -1e-12) return fail(CH_IB_EINVAL, "S is below the stability bound Cn sqrt(6 Pe/dt)");
+  disc = std::max(disc, 0.0);
+  const double al = -(Sv / (2.0 * Cn * Cn)) * (1.0 + std::sqrt(disc));
+  if (S) *S = Sv;
+  if (alpha_s) *alpha_s = al;
+  if (a) *a = al + Sv / (Cn * Cn);
+  return CH_IB_OK;
+}
+
+}  // namespace
+
+struct ch_ib_state {
+  ch_ib_geometry geom;  // copy of grid info and host tables (alpha kept only on device)
+  ch_ib_params prm{};
+  int es = 8;
+  chib::Plan plan;
+  char *ws = nullptr;
+  Offsets off{};
+  int cur = 0;
+  int needs_init = 1;
+  int64_t step = 0;
+  int sticky = CH_IB_OK;
+  int has_alpha = 0;
+};
+
+static int hip_fail(ch_ib_state *st, hipError_t e, const char *where) {
+  std::string m = std::string(where) + ": " + hipGetErrorString(e);
+  if (st) st->sticky = CH_IB_EHIP;
+  return fail(CH_IB_EHIP, m);
+}
+
+template <typename T>
+static void upload(std::vector<T> &host_keep, const std::vector<double> &src, void *dst, hipStream_t s) {
+  host_keep.assign(src.begin(), src.end());
+  if (!host_keep.empty())
+    (void)hipMemcpyAsync(dst, host_keep.data(), host_keep.size() * sizeof(T), hipMemcpyHostToDevice, s);
+}
+
+extern "C" const char *ch_ib_strerror(int status) {
+  switch (status) {
+    case CH_IB_OK: return "ok";
+    case CH_IB_EINVAL: return "invalid argument";
+    case CH_IB_EGEOM: return "geometry preprocessing failed";
+    case CH_IB_EHIP: return "HIP runtime error";
+    case CH_IB_ENOMEM: return "workspace or buffer too small";
+    case CH_IB_ENAN: return "non-finite value in the state";
+    case CH_IB_EUNSUPPORTED: return "unsupported request";
+    default: return "unknown status";
+  }
+}
+
+extern "C" int ch_ib_version(void) { return kVersion; }
+
+extern "C" int ch_ib_coefficients(const ch_ib_params *params, double *S, double *alpha_s, double *a) {
+  return check_params(params, S, alpha_s, a);
+}
+
+extern "C" size_t ch_ib_workspace_bytes(const ch_ib_grid *grid, const ch_ib_geometry *geom,
+                                        const ch_ib_params *params) {
+  if (!grid || !geom || !params) return 0;
+  ch_ib_geometry tmp;
+  if (chib::check_grid(grid, &tmp)) return 0;
+  if (tmp.cells != geom->cells || tmp.ndim != geom->ndim) return 0;
+  if (params->precision != 64 && params->precision != 32) return 0;
+  const int es = params->precision == 64 ? 8 : 4;
+  FaceList fl = build_faces(*geom);
+  return plan_layout(*geom, es, (int64_t)fl.cell.size()).total + 256;
+}
+
+extern "C" int ch_ib_state_create(const ch_ib_grid *grid, const ch_ib_geometry *geom, const ch_ib_params *params,
+                                  void *device_workspace, size_t bytes, void *hip_stream, ch_ib_state **out) {
+  if (!out) return fail(CH_IB_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!geom || !device_workspace) return fail(CH_IB_EINVAL, "NULL geometry or workspace");
+  double S, al, a;
+  int rc = check_params(params, &S, &al, &a);
+  if (rc) return rc;
+  ch_ib_geometry chk;
+  if ((rc = chib::check_grid(grid, &chk))) return rc;
+  if (chk.cells != geom->cells || chk.ndim != geom->ndim) return fail(CH_IB_EINVAL, "geometry built for another grid");
+  const size_t need = ch_ib_workspace_bytes(grid, geom, params);
+  if (bytes < need) return fail(CH_IB_ENOMEM, "workspace too small: need " + std::to_string(need) + " bytes");
+  if (((uintptr_t)device_workspace) & 255) return fail(CH_IB_EINVAL, "workspace must be 256-byte aligned");
+
+  auto *st = new ch_ib_state();
+  st->geom = *geom;
+  st->prm = *params;
+  st->es = params->precision == 64 ? 8 : 4;
+  st->ws = (char *)device_workspace;
+  st->has_alpha = !geom->alpha.empty();
+  FaceList fl = build_faces(*geom);
+  const int64_t NF = (int64_t)fl.cell.size();
+  st->off = plan_layout(*geom, st->es, NF);
+  const Offsets &o = st->off;
+  chib::Plan &p = st->plan;
+  const int d = geom->ndim;
+  p.d = d;
+  for (int ax = 0; ax < 3; ++ax) {
+    p.n[ax] = geom->n[ax];
+    int l = 0;
+    while ((1 << l) < geom->n[ax]) ++l;
+    p.logn[ax] = l;
+  }
+  p.N = geom->cells;
+  p.h = geom->h;
+  p.Pe = params->Pe;
+  p.Cn = params->Cn;
+  p.dt = params->dt;
+  p.S = S;
+  p.alpha_s = al;
+  p.a = a;
+  p.cos_t = std::cos(params->theta_deg * M_PI / 180.0);
+  p.Ca = params->Ca;
+  p.mu = params->mu;
+  p.ls = params->slip_length;
+  p.Vs = params->Vs;
+  p.vel_fill = (params->flags & CH_IB_FLAG_VELOCITY_FILL) ? 1 : 0;
+  p.dynamic = params->Vs > 0 ? 1 : 0;
+  char *W0 = st->ws;
+  p.C[0] = W0 + o.C[0];
+  p.C[1] = W0 + o.C[1];
+  for (int ax = 0; ax < 3; ++ax) p.F[ax] = ax < d ? W0 + o.F[ax] : nullptr;
+  p.W = W0 + o.W;
+  p.alpha = st->has_alpha ? W0 + o.alpha : nullptr;
+  p.G = geom->n_ghost;
+  p.K = geom->n_ap;
+  p.gidx = (const int *)(W0 + o.gidx);
+  p.normal = W0 + o.normal;
+  p.dn = W0 + o.dn;
+  p.gamma = W0 + o.gamma;
+  p.ap = (const int *)(W0 + o.ap);
+  p.w = W0 + o.w;
+  p.CGn = W0 + o.CGn;
+  p.CGnm1 = W0 + o.CGnm1;
+  p.CMs = W0 + o.CMs;
+  p.CI = W0 + o.CI;
+  p.CGnew = W0 + o.CGnew;
+  p.UG = W0 + o.UG;
+  p.NF = NF;
+  p.f_cell = (const int *)(W0 + o.f_cell);
+  p.f_axis = (const int *)(W0 + o.f_axis);
+  p.f_gL = (const int *)(W0 + o.f_gL);
+  p.f_gR = (const int *)(W0 + o.f_gR);
+  p.stashL = W0 + o.stashL;
+  p.stashR = W0 + o.stashR;
+  for (int ax = 0; ax < 3; ++ax) {
+    p.twr[ax] = ax < d ? W0 + o.twr[ax] : nullptr;
+    p.twi[ax] = ax < d ? W0 + o.twi[ax] : nullptr;
+    p.lam[ax] = ax < d ? W0 + o.lam[ax] : nullptr;
+  }
+  p.dctc = W0 + o.dctc;
+  p.dcts = W0 + o.dcts;
+  p.partial = W0 + o.partial;
+  p.red_out = W0 + o.red_out;
+  p.nred = (int)std::min<int64_t>(kNred, (p.N + 255) / 256);
+  p.stream = (hipStream_t)hip_stream;
+
+  // host-side tables in double, converted to the element type on upload
+  const int64_t G = geom->n_ghost;
+  const double h = geom->h;
+  std::vector<double> tw[3][2], lam[3], dctc, dcts;
+  for (int ax = 0; ax < d; ++ax) {
+    const int n = geom->n[ax];
+    tw[ax][0].resize(n);
+    tw[ax][1].resize(n);
+    lam[ax].resize(n);
+    for (int m = 0; m < n; ++m) {
+      const double ang = 2.0 * M_PI * (double)m / (double)n;
+      tw[ax][0][m] = std::cos(ang);
+      tw[ax][1][m] = -std::sin(ang);
+      const double sarg = ax < d - 1 ? M_PI * (double)m / (double)n : M_PI * (double)m / (2.0 * n);
+      const double sv = std::sin(sarg);
+      lam[ax][m] = -(4.0 / (h * h)) * sv * sv;
+    }
+  }
+  {
+    const int n = geom->n[d - 1];
+    dctc.resize(n / 2 + 1);
+    dcts.resize(n / 2 + 1);
+    for (int k = 0; k <= n / 2; ++k) {
+      dctc[k] = std::cos(M_PI * (double)k / (2.0 * n));
+      dcts[k] = std::sin(M_PI * (double)k / (2.0 * n));
+    }
+  }
+  std::vector<int> gidx32(G), ap32(geom->ap.size());
+  for (int64_t i = 0; i < G; ++i) gidx32[i] = (int)geom->gidx[i];
+  for (size_t i = 0; i < geom->ap.size(); ++i) ap32[i] = (int)geom->ap[i];
+  hipStream_t s = p.stream;
+  std::vector<std::vector<double>> keep_d;
+  std::vector<std::vector<float>> keep_f;
+  keep_d.reserve(32);
+  keep_f.reserve(32);
+  auto up = [&](const std::vector<double> &src, void *dst) {
+    if (st->es == 8) {
+      keep_d.emplace_back();
+      upload(keep_d.back(), src, dst, s);
+    } else {
+      keep_f.emplace_back();
+      upload(keep_f.back(), src, dst, s);
+    }
+  };
+  hipError_t e = hipSuccess;
+  if (G) {
+    e = hipMemcpyAsync((void *)p.gidx, gidx32.data(), G * 4, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync((void *)p.ap, ap32.data(), ap32.size() * 4, hipMemcpyHostToDevice, s);
+    up(geom->normal, (void *)p.normal);
+    up(geom->dn, (void *)p.dn);
+    up(geom->gamma, (void *)p.gamma);
+    up(geom->w, (void *)p.w);
+  }
+  if (NF && e == hipSuccess) {
+    e = hipMemcpyAsync((void *)p.f_cell, fl.cell.data(), NF * 4, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync((void *)p.f_axis, fl.axis.data(), NF * 4, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync((void *)p.f_gL, fl.gL.data(), NF * 4, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync((void *)p.f_gR, fl.gR.data(), NF * 4, hipMemcpyHostToDevice, s);
+  }
+  for (int ax = 0; ax < d; ++ax) {
+    up(tw[ax][0], (void *)p.twr[ax]);
+    up(tw[ax][1], (void *)p.twi[ax]);
+    up(lam[ax], (void *)p.lam[ax]);
+  }
+  up(dctc, (void *)p.dctc);
+  up(dcts, (void *)p.dcts);
+  if (st->has_alpha) up(geom->alpha, p.alpha);
+  // fields start at zero
+  if (e == hipSuccess) e = hipMemsetAsync(p.C[0], 0, (size_t)p.N * st->es, s);
+  if (e == hipSuccess) e = hipMemsetAsync(p.C[1], 0, (size_t)p.N * st->es, s);
+  for (int ax = 0; ax < d && e == hipSuccess; ++ax) e = hipMemsetAsync(p.F[ax], 0, (size_t)p.N * st->es, s);
+  if (G && e == hipSuccess) e = hipMemsetAsync(p.CI, 0, (size_t)G * st->es, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e == hipSuccess) e = hipGetLastError();
+  if (e != hipSuccess) {
+    delete st;
+    return hip_fail(nullptr, e, "state upload");
+  }
+  st->geom.alpha.clear();
+  st->geom.alpha.shrink_to_fit();
+  *out = st;
+  return CH_IB_OK;
+}
+
+static int64_t field_count(const ch_ib_state *st, int field) {
+  switch (field) {
+    case CH_IB_FIELD_C:
+    case CH_IB_FIELD_C_PREV:
+    case CH_IB_FIELD_ALPHA:
+    case CH_IB_FIELD_PHI: return st->plan.N;
+    case CH_IB_FIELD_U:
+    case CH_IB_FIELD_V: return st->plan.N;
+    case CH_IB_FIELD_W: return st->plan.d == 3 ? st->plan.N : -1;
+    case CH_IB_FIELD_CI: return st->plan.G;
+    default: return -1;
+  }
+}
+
+extern "C" int ch_ib_state_set(ch_ib_state *st, int field, const void *src, int src_on_device) {
+  if (!st || !src) return fail(CH_IB_EINVAL, "NULL argument");
+  const int64_t cnt = field_count(st, field);
+  if (cnt < 0) return fail(CH_IB_EINVAL, "unknown field for this grid");
+  void *dst = nullptr;
+  chib::Plan &p = st->plan;
+  switch (field) {
+    case CH_IB_FIELD_C: dst = p.C[st->cur]; break;
+    case CH_IB_FIELD_U: dst = p.F[0]; break;
+    case CH_IB_FIELD_V: dst = p.F[1]; break;
+    case CH_IB_FIELD_W: dst = p.F[2]; break;
+    case CH_IB_FIELD_CI: dst = p.CI; break;
+    default: return fail(CH_IB_EINVAL, "field is read-only");
+  }
+  if (cnt == 0) return CH_IB_OK;
+  hipError_t e = hipMemcpyAsync(dst, src, (size_t)cnt * st->es,
+                                src_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, p.stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(p.stream);
+  if (e != hipSuccess) return hip_fail(st, e, "state_set");
+  if (field != CH_IB_FIELD_CI) st->needs_init = 1;
+  return CH_IB_OK;
+}
+
+template <typename T>
+static hipError_t run_init(ch_ib_state *st) {
+  return chib::enqueue_initial_fill<T>(st->plan, st->cur);
+}
+
+static int ensure_init(ch_ib_state *st) {
+  if (!st->needs_init) return CH_IB_OK;
+  hipError_t e = st->es == 8 ? run_init<double>(st) : run_init<float>(st);
+  if (e != hipSuccess) return hip_fail(st, e, "initial fill");
+  st->needs_init = 0;
+  return CH_IB_OK;
+}
+
+extern "C" int ch_ib_state_get(ch_ib_state *st, int field, void *dst, int dst_on_device) {
+  if (!st || !dst) return fail(CH_IB_EINVAL, "NULL argument");
+  const int64_t cnt = field_count(st, field);
+  if (cnt < 0) return fail(CH_IB_EINVAL, "unknown field for this grid");
+  chib::Plan &p = st->plan;
+  const void *src = nullptr;
+  hipError_t e = hipSuccess;
+  switch (field) {
+    case CH_IB_FIELD_C: src = p.C[st->cur]; break;
+    case CH_IB_FIELD_C_PREV: src = p.C[1 - st->cur]; break;
+    case CH_IB_FIELD_U: src = p.F[0]; break;
+    case CH_IB_FIELD_V: src = p.F[1]; break;
+    case CH_IB_FIELD_W: src = p.F[2]; break;
+    case CH_IB_FIELD_CI: src = p.CI; break;
+    case CH_IB_FIELD_ALPHA:
+      if (!st->has_alpha) {
+        if (st->es == 8) {
+          std::vector<double> ones(cnt, 1.0);
+          e = hipMemcpyAsync(p.W, ones.data(), cnt * 8, hipMemcpyHostToDevice, p.stream);
+          if (e == hipSuccess) e = hipStreamSynchronize(p.stream);
+        } else {
+          std::vector<float> ones(cnt, 1.0f);
+          e = hipMemcpyAsync(p.W, ones.data(), cnt * 4, hipMemcpyHostToDevice, p.stream);
+          if (e == hipSuccess) e = hipStreamSynchronize(p.stream);
+        }
+        src = p.W;
+      } else {
+        src = p.alpha;
+      }
+      break;
+    case CH_IB_FIELD_PHI: {
+      int rc = ensure_init(st);
+      if (rc) return rc;
+      e = st->es == 8 ? chib::enqueue_phi<double>(p, st->cur, p.W) : chib::enqueue_phi<float>(p, st->cur, p.W);
+      src = p.W;
+      break;
+    }
+    default: return fail(CH_IB_EINVAL, "bad field");
+  }
+  if (e != hipSuccess) return hip_fail(st, e, "state_get");
+  if (cnt == 0) return CH_IB_OK;
+  e = hipMemcpyAsync(dst, src, (size_t)cnt * st->es, dst_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
+                     p.stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(p.stream);
+  if (e != hipSuccess) return hip_fail(st, e, "state_get");
+  return CH_IB_OK;
+}
+
+extern "C" int ch_ib_step(ch_ib_state *st, int n_steps) {
+  if (!st) return fail(CH_IB_EINVAL, "NULL state");
+  if (n_steps < 0) return fail(CH_IB_EINVAL, "n_steps must be >= 0");
+  if (st->sticky) return fail(st->sticky, "state is in an error state");
+  int rc = ensure_init(st);
+  if (rc) return rc;
+  for (int i = 0; i < n_steps; ++i) {
+    hipError_t e = st->es == 8 ? chib::enqueue_step<double>(st->plan, st->cur)
+                               : chib::enqueue_step<float>(st->plan, st->cur);
+    if (e != hipSuccess) return hip_fail(st, e, "step");
+    st->cur = 1 - st->cur;
+    st->step++;
+  }
+  return CH_IB_OK;
+}
+
+extern "C" int ch_ib_step_timed(ch_ib_state *st, int n_steps, int max_kernels, double *ms_out,
+                                const char **names_out, int *n_kernels) {
+  if (!st || !ms_out || !names_out || !n_kernels) return fail(CH_IB_EINVAL, "NULL argument");
+  if (n_steps < 1 || n_steps > 4096) return fail(CH_IB_EINVAL, "n_steps must be in 1..4096");
+  if (st->sticky) return fail(st->sticky, "state is in an error state");
+  int rc = ensure_init(st);
+  if (rc) return rc;
+  constexpr int ne = chib::KernelTimer::kMax + 1;
+  std::vector<chib::KernelTimer> tms((size_t)n_steps);
+  hipError_t e = hipSuccess;
+  size_t created = 0;
+  for (auto &tm : tms)
+    for (int k = 0; k < ne && e == hipSuccess; ++k, ++created) e = hipEventCreate(&tm.ev[k]);
+  // all steps are enqueued back to back; one wait at the end
+  for (int s = 0; s < n_steps && e == hipSuccess; ++s) {
+    tms[s].n = 0;
+    e = st->es == 8 ? chib::enqueue_step<double>(st->plan, st->cur, &tms[s])
+                    : chib::enqueue_step<float>(st->plan, st->cur, &tms[s]);
+    if (e != hipSuccess) break;
+    st->cur = 1 - st->cur;
+    st->step++;
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(st->plan.stream);
+  std::vector<double> acc(chib::KernelTimer::kMax, 0.0);
+  const int nk = tms[0].n;
+  for (int s = 0; s < n_steps && e == hipSuccess; ++s)
+    for (int k = 0; k < nk && e == hipSuccess; ++k) {
+      float ms = 0.f;
+      e = hipEventElapsedTime(&ms, tms[s].ev[k], tms[s].ev[k + 1]);
+      acc[k] += ms;
+    }
+  size_t destroyed = 0;
+  for (auto &tm : tms)
+    for (int k = 0; k < ne && destroyed < created; ++k, ++destroyed) (void)hipEventDestroy(tm.ev[k]);
+  if (e != hipSuccess) return hip_fail(st, e, "step_timed");
+  if (nk > max_kernels) return fail(CH_IB_ENOMEM, "more kernels per step than max_kernels");
+  for (int k = 0; k < nk; ++k) {
+    ms_out[k] = acc[k] / n_steps;
+    names_out[k] = tms[0].names[k];
+  }
+  *n_kernels = nk;
+  return CH_IB_OK;
+}
+
+extern "C" int ch_ib_sync(ch_ib_state *st) {
+  if (!st) return fail(CH_IB_EINVAL, "NULL state");
+  hipError_t e = hipStreamSynchronize(st->plan.stream);
+  if (e != hipSuccess) return hip_fail(st, e, "sync");
+  return st->sticky;
+}
+
+extern "C" int ch_ib_diagnostics(ch_ib_state *st, ch_ib_diag *out) {
+  if (!st || !out) return fail(CH_IB_EINVAL, "NULL argument");
+  int rc = ensure_init(st);
+  if (rc) return rc;
+  chib::Plan &p = st->plan;
+  hipError_t e = st->es == 8 ? chib::enqueue_diag<double>(p, st->cur) : chib::enqueue_diag<float>(p, st->cur);
+  double r[8];
+  if (e == hipSuccess) e = hipMemcpyAsync(r, p.red_out, sizeof(r), hipMemcpyDeviceToHost, p.stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(p.stream);
+  if (e != hipSuccess) return hip_fail(st, e, "diagnostics");
+  const double vol = std::pow(p.h, p.d);
+  out->mass_box = vol * r[0];
+  out->mass_fluid = vol * r[1];
+  out->free_energy = vol * (r[2] - (2.0 * std::sqrt(2.0) / 3.0) * p.cos_t * r[3]);
+  out->max_abs_C = r[4];
+  out->step = st->step;
+  out->status = r[5] > 0 ? CH_IB_ENAN : CH_IB_OK;
+  out->pad_ = 0;
+  if (out->status) return fail(CH_IB_ENAN, "non-finite value in C");
+  return CH_IB_OK;
+}
+
+extern "C" int ch_ib_stage(ch_ib_state *st, int stage, const void *in_device, void *out_device) {
+  if (!st || !out_device) return fail(CH_IB_EINVAL, "NULL argument");
+  chib::Plan &p = st->plan;
+  hipError_t e = hipSuccess;
+  int rc = ensure_init(st);
+  if (rc) return rc;
+  switch (stage) {
+    case CH_IB_STAGE_RHS:
+      e = st->es == 8 ? chib::enqueue_rhs<double>(p, st->cur, out_device) : chib::enqueue_rhs<float>(p, st->cur, out_device);
+      break;
+    case CH_IB_STAGE_SOLVE:
+      if (!in_device) return fail(CH_IB_EINVAL, "SOLVE needs an input");
+      e = st->es == 8 ? chib::enqueue_solve<double>(p, in_device, out_device)
+                      : chib::enqueue_solve<float>(p, in_device, out_device);
+      break;
+    case CH_IB_STAGE_PHI:
+      e = st->es == 8 ? chib::enqueue_phi<double>(p, st->cur, out_device) : chib::enqueue_phi<float>(p, st->cur, out_device);
+      break;
+    default: return fail(CH_IB_EINVAL, "unknown stage");
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(p.stream);
+  if (e != hipSuccess) return hip_fail(st, e, "stage");
+  return CH_IB_OK;
+}
+
+namespace {
+struct BlobHeader {
+  uint32_t magic, version;
+  int32_t es, d, n[3], needs_init;
+  int64_t G, NF, step;
+};
+}  // namespace
+
+extern "C" int ch_ib_state_save(ch_ib_state *st, void *buf, size_t *len) {
+  if (!st || !len) return fail(CH_IB_EINVAL, "NULL argument");
+  const chib::Plan &p = st->plan;
+  const size_t fb = (size_t)p.N * st->es, gb = (size_t)p.G * st->es;
+  const size_t need = sizeof(BlobHeader) + (2 + p.d) * fb + 3 * gb;
+  if (!buf) {
+    *len = need;
+    return CH_IB_OK;
+  }
+  if (*len < need) return fail(CH_IB_ENOMEM, "buffer too small");
+  BlobHeader hd{kMagic, 1, st->es, p.d, {p.n[0], p.n[1], p.n[2]}, st->needs_init, p.G, p.NF, st->step};
+  char *b = (char *)buf;
+  std::memcpy(b, &hd, sizeof(hd));
+  b += sizeof(hd);
+  const void *srcs[8];
+  size_t sz[8];
+  int ns = 0;
+  srcs[ns] = p.C[st->cur], sz[ns++] = fb;
+  srcs[ns] = p.C[1 - st->cur], sz[ns++] = fb;
+  for (int a = 0; a < p.d; ++a) srcs[ns] = p.F[a], sz[ns++] = fb;
+  srcs[ns] = p.CGn, sz[ns++] = gb;
+  srcs[ns] = p.CGnm1, sz[ns++] = gb;
+  srcs[ns] = p.CI, sz[ns++] = gb;
+  hipError_t e = hipSuccess;
+  for (int i = 0; i < ns && e == hipSuccess; ++i) {
+    if (sz[i]) e = hipMemcpyAsync(b, srcs[i], sz[i], hipMemcpyDeviceToHost, p.stream);
+    b += sz[i];
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(p.stream);
+  if (e != hipSuccess) return hip_fail(st, e, "save");
+  *len = need;
+  return CH_IB_OK;
+}
+
+extern "C" int ch_ib_state_load(ch_ib_state *st, const void *buf, size_t len) {
+  if (!st || !buf) return fail(CH_IB_EINVAL, "NULL argument");
+  chib::Plan &p = st->plan;
+  BlobHeader hd;
+  if (len < sizeof(hd)) return fail(CH_IB_EINVAL, "blob too short");
+  std::memcpy(&hd, buf, sizeof(hd));
+  if (hd.magic != kMagic || hd.version != 1) return fail(CH_IB_EINVAL, "not a state blob");
+  if (hd.es != st->es || hd.d != p.d || hd.n[0] != p.n[0] || hd.n[1] != p.n[1] || hd.n[2] != p.n[2] ||
+      hd.G != p.G || hd.NF != p.NF)
+    return fail(CH_IB_EINVAL, "blob saved from a different grid, geometry or precision");
+  const size_t fb = (size_t)p.N * st->es, gb = (size_t)p.G * st->es;
+  const size_t need = sizeof(BlobHeader) + (2 + p.d) * fb + 3 * gb;
+  if (len < need) return fail(CH_IB_EINVAL, "blob too short");
+  const char *b = (const char *)buf + sizeof(hd);
+  st->cur = 0;
+  void *dsts[8];
+  size_t sz[8];
+  int ns = 0;
+  dsts[ns] = p.C[0], sz[ns++] = fb;
+  dsts[ns] = p.C[1], sz[ns++] = fb;
+  for (int a = 0; a < p.d; ++a) dsts[ns] = p.F[a], sz[ns++] = fb;
+  dsts[ns] = p.CGn, sz[ns++] = gb;
+  dsts[ns] = p.CGnm1, sz[ns++] = gb;
+  dsts[ns] = p.CI, sz[ns++] = gb;
+  hipError_t e = hipSuccess;
+  for (int i = 0; i < ns && e == hipSuccess; ++i) {
+    if (sz[i]) e = hipMemcpyAsync(dsts[i], b, sz[i], hipMemcpyHostToDevice, p.stream);
+    b += sz[i];
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(p.stream);
+  if (e != hipSuccess) return hip_fail(st, e, "load");
+  st->step = hd.step;
+  st->needs_init = hd.needs_init;
+  st->sticky = CH_IB_OK;
+  return CH_IB_OK;
+}
+
+extern "C" void ch_ib_state_free(ch_ib_state *st) { delete st; }

@@ -1,0 +1,89 @@
+// Internal launch interface between the host driver and the device kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace chib {
+
+// Everything one step needs, as plain values and device pointers (element type T chosen
+// by the launcher: double for precision 64, float for precision 32).
+struct Plan {
+  int d = 2;
+  int n[3] = {1, 1, 1};
+  int logn[3] = {0, 0, 0};
+  int64_t N = 0;       // cells
+  double h = 0;
+
+  // coefficients of the step (non-dimensional, see ch_ib.h)
+  double Pe = 0, Cn = 0, dt = 0, S = 0, alpha_s = 0, a = 0;
+  double cos_t = 0, Ca = 1, mu = 1, ls = 0, Vs = 0;
+  int vel_fill = 0, dynamic = 0;
+
+  // fields
+  void *C[2] = {nullptr, nullptr};
+  void *F[3] = {nullptr, nullptr, nullptr};
+  void *W = nullptr;        // spectral workspace, N elements
+  void *alpha = nullptr;    // N elements or nullptr (then alpha = 1)
+
+  // ghost tables (SoA, sorted by cell)
+  int64_t G = 0;
+  int K = 0;
+  const int *gidx = nullptr;       // [G]
+  const void *normal = nullptr;    // [d][G]
+  const void *dn = nullptr;        // [G]
+  const void *gamma = nullptr;     // [G]
+  const int *ap = nullptr;         // [2][K][G]
+  const void *w = nullptr;         // [2][K][G]
+  void *CGn = nullptr, *CGnm1 = nullptr, *CMs = nullptr, *CI = nullptr, *CGnew = nullptr;
+  void *UG = nullptr;              // [d][G]
+
+  // faces touching ghosts (velocity fill)
+  int64_t NF = 0;
+  const int *f_cell = nullptr;     // left cell of the face
+  const int *f_axis = nullptr;
+  const int *f_gL = nullptr;       // ghost index of the left cell or -1
+  const int *f_gR = nullptr;       // ghost index of the right cell or -1
+  void *stashL = nullptr, *stashR = nullptr;
+
+  // transform tables (element type T): FFT twiddles exp(-2 pi i m / n_a) per axis,
+  // cos/sin(pi k / (2 n_last)) for the cosine transform, 1D eigenvalues per axis
+  const void *twr[3] = {nullptr, nullptr, nullptr};
+  const void *twi[3] = {nullptr, nullptr, nullptr};
+  const void *dctc = nullptr, *dcts = nullptr;
+  const void *lam[3] = {nullptr, nullptr, nullptr};
+
+  // reduction scratch: partial[nred][8] and out[8] in double
+  void *partial = nullptr;
+  void *red_out = nullptr;
+  int nred = 0;
+
+  hipStream_t stream = nullptr;
+};
+
+// Optional per-kernel event recorder for measured steps.
+struct KernelTimer {
+  static constexpr int kMax = 16;
+  hipEvent_t ev[kMax + 1];
+  const char *names[kMax];
+  int n = 0;
+  hipError_t mark(const char *name, hipStream_t s) {
+    if (n >= kMax) return hipErrorInvalidValue;
+    names[n] = name;
+    return hipEventRecord(ev[n++], s);
+  }
+  hipError_t end(hipStream_t s) { return hipEventRecord(ev[n], s); }
+};
+
+template <typename T> hipError_t enqueue_step(const Plan &p, int cur, KernelTimer *tm = nullptr);
+template <typename T> hipError_t enqueue_initial_fill(const Plan &p, int cur);
+template <typename T> hipError_t enqueue_rhs(const Plan &p, int cur, void *out);
+template <typename T> hipError_t enqueue_solve(const Plan &p, const void *in, void *out);
+template <typename T> hipError_t enqueue_phi(const Plan &p, int cur, void *out);
+template <typename T> hipError_t enqueue_diag(const Plan &p, int cur);
+
+// Launch-shape helpers shared with the host (elements per LDS tile).
+template <typename T> constexpr int tile_elems() { return 32768 / (int)sizeof(T); }  // 32 KB of LDS
+
+}  // namespace chib

@@ -1,0 +1,1105 @@
+// Device kernels of one time step of the hybrid ghost-cell IB / Cahn-Hilliard method
+// (Appendix A.1 and sections 4.2.2, 4.4 of the paper), written for gfx950 (CDNA4):
+// 64-wide wavefronts, 256-thread workgroups, 32 KB LDS tiles, XCD-aware tile order.
+//
+// Step pipeline (C^n in C[cur], C^(n-1) in C[1-cur]; the step overwrites C[1-cur]):
+//   K1  rhs + Hartley transform along x     C^n, C^(n-1), faces -> W       (contiguous lines)
+//   K2  Hartley transform along y (3D)      W -> W                          (strided columns)
+//   K3  cosine transform along the bounded axis, division by (lam-a)(lam+alpha_s),
+//       inverse cosine transform            W -> W                          (strided columns)
+//   K4  Hartley transform along y (3D)      W -> W
+//   K5  Hartley transform along x           W -> C[1-cur]  (= C* on every cell)
+//   K6  contact-angle ghost fill of C       C[1-cur] at ghost cells
+//   K7  no-penetration / Navier-slip fill of faces touching ghosts
+//
+// The Hartley transform H[k] = sum x[n] cas(2 pi k n / N) diagonalises the periodic second
+// difference exactly as the Fourier transform does (modes k and N-k share an eigenvalue) and
+// keeps every array real: N values per line, no half-spectrum padding.  Two real lines are
+// transformed at once as the real and imaginary parts of one complex FFT.  The cosine
+// transform (type II) diagonalises the second difference with reflecting box walls; it is
+// computed from one complex FFT of the even/odd reordered sequence, again two lines at once.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "kernels.h"
+
+namespace chib {
+
+namespace {
+
+constexpr int kThreads = 256;
+
+struct Dims {
+  int nx, ny, nz;
+  int lnx, lny, lnz;
+  int64_t plane;
+};
+
+template <typename T>
+struct RhsCoef {
+  T pe_cn2;   // Pe / Cn^2
+  T inv_dt;
+  T S;
+  T inv_cn2;  // 1 / Cn^2
+  T inv_h;
+  T inv_h2;
+};
+
+// Consecutive logical tiles on the same XCD (blocks are dealt round-robin to the 8 XCDs),
+// so that tiles sharing halo lines and cache lines share an L2.
+__device__ __forceinline__ int xcd_tile(int b, int nb) {
+  if ((nb & 7) == 0) {
+    const int per = nb >> 3;
+    return (b & 7) * per + (b >> 3);
+  }
+  return b;
+}
+
+template <typename T>
+__device__ __forceinline__ T lds_dummy();
+
+// ---------------------------------------------------------------------------------------
+// Complex FFT of `np` independent length-N sequences held in LDS (Stockham autosort,
+// radix 4 with one leading radix-2 stage when log2 N is odd).  Element n of sequence b has
+// its real part at s[b*ps + n*ns] and its imaginary part io elements further.  Every stage
+// stages its inputs in registers, so one LDS buffer suffices.  `bfast` orders work items
+// sequence-fastest (for interleaved column layouts), otherwise element-fastest.
+// Forward: exp(-2 pi i m / N); INV: conjugate twiddles, no 1/N scaling.
+template <typename T, int MAXIT, bool INV>
+__device__ __forceinline__ void lds_fft(T *__restrict__ s, int logN, int lognp, int ps, int ns, int io,
+                                        bool bfast, const T *__restrict__ twr, const T *__restrict__ twi) {
+  const int nt = blockDim.x;
+  const int tid = threadIdx.x;
+  const int npm = (1 << lognp) - 1;
+  int lp = 0;
+  if (logN & 1) {
+    const int lh = logN - 1;
+    const int total = 1 << (lognp + lh);
+    T xr[2 * MAXIT], xi[2 * MAXIT], yr[2 * MAXIT], yi[2 * MAXIT];
+#pragma unroll
+    for (int it = 0; it < 2 * MAXIT; ++it) {
+      const int item = tid + it * nt;
+      if (item < total) {
+        int b, i;
+        if (bfast) {
+          b = item & npm;
+          i = item >> lognp;
+        } else {
+          i = item & ((1 << lh) - 1);
+          b = item >> lh;
+        }
+        const int a0 = b * ps + i * ns;
+        const int a1 = a0 + (ns << lh);
+        xr[it] = s[a0];
+        xi[it] = s[a0 + io];
+        yr[it] = s[a1];
+        yi[it] = s[a1 + io];
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < 2 * MAXIT; ++it) {
+      const int item = tid + it * nt;
+      if (item < total) {
+        int b, i;
+        if (bfast) {
+          b = item & npm;
+          i = item >> lognp;
+        } else {
+          i = item & ((1 << lh) - 1);
+          b = item >> lh;
+        }
+        const int o0 = b * ps + (2 * i) * ns;
+        s[o0] = xr[it] + yr[it];
+        s[o0 + io] = xi[it] + yi[it];
+        s[o0 + ns] = xr[it] - yr[it];
+        s[o0 + ns + io] = xi[it] - yi[it];
+      }
+    }
+    __syncthreads();
+    lp = 1;
+  }
+  const int lq = logN - 2;
+  for (; lp < logN; lp += 2) {
+    const int p = 1 << lp;
+    const int total = 1 << (lognp + lq);
+    const int sh = logN - 2 - lp;
+    const int q4 = ns << lq;
+    T ur[4][MAXIT], ui[4][MAXIT];
+#pragma unroll
+    for (int it = 0; it < MAXIT; ++it) {
+      const int item = tid + it * nt;
+      if (item < total) {
+        int b, i;
+        if (bfast) {
+          b = item & npm;
+          i = item >> lognp;
+        } else {
+          i = item & ((1 << lq) - 1);
+          b = item >> lq;
+        }
+        const int a = b * ps + i * ns;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          ur[r][it] = s[a + r * q4];
+          ui[r][it] = s[a + r * q4 + io];
+        }
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < MAXIT; ++it) {
+      const int item = tid + it * nt;
+      if (item < total) {
+        int b, i;
+        if (bfast) {
+          b = item & npm;
+          i = item >> lognp;
+        } else {
+          i = item & ((1 << lq) - 1);
+          b = item >> lq;
+        }
+        const int k = i & (p - 1);
+        const int m1 = k << sh;
+        T vr[4], vi[4];
+        vr[0] = ur[0][it];
+        vi[0] = ui[0][it];
+#pragma unroll
+        for (int r = 1; r < 4; ++r) {
+          const int m = r * m1;
+          const T wr = twr[m];
+          const T wi = INV ? -twi[m] : twi[m];
+          vr[r] = ur[r][it] * wr - ui[r][it] * wi;
+          vi[r] = ur[r][it] * wi + ui[r][it] * wr;
+        }
+        const T ar = vr[0] + vr[2], ai = vi[0] + vi[2];
+        const T br = vr[0] - vr[2], bi = vi[0] - vi[2];
+        const T cr = vr[1] + vr[3], ci = vi[1] + vi[3];
+        const T dr = vr[1] - vr[3], di = vi[1] - vi[3];
+        const int j = ((i - k) << 2) + k;
+        const int o = b * ps + j * ns;
+        const int op = p * ns;
+        s[o] = ar + cr;
+        s[o + io] = ai + ci;
+        s[o + 2 * op] = ar - cr;
+        s[o + 2 * op + io] = ai - ci;
+        if (!INV) {  // y1 = b - i d, y3 = b + i d
+          s[o + op] = br + di;
+          s[o + op + io] = bi - dr;
+          s[o + 3 * op] = br - di;
+          s[o + 3 * op + io] = bi + dr;
+        } else {     // y1 = b + i d, y3 = b - i d
+          s[o + op] = br - di;
+          s[o + op + io] = bi + dr;
+          s[o + 3 * op] = br + di;
+          s[o + 3 * op + io] = bi - dr;
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------------------
+// Right-hand side Q of the first Helmholtz equation at one cell:
+//   Q = (Pe/Cn^2)(C^/dt - div_h(u C~)) + lap_h((C~^3 - C~ - S C~)/Cn^2)
+// with C~ = 2C^n - C^(n-1), C^ = 2C^n - C^(n-1)/2; periodic axes wrap, the bounded (last)
+// axis reflects for the Laplacian and has zero normal velocity on its box walls.
+template <typename T, int D>
+__device__ __forceinline__ T rhs_at(const T *__restrict__ Cn, const T *__restrict__ Cp, const T *__restrict__ F0,
+                                    const T *__restrict__ F1, const T *__restrict__ F2, int i, int j, int k,
+                                    const Dims &dm, const RhsCoef<T> &cf) {
+  const int nx = dm.nx;
+  const int64_t c = (int64_t)i + (int64_t)nx * ((int64_t)j + (int64_t)dm.ny * k);
+  auto ct = [&](int64_t q) { return T(2) * Cn[q] - Cp[q]; };
+  auto gf = [&](T v) { return (v * v * v - v - cf.S * v) * cf.inv_cn2; };
+  const int64_t rowb = c - i;
+  const int ip = (i + 1) & (nx - 1), im = (i - 1) & (nx - 1);
+  const T c0 = ct(c);
+  const T cxp = ct(rowb + ip), cxm = ct(rowb + im);
+  T flux = F0[c] * (c0 + cxp) - F0[rowb + im] * (cxm + c0);
+  T gsum = gf(cxp) + gf(cxm);
+  if (D == 2) {
+    const bool top = (j == dm.ny - 1), bot = (j == 0);
+    const T cyp = top ? c0 : ct(c + nx);
+    const T cym = bot ? c0 : ct(c - nx);
+    flux += (top ? T(0) : F1[c] * (c0 + cyp)) - (bot ? T(0) : F1[c - nx] * (cym + c0));
+    gsum += gf(cyp) + gf(cym);
+  } else {
+    const int jp = (j + 1) & (dm.ny - 1), jm = (j - 1) & (dm.ny - 1);
+    const int64_t cyp_i = c + (int64_t)(jp - j) * nx, cym_i = c + (int64_t)(jm - j) * nx;
+    const T cyp = ct(cyp_i), cym = ct(cym_i);
+    flux += F1[c] * (c0 + cyp) - F1[cym_i] * (cym + c0);
+    gsum += gf(cyp) + gf(cym);
+    const bool top = (k == dm.nz - 1), bot = (k == 0);
+    const T czp = top ? c0 : ct(c + dm.plane);
+    const T czm = bot ? c0 : ct(c - dm.plane);
+    flux += (top ? T(0) : F2[c] * (c0 + czp)) - (bot ? T(0) : F2[c - dm.plane] * (czm + c0));
+    gsum += gf(czp) + gf(czm);
+  }
+  const T A = flux * T(0.5) * cf.inv_h;
+  const T lap = (gsum - T(2 * D) * gf(c0)) * cf.inv_h2;
+  const T cc = T(2) * Cn[c] - T(0.5) * Cp[c];
+  return cf.pe_cn2 * (cc * cf.inv_dt - A) + lap;
+}
+
+// Untangles the complex FFT of the pair (a + i b) into the Hartley transforms of a and b:
+// with Z[k] = p + iq and Z[N-k] = r + is, H_a[k] = (p - q + r + s)/2, H_b[k] = (p + q - r + s)/2.
+template <typename T>
+__device__ __forceinline__ T hartley_of_pair(T p, T q, T r, T s, int par) {
+  return par ? (p + q - r + s) * T(0.5) : (p - q + r + s) * T(0.5);
+}
+
+// ---------------------------------------------------------------------------------------
+// K1: rhs of L consecutive x-lines into LDS, Hartley transform along x, store to W.
+template <typename T, int D, int MAXIT>
+__global__ __launch_bounds__(kThreads) void k_rhs_xdht(const T *__restrict__ Cn, const T *__restrict__ Cp,
+                                                       const T *__restrict__ F0, const T *__restrict__ F1,
+                                                       const T *__restrict__ F2, T *__restrict__ W, Dims dm,
+                                                       RhsCoef<T> cf, int logL, const T *__restrict__ twr,
+                                                       const T *__restrict__ twi) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T *s = reinterpret_cast<T *>(smem_raw);
+  const int L = 1 << logL;
+  const int nx = dm.nx;
+  const int line0 = xcd_tile(blockIdx.x, gridDim.x) * L;
+  const int tot = L << dm.lnx;
+  for (int e = threadIdx.x; e < tot; e += blockDim.x) {
+    const int l = e >> dm.lnx;
+    const int i = e & (nx - 1);
+    const int line = line0 + l;
+    int j, k;
+    if (D == 2) {
+      j = line;
+      k = 0;
+    } else {
+      j = line & (dm.ny - 1);
+      k = line >> dm.lny;
+    }
+    s[e] = rhs_at<T, D>(Cn, Cp, F0, F1, F2, i, j, k, dm, cf);
+  }
+  __syncthreads();
+  lds_fft<T, MAXIT, false>(s, dm.lnx, logL - 1, 2 * nx, 1, nx, false, twr, twi);
+  for (int e = threadIdx.x; e < tot; e += blockDim.x) {
+    const int l = e >> dm.lnx;
+    const int kx = e & (nx - 1);
+    const int kk = (nx - kx) & (nx - 1);
+    const T *pb = s + (l >> 1) * 2 * nx;
+    W[(int64_t)(line0 + l) * nx + kx] = hartley_of_pair(pb[kx], pb[nx + kx], pb[kk], pb[nx + kk], l & 1);
+  }
+}
+
+// K5 (and the forward x pass of the SOLVE stage): Hartley transform of L consecutive
+// contiguous lines of length nx from `in` to `out`.
+template <typename T, int MAXIT>
+__global__ __launch_bounds__(kThreads) void k_xdht(const T *__restrict__ in, T *__restrict__ out, int lnx,
+                                                   int logL, const T *__restrict__ twr, const T *__restrict__ twi) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T *s = reinterpret_cast<T *>(smem_raw);
+  const int L = 1 << logL;
+  const int nx = 1 << lnx;
+  const int line0 = xcd_tile(blockIdx.x, gridDim.x) * L;
+  const int tot = L << lnx;
+  const T *src = in + (int64_t)line0 * nx;
+  for (int e = threadIdx.x; e < tot; e += blockDim.x) s[e] = src[e];
+  __syncthreads();
+  lds_fft<T, MAXIT, false>(s, lnx, logL - 1, 2 * nx, 1, nx, false, twr, twi);
+  T *dst = out + (int64_t)line0 * nx;
+  for (int e = threadIdx.x; e < tot; e += blockDim.x) {
+    const int l = e >> lnx;
+    const int kx = e & (nx - 1);
+    const int kk = (nx - kx) & (nx - 1);
+    const T *pb = s + (l >> 1) * 2 * nx;
+    dst[e] = hartley_of_pair(pb[kx], pb[nx + kx], pb[kk], pb[nx + kk], l & 1);
+  }
+}
+
+// K2/K4: in-place Hartley transform along a strided axis of length N = 2^logN.  A tile is
+// B = 2^logB adjacent x-columns (contiguous in memory) times N positions; tile t covers
+// base = (t >> lognxb) * outer + (t & (nxb-1)) * B, element n at base + n*stride.
+template <typename T, int MAXIT>
+__global__ __launch_bounds__(kThreads) void k_strided_dht(T *__restrict__ W, int logN, int64_t stride, int logB,
+                                                          int lognxb, int64_t outer, const T *__restrict__ twr,
+                                                          const T *__restrict__ twi) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T *s = reinterpret_cast<T *>(smem_raw);
+  const int N = 1 << logN, B = 1 << logB;
+  const int t = xcd_tile(blockIdx.x, gridDim.x);
+  const int64_t base = (int64_t)(t >> lognxb) * outer + (int64_t)(t & ((1 << lognxb) - 1)) * B;
+  const int tot = N << logB;
+  for (int e = threadIdx.x; e < tot; e += blockDim.x) {
+    const int n = e >> logB, col = e & (B - 1);
+    s[e] = W[base + n * stride + col];
+  }
+  __syncthreads();
+  lds_fft<T, MAXIT, false>(s, logN, logB - 1, 2, B, 1, true, twr, twi);
+  for (int e = threadIdx.x; e < tot; e += blockDim.x) {
+    const int n = e >> logB, col = e & (B - 1);
+    const int nn = (N - n) & (N - 1);
+    const int cb = col & ~1;
+    W[base + n * stride + col] =
+        hartley_of_pair(s[n * B + cb], s[n * B + cb + 1], s[nn * B + cb], s[nn * B + cb + 1], col & 1);
+  }
+}
+
+// K3: along the bounded axis, per column: DCT-II (even/odd reorder + FFT + post-twiddle),
+// division by (lam - a)(lam + alpha_s) times the inverse normalisation, inverse DCT-II
+// (pre-twiddle + inverse FFT + reorder).  lam = lamx[kx] (+ lamy[ky]) + lamz[kz].
+template <typename T, int MAXIT>
+__global__ __launch_bounds__(kThreads) void k_neumann_solve(T *__restrict__ W, int logN, int64_t stride, int logB,
+                                                            int lognxb, int64_t outer, const T *__restrict__ lamx,
+                                                            const T *__restrict__ lamy, const T *__restrict__ lamz,
+                                                            T a, T alpha_s, T inv_norm, const T *__restrict__ twr,
+                                                            const T *__restrict__ twi, const T *__restrict__ dctc,
+                                                            const T *__restrict__ dcts) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T *s = reinterpret_cast<T *>(smem_raw);
+  const int N = 1 << logN, B = 1 << logB;
+  const int t = xcd_tile(blockIdx.x, gridDim.x);
+  const int xb = t & ((1 << lognxb) - 1);
+  const int oy = t >> lognxb;
+  const int64_t base = (int64_t)oy * outer + (int64_t)xb * B;
+  const int tot = N << logB;
+  for (int e = threadIdx.x; e < tot; e += blockDim.x) {
+    const int n = e >> logB, col = e & (B - 1);
+    const int pos = (n & 1) ? (N - 1 - (n >> 1)) : (n >> 1);
+    s[pos * B + col] = W[base + n * stride + col];
+  }
+  __syncthreads();
+  lds_fft<T, MAXIT, false>(s, logN, logB - 1, 2, B, 1, true, twr, twi);
+  const int half = N >> 1;
+  const int npairs = B >> 1;
+  const int items = npairs * (half + 1);
+  const T lam_y = lamy ? lamy[oy] : T(0);
+  for (int e = threadIdx.x; e < items; e += blockDim.x) {
+    const int b = e % npairs;
+    const int k = e / npairs;
+    const int kk = (N - k) & (N - 1);
+    T *zk = s + k * B + 2 * b;
+    T *zn = s + kk * B + 2 * b;
+    const T p = zk[0], q = zk[1], r = zn[0], sv = zn[1];
+    const T var = (p + r) * T(0.5), vai = (q - sv) * T(0.5);
+    const T vbr = (q + sv) * T(0.5), vbi = (r - p) * T(0.5);
+    const T c = dctc[k], sn = dcts[k];
+    const int kxa = xb * B + 2 * b;
+    const T la = lamx[kxa] + lam_y, lb = lamx[kxa + 1] + lam_y;
+    const T lk = lamz[k];
+    const T lnk = k ? lamz[N - k] : T(0);
+    // cosine-transform coefficients X[k], X[N-k] of both columns
+    T xa1 = T(2) * (c * var + sn * vai), xa2 = T(2) * (sn * var - c * vai);
+    T xb1 = T(2) * (c * vbr + sn * vbi), xb2 = T(2) * (sn * vbr - c * vbi);
+    xa1 *= inv_norm / ((la + lk - a) * (la + lk + alpha_s));
+    xb1 *= inv_norm / ((lb + lk - a) * (lb + lk + alpha_s));
+    if (k) {
+      xa2 *= inv_norm / ((la + lnk - a) * (la + lnk + alpha_s));
+      xb2 *= inv_norm / ((lb + lnk - a) * (lb + lnk + alpha_s));
+    } else {
+      xa2 = T(0);
+      xb2 = T(0);
+    }
+    // back to the reordered-sequence spectrum: V'[k] = e^{i pi k/2N} (X[k] - i X[N-k]) / 2
+    const T a1 = (c * xa1 + sn * xa2) * T(0.5), a2 = (sn * xa1 - c * xa2) * T(0.5);
+    const T b1 = (c * xb1 + sn * xb2) * T(0.5), b2 = (sn * xb1 - c * xb2) * T(0.5);
+    zk[0] = a1 - b2;
+    zk[1] = a2 + b1;
+    if (k != 0 && k != half) {
+      zn[0] = a1 + b2;
+      zn[1] = b1 - a2;
+    }
+  }
+  __syncthreads();
+  lds_fft<T, MAXIT, true>(s, logN, logB - 1, 2, B, 1, true, twr, twi);
+  for (int e = threadIdx.x; e < tot; e += blockDim.x) {
+    const int n = e >> logB, col = e & (B - 1);
+    const int pos = (n & 1) ? (N - 1 - (n >> 1)) : (n >> 1);
+    W[base + n * stride + col] = s[pos * B + col];
+  }
+}
+
+// ---------------------------------------------------------------------------------------
+// Ghost-cell helpers.
+
+template <typename T>
+__device__ __forceinline__ T mirror_gather(const T *__restrict__ f, const int *__restrict__ ap,
+                                           const T *__restrict__ w, int64_t g, int64_t G, int K) {
+  T o1 = T(0), o2 = T(0);
+  for (int k = 0; k < K; ++k) o1 += w[(int64_t)k * G + g] * f[ap[(int64_t)k * G + g]];
+  for (int k = 0; k < K; ++k) o2 += w[(int64_t)(K + k) * G + g] * f[ap[(int64_t)(K + k) * G + g]];
+  return T(2) * o1 - o2;
+}
+
+// Central-difference gradient at a cell (periodic axes wrap, the bounded axis reflects).
+template <typename T>
+__device__ __forceinline__ void grad_at(const T *__restrict__ f, int64_t c, const Dims &dm, int d, T inv2h, T *g) {
+  const int i = (int)(c & (dm.nx - 1));
+  const int64_t r = c >> dm.lnx;
+  const int j = (int)(r & (dm.ny - 1));
+  const int k = (int)(r >> dm.lny);
+  const int64_t rowb = c - i;
+  g[0] = (f[rowb + ((i + 1) & (dm.nx - 1))] - f[rowb + ((i - 1) & (dm.nx - 1))]) * inv2h;
+  if (d == 2) {
+    const int64_t up = j < dm.ny - 1 ? c + dm.nx : c;
+    const int64_t dnn = j > 0 ? c - dm.nx : c;
+    g[1] = (f[up] - f[dnn]) * inv2h;
+  } else {
+    const int jp = (j + 1) & (dm.ny - 1), jm = (j - 1) & (dm.ny - 1);
+    g[1] = (f[c + (int64_t)(jp - j) * dm.nx] - f[c + (int64_t)(jm - j) * dm.nx]) * inv2h;
+    const int64_t up = k < dm.nz - 1 ? c + dm.plane : c;
+    const int64_t dnn = k > 0 ? c - dm.plane : c;
+    g[2] = (f[up] - f[dnn]) * inv2h;
+  }
+}
+
+// Cell-centred velocity component a: mean of the two faces along a (box-wall faces read 0).
+template <typename T>
+__device__ __forceinline__ T centred_u(const T *__restrict__ Fa, int64_t c, int a, const Dims &dm, int d) {
+  int64_t step;
+  int idx, n;
+  const int i = (int)(c & (dm.nx - 1));
+  const int64_t r = c >> dm.lnx;
+  const int j = (int)(r & (dm.ny - 1));
+  const int k = (int)(r >> dm.lny);
+  if (a == 0) {
+    const int64_t rowb = c - i;
+    return T(0.5) * (Fa[rowb + ((i - 1) & (dm.nx - 1))] + Fa[c]);
+  }
+  if (a == 1) {
+    step = dm.nx;
+    idx = j;
+    n = dm.ny;
+  } else {
+    step = dm.plane;
+    idx = k;
+    n = dm.nz;
+  }
+  if (a < d - 1) {  // periodic y in 3D
+    const int jm = (j - 1) & (dm.ny - 1);
+    return T(0.5) * (Fa[c + (int64_t)(jm - j) * dm.nx] + Fa[c]);
+  }
+  const T lo = idx > 0 ? Fa[c - step] : T(0);
+  const T hi = idx < n - 1 ? Fa[c] : T(0);
+  return T(0.5) * (lo + hi);
+}
+
+// K6 (static condition, no contact-line friction): per ghost, C_M = 2 IDW(IP1) - IDW(IP2),
+// C_I solves b C_I^2 + C_I - (C_M + b) = 0 with b = gamma dn cos(theta)/(sqrt2 Cn) (the
+// algebraic wall condition of Eq. WallBCS with mu_f = 0 together with Eqs.
+// interpolationAtWall and ProjectingToNT), C_G = ((gamma+1) C_I - C_M)/gamma (Eq. UpdateC).
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_fill_static(T *__restrict__ C, const int *__restrict__ gidx,
+                                                          const T *__restrict__ dn, const T *__restrict__ gam,
+                                                          const int *__restrict__ ap, const T *__restrict__ w,
+                                                          T *__restrict__ CGn, T *__restrict__ CGnm1,
+                                                          T *__restrict__ CMs, int64_t G, int K, T cb, int init) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= G) return;
+  const T CM = mirror_gather(C, ap, w, g, G, K);
+  const T ga = gam[g];
+  const T b = ga * dn[g] * cb;
+  const T q = CM + b;
+  T disc = T(1) + T(4) * b * q;
+  disc = disc > T(0) ? disc : T(0);
+  const T CI = T(2) * q / (T(1) + sqrt(disc));
+  const T CG = ((ga + T(1)) * CI - CM) / ga;
+  C[gidx[g]] = CG;
+  CMs[g] = CM;
+  CGnm1[g] = init ? CG : CGn[g];
+  CGn[g] = CG;
+}
+
+// Dynamic condition, part 1: provisional ghost values C^_G = 2 C^n_G - C^(n-1)_G.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_scatter_pg(T *__restrict__ C, const int *__restrict__ gidx,
+                                                         const T *__restrict__ CGn, const T *__restrict__ CGnm1,
+                                                         int64_t G) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= G) return;
+  C[gidx[g]] = T(2) * CGn[g] - CGnm1[g];
+}
+
+// Dynamic condition, part 2 (Eqs. interpolationAtWall, ProjectingToNT, WallBCS_recast):
+// C_I <- C_I + dt [ -u_I . grad_t C_I + Vs (Cn dC/dn + cos(theta)(1 - C_I*^2)/sqrt2) ],
+// C_I* = (gamma C^_G + C_M)/(gamma+1), dC/dn = (C_M - C^_G)/((1+gamma) dn); then
+// C_G = ((gamma+1) C_I - C_M)/gamma.  All reads from the provisional field (Jacobi).
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_fill_dynamic(
+    const T *__restrict__ C, const T *__restrict__ F0, const T *__restrict__ F1, const T *__restrict__ F2,
+    const int *__restrict__ gidx, const T *__restrict__ nrm, const T *__restrict__ dn, const T *__restrict__ gam,
+    const int *__restrict__ ap, const T *__restrict__ w, T *__restrict__ CI, T *__restrict__ CGnew,
+    T *__restrict__ CMs, int64_t G, int K, Dims dm, int d, T inv2h, T Cn, T Vs, T cos_t, T dt, int init) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= G) return;
+  const int64_t cg = gidx[g];
+  const T PG = C[cg];
+  const T CM = mirror_gather(C, ap, w, g, G, K);
+  const T ga = gam[g];
+  const T CIs = (ga * PG + CM) / (ga + T(1));
+  CMs[g] = CM;
+  if (init) {
+    CI[g] = CIs;
+    CGnew[g] = PG;
+    return;
+  }
+  T gG[3] = {0, 0, 0}, gM[3] = {0, 0, 0}, n[3] = {0, 0, 0}, uG[3] = {0, 0, 0}, uM[3] = {0, 0, 0};
+  grad_at(C, cg, dm, d, inv2h, gG);
+  const T *Fs[3] = {F0, F1, F2};
+  for (int jp = 0; jp < 2; ++jp) {
+    const T coef = jp == 0 ? T(2) : T(-1);
+    for (int k = 0; k < K; ++k) {
+      const int64_t sl = (int64_t)(jp * K + k) * G + g;
+      const T wk = w[sl];
+      const int64_t c = ap[sl];
+      T gk[3];
+      grad_at(C, c, dm, d, inv2h, gk);
+      for (int a = 0; a < d; ++a) {
+        gM[a] += coef * wk * gk[a];
+        uM[a] += coef * wk * centred_u(Fs[a], c, a, dm, d);
+      }
+    }
+  }
+  T gn = T(0), un = T(0);
+  for (int a = 0; a < d; ++a) {
+    n[a] = nrm[(int64_t)a * G + g];
+    uG[a] = centred_u(Fs[a], cg, a, dm, d);
+  }
+  T gI[3], uI[3];
+  for (int a = 0; a < d; ++a) {
+    gI[a] = (ga * gG[a] + gM[a]) / (ga + T(1));
+    uI[a] = (ga * uG[a] + uM[a]) / (ga + T(1));
+    gn += gI[a] * n[a];
+  }
+  T adv = T(0);
+  for (int a = 0; a < d; ++a) adv += uI[a] * (gI[a] - gn * n[a]);
+  (void)un;
+  const T dCdn = (CM - PG) / ((T(1) + ga) * dn[g]);
+  const T rhs = -adv + Vs * (Cn * dCdn + cos_t * (T(1) - CIs * CIs) * T(0.70710678118654752440));
+  const T ci = CI[g] + dt * rhs;
+  CI[g] = ci;
+  CGnew[g] = ((ga + T(1)) * ci - CM) / ga;
+}
+
+// Dynamic condition, part 3: write the new ghost values and rotate the per-ghost history.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_commit_ghosts(T *__restrict__ C, const int *__restrict__ gidx,
+                                                            const T *__restrict__ CGnew, T *__restrict__ CGn,
+                                                            T *__restrict__ CGnm1, int64_t G, int init) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= G) return;
+  const T v = CGnew[g];
+  C[gidx[g]] = v;
+  CGnm1[g] = init ? v : CGn[g];
+  CGn[g] = v;
+}
+
+// K7a: ghost velocities (Eqs. NoPenetration, UpdateVtan, UpdateVandW in vector form) and,
+// for the faces touching ghosts, the cell-centred velocity of their non-ghost side, all
+// from the faces as they are before this fill.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_vel_ghosts(
+    const T *__restrict__ C, const T *__restrict__ F0, const T *__restrict__ F1, const T *__restrict__ F2,
+    const int *__restrict__ gidx, const T *__restrict__ nrm, const T *__restrict__ dn, const T *__restrict__ gam,
+    const int *__restrict__ ap, const T *__restrict__ w, const T *__restrict__ CMs, T *__restrict__ UG, int64_t G,
+    int K, const int *__restrict__ f_cell, const int *__restrict__ f_axis, const int *__restrict__ f_gL,
+    const int *__restrict__ f_gR, T *__restrict__ stashL, T *__restrict__ stashR, int64_t NF, Dims dm, int d,
+    T inv2h, T Cn, T cos_t, T inv_Ca, T inv_mu, T ls) {
+  const int64_t tg = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const T *Fs[3] = {F0, F1, F2};
+  if (tg >= G) {
+    const int64_t f = tg - G;
+    if (f >= NF) return;
+    const int a = f_axis[f];
+    const int64_t cL = f_cell[f];
+    int64_t cR;
+    {
+      const int i = (int)(cL & (dm.nx - 1));
+      const int64_t r = cL >> dm.lnx;
+      const int j = (int)(r & (dm.ny - 1));
+      if (a == 0) cR = cL - i + ((i + 1) & (dm.nx - 1));
+      else if (a == 1) cR = (d == 3) ? cL + (int64_t)(((j + 1) & (dm.ny - 1)) - j) * dm.nx : cL + dm.nx;
+      else cR = cL + dm.plane;
+    }
+    stashL[f] = f_gL[f] < 0 ? centred_u(Fs[a], cL, a, dm, d) : T(0);
+    stashR[f] = f_gR[f] < 0 ? centred_u(Fs[a], cR, a, dm, d) : T(0);
+    return;
+  }
+  const int64_t g = tg;
+  const int64_t cg = gidx[g];
+  const T ga = gam[g], dng = dn[g];
+  T n[3] = {0, 0, 0}, uM[3] = {0, 0, 0}, gG[3] = {0, 0, 0}, gM[3] = {0, 0, 0};
+  for (int a = 0; a < d; ++a) n[a] = nrm[(int64_t)a * G + g];
+  grad_at(C, cg, dm, d, inv2h, gG);
+  for (int jp = 0; jp < 2; ++jp) {
+    const T coef = jp == 0 ? T(2) : T(-1);
+    for (int k = 0; k < K; ++k) {
+      const int64_t sl = (int64_t)(jp * K + k) * G + g;
+      const T wk = w[sl];
+      const int64_t c = ap[sl];
+      T gk[3];
+      grad_at(C, c, dm, d, inv2h, gk);
+      for (int a = 0; a < d; ++a) {
+        gM[a] += coef * wk * gk[a];
+        uM[a] += coef * wk * centred_u(Fs[a], c, a, dm, d);
+      }
+    }
+  }
+  T VnM = T(0), gIn = T(0), gI[3];
+  for (int a = 0; a < d; ++a) {
+    VnM += uM[a] * n[a];
+    gI[a] = (ga * gG[a] + gM[a]) / (ga + T(1));
+    gIn += gI[a] * n[a];
+  }
+  const T VnG = -VnM / ga;
+  const T CG = C[cg], CM = CMs[g];
+  const T CIv = (ga * CG + CM) / (ga + T(1));
+  const T dCdn = (CM - CG) / ((T(1) + ga) * dng);
+  const T Kc = (T(1.06066017177982128660) * Cn * dCdn + T(0.75) * cos_t * (T(1) - CIv * CIv)) * inv_Ca;
+  const T den = ls + ga * dng;
+  const T fM = (ls - dng) / den;
+  const T fK = ls * (ga + T(1)) * dng * inv_mu / den;
+  for (int a = 0; a < d; ++a) {
+    const T VtM = uM[a] - VnM * n[a];
+    const T gt = gI[a] - gIn * n[a];
+    const T VtG = VtM * fM - Kc * gt * fK;
+    UG[(int64_t)a * G + g] = VnG * n[a] + VtG;
+  }
+}
+
+// K7b: every face touching a ghost becomes the mean of its two cell-centred values.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_vel_faces(T *__restrict__ F0, T *__restrict__ F1, T *__restrict__ F2,
+                                                        const T *__restrict__ UG, int64_t G,
+                                                        const int *__restrict__ f_cell, const int *__restrict__ f_axis,
+                                                        const int *__restrict__ f_gL, const int *__restrict__ f_gR,
+                                                        const T *__restrict__ stashL, const T *__restrict__ stashR,
+                                                        int64_t NF) {
+  const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= NF) return;
+  const int a = f_axis[f];
+  const int gL = f_gL[f], gR = f_gR[f];
+  const T vL = gL >= 0 ? UG[(int64_t)a * G + gL] : stashL[f];
+  const T vR = gR >= 0 ? UG[(int64_t)a * G + gR] : stashR[f];
+  T *Fa = a == 0 ? F0 : (a == 1 ? F1 : F2);
+  Fa[f_cell[f]] = T(0.5) * (vL + vR);
+}
+
+// ---------------------------------------------------------------------------------------
+// Chemical potential phi = C^3 - C - Cn^2 lap_h C on every cell, then the mirror value at
+// the ghosts (dphi/dn = 0).
+template <typename T, int D>
+__global__ __launch_bounds__(kThreads) void k_phi(const T *__restrict__ C, T *__restrict__ phi, Dims dm, T cn2,
+                                                  T inv_h2, int64_t N) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= N) return;
+  const int i = (int)(c & (dm.nx - 1));
+  const int64_t r = c >> dm.lnx;
+  const int j = (int)(r & (dm.ny - 1));
+  const int k = (int)(r >> dm.lny);
+  const int64_t rowb = c - i;
+  const T c0 = C[c];
+  T sum = C[rowb + ((i + 1) & (dm.nx - 1))] + C[rowb + ((i - 1) & (dm.nx - 1))];
+  if (D == 2) {
+    sum += (j < dm.ny - 1 ? C[c + dm.nx] : c0) + (j > 0 ? C[c - dm.nx] : c0);
+  } else {
+    const int jp = (j + 1) & (dm.ny - 1), jm = (j - 1) & (dm.ny - 1);
+    sum += C[c + (int64_t)(jp - j) * dm.nx] + C[c + (int64_t)(jm - j) * dm.nx];
+    sum += (k < dm.nz - 1 ? C[c + dm.plane] : c0) + (k > 0 ? C[c - dm.plane] : c0);
+  }
+  const T lap = (sum - T(2 * D) * c0) * inv_h2;
+  phi[c] = c0 * c0 * c0 - c0 - cn2 * lap;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_phi_ghost(T *__restrict__ phi, const int *__restrict__ gidx,
+                                                        const int *__restrict__ ap, const T *__restrict__ w,
+                                                        int64_t G, int K) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= G) return;
+  phi[gidx[g]] = mirror_gather(phi, ap, w, g, G, K);
+}
+
+template <typename T, int D>
+__global__ __launch_bounds__(kThreads) void k_rhs_only(const T *__restrict__ Cn, const T *__restrict__ Cp,
+                                                       const T *__restrict__ F0, const T *__restrict__ F1,
+                                                       const T *__restrict__ F2, T *__restrict__ Q, Dims dm,
+                                                       RhsCoef<T> cf, int64_t N) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= N) return;
+  const int i = (int)(c & (dm.nx - 1));
+  const int64_t r = c >> dm.lnx;
+  const int j = (int)(r & (dm.ny - 1));
+  const int k = (int)(r >> dm.lny);
+  Q[c] = rhs_at<T, D>(Cn, Cp, F0, F1, F2, i, j, k, dm, cf);
+}
+
+// ---------------------------------------------------------------------------------------
+// Diagnostics: fixed-order two-pass reductions (deterministic).  Slots: 0 sum C, 1 sum
+// alpha C, 2 sum alpha (bulk + gradient energy density), 3 sum |grad alpha| g(C),
+// 4 max |C|, 5 count of non-finite C.
+template <typename T, int D>
+__global__ __launch_bounds__(kThreads) void k_diag_partial(const T *__restrict__ C, const T *__restrict__ alpha,
+                                                           double *__restrict__ partial, Dims dm, double Cn,
+                                                           double inv_h, int64_t N) {
+  __shared__ double red[6][kThreads];
+  double acc[6] = {0, 0, 0, 0, 0, 0};
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < N; c += stride) {
+    const double v = (double)C[c];
+    const double al = alpha ? (double)alpha[c] : 1.0;
+    if (!(v == v) || v - v != 0.0) {
+      acc[5] += 1.0;
+      continue;
+    }
+    const int i = (int)(c & (dm.nx - 1));
+    const int64_t r = c >> dm.lnx;
+    const int j = (int)(r & (dm.ny - 1));
+    const int k = (int)(r >> dm.lny);
+    const int64_t rowb = c - i;
+    double g2 = 0.0;
+    double ga2 = 0.0;
+    {
+      const double dx = ((double)C[rowb + ((i + 1) & (dm.nx - 1))] - v) * inv_h;
+      g2 += dx * dx;
+      if (alpha) {
+        const double da = ((double)alpha[rowb + ((i + 1) & (dm.nx - 1))] -
+                           (double)alpha[rowb + ((i - 1) & (dm.nx - 1))]) * 0.5 * inv_h;
+        ga2 += da * da;
+      }
+    }
+    if (D == 2) {
+      const double up = j < dm.ny - 1 ? (double)C[c + dm.nx] : v;
+      const double dy = (up - v) * inv_h;
+      g2 += dy * dy;
+      if (alpha) {
+        const double au = j < dm.ny - 1 ? (double)alpha[c + dm.nx] : al;
+        const double ad = j > 0 ? (double)alpha[c - dm.nx] : al;
+        const double da = (au - ad) * 0.5 * inv_h;
+        ga2 += da * da;
+      }
+    } else {
+      const int jp = (j + 1) & (dm.ny - 1), jm = (j - 1) & (dm.ny - 1);
+      const double dy = ((double)C[c + (int64_t)(jp - j) * dm.nx] - v) * inv_h;
+      g2 += dy * dy;
+      const double up = k < dm.nz - 1 ? (double)C[c + dm.plane] : v;
+      const double dz = (up - v) * inv_h;
+      g2 += dz * dz;
+      if (alpha) {
+        const double day = ((double)alpha[c + (int64_t)(jp - j) * dm.nx] -
+                            (double)alpha[c + (int64_t)(jm - j) * dm.nx]) * 0.5 * inv_h;
+        const double au = k < dm.nz - 1 ? (double)alpha[c + dm.plane] : al;
+        const double ad = k > 0 ? (double)alpha[c - dm.plane] : al;
+        const double daz = (au - ad) * 0.5 * inv_h;
+        ga2 += day * day + daz * daz;
+      }
+    }
+    const double bulk = (v * v - 1.0) * (v * v - 1.0) / (4.0 * Cn);
+    acc[0] += v;
+    acc[1] += al * v;
+    acc[2] += al * (bulk + 0.5 * Cn * g2);
+    acc[3] += sqrt(ga2) * (2.0 + 3.0 * v - v * v * v) * 0.25;
+    acc[4] = fmax(acc[4], fabs(v));
+  }
+  for (int s = 0; s < 6; ++s) red[s][threadIdx.x] = acc[s];
+  __syncthreads();
+  for (int w = kThreads / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      for (int s = 0; s < 6; ++s) {
+        if (s == 4) red[s][threadIdx.x] = fmax(red[s][threadIdx.x], red[s][threadIdx.x + w]);
+        else red[s][threadIdx.x] += red[s][threadIdx.x + w];
+      }
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x < 6) partial[(int64_t)blockIdx.x * 8 + threadIdx.x] = red[threadIdx.x][0];
+}
+
+__global__ __launch_bounds__(kThreads) void k_diag_final(const double *__restrict__ partial, int nred,
+                                                         double *__restrict__ out) {
+  __shared__ double red[6][kThreads];
+  double acc[6] = {0, 0, 0, 0, 0, 0};
+  for (int b = threadIdx.x; b < nred; b += blockDim.x)
+    for (int s = 0; s < 6; ++s) {
+      const double v = partial[(int64_t)b * 8 + s];
+      if (s == 4) acc[s] = fmax(acc[s], v);
+      else acc[s] += v;
+    }
+  for (int s = 0; s < 6; ++s) red[s][threadIdx.x] = acc[s];
+  __syncthreads();
+  for (int w = kThreads / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w)
+      for (int s = 0; s < 6; ++s) {
+        if (s == 4) red[s][threadIdx.x] = fmax(red[s][threadIdx.x], red[s][threadIdx.x + w]);
+        else red[s][threadIdx.x] += red[s][threadIdx.x + w];
+      }
+    __syncthreads();
+  }
+  if (threadIdx.x < 6) out[threadIdx.x] = red[threadIdx.x][0];
+}
+
+// ---------------------------------------------------------------------------------------
+// Host-side launch shapes.
+
+inline int ilog2(int v) {
+  int l = 0;
+  while ((1 << l) < v) ++l;
+  return l;
+}
+
+inline Dims make_dims(const Plan &p) {
+  Dims dm;
+  dm.nx = p.n[0];
+  dm.ny = p.n[1];
+  dm.nz = p.d == 3 ? p.n[2] : 1;
+  dm.lnx = p.logn[0];
+  dm.lny = p.logn[1];
+  dm.lnz = p.d == 3 ? p.logn[2] : 0;
+  dm.plane = (int64_t)dm.nx * dm.ny;
+  return dm;
+}
+
+template <typename T>
+inline RhsCoef<T> make_coef(const Plan &p) {
+  RhsCoef<T> cf;
+  cf.pe_cn2 = (T)(p.Pe / (p.Cn * p.Cn));
+  cf.inv_dt = (T)(1.0 / p.dt);
+  cf.S = (T)p.S;
+  cf.inv_cn2 = (T)(1.0 / (p.Cn * p.Cn));
+  cf.inv_h = (T)(1.0 / p.h);
+  cf.inv_h2 = (T)(1.0 / (p.h * p.h));
+  return cf;
+}
+
+inline unsigned blocks_for(int64_t n) { return (unsigned)((n + kThreads - 1) / kThreads); }
+
+template <typename T>
+constexpr int kMaxIt = tile_elems<T>() / (8 * kThreads);
+
+// Lines per tile for the contiguous x passes: as many as fit the 32 KB LDS tile.
+inline int lines_log(const Plan &p, int E) {
+  const int lines = p.d == 3 ? p.n[1] * p.n[2] : p.n[1];
+  int L = E / p.n[0];
+  if (L > lines) L = lines;
+  if (L < 2) L = 2;
+  return ilog2(L);
+}
+
+inline int cols_log(const Plan &p, int N, int E) {
+  int B = E / N;
+  if (B > p.n[0]) B = p.n[0];
+  if (B < 2) B = 2;
+  return ilog2(B);
+}
+
+template <typename T>
+hipError_t launch_xdht(const Plan &p, const T *in, T *out) {
+  constexpr int E = tile_elems<T>();
+  const int logL = lines_log(p, E);
+  const int lines = p.d == 3 ? p.n[1] * p.n[2] : p.n[1];
+  const unsigned nb = (unsigned)(lines >> logL);
+  const size_t lds = (size_t)(1 << logL) * p.n[0] * sizeof(T);
+  hipLaunchKernelGGL((k_xdht<T, kMaxIt<T>>), dim3(nb), dim3(kThreads), lds, p.stream, in, out, p.logn[0], logL,
+                     (const T *)p.twr[0], (const T *)p.twi[0]);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_spectral_tail(const Plan &p, KernelTimer *tm = nullptr) {
+  constexpr int E = tile_elems<T>();
+  T *W = (T *)p.W;
+  const int nx = p.n[0];
+  hipError_t e = hipSuccess;
+  auto mark = [&](const char *name) {
+    if (tm && e == hipSuccess) e = tm->mark(name, p.stream);
+  };
+  if (p.d == 3) {
+    mark("ydht_fwd");
+    const int lb = cols_log(p, p.n[1], E);
+    const int lxb = p.logn[0] - lb;
+    const unsigned nb = (unsigned)((nx >> lb) * p.n[2]);
+    const size_t lds = (size_t)(1 << lb) * p.n[1] * sizeof(T);
+    hipLaunchKernelGGL((k_strided_dht<T, kMaxIt<T>>), dim3(nb), dim3(kThreads), lds, p.stream, W, p.logn[1],
+                       (int64_t)nx, lb, lxb, (int64_t)nx * p.n[1], (const T *)p.twr[1], (const T *)p.twi[1]);
+  }
+  {
+    mark("neumann_solve");
+    const int ax = p.d - 1;
+    const int Nn = p.n[ax];
+    const int lb = cols_log(p, Nn, E);
+    const int lxb = p.logn[0] - lb;
+    const int64_t stride = p.d == 3 ? (int64_t)nx * p.n[1] : (int64_t)nx;
+    const int64_t outer = p.d == 3 ? (int64_t)nx : 0;
+    const unsigned nb = (unsigned)((nx >> lb) * (p.d == 3 ? p.n[1] : 1));
+    const size_t lds = (size_t)(1 << lb) * Nn * sizeof(T);
+    double norm = (double)p.N;  // 1/(nx [ny] n_last): inverse Hartley scales and the inverse FFT
+    hipLaunchKernelGGL((k_neumann_solve<T, kMaxIt<T>>), dim3(nb), dim3(kThreads), lds, p.stream, W, p.logn[ax],
+                       stride, lb, lxb, outer, (const T *)p.lam[0], p.d == 3 ? (const T *)p.lam[1] : (const T *)nullptr,
+                       (const T *)p.lam[ax], (T)p.a, (T)p.alpha_s, (T)(1.0 / norm), (const T *)p.twr[ax],
+                       (const T *)p.twi[ax], (const T *)p.dctc, (const T *)p.dcts);
+  }
+  if (p.d == 3) {
+    mark("ydht_inv");
+    const int lb = cols_log(p, p.n[1], E);
+    const int lxb = p.logn[0] - lb;
+    const unsigned nb = (unsigned)((nx >> lb) * p.n[2]);
+    const size_t lds = (size_t)(1 << lb) * p.n[1] * sizeof(T);
+    hipLaunchKernelGGL((k_strided_dht<T, kMaxIt<T>>), dim3(nb), dim3(kThreads), lds, p.stream, W, p.logn[1],
+                       (int64_t)nx, lb, lxb, (int64_t)nx * p.n[1], (const T *)p.twr[1], (const T *)p.twi[1]);
+  }
+  if (e != hipSuccess) return e;
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_ghost_fill(const Plan &p, T *Cout, int init) {
+  if (p.G == 0) return hipSuccess;
+  const unsigned nb = blocks_for(p.G);
+  const Dims dm = make_dims(p);
+  if (!p.dynamic) {
+    const T cb = (T)(p.cos_t / (1.4142135623730951 * p.Cn));
+    hipLaunchKernelGGL((k_fill_static<T>), dim3(nb), dim3(kThreads), 0, p.stream, Cout, p.gidx, (const T *)p.dn,
+                       (const T *)p.gamma, p.ap, (const T *)p.w, (T *)p.CGn, (T *)p.CGnm1, (T *)p.CMs, p.G, p.K, cb,
+                       init);
+  } else {
+    if (!init)
+      hipLaunchKernelGGL((k_scatter_pg<T>), dim3(nb), dim3(kThreads), 0, p.stream, Cout, p.gidx,
+                         (const T *)p.CGn, (const T *)p.CGnm1, p.G);
+    hipLaunchKernelGGL((k_fill_dynamic<T>), dim3(nb), dim3(kThreads), 0, p.stream, (const T *)Cout,
+                       (const T *)p.F[0], (const T *)p.F[1], (const T *)p.F[2], p.gidx, (const T *)p.normal,
+                       (const T *)p.dn, (const T *)p.gamma, p.ap, (const T *)p.w, (T *)p.CI, (T *)p.CGnew,
+                       (T *)p.CMs, p.G, p.K, dm, p.d, (T)(0.5 / p.h), (T)p.Cn, (T)p.Vs, (T)p.cos_t, (T)p.dt, init);
+    hipLaunchKernelGGL((k_commit_ghosts<T>), dim3(nb), dim3(kThreads), 0, p.stream, Cout, p.gidx,
+                       (const T *)p.CGnew, (T *)p.CGn, (T *)p.CGnm1, p.G, init);
+  }
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_velocity_fill(const Plan &p, const T *Cfin) {
+  if (!p.vel_fill || p.G == 0) return hipSuccess;
+  const Dims dm = make_dims(p);
+  hipLaunchKernelGGL((k_vel_ghosts<T>), dim3(blocks_for(p.G + p.NF)), dim3(kThreads), 0, p.stream, Cfin,
+                     (const T *)p.F[0], (const T *)p.F[1], (const T *)p.F[2], p.gidx, (const T *)p.normal,
+                     (const T *)p.dn, (const T *)p.gamma, p.ap, (const T *)p.w, (const T *)p.CMs, (T *)p.UG, p.G,
+                     p.K, p.f_cell, p.f_axis, p.f_gL, p.f_gR, (T *)p.stashL, (T *)p.stashR, p.NF, dm, p.d,
+                     (T)(0.5 / p.h), (T)p.Cn, (T)p.cos_t, (T)(1.0 / p.Ca), (T)(1.0 / p.mu), (T)p.ls);
+  if (p.NF)
+    hipLaunchKernelGGL((k_vel_faces<T>), dim3(blocks_for(p.NF)), dim3(kThreads), 0, p.stream, (T *)p.F[0],
+                       (T *)p.F[1], (T *)p.F[2], (const T *)p.UG, p.G, p.f_cell, p.f_axis, p.f_gL, p.f_gR,
+                       (const T *)p.stashL, (const T *)p.stashR, p.NF);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+template <typename T>
+hipError_t enqueue_step(const Plan &p, int cur, KernelTimer *tm) {
+  constexpr int E = tile_elems<T>();
+  const T *Cn = (const T *)p.C[cur];
+  T *Cp = (T *)p.C[1 - cur];
+  const Dims dm = make_dims(p);
+  const RhsCoef<T> cf = make_coef<T>(p);
+  const int logL = lines_log(p, E);
+  const int lines = p.d == 3 ? p.n[1] * p.n[2] : p.n[1];
+  const unsigned nb = (unsigned)(lines >> logL);
+  const size_t lds = (size_t)(1 << logL) * p.n[0] * sizeof(T);
+  hipError_t e = hipSuccess;
+  auto mark = [&](const char *name) {
+    if (tm && e == hipSuccess) e = tm->mark(name, p.stream);
+  };
+  mark("rhs_xdht");
+  if (p.d == 2)
+    hipLaunchKernelGGL((k_rhs_xdht<T, 2, kMaxIt<T>>), dim3(nb), dim3(kThreads), lds, p.stream, Cn, (const T *)Cp,
+                       (const T *)p.F[0], (const T *)p.F[1], (const T *)p.F[1], (T *)p.W, dm, cf, logL,
+                       (const T *)p.twr[0], (const T *)p.twi[0]);
+  else
+    hipLaunchKernelGGL((k_rhs_xdht<T, 3, kMaxIt<T>>), dim3(nb), dim3(kThreads), lds, p.stream, Cn, (const T *)Cp,
+                       (const T *)p.F[0], (const T *)p.F[1], (const T *)p.F[2], (T *)p.W, dm, cf, logL,
+                       (const T *)p.twr[0], (const T *)p.twi[0]);
+  if (e == hipSuccess) e = hipGetLastError();
+  if (e == hipSuccess) e = launch_spectral_tail<T>(p, tm);
+  mark("xdht_out");
+  if (e == hipSuccess) e = launch_xdht<T>(p, (const T *)p.W, Cp);
+  mark("ghost_fill_C");
+  if (e == hipSuccess) e = launch_ghost_fill<T>(p, Cp, 0);
+  if (p.vel_fill && p.G) mark("ghost_fill_u");
+  if (e == hipSuccess) e = launch_velocity_fill<T>(p, Cp);
+  if (tm && e == hipSuccess) e = tm->end(p.stream);
+  return e;
+}
+
+template <typename T>
+hipError_t enqueue_initial_fill(const Plan &p, int cur) {
+  T *C = (T *)p.C[cur];
+  hipError_t e = launch_ghost_fill<T>(p, C, 1);
+  if (e != hipSuccess) return e;
+  e = launch_velocity_fill<T>(p, C);
+  if (e != hipSuccess) return e;
+  return hipMemcpyAsync(p.C[1 - cur], p.C[cur], (size_t)p.N * sizeof(T), hipMemcpyDeviceToDevice, p.stream);
+}
+
+template <typename T>
+hipError_t enqueue_rhs(const Plan &p, int cur, void *out) {
+  const Dims dm = make_dims(p);
+  const RhsCoef<T> cf = make_coef<T>(p);
+  const T *F2 = (const T *)(p.d == 3 ? p.F[2] : p.F[1]);
+  if (p.d == 2)
+    hipLaunchKernelGGL((k_rhs_only<T, 2>), dim3(blocks_for(p.N)), dim3(kThreads), 0, p.stream, (const T *)p.C[cur],
+                       (const T *)p.C[1 - cur], (const T *)p.F[0], (const T *)p.F[1], F2, (T *)out, dm, cf, p.N);
+  else
+    hipLaunchKernelGGL((k_rhs_only<T, 3>), dim3(blocks_for(p.N)), dim3(kThreads), 0, p.stream, (const T *)p.C[cur],
+                       (const T *)p.C[1 - cur], (const T *)p.F[0], (const T *)p.F[1], F2, (T *)out, dm, cf, p.N);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t enqueue_solve(const Plan &p, const void *in, void *out) {
+  hipError_t e = launch_xdht<T>(p, (const T *)in, (T *)p.W);
+  if (e != hipSuccess) return e;
+  if ((e = launch_spectral_tail<T>(p)) != hipSuccess) return e;
+  return launch_xdht<T>(p, (const T *)p.W, (T *)out);
+}
+
+template <typename T>
+hipError_t enqueue_phi(const Plan &p, int cur, void *out) {
+  const Dims dm = make_dims(p);
+  const T cn2 = (T)(p.Cn * p.Cn), ih2 = (T)(1.0 / (p.h * p.h));
+  if (p.d == 2)
+    hipLaunchKernelGGL((k_phi<T, 2>), dim3(blocks_for(p.N)), dim3(kThreads), 0, p.stream, (const T *)p.C[cur],
+                       (T *)out, dm, cn2, ih2, p.N);
+  else
+    hipLaunchKernelGGL((k_phi<T, 3>), dim3(blocks_for(p.N)), dim3(kThreads), 0, p.stream, (const T *)p.C[cur],
+                       (T *)out, dm, cn2, ih2, p.N);
+  if (p.G)
+    hipLaunchKernelGGL((k_phi_ghost<T>), dim3(blocks_for(p.G)), dim3(kThreads), 0, p.stream, (T *)out, p.gidx, p.ap,
+                       (const T *)p.w, p.G, p.K);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t enqueue_diag(const Plan &p, int cur) {
+  const Dims dm = make_dims(p);
+  if (p.d == 2)
+    hipLaunchKernelGGL((k_diag_partial<T, 2>), dim3(p.nred), dim3(kThreads), 0, p.stream, (const T *)p.C[cur],
+                       (const T *)p.alpha, (double *)p.partial, dm, p.Cn, 1.0 / p.h, p.N);
+  else
+    hipLaunchKernelGGL((k_diag_partial<T, 3>), dim3(p.nred), dim3(kThreads), 0, p.stream, (const T *)p.C[cur],
+                       (const T *)p.alpha, (double *)p.partial, dm, p.Cn, 1.0 / p.h, p.N);
+  hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(kThreads), 0, p.stream, (const double *)p.partial, p.nred,
+                     (double *)p.red_out);
+  return hipGetLastError();
+}
+
+template hipError_t enqueue_step<double>(const Plan &, int, KernelTimer *);
+template hipError_t enqueue_step<float>(const Plan &, int, KernelTimer *);
+template hipError_t enqueue_initial_fill<double>(const Plan &, int);
+template hipError_t enqueue_initial_fill<float>(const Plan &, int);
+template hipError_t enqueue_rhs<double>(const Plan &, int, void *);
+template hipError_t enqueue_rhs<float>(const Plan &, int, void *);
+template hipError_t enqueue_solve<double>(const Plan &, const void *, void *);
+template hipError_t enqueue_solve<float>(const Plan &, const void *, void *);
+template hipError_t enqueue_phi<double>(const Plan &, int, void *);
+template hipError_t enqueue_phi<float>(const Plan &, int, void *);
+template hipError_t enqueue_diag<double>(const Plan &, int);
+template hipError_t enqueue_diag<float>(const Plan &, int);
+
+}  // namespace chib

@@ -1,0 +1,99 @@
+"""CPU-side checks of the C ABI library: it loads, exports every declared entry point,
+rejects bad input before touching a GPU, and its host geometry matches the oracle's."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle.geometry import build_tables
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _chib():
+    from paper_2104_00350_amd import chib
+    return chib
+
+
+def test_library_exports_every_declared_symbol():
+    chib = _chib()
+    hdr = open(os.path.join(ROOT, "include", "ch_ib.h")).read()
+    names = set(re.findall(r"\b(ch_ib_[a-z_]+)\s*\(", hdr))
+    assert len(names) >= 20
+    for n in sorted(names):
+        assert hasattr(chib.lib, n), n
+    assert chib.lib.ch_ib_version() == 10000
+    assert chib.lib.ch_ib_strerror(-2).decode() == "geometry preprocessing failed"
+
+
+@pytest.mark.parametrize("maker", [
+    lambda: W.config1(), lambda: W.config2(0), lambda: W.config2(5),
+    lambda: W.small_case(64, 32, kind="circle"), lambda: W.small_case(64, 32, kind="tilted"),
+    lambda: W.small_case_3d(32), lambda: W.config4_cases(4)[3]])
+def test_host_geometry_matches_oracle_tables(maker):
+    chib = _chib()
+    c = maker()
+    g = c.grid
+    lib_t = chib.Geometry.build(g.n, g.lo, g.hi, c.shapes, c.params).export()
+    T = build_tables(g, c.shapes, c.params)
+    assert np.array_equal(lib_t["gidx"], T.gidx)
+    assert np.array_equal(lib_t["ap"], T.ap)
+    assert np.array_equal(lib_t["alpha"], T.alpha.reshape(-1))
+    for key, ref in (("normal", T.normal), ("dn", T.dn), ("gamma", T.gamma), ("w", T.w)):
+        assert np.max(np.abs(lib_t[key] - ref)) <= 1e-12 * max(1.0, np.max(np.abs(ref))), key
+
+
+def test_import_export_round_trip():
+    chib = _chib()
+    c = W.small_case(64, 32, kind="sin")
+    T = build_tables(c.grid, c.shapes, c.params)
+    geo = chib.Geometry.from_tables(c.grid.n, c.grid.lo, c.grid.hi, T.gidx, T.normal, T.dn, T.gamma, T.ap, T.w,
+                                    T.alpha)
+    e = geo.export()
+    assert np.array_equal(e["gidx"], T.gidx) and np.array_equal(e["ap"], T.ap)
+    assert np.array_equal(e["w"], T.w) and np.array_equal(e["normal"], T.normal)
+    assert np.array_equal(e["alpha"], T.alpha.reshape(-1))
+
+
+def test_geometry_errors():
+    chib = _chib()
+    g = W.Grid((16, 8), (0.0, 0.0), (1.0, 0.5))
+    prm = W.Params(Cn=0.05, Pe=10.0)
+    with pytest.raises(chib.ChibError) as e:
+        chib.Geometry.build(g.n, g.lo, g.hi, [W.Shape(W.HALFPLANE, (0.0, 0.05, 0.0, 0.0, 1.0, 0.0))], prm)
+    assert e.value.code == chib.EGEOM
+    with pytest.raises(chib.ChibError) as e:
+        chib.Geometry.build((12, 8), (0.0, 0.0), (1.5, 1.0), [], prm)
+    assert e.value.code == chib.EUNSUPPORTED
+    with pytest.raises(chib.ChibError) as e:
+        chib.Geometry.build((16, 8), (0.0, 0.0), (1.0, 1.0), [], prm)   # non-uniform spacing
+    assert e.value.code == chib.EINVAL
+
+
+def test_state_create_validates_before_any_device_call():
+    chib = _chib()
+    c = W.config1()
+    g = chib.make_grid(c.grid.n, c.grid.lo, c.grid.hi)
+    geo = chib.Geometry.build(c.grid.n, c.grid.lo, c.grid.hi, c.shapes, c.params)
+    p = chib.make_params(c.params)
+    need = chib.lib.ch_ib_workspace_bytes(C.byref(g), geo.h, C.byref(p))
+    assert need > 0
+    out = C.c_void_p()
+    fake = C.c_void_p(1 << 20)  # never dereferenced: validation fails first
+    assert chib.lib.ch_ib_state_create(C.byref(g), geo.h, C.byref(p), fake, need - 1, None, C.byref(out)) == chib.ENOMEM
+    p.S = 1.0   # below Cn sqrt(6 Pe/dt)
+    assert chib.lib.ch_ib_state_create(C.byref(g), geo.h, C.byref(p), fake, need, None, C.byref(out)) == chib.EINVAL
+    assert "stability bound" in chib.lib.ch_ib_last_error().decode()
+    p.S = 0.0
+    p.precision = 16
+    assert chib.lib.ch_ib_state_create(C.byref(g), geo.h, C.byref(p), fake, need, None, C.byref(out)) == chib.EINVAL
+
+
+def test_coefficients_match_oracle():
+    chib = _chib()
+    from oracle.solver import derived_coefficients
+    for c in (W.config1(), W.config2(0), W.config3(32)):
+        assert chib.coefficients(c.params) == derived_coefficients(c.params)
