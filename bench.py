@@ -71,6 +71,7 @@ def main() -> int:
     ap.add_argument("--n", type=int, default=256, help="cells per axis of the sphere workload")
     ap.add_argument("--cpu-steps", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-tune", action="store_true", help="keep the default launch shapes")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="also run one plain device copy of this size (for counter calibration)")
     args = ap.parse_args()
@@ -94,9 +95,12 @@ def main() -> int:
     st = chib.State(geo, case.params, args.precision)
     C0, faces = case.initial_fields()
     st.set_initial(C0, faces)
+    st.step(1)
+    shapes = st.shapes() if args.no_tune else st.tune(5)   # launch shapes, chosen before timing
     st.step(max(args.warmup, 1))
     st.sync()
-    print(f"[bench] geometry {t_geom:.1f}s, ghosts {st.G}, warmup done", file=sys.stderr, flush=True)
+    print(f"[bench] geometry {t_geom:.1f}s, ghosts {st.G}, shapes {shapes}, warmup done", file=sys.stderr,
+          flush=True)
 
     if args.copy_calibration_mib:
         nel = args.copy_calibration_mib * (1 << 20) // 8
@@ -154,7 +158,8 @@ def main() -> int:
         "data": "synthetic",
         "config": {"workload": f"3D sphere wall r=1 in [-2,2]^3, {args.n}^3 cells, droplet R=0.5 on top, "
                                "Cn=0.015 Pe=200 Ca=0.05 theta=90 ls=0.01 dt=1e-4, velocity fill on",
-                   "grid": list(g.n), "ghosts": st.G, "faces_touching_ghosts": NF},
+                   "grid": list(g.n), "ghosts": st.G, "faces_touching_ghosts": NF,
+                   "launch_shapes": shapes},
         "roofline": {"bound": "hbm", "kernel": dominant, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None},
         "gpu_ms_per_step_events": round(gpu_ms, 5),

@@ -206,6 +206,21 @@ int ch_ib_stage(ch_ib_state *st, int stage, const void *in_device, void *out_dev
 int ch_ib_step_timed(ch_ib_state *st, int n_steps, int max_kernels, double *ms_out, const char **names_out,
                      int *n_kernels);
 
+/* ---- launch-shape autotuning ------------------------------------------------------------------
+ * The four field passes of a step (0 fused rhs + x transform, 1 strided y transform (3D only),
+ * 2 bounded-axis solve, 3 x transform out) each have a launch shape of three ints:
+ * {log2 lines or columns per tile, largest FFT radix (8 or 16), cells in flight per thread
+ * (pass 0 only; 1 or 2)}.  Shapes change speed, never results: every shape computes the same
+ * sums in the same order per element except for the FFT radix, which changes rounding only.
+ * ch_ib_tune: times every candidate shape of each pass reps times with HIP events on the state's
+ *   buffers (the fields are left unchanged), keeps the fastest and writes the 12 chosen ints to
+ *   shapes_out (may be NULL).  Synchronous.
+ * ch_ib_get_shapes / ch_ib_set_shapes: read or impose the 12 ints (e.g. from a cache); values
+ *   are clamped to what the grid and the LDS tile allow; EINVAL on a radix other than 8 or 16. */
+int ch_ib_tune(ch_ib_state *st, int reps, int *shapes_out);
+int ch_ib_get_shapes(const ch_ib_state *st, int *shapes_out);
+int ch_ib_set_shapes(ch_ib_state *st, const int *shapes);
+
 /* ---- checkpoint / resume ---------------------------------------------------------------------
  * ch_ib_state_save: if buf is NULL, *len receives the size needed; otherwise writes a versioned
  *   blob (C^n, C^(n-1), faces, per-ghost history, step counter) and sets *len.  Synchronous.

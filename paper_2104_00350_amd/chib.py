@@ -80,6 +80,9 @@ def _load():
         "ch_ib_step_timed": (i32, [vp, i32, i32, C.POINTER(C.c_double), C.POINTER(C.c_char_p),
                                    C.POINTER(C.c_int)]),
         "ch_ib_diagnostics": (i32, [vp, C.POINTER(Diag)]),
+        "ch_ib_tune": (i32, [vp, i32, C.POINTER(C.c_int)]),
+        "ch_ib_get_shapes": (i32, [vp, C.POINTER(C.c_int)]),
+        "ch_ib_set_shapes": (i32, [vp, C.POINTER(C.c_int)]),
         "ch_ib_stage": (i32, [vp, i32, vp, vp]),
         "ch_ib_state_save": (i32, [vp, vp, C.POINTER(C.c_size_t)]),
         "ch_ib_state_load": (i32, [vp, vp, C.c_size_t]),
@@ -284,6 +287,21 @@ class State:
 
     def sync(self) -> None:
         check(lib.ch_ib_sync(self.h))
+
+    def tune(self, reps: int = 5) -> list:
+        """Autotunes the launch shapes of the four field passes; returns them (4 x [log_tile, radix, unroll])."""
+        out = (C.c_int * 12)()
+        check(lib.ch_ib_tune(self.h, int(reps), out))
+        return [list(out[3 * k:3 * k + 3]) for k in range(4)]
+
+    def shapes(self) -> list:
+        out = (C.c_int * 12)()
+        check(lib.ch_ib_get_shapes(self.h, out))
+        return [list(out[3 * k:3 * k + 3]) for k in range(4)]
+
+    def set_shapes(self, shapes) -> None:
+        flat = (C.c_int * 12)(*[int(v) for row in shapes for v in row])
+        check(lib.ch_ib_set_shapes(self.h, flat))
 
     def step_timed(self, n: int) -> dict:
         """Runs n steps with HIP events between kernels; returns {kernel name: mean ms per step}."""

@@ -527,6 +527,39 @@ extern "C" int ch_ib_step_timed(ch_ib_state *st, int n_steps, int max_kernels, d
   return CH_IB_OK;
 }
 
+extern "C" int ch_ib_get_shapes(const ch_ib_state *st, int *out) {
+  if (!st || !out) return fail(CH_IB_EINVAL, "NULL argument");
+  for (int k = 0; k < 4; ++k) {
+    out[3 * k] = st->plan.shape[k].log_tile;
+    out[3 * k + 1] = st->plan.shape[k].radix;
+    out[3 * k + 2] = st->plan.shape[k].unroll;
+  }
+  return CH_IB_OK;
+}
+
+extern "C" int ch_ib_set_shapes(ch_ib_state *st, const int *in) {
+  if (!st || !in) return fail(CH_IB_EINVAL, "NULL argument");
+  for (int k = 0; k < 4; ++k)
+    if ((in[3 * k + 1] != 8 && in[3 * k + 1] != 16) || in[3 * k] < 1 || in[3 * k] > 11 || in[3 * k + 2] < 1 ||
+        in[3 * k + 2] > 2)
+      return fail(CH_IB_EINVAL, "shape out of range");
+  for (int k = 0; k < 4; ++k) st->plan.shape[k] = {in[3 * k], in[3 * k + 1], in[3 * k + 2]};
+  return CH_IB_OK;
+}
+
+extern "C" int ch_ib_tune(ch_ib_state *st, int reps, int *out) {
+  if (!st) return fail(CH_IB_EINVAL, "NULL state");
+  if (reps < 1 || reps > 100) return fail(CH_IB_EINVAL, "reps must be in 1..100");
+  if (st->sticky) return fail(st->sticky, "state is in an error state");
+  int rc = ensure_init(st);
+  if (rc) return rc;
+  hipError_t e = st->es == 8 ? chib::tune_shapes<double>(st->plan, st->cur, reps)
+                             : chib::tune_shapes<float>(st->plan, st->cur, reps);
+  if (e == hipSuccess) e = hipStreamSynchronize(st->plan.stream);
+  if (e != hipSuccess) return hip_fail(st, e, "tune");
+  return out ? ch_ib_get_shapes(st, out) : CH_IB_OK;
+}
+
 extern "C" int ch_ib_sync(ch_ib_state *st) {
   if (!st) return fail(CH_IB_EINVAL, "NULL state");
   hipError_t e = hipStreamSynchronize(st->plan.stream);

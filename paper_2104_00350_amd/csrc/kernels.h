@@ -59,6 +59,15 @@ struct Plan {
   void *red_out = nullptr;
   int nred = 0;
 
+  // launch shapes of the four field passes: 0 fused rhs + x transform, 1 strided y
+  // transform (3D), 2 bounded-axis solve, 3 x transform out
+  struct Shape {
+    int log_tile;  // log2 lines (x passes) or columns (strided passes) per tile
+    int radix;     // largest FFT radix: 8 or 16
+    int unroll;    // cells in flight per thread (rhs pass)
+  };
+  Shape shape[4] = {{3, 8, 2}, {4, 16, 1}, {4, 16, 1}, {4, 16, 1}};
+
   hipStream_t stream = nullptr;
 };
 
@@ -78,6 +87,7 @@ struct KernelTimer {
 
 template <typename T> hipError_t enqueue_step(const Plan &p, int cur, KernelTimer *tm = nullptr);
 template <typename T> hipError_t enqueue_initial_fill(const Plan &p, int cur);
+template <typename T> hipError_t tune_shapes(Plan &p, int cur, int reps);
 template <typename T> hipError_t enqueue_rhs(const Plan &p, int cur, void *out);
 template <typename T> hipError_t enqueue_solve(const Plan &p, const void *in, void *out);
 template <typename T> hipError_t enqueue_phi(const Plan &p, int cur, void *out);

@@ -56,150 +56,252 @@ __device__ __forceinline__ int xcd_tile(int b, int nb) {
   return b;
 }
 
-template <typename T>
-__device__ __forceinline__ T lds_dummy();
-
 // ---------------------------------------------------------------------------------------
-// Complex FFT of `np` independent length-N sequences held in LDS (Stockham autosort,
-// radix 4 with one leading radix-2 stage when log2 N is odd).  Element n of sequence b has
-// its real part at s[b*ps + n*ns] and its imaginary part io elements further.  Every stage
-// stages its inputs in registers, so one LDS buffer suffices.  `bfast` orders work items
-// sequence-fastest (for interleaved column layouts), otherwise element-fastest.
-// Forward: exp(-2 pi i m / N); INV: conjugate twiddles, no 1/N scaling.
-template <typename T, int MAXIT, bool INV>
-__device__ __forceinline__ void lds_fft(T *__restrict__ s, int logN, int lognp, int ps, int ns, int io,
-                                        bool bfast, const T *__restrict__ twr, const T *__restrict__ twi) {
-  const int nt = blockDim.x;
-  const int tid = threadIdx.x;
-  const int npm = (1 << lognp) - 1;
-  int lp = 0;
-  if (logN & 1) {
-    const int lh = logN - 1;
-    const int total = 1 << (lognp + lh);
-    T xr[2 * MAXIT], xi[2 * MAXIT], yr[2 * MAXIT], yi[2 * MAXIT];
-#pragma unroll
-    for (int it = 0; it < 2 * MAXIT; ++it) {
-      const int item = tid + it * nt;
-      if (item < total) {
-        int b, i;
-        if (bfast) {
-          b = item & npm;
-          i = item >> lognp;
-        } else {
-          i = item & ((1 << lh) - 1);
-          b = item >> lh;
-        }
-        const int a0 = b * ps + i * ns;
-        const int a1 = a0 + (ns << lh);
-        xr[it] = s[a0];
-        xi[it] = s[a0 + io];
-        yr[it] = s[a1];
-        yi[it] = s[a1 + io];
-      }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int it = 0; it < 2 * MAXIT; ++it) {
-      const int item = tid + it * nt;
-      if (item < total) {
-        int b, i;
-        if (bfast) {
-          b = item & npm;
-          i = item >> lognp;
-        } else {
-          i = item & ((1 << lh) - 1);
-          b = item >> lh;
-        }
-        const int o0 = b * ps + (2 * i) * ns;
-        s[o0] = xr[it] + yr[it];
-        s[o0 + io] = xi[it] + yi[it];
-        s[o0 + ns] = xr[it] - yr[it];
-        s[o0 + ns + io] = xi[it] - yi[it];
-      }
-    }
-    __syncthreads();
-    lp = 1;
+// Register DFTs of length R in {2, 4, 8, 16}, natural order in and out.  Forward uses
+// exp(-2 pi i / R); INV the conjugate.  Twiddles are powers of w16 = exp(-2 pi i / 16).
+constexpr double kC16[16] = {1.0, 0.92387953251128675613, 0.70710678118654752440, 0.38268343236508977173,
+                             0.0, -0.38268343236508977173, -0.70710678118654752440, -0.92387953251128675613,
+                             -1.0, -0.92387953251128675613, -0.70710678118654752440, -0.38268343236508977173,
+                             0.0, 0.38268343236508977173, 0.70710678118654752440, 0.92387953251128675613};
+constexpr double kS16[16] = {0.0, 0.38268343236508977173, 0.70710678118654752440, 0.92387953251128675613,
+                             1.0, 0.92387953251128675613, 0.70710678118654752440, 0.38268343236508977173,
+                             0.0, -0.38268343236508977173, -0.70710678118654752440, -0.92387953251128675613,
+                             -1.0, -0.92387953251128675613, -0.70710678118654752440, -0.38268343236508977173};
+
+// x <- x * w16^e (forward) or x * conj(w16^e) (INV); e is a compile-time constant after unrolling.
+template <typename T, bool INV>
+__device__ __forceinline__ void rot16(T &re, T &im, int e) {
+  e &= 15;
+  if (e == 0) return;
+  if (e == 8) {
+    re = -re;
+    im = -im;
+    return;
   }
-  const int lq = logN - 2;
-  for (; lp < logN; lp += 2) {
-    const int p = 1 << lp;
-    const int total = 1 << (lognp + lq);
-    const int sh = logN - 2 - lp;
-    const int q4 = ns << lq;
-    T ur[4][MAXIT], ui[4][MAXIT];
-#pragma unroll
-    for (int it = 0; it < MAXIT; ++it) {
-      const int item = tid + it * nt;
-      if (item < total) {
-        int b, i;
-        if (bfast) {
-          b = item & npm;
-          i = item >> lognp;
-        } else {
-          i = item & ((1 << lq) - 1);
-          b = item >> lq;
-        }
-        const int a = b * ps + i * ns;
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          ur[r][it] = s[a + r * q4];
-          ui[r][it] = s[a + r * q4 + io];
-        }
-      }
+  if (e == 4 || e == 12) {  // -i (forward, e=4) / +i
+    const bool minus_i = (e == 4) != INV;
+    const T r = re;
+    if (minus_i) {
+      re = im;
+      im = -r;
+    } else {
+      re = -im;
+      im = r;
     }
-    __syncthreads();
+    return;
+  }
+  const T c = (T)kC16[e];
+  const T sn = INV ? (T)kS16[e] : -(T)kS16[e];
+  const T r = re;
+  re = r * c - im * sn;
+  im = r * sn + im * c;
+}
+
+template <typename T, int R, bool INV>
+__device__ __forceinline__ void dft_reg(T *xr, T *xi);
+
+template <typename T, int R1, int R2, bool INV>
+__device__ __forceinline__ void dft_split(T *xr, T *xi) {
+  constexpr int R = R1 * R2;
+  T yr[R], yi[R];
 #pragma unroll
-    for (int it = 0; it < MAXIT; ++it) {
-      const int item = tid + it * nt;
-      if (item < total) {
-        int b, i;
-        if (bfast) {
-          b = item & npm;
-          i = item >> lognp;
-        } else {
-          i = item & ((1 << lq) - 1);
-          b = item >> lq;
-        }
-        const int k = i & (p - 1);
-        const int m1 = k << sh;
-        T vr[4], vi[4];
-        vr[0] = ur[0][it];
-        vi[0] = ui[0][it];
+  for (int n1 = 0; n1 < R1; ++n1) {
+    T ar[R2], ai[R2];
 #pragma unroll
-        for (int r = 1; r < 4; ++r) {
-          const int m = r * m1;
-          const T wr = twr[m];
-          const T wi = INV ? -twi[m] : twi[m];
-          vr[r] = ur[r][it] * wr - ui[r][it] * wi;
-          vi[r] = ur[r][it] * wi + ui[r][it] * wr;
-        }
-        const T ar = vr[0] + vr[2], ai = vi[0] + vi[2];
-        const T br = vr[0] - vr[2], bi = vi[0] - vi[2];
-        const T cr = vr[1] + vr[3], ci = vi[1] + vi[3];
-        const T dr = vr[1] - vr[3], di = vi[1] - vi[3];
-        const int j = ((i - k) << 2) + k;
-        const int o = b * ps + j * ns;
-        const int op = p * ns;
-        s[o] = ar + cr;
-        s[o + io] = ai + ci;
-        s[o + 2 * op] = ar - cr;
-        s[o + 2 * op + io] = ai - ci;
-        if (!INV) {  // y1 = b - i d, y3 = b + i d
-          s[o + op] = br + di;
-          s[o + op + io] = bi - dr;
-          s[o + 3 * op] = br - di;
-          s[o + 3 * op + io] = bi + dr;
-        } else {     // y1 = b + i d, y3 = b - i d
-          s[o + op] = br - di;
-          s[o + op + io] = bi + dr;
-          s[o + 3 * op] = br + di;
-          s[o + 3 * op + io] = bi - dr;
-        }
-      }
+    for (int n2 = 0; n2 < R2; ++n2) {
+      ar[n2] = xr[n1 + R1 * n2];
+      ai[n2] = xi[n1 + R1 * n2];
     }
-    __syncthreads();
+    dft_reg<T, R2, INV>(ar, ai);
+#pragma unroll
+    for (int k2 = 0; k2 < R2; ++k2) {
+      rot16<T, INV>(ar[k2], ai[k2], n1 * k2 * (16 / R));
+      yr[n1 * R2 + k2] = ar[k2];
+      yi[n1 * R2 + k2] = ai[k2];
+    }
+  }
+#pragma unroll
+  for (int k2 = 0; k2 < R2; ++k2) {
+    T ar[R1], ai[R1];
+#pragma unroll
+    for (int n1 = 0; n1 < R1; ++n1) {
+      ar[n1] = yr[n1 * R2 + k2];
+      ai[n1] = yi[n1 * R2 + k2];
+    }
+    dft_reg<T, R1, INV>(ar, ai);
+#pragma unroll
+    for (int k1 = 0; k1 < R1; ++k1) {
+      xr[k2 + R2 * k1] = ar[k1];
+      xi[k2 + R2 * k1] = ai[k1];
+    }
   }
 }
+
+template <typename T, int R, bool INV>
+__device__ __forceinline__ void dft_reg(T *xr, T *xi) {
+  if constexpr (R == 2) {
+    const T ar = xr[0], ai = xi[0];
+    xr[0] = ar + xr[1];
+    xi[0] = ai + xi[1];
+    xr[1] = ar - xr[1];
+    xi[1] = ai - xi[1];
+  } else if constexpr (R == 4) {
+    const T ar = xr[0] + xr[2], ai = xi[0] + xi[2];
+    const T br = xr[0] - xr[2], bi = xi[0] - xi[2];
+    const T cr = xr[1] + xr[3], ci = xi[1] + xi[3];
+    const T dr = xr[1] - xr[3], di = xi[1] - xi[3];
+    xr[0] = ar + cr;
+    xi[0] = ai + ci;
+    xr[2] = ar - cr;
+    xi[2] = ai - ci;
+    if (!INV) {  // y1 = b - i d, y3 = b + i d
+      xr[1] = br + di;
+      xi[1] = bi - dr;
+      xr[3] = br - di;
+      xi[3] = bi + dr;
+    } else {
+      xr[1] = br - di;
+      xi[1] = bi + dr;
+      xr[3] = br + di;
+      xi[3] = bi - dr;
+    }
+  } else if constexpr (R == 8) {
+    dft_split<T, 2, 4, INV>(xr, xi);
+  } else {
+    static_assert(R == 16, "radix");
+    dft_split<T, 4, 4, INV>(xr, xi);
+  }
+}
+
+constexpr int ilog2c(int v) { return v <= 1 ? 0 : 1 + ilog2c(v >> 1); }
+
+// LDS address of element n of sequence b: b*ps + n*ns, plus padw extra elements after every
+// 16 positions (keeps the stride-16 accesses of the radix-16 stages off a single bank).
+__device__ __forceinline__ int lds_at(int b, int n, int ps, int ns, int padw) {
+  return b * ps + n * ns + (n >> 4) * padw;
+}
+
+// w^r for r = 1..R-1 from w = w^1 by products of at most four factors.
+template <typename T, int R>
+__device__ __forceinline__ void twiddle_powers(T w1r, T w1i, T *wr, T *wi) {
+  wr[1] = w1r;
+  wi[1] = w1i;
+#pragma unroll
+  for (int r = 2; r < R; ++r) {
+    const int a = (r & 1) ? r - 1 : r / 2;   // r = a + (r - a)
+    const int c = r - a;
+    wr[r] = wr[a] * wr[c] - wi[a] * wi[c];
+    wi[r] = wr[a] * wi[c] + wi[a] * wr[c];
+  }
+}
+
+// One Stockham stage of radix R over `np` sequences of length N in LDS.  p = 2^lp is the
+// product of the radices of the previous stages.  Inputs are staged in registers.
+template <typename T, int R, int IT, bool INV>
+__device__ __forceinline__ void fft_stage(T *__restrict__ s, int logN, int lognp, int ps, int ns, int io, int padw,
+                                          bool bfast, int lp, const T *__restrict__ twr, const T *__restrict__ twi) {
+  constexpr int LR = ilog2c(R);
+  const int nt = blockDim.x;
+  const int tid = threadIdx.x;
+  const int lq = logN - LR;
+  const int total = 1 << (lognp + lq);
+  const int p = 1 << lp;
+  const int sh = logN - LR - lp;
+  const int npm = (1 << lognp) - 1;
+  T xr[IT][R], xi[IT][R];
+#pragma unroll
+  for (int it = 0; it < IT; ++it) {
+    const int item = tid + it * nt;
+    if (item < total) {
+      int b, i;
+      if (bfast) {
+        b = item & npm;
+        i = item >> lognp;
+      } else {
+        i = item & ((1 << lq) - 1);
+        b = item >> lq;
+      }
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int a = lds_at(b, i + (r << lq), ps, ns, padw);
+        xr[it][r] = s[a];
+        xi[it][r] = s[a + io];
+      }
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int it = 0; it < IT; ++it) {
+    const int item = tid + it * nt;
+    if (item < total) {
+      int b, i;
+      if (bfast) {
+        b = item & npm;
+        i = item >> lognp;
+      } else {
+        i = item & ((1 << lq) - 1);
+        b = item >> lq;
+      }
+      const int k = i & (p - 1);
+      if (lp > 0) {
+        const int m = k << sh;
+        T wr[R], wi[R];
+        twiddle_powers<T, R>(twr[m], INV ? -twi[m] : twi[m], wr, wi);
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+          const T ur = xr[it][r];
+          xr[it][r] = ur * wr[r] - xi[it][r] * wi[r];
+          xi[it][r] = ur * wi[r] + xi[it][r] * wr[r];
+        }
+      }
+      dft_reg<T, R, INV>(xr[it], xi[it]);
+      const int j = ((i - k) << LR) + k;
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int a = lds_at(b, j + r * p, ps, ns, padw);
+        s[a] = xr[it][r];
+        s[a + io] = xi[it][r];
+      }
+    }
+  }
+  __syncthreads();
+}
+
+// Complex FFT of 2^lognp independent length-2^logN sequences held in LDS: mixed-radix
+// Stockham autosort with register-resident radix-16 butterflies (then 8, 4 or 2 for the
+// remaining factor).  E bounds the tile (elements of T) so that every thread holds at most
+// 16 complex values per stage.  No 1/N scaling.
+template <typename T, int E, bool INV, int MAXR = 16, int NT = 256>
+__device__ __forceinline__ void lds_fft(T *__restrict__ s, int logN, int lognp, int ps, int ns, int io, int padw,
+                                        bool bfast, const T *__restrict__ twr, const T *__restrict__ twi) {
+  constexpr int IT16 = (E / 2 / 16 + NT - 1) / NT;
+  constexpr int IT8 = (E / 2 / 8 + NT - 1) / NT;
+  constexpr int IT4 = (E / 2 / 4 + NT - 1) / NT;
+  constexpr int IT2 = (E / 2 / 2 + NT - 1) / NT;
+  int lp = 0;
+  int rem = logN;
+  if constexpr (MAXR >= 16) {
+    while (rem >= 4) {
+      fft_stage<T, 16, IT16, INV>(s, logN, lognp, ps, ns, io, padw, bfast, lp, twr, twi);
+      lp += 4;
+      rem -= 4;
+    }
+  } else {
+    while (rem >= 3) {
+      fft_stage<T, 8, IT8, INV>(s, logN, lognp, ps, ns, io, padw, bfast, lp, twr, twi);
+      lp += 3;
+      rem -= 3;
+    }
+  }
+  if (rem == 3) fft_stage<T, 8, IT8, INV>(s, logN, lognp, ps, ns, io, padw, bfast, lp, twr, twi);
+  else if (rem == 2) fft_stage<T, 4, IT4, INV>(s, logN, lognp, ps, ns, io, padw, bfast, lp, twr, twi);
+  else if (rem == 1) fft_stage<T, 2, IT2, INV>(s, logN, lognp, ps, ns, io, padw, bfast, lp, twr, twi);
+}
+
+// Padded LDS pitch of a contiguous line of n elements (one pad element per 16).
+__host__ __device__ __forceinline__ int line_pitch(int n) { return n + (n >> 4); }
+// Padded LDS size (elements) of a tile of B interleaved columns by N positions.
+__host__ __device__ __forceinline__ int col_tile(int N, int B) { return N * B + (N >> 4) * 2; }
 
 // ---------------------------------------------------------------------------------------
 // Right-hand side Q of the first Helmholtz equation at one cell:
@@ -253,7 +355,7 @@ __device__ __forceinline__ T hartley_of_pair(T p, T q, T r, T s, int par) {
 
 // ---------------------------------------------------------------------------------------
 // K1: rhs of L consecutive x-lines into LDS, Hartley transform along x, store to W.
-template <typename T, int D, int MAXIT>
+template <typename T, int D, int E, int U = 1, int MAXR = 16>
 __global__ __launch_bounds__(kThreads) void k_rhs_xdht(const T *__restrict__ Cn, const T *__restrict__ Cp,
                                                        const T *__restrict__ F0, const T *__restrict__ F1,
                                                        const T *__restrict__ F2, T *__restrict__ W, Dims dm,
@@ -265,34 +367,57 @@ __global__ __launch_bounds__(kThreads) void k_rhs_xdht(const T *__restrict__ Cn,
   const int nx = dm.nx;
   const int line0 = xcd_tile(blockIdx.x, gridDim.x) * L;
   const int tot = L << dm.lnx;
-  for (int e = threadIdx.x; e < tot; e += blockDim.x) {
-    const int l = e >> dm.lnx;
-    const int i = e & (nx - 1);
-    const int line = line0 + l;
-    int j, k;
-    if (D == 2) {
-      j = line;
-      k = 0;
-    } else {
-      j = line & (dm.ny - 1);
-      k = line >> dm.lny;
+  const int pitch = line_pitch(nx);
+  // U cells per iteration so that their loads are in flight together
+  for (int e0 = threadIdx.x; e0 < tot; e0 += U * blockDim.x) {
+    T q[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int e = e0 + u * blockDim.x;
+      if (e < tot) {
+        const int l = e >> dm.lnx;
+        const int i = e & (nx - 1);
+        const int line = line0 + l;
+        int j, k;
+        if (D == 2) {
+          j = line;
+          k = 0;
+        } else {
+          j = line & (dm.ny - 1);
+          k = line >> dm.lny;
+        }
+        q[u] = rhs_at<T, D>(Cn, Cp, F0, F1, F2, i, j, k, dm, cf);
+      }
     }
-    s[e] = rhs_at<T, D>(Cn, Cp, F0, F1, F2, i, j, k, dm, cf);
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int e = e0 + u * blockDim.x;
+      if (e < tot) {
+        const int l = e >> dm.lnx;
+        const int i = e & (nx - 1);
+        s[l * pitch + i + (i >> 4)] = q[u];
+      }
+    }
   }
   __syncthreads();
-  lds_fft<T, MAXIT, false>(s, dm.lnx, logL - 1, 2 * nx, 1, nx, false, twr, twi);
-  for (int e = threadIdx.x; e < tot; e += blockDim.x) {
-    const int l = e >> dm.lnx;
+  lds_fft<T, E, false, MAXR>(s, dm.lnx, logL - 1, 2 * pitch, 1, pitch, 1, false, twr, twi);
+  const int half = tot >> 1;
+  for (int e = threadIdx.x; e < half; e += blockDim.x) {
+    const int b = e >> dm.lnx;
     const int kx = e & (nx - 1);
     const int kk = (nx - kx) & (nx - 1);
-    const T *pb = s + (l >> 1) * 2 * nx;
-    W[(int64_t)(line0 + l) * nx + kx] = hartley_of_pair(pb[kx], pb[nx + kx], pb[kk], pb[nx + kk], l & 1);
+    const T *pb = s + b * 2 * pitch;
+    const int ak = kx + (kx >> 4), an = kk + (kk >> 4);
+    const T p = pb[ak], q = pb[pitch + ak], r = pb[an], sv = pb[pitch + an];
+    T *o = W + (int64_t)(line0 + 2 * b) * nx + kx;
+    o[0] = (p - q + r + sv) * T(0.5);
+    o[nx] = (p + q - r + sv) * T(0.5);
   }
 }
 
 // K5 (and the forward x pass of the SOLVE stage): Hartley transform of L consecutive
 // contiguous lines of length nx from `in` to `out`.
-template <typename T, int MAXIT>
+template <typename T, int E, int MAXR = 16>
 __global__ __launch_bounds__(kThreads) void k_xdht(const T *__restrict__ in, T *__restrict__ out, int lnx,
                                                    int logL, const T *__restrict__ twr, const T *__restrict__ twi) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -301,52 +426,73 @@ __global__ __launch_bounds__(kThreads) void k_xdht(const T *__restrict__ in, T *
   const int nx = 1 << lnx;
   const int line0 = xcd_tile(blockIdx.x, gridDim.x) * L;
   const int tot = L << lnx;
+  const int pitch = line_pitch(nx);
   const T *src = in + (int64_t)line0 * nx;
-  for (int e = threadIdx.x; e < tot; e += blockDim.x) s[e] = src[e];
-  __syncthreads();
-  lds_fft<T, MAXIT, false>(s, lnx, logL - 1, 2 * nx, 1, nx, false, twr, twi);
-  T *dst = out + (int64_t)line0 * nx;
   for (int e = threadIdx.x; e < tot; e += blockDim.x) {
-    const int l = e >> lnx;
+    const int l = e >> lnx, i = e & (nx - 1);
+    s[l * pitch + i + (i >> 4)] = src[e];
+  }
+  __syncthreads();
+  lds_fft<T, E, false, MAXR>(s, lnx, logL - 1, 2 * pitch, 1, pitch, 1, false, twr, twi);
+  T *dst = out + (int64_t)line0 * nx;
+  const int half = tot >> 1;
+  for (int e = threadIdx.x; e < half; e += blockDim.x) {
+    const int b = e >> lnx;
     const int kx = e & (nx - 1);
     const int kk = (nx - kx) & (nx - 1);
-    const T *pb = s + (l >> 1) * 2 * nx;
-    dst[e] = hartley_of_pair(pb[kx], pb[nx + kx], pb[kk], pb[nx + kk], l & 1);
+    const T *pb = s + b * 2 * pitch;
+    const int ak = kx + (kx >> 4), an = kk + (kk >> 4);
+    const T p = pb[ak], q = pb[pitch + ak], r = pb[an], sv = pb[pitch + an];
+    T *o = dst + (int64_t)(2 * b) * nx + kx;
+    o[0] = (p - q + r + sv) * T(0.5);
+    o[nx] = (p + q - r + sv) * T(0.5);
   }
 }
 
+template <typename T> struct Vec2;
+template <> struct Vec2<double> { using type = double2; };
+template <> struct Vec2<float> { using type = float2; };
+
 // K2/K4: in-place Hartley transform along a strided axis of length N = 2^logN.  A tile is
 // B = 2^logB adjacent x-columns (contiguous in memory) times N positions; tile t covers
-// base = (t >> lognxb) * outer + (t & (nxb-1)) * B, element n at base + n*stride.
-template <typename T, int MAXIT>
+// base = (t >> lognxb) * outer + (t & (nxb-1)) * B, element n at base + n*stride.  Columns
+// 2b and 2b+1 form the pair b (real and imaginary parts of one complex line).
+template <typename T, int E, int MAXR = 16>
 __global__ __launch_bounds__(kThreads) void k_strided_dht(T *__restrict__ W, int logN, int64_t stride, int logB,
                                                           int lognxb, int64_t outer, const T *__restrict__ twr,
                                                           const T *__restrict__ twi) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T *s = reinterpret_cast<T *>(smem_raw);
+  using V2 = typename Vec2<T>::type;
   const int N = 1 << logN, B = 1 << logB;
   const int t = xcd_tile(blockIdx.x, gridDim.x);
   const int64_t base = (int64_t)(t >> lognxb) * outer + (int64_t)(t & ((1 << lognxb) - 1)) * B;
   const int tot = N << logB;
   for (int e = threadIdx.x; e < tot; e += blockDim.x) {
     const int n = e >> logB, col = e & (B - 1);
-    s[e] = W[base + n * stride + col];
+    s[n * B + (n >> 4) * 2 + col] = W[base + n * stride + col];
   }
   __syncthreads();
-  lds_fft<T, MAXIT, false>(s, logN, logB - 1, 2, B, 1, true, twr, twi);
-  for (int e = threadIdx.x; e < tot; e += blockDim.x) {
-    const int n = e >> logB, col = e & (B - 1);
+  lds_fft<T, E, false, MAXR>(s, logN, logB - 1, 2, B, 1, 2, true, twr, twi);
+  const int lp = logB - 1;
+  const int half = tot >> 1;
+  for (int e = threadIdx.x; e < half; e += blockDim.x) {
+    const int b = e & ((1 << lp) - 1), n = e >> lp;
     const int nn = (N - n) & (N - 1);
-    const int cb = col & ~1;
-    W[base + n * stride + col] =
-        hartley_of_pair(s[n * B + cb], s[n * B + cb + 1], s[nn * B + cb], s[nn * B + cb + 1], col & 1);
+    const int a0 = n * B + (n >> 4) * 2 + 2 * b, a1 = nn * B + (nn >> 4) * 2 + 2 * b;
+    const T p = s[a0], q = s[a0 + 1];
+    const T r = s[a1], sv = s[a1 + 1];
+    V2 v;
+    v.x = (p - q + r + sv) * T(0.5);
+    v.y = (p + q - r + sv) * T(0.5);
+    *reinterpret_cast<V2 *>(W + base + n * stride + 2 * b) = v;
   }
 }
 
 // K3: along the bounded axis, per column: DCT-II (even/odd reorder + FFT + post-twiddle),
 // division by (lam - a)(lam + alpha_s) times the inverse normalisation, inverse DCT-II
 // (pre-twiddle + inverse FFT + reorder).  lam = lamx[kx] (+ lamy[ky]) + lamz[kz].
-template <typename T, int MAXIT>
+template <typename T, int E, int MAXR = 16>
 __global__ __launch_bounds__(kThreads) void k_neumann_solve(T *__restrict__ W, int logN, int64_t stride, int logB,
                                                             int lognxb, int64_t outer, const T *__restrict__ lamx,
                                                             const T *__restrict__ lamy, const T *__restrict__ lamz,
@@ -364,10 +510,10 @@ __global__ __launch_bounds__(kThreads) void k_neumann_solve(T *__restrict__ W, i
   for (int e = threadIdx.x; e < tot; e += blockDim.x) {
     const int n = e >> logB, col = e & (B - 1);
     const int pos = (n & 1) ? (N - 1 - (n >> 1)) : (n >> 1);
-    s[pos * B + col] = W[base + n * stride + col];
+    s[pos * B + (pos >> 4) * 2 + col] = W[base + n * stride + col];
   }
   __syncthreads();
-  lds_fft<T, MAXIT, false>(s, logN, logB - 1, 2, B, 1, true, twr, twi);
+  lds_fft<T, E, false, MAXR>(s, logN, logB - 1, 2, B, 1, 2, true, twr, twi);
   const int half = N >> 1;
   const int npairs = B >> 1;
   const int items = npairs * (half + 1);
@@ -376,8 +522,8 @@ __global__ __launch_bounds__(kThreads) void k_neumann_solve(T *__restrict__ W, i
     const int b = e % npairs;
     const int k = e / npairs;
     const int kk = (N - k) & (N - 1);
-    T *zk = s + k * B + 2 * b;
-    T *zn = s + kk * B + 2 * b;
+    T *zk = s + k * B + (k >> 4) * 2 + 2 * b;
+    T *zn = s + kk * B + (kk >> 4) * 2 + 2 * b;
     const T p = zk[0], q = zk[1], r = zn[0], sv = zn[1];
     const T var = (p + r) * T(0.5), vai = (q - sv) * T(0.5);
     const T vbr = (q + sv) * T(0.5), vbi = (r - p) * T(0.5);
@@ -409,11 +555,11 @@ __global__ __launch_bounds__(kThreads) void k_neumann_solve(T *__restrict__ W, i
     }
   }
   __syncthreads();
-  lds_fft<T, MAXIT, true>(s, logN, logB - 1, 2, B, 1, true, twr, twi);
+  lds_fft<T, E, true, MAXR>(s, logN, logB - 1, 2, B, 1, 2, true, twr, twi);
   for (int e = threadIdx.x; e < tot; e += blockDim.x) {
     const int n = e >> logB, col = e & (B - 1);
     const int pos = (n & 1) ? (N - 1 - (n >> 1)) : (n >> 1);
-    W[base + n * stride + col] = s[pos * B + col];
+    W[base + n * stride + col] = s[pos * B + (pos >> 4) * 2 + col];
   }
 }
 
@@ -871,11 +1017,11 @@ inline RhsCoef<T> make_coef(const Plan &p) {
 
 inline unsigned blocks_for(int64_t n) { return (unsigned)((n + kThreads - 1) / kThreads); }
 
-template <typename T>
-constexpr int kMaxIt = tile_elems<T>() / (8 * kThreads);
-
-// Lines per tile for the contiguous x passes: as many as fit the 32 KB LDS tile.
-inline int lines_log(const Plan &p, int E) {
+// Launch shapes.  Each pass has a runtime-selected variant (see Plan::Shape): the log2 of
+// its lines (x passes) or columns (strided passes) per tile, the largest FFT radix (8 or
+// 16: fewer LDS passes against fewer registers) and, for the fused rhs pass, how many cells
+// each thread keeps in flight.
+inline int max_log_lines(const Plan &p, int E) {
   const int lines = p.d == 3 ? p.n[1] * p.n[2] : p.n[1];
   int L = E / p.n[0];
   if (L > lines) L = lines;
@@ -883,70 +1029,116 @@ inline int lines_log(const Plan &p, int E) {
   return ilog2(L);
 }
 
-inline int cols_log(const Plan &p, int N, int E) {
+inline int max_log_cols(const Plan &p, int N, int E) {
   int B = E / N;
   if (B > p.n[0]) B = p.n[0];
   if (B < 2) B = 2;
   return ilog2(B);
 }
 
+inline int clamp_log(int v, int hi) { return v < 1 ? 1 : (v > hi ? hi : v); }
+
 template <typename T>
-hipError_t launch_xdht(const Plan &p, const T *in, T *out) {
+hipError_t launch_xdht(const Plan &p, const T *in, T *out, const Plan::Shape &sh) {
   constexpr int E = tile_elems<T>();
-  const int logL = lines_log(p, E);
+  const int logL = clamp_log(sh.log_tile, max_log_lines(p, E));
   const int lines = p.d == 3 ? p.n[1] * p.n[2] : p.n[1];
   const unsigned nb = (unsigned)(lines >> logL);
-  const size_t lds = (size_t)(1 << logL) * p.n[0] * sizeof(T);
-  hipLaunchKernelGGL((k_xdht<T, kMaxIt<T>>), dim3(nb), dim3(kThreads), lds, p.stream, in, out, p.logn[0], logL,
-                     (const T *)p.twr[0], (const T *)p.twi[0]);
+  const size_t lds = (size_t)(1 << logL) * line_pitch(p.n[0]) * sizeof(T);
+  if (sh.radix == 8)
+    hipLaunchKernelGGL((k_xdht<T, E, 8>), dim3(nb), dim3(kThreads), lds, p.stream, in, out, p.logn[0], logL,
+                       (const T *)p.twr[0], (const T *)p.twi[0]);
+  else
+    hipLaunchKernelGGL((k_xdht<T, E, 16>), dim3(nb), dim3(kThreads), lds, p.stream, in, out, p.logn[0], logL,
+                       (const T *)p.twr[0], (const T *)p.twi[0]);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_ydht(const Plan &p, const Plan::Shape &sh) {
+  constexpr int E = tile_elems<T>();
+  const int nx = p.n[0];
+  const int lb = clamp_log(sh.log_tile, max_log_cols(p, p.n[1], E));
+  const int lxb = p.logn[0] - lb;
+  const unsigned nb = (unsigned)((nx >> lb) * p.n[2]);
+  const size_t lds = (size_t)col_tile(p.n[1], 1 << lb) * sizeof(T);
+  if (sh.radix == 8)
+    hipLaunchKernelGGL((k_strided_dht<T, E, 8>), dim3(nb), dim3(kThreads), lds, p.stream, (T *)p.W, p.logn[1],
+                       (int64_t)nx, lb, lxb, (int64_t)nx * p.n[1], (const T *)p.twr[1], (const T *)p.twi[1]);
+  else
+    hipLaunchKernelGGL((k_strided_dht<T, E, 16>), dim3(nb), dim3(kThreads), lds, p.stream, (T *)p.W, p.logn[1],
+                       (int64_t)nx, lb, lxb, (int64_t)nx * p.n[1], (const T *)p.twr[1], (const T *)p.twi[1]);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_neumann(const Plan &p, const Plan::Shape &sh) {
+  constexpr int E = tile_elems<T>();
+  const int nx = p.n[0];
+  const int ax = p.d - 1;
+  const int Nn = p.n[ax];
+  const int lb = clamp_log(sh.log_tile, max_log_cols(p, Nn, E));
+  const int lxb = p.logn[0] - lb;
+  const int64_t stride = p.d == 3 ? (int64_t)nx * p.n[1] : (int64_t)nx;
+  const int64_t outer = p.d == 3 ? (int64_t)nx : 0;
+  const unsigned nb = (unsigned)((nx >> lb) * (p.d == 3 ? p.n[1] : 1));
+  const size_t lds = (size_t)col_tile(Nn, 1 << lb) * sizeof(T);
+  const double norm = (double)p.N;  // 1/(nx [ny] n_last): inverse Hartley scales and the inverse FFT
+  const T *lamy = p.d == 3 ? (const T *)p.lam[1] : (const T *)nullptr;
+  if (sh.radix == 8)
+    hipLaunchKernelGGL((k_neumann_solve<T, E, 8>), dim3(nb), dim3(kThreads), lds, p.stream, (T *)p.W, p.logn[ax],
+                       stride, lb, lxb, outer, (const T *)p.lam[0], lamy, (const T *)p.lam[ax], (T)p.a, (T)p.alpha_s,
+                       (T)(1.0 / norm), (const T *)p.twr[ax], (const T *)p.twi[ax], (const T *)p.dctc,
+                       (const T *)p.dcts);
+  else
+    hipLaunchKernelGGL((k_neumann_solve<T, E, 16>), dim3(nb), dim3(kThreads), lds, p.stream, (T *)p.W, p.logn[ax],
+                       stride, lb, lxb, outer, (const T *)p.lam[0], lamy, (const T *)p.lam[ax], (T)p.a, (T)p.alpha_s,
+                       (T)(1.0 / norm), (const T *)p.twr[ax], (const T *)p.twi[ax], (const T *)p.dctc,
+                       (const T *)p.dcts);
+  return hipGetLastError();
+}
+
+template <typename T, int D, int U, int R>
+void launch_rhs_variant(const Plan &p, const T *Cn, const T *Cp, int logL, unsigned nb, size_t lds) {
+  const Dims dm = make_dims(p);
+  const RhsCoef<T> cf = make_coef<T>(p);
+  hipLaunchKernelGGL((k_rhs_xdht<T, D, tile_elems<T>(), U, R>), dim3(nb), dim3(kThreads), lds, p.stream, Cn, Cp,
+                     (const T *)p.F[0], (const T *)p.F[1], (const T *)(D == 3 ? p.F[2] : p.F[1]), (T *)p.W, dm, cf,
+                     logL, (const T *)p.twr[0], (const T *)p.twi[0]);
+}
+
+template <typename T, int D>
+hipError_t launch_rhs(const Plan &p, const T *Cn, const T *Cp, const Plan::Shape &sh) {
+  constexpr int E = tile_elems<T>();
+  const int logL = clamp_log(sh.log_tile, max_log_lines(p, E));
+  const int lines = p.d == 3 ? p.n[1] * p.n[2] : p.n[1];
+  const unsigned nb = (unsigned)(lines >> logL);
+  const size_t lds = (size_t)(1 << logL) * line_pitch(p.n[0]) * sizeof(T);
+  const bool r8 = sh.radix == 8, u2 = sh.unroll >= 2;
+  if (r8 && u2) launch_rhs_variant<T, D, 2, 8>(p, Cn, Cp, logL, nb, lds);
+  else if (r8) launch_rhs_variant<T, D, 1, 8>(p, Cn, Cp, logL, nb, lds);
+  else if (u2) launch_rhs_variant<T, D, 2, 16>(p, Cn, Cp, logL, nb, lds);
+  else launch_rhs_variant<T, D, 1, 16>(p, Cn, Cp, logL, nb, lds);
   return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_spectral_tail(const Plan &p, KernelTimer *tm = nullptr) {
-  constexpr int E = tile_elems<T>();
-  T *W = (T *)p.W;
-  const int nx = p.n[0];
   hipError_t e = hipSuccess;
   auto mark = [&](const char *name) {
     if (tm && e == hipSuccess) e = tm->mark(name, p.stream);
   };
   if (p.d == 3) {
     mark("ydht_fwd");
-    const int lb = cols_log(p, p.n[1], E);
-    const int lxb = p.logn[0] - lb;
-    const unsigned nb = (unsigned)((nx >> lb) * p.n[2]);
-    const size_t lds = (size_t)(1 << lb) * p.n[1] * sizeof(T);
-    hipLaunchKernelGGL((k_strided_dht<T, kMaxIt<T>>), dim3(nb), dim3(kThreads), lds, p.stream, W, p.logn[1],
-                       (int64_t)nx, lb, lxb, (int64_t)nx * p.n[1], (const T *)p.twr[1], (const T *)p.twi[1]);
+    if (e == hipSuccess) e = launch_ydht<T>(p, p.shape[1]);
   }
-  {
-    mark("neumann_solve");
-    const int ax = p.d - 1;
-    const int Nn = p.n[ax];
-    const int lb = cols_log(p, Nn, E);
-    const int lxb = p.logn[0] - lb;
-    const int64_t stride = p.d == 3 ? (int64_t)nx * p.n[1] : (int64_t)nx;
-    const int64_t outer = p.d == 3 ? (int64_t)nx : 0;
-    const unsigned nb = (unsigned)((nx >> lb) * (p.d == 3 ? p.n[1] : 1));
-    const size_t lds = (size_t)(1 << lb) * Nn * sizeof(T);
-    double norm = (double)p.N;  // 1/(nx [ny] n_last): inverse Hartley scales and the inverse FFT
-    hipLaunchKernelGGL((k_neumann_solve<T, kMaxIt<T>>), dim3(nb), dim3(kThreads), lds, p.stream, W, p.logn[ax],
-                       stride, lb, lxb, outer, (const T *)p.lam[0], p.d == 3 ? (const T *)p.lam[1] : (const T *)nullptr,
-                       (const T *)p.lam[ax], (T)p.a, (T)p.alpha_s, (T)(1.0 / norm), (const T *)p.twr[ax],
-                       (const T *)p.twi[ax], (const T *)p.dctc, (const T *)p.dcts);
-  }
+  mark("neumann_solve");
+  if (e == hipSuccess) e = launch_neumann<T>(p, p.shape[2]);
   if (p.d == 3) {
     mark("ydht_inv");
-    const int lb = cols_log(p, p.n[1], E);
-    const int lxb = p.logn[0] - lb;
-    const unsigned nb = (unsigned)((nx >> lb) * p.n[2]);
-    const size_t lds = (size_t)(1 << lb) * p.n[1] * sizeof(T);
-    hipLaunchKernelGGL((k_strided_dht<T, kMaxIt<T>>), dim3(nb), dim3(kThreads), lds, p.stream, W, p.logn[1],
-                       (int64_t)nx, lb, lxb, (int64_t)nx * p.n[1], (const T *)p.twr[1], (const T *)p.twi[1]);
+    if (e == hipSuccess) e = launch_ydht<T>(p, p.shape[1]);
   }
-  if (e != hipSuccess) return e;
-  return hipGetLastError();
+  return e;
 }
 
 template <typename T>
@@ -993,37 +1185,129 @@ hipError_t launch_velocity_fill(const Plan &p, const T *Cfin) {
 
 template <typename T>
 hipError_t enqueue_step(const Plan &p, int cur, KernelTimer *tm) {
-  constexpr int E = tile_elems<T>();
   const T *Cn = (const T *)p.C[cur];
   T *Cp = (T *)p.C[1 - cur];
-  const Dims dm = make_dims(p);
-  const RhsCoef<T> cf = make_coef<T>(p);
-  const int logL = lines_log(p, E);
-  const int lines = p.d == 3 ? p.n[1] * p.n[2] : p.n[1];
-  const unsigned nb = (unsigned)(lines >> logL);
-  const size_t lds = (size_t)(1 << logL) * p.n[0] * sizeof(T);
   hipError_t e = hipSuccess;
   auto mark = [&](const char *name) {
     if (tm && e == hipSuccess) e = tm->mark(name, p.stream);
   };
   mark("rhs_xdht");
-  if (p.d == 2)
-    hipLaunchKernelGGL((k_rhs_xdht<T, 2, kMaxIt<T>>), dim3(nb), dim3(kThreads), lds, p.stream, Cn, (const T *)Cp,
-                       (const T *)p.F[0], (const T *)p.F[1], (const T *)p.F[1], (T *)p.W, dm, cf, logL,
-                       (const T *)p.twr[0], (const T *)p.twi[0]);
-  else
-    hipLaunchKernelGGL((k_rhs_xdht<T, 3, kMaxIt<T>>), dim3(nb), dim3(kThreads), lds, p.stream, Cn, (const T *)Cp,
-                       (const T *)p.F[0], (const T *)p.F[1], (const T *)p.F[2], (T *)p.W, dm, cf, logL,
-                       (const T *)p.twr[0], (const T *)p.twi[0]);
-  if (e == hipSuccess) e = hipGetLastError();
+  if (e == hipSuccess)
+    e = p.d == 2 ? launch_rhs<T, 2>(p, Cn, Cp, p.shape[0]) : launch_rhs<T, 3>(p, Cn, Cp, p.shape[0]);
   if (e == hipSuccess) e = launch_spectral_tail<T>(p, tm);
   mark("xdht_out");
-  if (e == hipSuccess) e = launch_xdht<T>(p, (const T *)p.W, Cp);
+  if (e == hipSuccess) e = launch_xdht<T>(p, (const T *)p.W, Cp, p.shape[3]);
   mark("ghost_fill_C");
   if (e == hipSuccess) e = launch_ghost_fill<T>(p, Cp, 0);
   if (p.vel_fill && p.G) mark("ghost_fill_u");
   if (e == hipSuccess) e = launch_velocity_fill<T>(p, Cp);
   if (tm && e == hipSuccess) e = tm->end(p.stream);
+  return e;
+}
+
+// Times every candidate shape of each pass on the state's buffers (the spectral workspace
+// only; the fields are not modified) and keeps the fastest.  `out` receives the chosen
+// shapes.  The candidates: lines/columns per tile from 2 to the 32 KB LDS limit, radix 8 or
+// 16, and 1 or 2 cells in flight per thread in the fused rhs pass.
+template <typename T>
+hipError_t tune_shapes(Plan &p, int cur, int reps) {
+  constexpr int E = tile_elems<T>();
+  hipEvent_t e0, e1;
+  hipError_t e = hipEventCreate(&e0);
+  if (e != hipSuccess) return e;
+  e = hipEventCreate(&e1);
+  if (e != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return e;
+  }
+  auto time_it = [&](auto &&launch) -> float {
+    float best = 1e30f;
+    for (int w = 0; w < 2 && e == hipSuccess; ++w) e = launch();
+    for (int r = 0; r < reps && e == hipSuccess; ++r) {
+      e = hipEventRecord(e0, p.stream);
+      if (e == hipSuccess) e = launch();
+      if (e == hipSuccess) e = hipEventRecord(e1, p.stream);
+      if (e == hipSuccess) e = hipEventSynchronize(e1);
+      float ms = 0.f;
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+      if (ms < best) best = ms;
+    }
+    return best;
+  };
+  const T *Cn = (const T *)p.C[cur];
+  const T *Cp = (const T *)p.C[1 - cur];
+  // pass 0: fused rhs
+  {
+    const int hi = max_log_lines(p, E);
+    float best = 1e30f;
+    Plan::Shape bs = p.shape[0];
+    for (int lt = 1; lt <= hi; ++lt)
+      for (int radix : {8, 16})
+        for (int un : {1, 2}) {
+          Plan::Shape sh{lt, radix, un};
+          const float t = time_it([&]() {
+            return p.d == 2 ? launch_rhs<T, 2>(p, Cn, Cp, sh) : launch_rhs<T, 3>(p, Cn, Cp, sh);
+          });
+          if (e != hipSuccess) break;
+          if (t < best) {
+            best = t;
+            bs = sh;
+          }
+        }
+    p.shape[0] = bs;
+  }
+  // pass 1: strided Hartley (3D); pass 2: bounded-axis solve (in place on W)
+  if (p.d == 3 && e == hipSuccess) {
+    const int hi = max_log_cols(p, p.n[1], E);
+    float best = 1e30f;
+    Plan::Shape bs = p.shape[1];
+    for (int lt = 1; lt <= hi; ++lt)
+      for (int radix : {8, 16}) {
+        Plan::Shape sh{lt, radix, 1};
+        const float t = time_it([&]() { return launch_ydht<T>(p, sh); });
+        if (e != hipSuccess) break;
+        if (t < best) {
+          best = t;
+          bs = sh;
+        }
+      }
+    p.shape[1] = bs;
+  }
+  if (e == hipSuccess) {
+    const int hi = max_log_cols(p, p.n[p.d - 1], E);
+    float best = 1e30f;
+    Plan::Shape bs = p.shape[2];
+    for (int lt = 1; lt <= hi; ++lt)
+      for (int radix : {8, 16}) {
+        Plan::Shape sh{lt, radix, 1};
+        const float t = time_it([&]() { return launch_neumann<T>(p, sh); });
+        if (e != hipSuccess) break;
+        if (t < best) {
+          best = t;
+          bs = sh;
+        }
+      }
+    p.shape[2] = bs;
+  }
+  // pass 3: x Hartley, W -> W (in place: each tile is read whole before it is written)
+  if (e == hipSuccess) {
+    const int hi = max_log_lines(p, E);
+    float best = 1e30f;
+    Plan::Shape bs = p.shape[3];
+    for (int lt = 1; lt <= hi; ++lt)
+      for (int radix : {8, 16}) {
+        Plan::Shape sh{lt, radix, 1};
+        const float t = time_it([&]() { return launch_xdht<T>(p, (const T *)p.W, (T *)p.W, sh); });
+        if (e != hipSuccess) break;
+        if (t < best) {
+          best = t;
+          bs = sh;
+        }
+      }
+    p.shape[3] = bs;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
   return e;
 }
 
@@ -1053,10 +1337,10 @@ hipError_t enqueue_rhs(const Plan &p, int cur, void *out) {
 
 template <typename T>
 hipError_t enqueue_solve(const Plan &p, const void *in, void *out) {
-  hipError_t e = launch_xdht<T>(p, (const T *)in, (T *)p.W);
+  hipError_t e = launch_xdht<T>(p, (const T *)in, (T *)p.W, p.shape[3]);
   if (e != hipSuccess) return e;
   if ((e = launch_spectral_tail<T>(p)) != hipSuccess) return e;
-  return launch_xdht<T>(p, (const T *)p.W, (T *)out);
+  return launch_xdht<T>(p, (const T *)p.W, (T *)out, p.shape[3]);
 }
 
 template <typename T>
@@ -1089,6 +1373,8 @@ hipError_t enqueue_diag(const Plan &p, int cur) {
   return hipGetLastError();
 }
 
+template hipError_t tune_shapes<double>(Plan &, int, int);
+template hipError_t tune_shapes<float>(Plan &, int, int);
 template hipError_t enqueue_step<double>(const Plan &, int, KernelTimer *);
 template hipError_t enqueue_step<float>(const Plan &, int, KernelTimer *);
 template hipError_t enqueue_initial_fill<double>(const Plan &, int);

@@ -227,3 +227,23 @@ def test_nan_is_reported(chib):
     st.set(chib.FIELD_C, C0)
     dg = st.diagnostics()
     assert dg["status"] == chib.ENAN
+
+
+def test_tuned_shapes_keep_parity(chib):
+    """Launch shapes chosen by the autotuner change speed, not results (beyond FFT rounding)."""
+    case = W.small_case_3d(32)
+    st, orc, _ = _pair(chib, case)
+    shapes = st.tune(2)
+    _say("tuned shapes", shapes)
+    assert all(s[1] in (8, 16) for s in shapes)
+    st.step(20)
+    orc.step(20)
+    assert _linf(st.get(chib.FIELD_C), orc.C) <= 1e-9
+    for radix in (8, 16):
+        for lt in (1, 2, 3):
+            st.set_shapes([[lt, radix, 1 + (lt & 1)]] * 4)
+            out = st.stage(chib.STAGE_SOLVE, orc.rhs())
+            ref = orc.provisional()
+            assert _linf(out, ref) <= 1e-12 * np.max(np.abs(ref))
+    with pytest.raises(chib.ChibError):
+        st.set_shapes([[2, 4, 1]] * 4)
