@@ -209,8 +209,10 @@ int ch_ib_step_timed(ch_ib_state *st, int n_steps, int max_kernels, double *ms_o
 /* ---- launch-shape autotuning ------------------------------------------------------------------
  * The four field passes of a step (0 fused rhs + x transform, 1 strided y transform (3D only),
  * 2 bounded-axis solve, 3 x transform out) each have a launch shape of three ints:
- * {log2 lines or columns per tile, largest FFT radix (8 or 16), cells in flight per thread
- * (pass 0 only; 1 or 2)}.  Shapes change speed, never results: every shape computes the same
+ * {log2 lines or columns per tile, largest FFT radix (8 or 16), third field}.  The third field is
+ * 1 for passes 1-3; for pass 0 it is the cells in flight per thread (1 or 2) of the line-tiled
+ * kernel, or 3..5 to select the z-marching kernel (3D grids with nx = 256 or 512 only) with
+ * 2^value planes per workgroup.  Shapes change speed, never results: every shape computes the same
  * sums in the same order per element except for the FFT radix, which changes rounding only.
  * ch_ib_tune: times every candidate shape of each pass reps times with HIP events on the state's
  *   buffers (the fields are left unchanged), keeps the fastest and writes the 12 chosen ints to

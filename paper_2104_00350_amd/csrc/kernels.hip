@@ -415,6 +415,135 @@ __global__ __launch_bounds__(kThreads) void k_rhs_xdht(const T *__restrict__ Cn,
   }
 }
 
+// K1 for 3D grids, marching in z (2.5D blocking): a workgroup owns L consecutive y rows and
+// a chunk of ZC planes.  Thread t owns the x positions x = t + 256 m (m < nx/256, nx >= 256)
+// of rows -1..L of the tile, i.e. whole column segments including the two halo rows, and
+// keeps C~ of planes z-1, z, z+1 in registers, so y and z neighbours never leave the thread;
+// x neighbours come from one LDS plane buffer.  Each plane's L rows of Q go through the same
+// Hartley transform as K1 and are stored to W.  Requires nx a multiple of 256.
+template <typename T, int L, int XM, int R>
+__global__ __launch_bounds__(kThreads) void k_rhs_xdht_zm(const T *__restrict__ Cn, const T *__restrict__ Cp,
+                                                          const T *__restrict__ F0, const T *__restrict__ F1,
+                                                          const T *__restrict__ F2, T *__restrict__ W, Dims dm,
+                                                          RhsCoef<T> cf, int zc_log, const T *__restrict__ twr,
+                                                          const T *__restrict__ twi) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T *plane = reinterpret_cast<T *>(smem_raw);        // L rows x nx: C~ of plane z
+  const int nx = dm.nx;
+  const int pitch = line_pitch(nx);
+  T *fb = plane + L * nx;                              // L rows x pitch: FFT tile
+  const int nyt = dm.ny / L;
+  const int t = xcd_tile(blockIdx.x, gridDim.x);
+  const int yt = t % nyt;
+  const int zc = t / nyt;
+  const int y0 = yt * L;
+  const int ZC = 1 << zc_log;
+  const int z0 = zc * ZC;
+  const int tid = threadIdx.x;
+  auto gf = [&](T v) { return (v * v * v - v - cf.S * v) * cf.inv_cn2; };
+  auto row_of = [&](int r) { return (y0 + r + dm.ny) & (dm.ny - 1); };  // r in -1..L
+  // registers: C~ at rows -1..L for planes z-1 (rows 0..L-1 used), z, z+1
+  // and C^ = 2C^n - C^(n-1)/2 of the own rows for planes z, z+1
+  T cm[XM][L], c0[XM][L + 2], cp[XM][L + 2], uzm[XM][L], h0[XM][L], hp[XM][L];
+  auto load_plane = [&](int z, T (&dst)[XM][L + 2], T (&hat)[XM][L]) {
+    const int zz = z < 0 ? 0 : (z >= dm.nz ? dm.nz - 1 : z);
+    const int64_t zb = (int64_t)zz * dm.plane;
+#pragma unroll
+    for (int m = 0; m < XM; ++m)
+#pragma unroll
+      for (int r = 0; r < L + 2; ++r) {
+        const int64_t q = zb + (int64_t)row_of(r - 1) * nx + tid + 256 * m;
+        const T a = Cn[q], b = Cp[q];
+        dst[m][r] = T(2) * a - b;
+        if (r >= 1 && r <= L) hat[m][r - 1] = T(2) * a - T(0.5) * b;
+      }
+  };
+  {
+    T tmp[XM][L + 2], th[XM][L];
+    load_plane(z0 - 1, tmp, th);   // the reflecting wall below plane 0 is plane 0 itself
+#pragma unroll
+    for (int m = 0; m < XM; ++m)
+#pragma unroll
+      for (int r = 0; r < L; ++r) cm[m][r] = tmp[m][r + 1];
+  }
+  load_plane(z0, c0, h0);
+#pragma unroll
+  for (int m = 0; m < XM; ++m)
+#pragma unroll
+    for (int r = 0; r < L; ++r) {
+      const int64_t c = (int64_t)z0 * dm.plane + (int64_t)row_of(r) * nx + tid + 256 * m;
+      uzm[m][r] = z0 > 0 ? F2[c - dm.plane] : T(0);
+    }
+  for (int zi = 0; zi < ZC; ++zi) {
+    const int z = z0 + zi;
+    const int64_t zb = (int64_t)z * dm.plane;
+    load_plane(z + 1, cp, hp);  // the reflecting wall above the last plane is that plane itself
+    const bool top = z == dm.nz - 1, bot = z == 0;
+#pragma unroll
+    for (int m = 0; m < XM; ++m)
+#pragma unroll
+      for (int r = 0; r < L; ++r) plane[r * nx + tid + 256 * m] = c0[m][r + 1];
+    __syncthreads();
+    T q[XM][L];
+#pragma unroll
+    for (int m = 0; m < XM; ++m) {
+      const int i = tid + 256 * m;
+      const int ip = (i + 1) & (nx - 1), im = (i - 1) & (nx - 1);
+#pragma unroll
+      for (int r = 0; r < L; ++r) {
+        const int64_t c = zb + (int64_t)row_of(r) * nx + i;
+        const int64_t rowb = c - i;
+        const T v0 = c0[m][r + 1];
+        const T cxp = plane[r * nx + ip], cxm = plane[r * nx + im];
+        const T cyp = c0[m][r + 2], cym = c0[m][r];
+        const T czp = top ? v0 : cp[m][r + 1];
+        const T czm = bot ? v0 : cm[m][r];
+        const T uz = F2[c];
+        T flux = F0[c] * (v0 + cxp) - F0[rowb + im] * (cxm + v0);
+        flux += F1[c] * (v0 + cyp) - F1[zb + (int64_t)row_of(r - 1) * nx + i] * (cym + v0);
+        flux += (top ? T(0) : uz * (v0 + czp)) - (bot ? T(0) : uzm[m][r] * (czm + v0));
+        uzm[m][r] = uz;
+        const T gsum = gf(cxp) + gf(cxm) + gf(cyp) + gf(cym) + gf(czp) + gf(czm);
+        const T A = flux * T(0.5) * cf.inv_h;
+        const T lap = (gsum - T(6) * gf(v0)) * cf.inv_h2;
+        q[m][r] = cf.pe_cn2 * (h0[m][r] * cf.inv_dt - A) + lap;
+      }
+    }
+#pragma unroll
+    for (int m = 0; m < XM; ++m)
+#pragma unroll
+      for (int r = 0; r < L; ++r) {
+        const int i = tid + 256 * m;
+        fb[r * pitch + i + (i >> 4)] = q[m][r];
+      }
+    __syncthreads();
+    lds_fft<T, L * 256 * XM, false, R>(fb, dm.lnx, ilog2c(L) - 1, 2 * pitch, 1, pitch, 1, false, twr, twi);
+    const int half = (L * nx) >> 1;
+    const int64_t line0 = (int64_t)z * dm.ny + y0;
+    for (int e = tid; e < half; e += blockDim.x) {
+      const int b = e >> dm.lnx;
+      const int kx = e & (nx - 1);
+      const int kk = (nx - kx) & (nx - 1);
+      const T *pb = fb + b * 2 * pitch;
+      const int ak = kx + (kx >> 4), an = kk + (kk >> 4);
+      const T p = pb[ak], qq = pb[pitch + ak], rr = pb[an], sv = pb[pitch + an];
+      T *o = W + (line0 + 2 * b) * nx + kx;
+      o[0] = (p - qq + rr + sv) * T(0.5);
+      o[nx] = (p + qq - rr + sv) * T(0.5);
+    }
+    // rotate planes (the FFT's final barrier protects the plane buffer for the next write)
+#pragma unroll
+    for (int m = 0; m < XM; ++m) {
+#pragma unroll
+      for (int r = 0; r < L; ++r) cm[m][r] = c0[m][r + 1];
+#pragma unroll
+      for (int r = 0; r < L + 2; ++r) c0[m][r] = cp[m][r];
+#pragma unroll
+      for (int r = 0; r < L; ++r) h0[m][r] = hp[m][r];
+    }
+  }
+}
+
 // K5 (and the forward x pass of the SOLVE stage): Hartley transform of L consecutive
 // contiguous lines of length nx from `in` to `out`.
 template <typename T, int E, int MAXR = 16>
@@ -628,19 +757,36 @@ __device__ __forceinline__ T centred_u(const T *__restrict__ Fa, int64_t c, int 
   return T(0.5) * (lo + hi);
 }
 
+// Sum over the 16 lanes of an aligned lane group (fixed order: deterministic).
+template <typename T>
+__device__ __forceinline__ T group16_sum(T v) {
+  v += __shfl_xor(v, 8);
+  v += __shfl_xor(v, 4);
+  v += __shfl_xor(v, 2);
+  v += __shfl_xor(v, 1);
+  return v;
+}
+
 // K6 (static condition, no contact-line friction): per ghost, C_M = 2 IDW(IP1) - IDW(IP2),
 // C_I solves b C_I^2 + C_I - (C_M + b) = 0 with b = gamma dn cos(theta)/(sqrt2 Cn) (the
 // algebraic wall condition of Eq. WallBCS with mu_f = 0 together with Eqs.
 // interpolationAtWall and ProjectingToNT), C_G = ((gamma+1) C_I - C_M)/gamma (Eq. UpdateC).
+// Sixteen lanes per ghost: lane s < 2K gathers one weighted averaging point.
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_fill_static(T *__restrict__ C, const int *__restrict__ gidx,
                                                           const T *__restrict__ dn, const T *__restrict__ gam,
                                                           const int *__restrict__ ap, const T *__restrict__ w,
                                                           T *__restrict__ CGn, T *__restrict__ CGnm1,
                                                           T *__restrict__ CMs, int64_t G, int K, T cb, int init) {
-  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= G) return;
-  const T CM = mirror_gather(C, ap, w, g, G, K);
+  const int64_t g = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 4;
+  const int sl = threadIdx.x & 15;
+  T v = T(0);
+  if (g < G && sl < 2 * K) {
+    const int64_t i = (int64_t)sl * G + g;
+    v = (sl < K ? T(2) : T(-1)) * w[i] * C[ap[i]];
+  }
+  const T CM = group16_sum(v);
+  if (g >= G || sl != 0) return;
   const T ga = gam[g];
   const T b = ga * dn[g] * cb;
   const T q = CM + b;
@@ -740,7 +886,9 @@ __global__ __launch_bounds__(kThreads) void k_commit_ghosts(T *__restrict__ C, c
 
 // K7a: ghost velocities (Eqs. NoPenetration, UpdateVtan, UpdateVandW in vector form) and,
 // for the faces touching ghosts, the cell-centred velocity of their non-ghost side, all
-// from the faces as they are before this fill.
+// from the faces as they are before this fill.  Blocks [0, nbg) take sixteen lanes per
+// ghost (lane s < 2K: one averaging point's gradient and centred velocity, lane 2K: the
+// ghost's own gradient); the remaining blocks take one face per thread.
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_vel_ghosts(
     const T *__restrict__ C, const T *__restrict__ F0, const T *__restrict__ F1, const T *__restrict__ F2,
@@ -748,11 +896,10 @@ __global__ __launch_bounds__(kThreads) void k_vel_ghosts(
     const int *__restrict__ ap, const T *__restrict__ w, const T *__restrict__ CMs, T *__restrict__ UG, int64_t G,
     int K, const int *__restrict__ f_cell, const int *__restrict__ f_axis, const int *__restrict__ f_gL,
     const int *__restrict__ f_gR, T *__restrict__ stashL, T *__restrict__ stashR, int64_t NF, Dims dm, int d,
-    T inv2h, T Cn, T cos_t, T inv_Ca, T inv_mu, T ls) {
-  const int64_t tg = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    T inv2h, T Cn, T cos_t, T inv_Ca, T inv_mu, T ls, unsigned nbg) {
   const T *Fs[3] = {F0, F1, F2};
-  if (tg >= G) {
-    const int64_t f = tg - G;
+  if (blockIdx.x >= nbg) {
+    const int64_t f = (int64_t)(blockIdx.x - nbg) * blockDim.x + threadIdx.x;
     if (f >= NF) return;
     const int a = f_axis[f];
     const int64_t cL = f_cell[f];
@@ -769,30 +916,39 @@ __global__ __launch_bounds__(kThreads) void k_vel_ghosts(
     stashR[f] = f_gR[f] < 0 ? centred_u(Fs[a], cR, a, dm, d) : T(0);
     return;
   }
-  const int64_t g = tg;
-  const int64_t cg = gidx[g];
-  const T ga = gam[g], dng = dn[g];
-  T n[3] = {0, 0, 0}, uM[3] = {0, 0, 0}, gG[3] = {0, 0, 0}, gM[3] = {0, 0, 0};
-  for (int a = 0; a < d; ++a) n[a] = nrm[(int64_t)a * G + g];
-  grad_at(C, cg, dm, d, inv2h, gG);
-  for (int jp = 0; jp < 2; ++jp) {
-    const T coef = jp == 0 ? T(2) : T(-1);
-    for (int k = 0; k < K; ++k) {
-      const int64_t sl = (int64_t)(jp * K + k) * G + g;
-      const T wk = w[sl];
-      const int64_t c = ap[sl];
-      T gk[3];
+  const int64_t g = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 4;
+  const int sl = threadIdx.x & 15;
+  T gm[3] = {0, 0, 0}, um[3] = {0, 0, 0}, gg[3] = {0, 0, 0};
+  if (g < G) {
+    if (sl < 2 * K) {
+      const int64_t i = (int64_t)sl * G + g;
+      const T cw = (sl < K ? T(2) : T(-1)) * w[i];
+      const int64_t c = ap[i];
+      T gk[3] = {0, 0, 0};
       grad_at(C, c, dm, d, inv2h, gk);
       for (int a = 0; a < d; ++a) {
-        gM[a] += coef * wk * gk[a];
-        uM[a] += coef * wk * centred_u(Fs[a], c, a, dm, d);
+        gm[a] = cw * gk[a];
+        um[a] = cw * centred_u(Fs[a], c, a, dm, d);
       }
+    } else if (sl == 2 * K) {
+      grad_at(C, (int64_t)gidx[g], dm, d, inv2h, gg);
     }
   }
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    gm[a] = group16_sum(gm[a]);
+    um[a] = group16_sum(um[a]);
+    gg[a] = group16_sum(gg[a]);
+  }
+  if (g >= G || sl != 0) return;
+  const int64_t cg = gidx[g];
+  const T ga = gam[g], dng = dn[g];
+  T n[3] = {0, 0, 0};
+  for (int a = 0; a < d; ++a) n[a] = nrm[(int64_t)a * G + g];
   T VnM = T(0), gIn = T(0), gI[3];
   for (int a = 0; a < d; ++a) {
-    VnM += uM[a] * n[a];
-    gI[a] = (ga * gG[a] + gM[a]) / (ga + T(1));
+    VnM += um[a] * n[a];
+    gI[a] = (ga * gg[a] + gm[a]) / (ga + T(1));
     gIn += gI[a] * n[a];
   }
   const T VnG = -VnM / ga;
@@ -804,7 +960,7 @@ __global__ __launch_bounds__(kThreads) void k_vel_ghosts(
   const T fM = (ls - dng) / den;
   const T fK = ls * (ga + T(1)) * dng * inv_mu / den;
   for (int a = 0; a < d; ++a) {
-    const T VtM = uM[a] - VnM * n[a];
+    const T VtM = um[a] - VnM * n[a];
     const T gt = gI[a] - gIn * n[a];
     const T VtG = VtM * fM - Kc * gt * fK;
     UG[(int64_t)a * G + g] = VnG * n[a] + VtG;
@@ -1107,9 +1263,46 @@ void launch_rhs_variant(const Plan &p, const T *Cn, const T *Cp, int logL, unsig
                      logL, (const T *)p.twr[0], (const T *)p.twi[0]);
 }
 
+// z-marching variant (3D, nx a multiple of 256 up to 512): unroll = log2 of the planes per chunk.
+inline bool zm_ok(const Plan &p) { return p.d == 3 && (p.n[0] == 256 || p.n[0] == 512) && p.n[1] >= 2; }
+
+template <typename T, int L, int XM, int R>
+void launch_zm_variant(const Plan &p, const T *Cn, const T *Cp, int zc_log) {
+  const Dims dm = make_dims(p);
+  const RhsCoef<T> cf = make_coef<T>(p);
+  const unsigned nb = (unsigned)((p.n[1] / L) * (p.n[2] >> zc_log));
+  const size_t lds = ((size_t)L * p.n[0] + (size_t)L * line_pitch(p.n[0])) * sizeof(T);
+  hipLaunchKernelGGL((k_rhs_xdht_zm<T, L, XM, R>), dim3(nb), dim3(kThreads), lds, p.stream, Cn, Cp,
+                     (const T *)p.F[0], (const T *)p.F[1], (const T *)p.F[2], (T *)p.W, dm, cf, zc_log,
+                     (const T *)p.twr[0], (const T *)p.twi[0]);
+}
+
+template <typename T, int XM>
+void launch_zm_xm(const Plan &p, const T *Cn, const T *Cp, int logL, int radix, int zc_log) {
+  if (logL <= 1) {
+    if (radix == 8) launch_zm_variant<T, 2, XM, 8>(p, Cn, Cp, zc_log);
+    else launch_zm_variant<T, 2, XM, 16>(p, Cn, Cp, zc_log);
+  } else if (logL == 2) {
+    if (radix == 8) launch_zm_variant<T, 4, XM, 8>(p, Cn, Cp, zc_log);
+    else launch_zm_variant<T, 4, XM, 16>(p, Cn, Cp, zc_log);
+  } else {
+    if (radix == 8) launch_zm_variant<T, 8, XM, 8>(p, Cn, Cp, zc_log);
+    else launch_zm_variant<T, 8, XM, 16>(p, Cn, Cp, zc_log);
+  }
+}
+
 template <typename T, int D>
 hipError_t launch_rhs(const Plan &p, const T *Cn, const T *Cp, const Plan::Shape &sh) {
   constexpr int E = tile_elems<T>();
+  if (D == 3 && sh.unroll >= 3 && zm_ok(p)) {
+    int logL = sh.log_tile < 1 ? 1 : (sh.log_tile > 3 ? 3 : sh.log_tile);
+    while ((1 << logL) > p.n[1]) --logL;
+    int zc_log = sh.unroll;
+    while ((1 << zc_log) > p.n[2]) --zc_log;
+    if (p.n[0] == 256) launch_zm_xm<T, 1>(p, Cn, Cp, logL, sh.radix, zc_log);
+    else launch_zm_xm<T, 2>(p, Cn, Cp, logL, sh.radix, zc_log);
+    return hipGetLastError();
+  }
   const int logL = clamp_log(sh.log_tile, max_log_lines(p, E));
   const int lines = p.d == 3 ? p.n[1] * p.n[2] : p.n[1];
   const unsigned nb = (unsigned)(lines >> logL);
@@ -1148,7 +1341,8 @@ hipError_t launch_ghost_fill(const Plan &p, T *Cout, int init) {
   const Dims dm = make_dims(p);
   if (!p.dynamic) {
     const T cb = (T)(p.cos_t / (1.4142135623730951 * p.Cn));
-    hipLaunchKernelGGL((k_fill_static<T>), dim3(nb), dim3(kThreads), 0, p.stream, Cout, p.gidx, (const T *)p.dn,
+    hipLaunchKernelGGL((k_fill_static<T>), dim3(blocks_for(p.G * 16)), dim3(kThreads), 0, p.stream, Cout, p.gidx,
+                       (const T *)p.dn,
                        (const T *)p.gamma, p.ap, (const T *)p.w, (T *)p.CGn, (T *)p.CGnm1, (T *)p.CMs, p.G, p.K, cb,
                        init);
   } else {
@@ -1169,11 +1363,12 @@ template <typename T>
 hipError_t launch_velocity_fill(const Plan &p, const T *Cfin) {
   if (!p.vel_fill || p.G == 0) return hipSuccess;
   const Dims dm = make_dims(p);
-  hipLaunchKernelGGL((k_vel_ghosts<T>), dim3(blocks_for(p.G + p.NF)), dim3(kThreads), 0, p.stream, Cfin,
+  const unsigned nbg = blocks_for(p.G * 16);
+  hipLaunchKernelGGL((k_vel_ghosts<T>), dim3(nbg + blocks_for(p.NF)), dim3(kThreads), 0, p.stream, Cfin,
                      (const T *)p.F[0], (const T *)p.F[1], (const T *)p.F[2], p.gidx, (const T *)p.normal,
                      (const T *)p.dn, (const T *)p.gamma, p.ap, (const T *)p.w, (const T *)p.CMs, (T *)p.UG, p.G,
                      p.K, p.f_cell, p.f_axis, p.f_gL, p.f_gR, (T *)p.stashL, (T *)p.stashR, p.NF, dm, p.d,
-                     (T)(0.5 / p.h), (T)p.Cn, (T)p.cos_t, (T)(1.0 / p.Ca), (T)(1.0 / p.mu), (T)p.ls);
+                     (T)(0.5 / p.h), (T)p.Cn, (T)p.cos_t, (T)(1.0 / p.Ca), (T)(1.0 / p.mu), (T)p.ls, nbg);
   if (p.NF)
     hipLaunchKernelGGL((k_vel_faces<T>), dim3(blocks_for(p.NF)), dim3(kThreads), 0, p.stream, (T *)p.F[0],
                        (T *)p.F[1], (T *)p.F[2], (const T *)p.UG, p.G, p.f_cell, p.f_axis, p.f_gL, p.f_gR,
@@ -1243,7 +1438,8 @@ hipError_t tune_shapes(Plan &p, int cur, int reps) {
     Plan::Shape bs = p.shape[0];
     for (int lt = 1; lt <= hi; ++lt)
       for (int radix : {8, 16})
-        for (int un : {1, 2}) {
+        for (int un : {1, 2, 3, 4, 5}) {
+          if (un >= 3 && (!zm_ok(p) || lt > 3 || (1 << lt) > p.n[1] || (1 << un) > p.n[2])) continue;
           Plan::Shape sh{lt, radix, un};
           const float t = time_it([&]() {
             return p.d == 2 ? launch_rhs<T, 2>(p, Cn, Cp, sh) : launch_rhs<T, 3>(p, Cn, Cp, sh);

@@ -247,3 +247,24 @@ def test_tuned_shapes_keep_parity(chib):
             assert _linf(out, ref) <= 1e-12 * np.max(np.abs(ref))
     with pytest.raises(chib.ChibError):
         st.set_shapes([[2, 4, 1]] * 4)
+
+
+def test_z_marching_rhs_variants(chib):
+    """Every shape of the z-marching fused rhs kernel (3D, nx = 256) matches the oracle step."""
+    grid = W.Grid((256, 16, 32), (-2.0, -0.125, -0.25), (2.0, 0.125, 0.25))
+    prm = W.Params(Cn=0.02, Pe=100.0, Ca=0.1, theta_deg=70.0, slip_length=0.01, dt=1e-4)
+    case = W.Case("slab3d", grid, [W.Shape(W.HALFPLANE, (0.0, 0.0, -0.1, 0.0, 0.0, 1.0))], prm, 10,
+                  (0.0, 0.0, -0.1), 0.2, 1e-3, 5)
+    faces = _random_faces(grid, 6, 0.3)
+    st, orc, _ = _pair(chib, case, faces)
+    st.step(0)
+    blob = st.save()
+    orc.step(6)
+    for lt in (1, 2, 3):
+        for radix in (8, 16):
+            for zc in (3, 4, 5):
+                st.load(blob)
+                st.set_shapes([[lt, radix, zc], [3, 8, 1], [4, 16, 1], [3, 8, 1]])
+                st.step(6)
+                err = _linf(st.get(chib.FIELD_C), orc.C)
+                assert err <= 1e-11, (lt, radix, zc, err)
