@@ -45,6 +45,47 @@ def algorithmic_bytes(name: str, cells: int, d: int, es: int, G: int, NF: int) -
     return 0.0
 
 
+def kernel_template(name: str, shapes, es: int, nx: int) -> list:
+    """Device kernel instantiation(s) behind a step kernel name, for the launch shapes in use."""
+    t = "double" if es == 8 else "float"
+    E = 32768 // es
+    if name == "rhs_xdht":
+        lt, r, u = shapes[0]
+        if u >= 3 and nx in (256, 512):
+            return [f"k_rhs_xdht_zm<{t}, {2 ** min(max(lt, 1), 3)}, {nx // 256}, {r}>"]
+        return [f"k_rhs_xdht<{t}, 3, {E}, {u}, {r}>"]
+    if name in ("ydht_fwd", "ydht_inv"):
+        return [f"k_strided_dht<{t}, {E}, {shapes[1][1]}>"]
+    if name == "neumann_solve":
+        return [f"k_neumann_solve<{t}, {E}, {shapes[2][1]}>"]
+    if name == "xdht_out":
+        return [f"k_xdht<{t}, {E}, {shapes[3][1]}>"]
+    if name == "ghost_fill_C":
+        return [f"k_fill_static<{t}>"]
+    if name == "ghost_fill_u":
+        return [f"k_vel_ghosts<{t}>", f"k_vel_faces<{t}>"]
+    return []
+
+
+def measured_traffic(name: str, shapes, es: int, nx: int):
+    """HBM bytes per launch from the committed counter summary, or None when the kernel source has
+    changed since the counters were taken (or the kernel was not profiled)."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "hbm_traffic_sphere256_fp64.json")
+    if es != 8 or not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    src = open(os.path.join(ROOT, "paper_2104_00350_amd", "csrc", "kernels.hip"), "rb").read()
+    if hashlib.sha256(src).hexdigest() != rec.get("kernels_hip_sha256"):
+        return None
+    total = 0
+    for k in kernel_template(name, shapes, es, nx):
+        if k not in rec["per_dispatch"]:
+            return None
+        total += rec["per_dispatch"][k]["hbm_bytes"]
+    return total
+
+
 def cpu_baseline(case, steps: int) -> dict:
     """The FP64 oracle on the host, on a bounded sample (a few steps) of the same workload."""
     from oracle.geometry import build_tables
@@ -72,6 +113,7 @@ def main() -> int:
     ap.add_argument("--cpu-steps", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="keep the default launch shapes")
+    ap.add_argument("--shapes", default="", help="fixed launch shapes 'a,b,c;d,e,f;g,h,i;j,k,l' instead of tuning")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="also run one plain device copy of this size (for counter calibration)")
     args = ap.parse_args()
@@ -96,7 +138,11 @@ def main() -> int:
     C0, faces = case.initial_fields()
     st.set_initial(C0, faces)
     st.step(1)
-    shapes = st.shapes() if args.no_tune else st.tune(5)   # launch shapes, chosen before timing
+    if args.shapes:
+        st.set_shapes([[int(v) for v in grp.split(",")] for grp in args.shapes.split(";")])
+        shapes = st.shapes()
+    else:
+        shapes = st.shapes() if args.no_tune else st.tune(5)   # launch shapes, chosen before timing
     st.step(max(args.warmup, 1))
     st.sync()
     print(f"[bench] geometry {t_geom:.1f}s, ghosts {st.G}, shapes {shapes}, warmup done", file=sys.stderr,
@@ -161,7 +207,9 @@ def main() -> int:
                    "grid": list(g.n), "ghosts": st.G, "faces_touching_ghosts": NF,
                    "launch_shapes": shapes},
         "roofline": {"bound": "hbm", "kernel": dominant, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None},
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": measured_traffic(dominant, shapes, es, g.n[0]),
+                     "alg_bytes_per_launch": dom["alg_bytes"]},
         "gpu_ms_per_step_events": round(gpu_ms, 5),
         "path_GB_s": round(sum(k["alg_bytes"] for k in kernels.values()) / (gpu_ms * 1e-3) / 1e9, 1),
         "kernels": kernels,
