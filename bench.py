@@ -86,6 +86,65 @@ def measured_traffic(name: str, shapes, es: int, nx: int):
     return total
 
 
+def sweep_benchmark(chib, torch, steps: int, count: int = 64) -> dict:
+    """Config-4 sweep: `count` uneven 2D sinusoidal-wall cases, time-to-solution of `steps` steps
+    each, stepped one case after another versus all together in one batch (grouped launches
+    replayed as a hipGraph).  Launch shapes are tuned once per distinct grid size for both."""
+    import workloads as W
+    cases = W.config4_cases(count)
+    geos = [chib.Geometry.build(c.grid.n, c.grid.lo, c.grid.hi, c.shapes, c.params) for c in cases]
+
+    def make_states():
+        out = []
+        for c, g in zip(cases, geos):
+            st = chib.State(g, c.params)
+            C0, faces = c.initial_fields()
+            st.set_initial(C0, faces)
+            st.step(0)
+            out.append(st)
+        return out
+
+    singles = make_states()
+    tuned = {}
+    for st in singles:
+        key = st.n
+        if key not in tuned:
+            tuned[key] = st.tune(3)
+        st.set_shapes(tuned[key])
+    members = make_states()
+    for st in members:
+        st.set_shapes(tuned[st.n])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for st in singles:
+        st.step(steps)
+    torch.cuda.synchronize()
+    t_single = time.perf_counter() - t0
+    batch = chib.Batch(members)
+    radix, unroll = batch.tune(3)
+    batch.sync()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    batch.step(steps)
+    batch.sync()
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    worst = max(float(abs(a.get(chib.FIELD_C) - b.get(chib.FIELD_C)).max()) for a, b in zip(singles, members))
+    diags = [st.diagnostics() for st in members]
+    nonfinite = [c.name for c, dg in zip(cases, diags) if dg["status"] != 0]
+    cells = sum(c.grid.cells for c in cases)
+    batch.close()
+    return {"cases": count, "steps_each": steps, "cells_total": cells,
+            "sizes": sorted({f"{c.grid.n[0]}x{c.grid.n[1]}" for c in cases}),
+            "one_by_one_s": round(t_single, 4), "batched_s": round(t_batch, 4),
+            "speedup": round(t_single / t_batch, 3),
+            "batched_cell_updates_per_s": cells * steps / t_batch,
+            "batch_radix_rhs_solve_out": radix, "batch_cells_in_flight": unroll,
+            "max_abs_diff_batched_vs_single": worst,
+            "max_abs_C_over_cases": max(dg["max_abs_C"] for dg in diags),
+            "cases_not_finite": nonfinite}
+
+
 def cpu_baseline(case, steps: int) -> dict:
     """The FP64 oracle on the host, on a bounded sample (a few steps) of the same workload."""
     from oracle.geometry import build_tables
@@ -114,6 +173,7 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="keep the default launch shapes")
     ap.add_argument("--shapes", default="", help="fixed launch shapes 'a,b,c;d,e,f;g,h,i;j,k,l' instead of tuning")
+    ap.add_argument("--sweep-steps", type=int, default=2000, help="steps per case of the batched sweep (0: skip)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="also run one plain device copy of this size (for counter calibration)")
     args = ap.parse_args()
@@ -214,6 +274,9 @@ def main() -> int:
         "path_GB_s": round(sum(k["alg_bytes"] for k in kernels.values()) / (gpu_ms * 1e-3) / 1e9, 1),
         "kernels": kernels,
     }
+    if args.sweep_steps > 0:
+        print("[bench] batched sweep (64 cases)", file=sys.stderr, flush=True)
+        out["batched_sweep"] = sweep_benchmark(chib, torch, args.sweep_steps)
     if not args.no_cpu_baseline:
         print(f"[bench] GPU done ({value:.3e} cell-updates/s); timing the CPU oracle", file=sys.stderr,
               flush=True)

@@ -94,7 +94,7 @@ typedef struct {
   double slip_length;
   double dt;
   double S;                   /* stabilisation of Appendix A.1; <= 0 selects Cn sqrt(6 Pe/dt) */
-  double d1_cells;            /* intersect-to-mirror distance in cells; <= 0 selects one cell diagonal */
+  double d1_cells;            /* intersect-to-mirror distance in cells; <= 0 selects 2 */
   double d2_cells;            /* mirror-to-interpolation-point spacing in cells (0.5 recommended) */
   int subgrid;                /* subgrid points per direction for the volume fraction; 0: 100 (2D) / 20 (3D) */
   int precision;              /* 64 (FP64) or 32 (FP32) arithmetic on the device */
@@ -222,6 +222,37 @@ int ch_ib_step_timed(ch_ib_state *st, int n_steps, int max_kernels, double *ms_o
 int ch_ib_tune(ch_ib_state *st, int reps, int *shapes_out);
 int ch_ib_get_shapes(const ch_ib_state *st, int *shapes_out);
 int ch_ib_set_shapes(ch_ib_state *st, const int *shapes);
+
+/* ---- batched sweep ------------------------------------------------------------------------------
+ * A batch advances many independent 2D states (uneven sizes allowed) together: every phase of
+ * the step is one grouped launch over all member states (block -> state through per-state tile
+ * offsets; per-state descriptors in device memory), and two consecutive steps are captured in
+ * one hipGraph that ch_ib_batch_step replays.  Results are the same as stepping each state on
+ * its own with the same launch shapes (bit for bit).
+ * ch_ib_batch_workspace_bytes: device bytes for the descriptors and offsets of n_states states.
+ * ch_ib_batch_create: states must be 2D, of one precision, with the static contact-angle
+ *   condition (Vs = 0); their pending initial fills are done here.  The batch keeps pointers to
+ *   the states: while it exists, the member states must not be stepped on their own or freed.
+ *   device_workspace (caller-owned, 256-byte aligned) must outlive the batch.  EUNSUPPORTED for
+ *   3D or dynamic states, EINVAL for mixed precisions.
+ * ch_ib_batch_step: enqueues n_steps steps for every member on the batch's stream (graph replays
+ *   plus at most one direct step; on the NULL stream, which cannot be captured, direct grouped
+ *   launches only); the members' step counters and buffer roles are updated.
+ * ch_ib_batch_tune: tunes the launch shapes of one member per distinct grid size
+ *   (ch_ib_tune), applies them to all members of that size, then times full batched steps for
+ *   the choices shared by the grouped kernels (greedy: rhs radix and cells in flight, then the
+ *   solve radix, then the output radix); radix_out[0..2] (rhs, solve, out) and *unroll_out
+ *   (either may be NULL) receive them.  Leaves the fields unchanged.  Synchronous.
+ * ch_ib_batch_sync: waits for the batch's stream.  ch_ib_batch_free: releases the graphs and the
+ *   host object (not the states). */
+typedef struct ch_ib_batch ch_ib_batch;
+size_t ch_ib_batch_workspace_bytes(int n_states);
+int ch_ib_batch_create(ch_ib_state *const *states, int n_states, void *device_workspace, size_t bytes,
+                       void *hip_stream, ch_ib_batch **out);
+int ch_ib_batch_step(ch_ib_batch *b, int n_steps);
+int ch_ib_batch_tune(ch_ib_batch *b, int reps, int *radix_out, int *unroll_out);
+int ch_ib_batch_sync(ch_ib_batch *b);
+void ch_ib_batch_free(ch_ib_batch *b);
 
 /* ---- checkpoint / resume ---------------------------------------------------------------------
  * ch_ib_state_save: if buf is NULL, *len receives the size needed; otherwise writes a versioned

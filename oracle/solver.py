@@ -264,16 +264,15 @@ class OracleState:
         P is the provisional field: the Helmholtz solution off the ghosts and
         C^_G = 2C^n_G - C^(n-1)_G at the ghosts (Eq. interpolationAtWall).  All
         reads come from P (Jacobi sweep), so the result is order independent.
-        Static condition (no contact-line friction, mu_f = 0): the wall equation
-        of Eq. WallBCS loses its time derivative and becomes algebraic at n+1,
-        (3/(2 sqrt2)) Cn dC/dn + cos(theta) g'(C_I) = 0 with g'(C) = 3(1 - C^2)/4,
-        C_I = (gamma C_G + C_M)/(gamma+1) and dC/dn = (C_M - C_G)/((1+gamma) dn).
-        Eliminating C_G leaves b C_I^2 + C_I - (C_M + b) = 0 with
-        b = gamma dn cos(theta)/(sqrt2 Cn); the root that tends to C_M as b -> 0
-        is C_I = 2(C_M + b)/(1 + sqrt(1 + 4 b (C_M + b))), and C_G follows from
-        Eq. UpdateC.  (Evaluating the nonlinear term with the extrapolated ghost
-        value instead makes the ghost update grow without bound when the
-        wall-normal slope is steep, so the condition is solved exactly.)
+        Static condition (no contact-line friction, mu_f = 0): Eq. WallBCS loses
+        its time derivative and reads (3/(2 sqrt2)) Cn dC/dn + cos(theta) g'(C) = 0,
+        g'(C) = 3(1 - C^2)/4, i.e. dC/dn = -cos(theta)(1 - C^2)/(sqrt2 Cn) along the
+        wall normal.  One explicit step of that relation from M back to I gives
+        C_I = C_M + b (1 - C_M^2), b = d1 cos(theta)/(sqrt2 Cn) = gamma dn cos(theta)/(sqrt2 Cn),
+        kept inside [-1, 1]; C_G then follows from Eq. UpdateC.  (Taking g' at C_I
+        and solving for it instead gives the ghost a gain 1/(1 - 2b) on the mirror
+        value against 1 + 2b here, and the step then has growing near-wall modes
+        for wetting angles below about 60 degrees at Cn/h ~ 1.3.)
         Dynamic condition: C_I advanced by one forward step of
         DC/Dt = Vs [Cn dC/dn + cos(theta)(1 - C_I^2)/sqrt2] (Eq. WallBCS_recast),
         then C_G = ((gamma+1) C_I - C_M)/gamma (Eq. UpdateC).
@@ -287,9 +286,7 @@ class OracleState:
         CIs = (gam * PG + CM) / (gam + 1.0)
         if prm.Vs <= 0.0:
             b = gam * T.dn * self.cos_theta / (SQRT2 * prm.Cn)
-            q = CM + b
-            disc = np.maximum(1.0 + 4.0 * b * q, 0.0)
-            CI = 2.0 * q / (1.0 + np.sqrt(disc))
+            CI = np.clip(CM + b * (1.0 - CM * CM), -1.0, 1.0)
             return ((gam + 1.0) * CI - CM) / gam
         if initial:
             self.CI = CIs.copy()
@@ -314,8 +311,10 @@ class OracleState:
 
         V_nG = -V_nM/gamma (Eq. NoPenetration);
         V_tG = V_tM (ls - dn)/(ls + gamma dn) - Kc grad_t C_I ls (gamma+1) dn / (mu (ls + gamma dn))
-        (Eq. UpdateVtan), Kc = [(3/(2 sqrt2)) Cn dC/dn + cos(theta) g'(C_I)]/Ca; the
-        ghost velocity is V_nG n + V_tG (vector form of Eq. UpdateVandW, with the
+        (Eq. UpdateVtan), Kc = [(3/(2 sqrt2)) Cn dC/dn + cos(theta) g'(C_w)]/Ca with
+        C_w = C_I for the dynamic condition and C_w = C_M for the static one (the
+        same discrete balance as the static fill, so Kc vanishes wherever that fill
+        was not clipped); the ghost velocity is V_nG n + V_tG (vector form of Eq. UpdateVandW, with the
         back-transform sign read so that it inverts Eq. CoordinateTransformation).
         Every face with a ghost on either side becomes the mean of its two
         cell-centred values, taken from the faces as they were before this fill.
@@ -338,7 +337,8 @@ class OracleState:
         gM = _mirror_grad(Cf, grid, T)
         gI = (gam * gG + gM) / (gam + 1.0)
         gt = gI - (gI * n).sum(axis=0) * n
-        Kc = ((3.0 / (2.0 * SQRT2)) * prm.Cn * dCdn + 0.75 * self.cos_theta * (1.0 - CI * CI)) / prm.Ca
+        Cw = CM if prm.Vs <= 0.0 else CI
+        Kc = ((3.0 / (2.0 * SQRT2)) * prm.Cn * dCdn + 0.75 * self.cos_theta * (1.0 - Cw * Cw)) / prm.Ca
         ls = prm.slip_length
         VtG = VtM * ((ls - dn) / (ls + gam * dn)) - Kc * gt * (ls * (gam + 1.0) * dn / (prm.mu * (ls + gam * dn)))
         uG = VnG * n + VtG

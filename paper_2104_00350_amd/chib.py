@@ -89,6 +89,12 @@ def _load():
         "ch_ib_state_free": (None, [vp]),
         "ch_ib_coefficients": (i32, [C.POINTER(Params), C.POINTER(C.c_double), C.POINTER(C.c_double),
                                      C.POINTER(C.c_double)]),
+        "ch_ib_batch_workspace_bytes": (C.c_size_t, [i32]),
+        "ch_ib_batch_create": (i32, [C.POINTER(vp), i32, vp, C.c_size_t, vp, C.POINTER(vp)]),
+        "ch_ib_batch_step": (i32, [vp, i32]),
+        "ch_ib_batch_tune": (i32, [vp, i32, C.POINTER(C.c_int), C.POINTER(C.c_int)]),
+        "ch_ib_batch_sync": (i32, [vp]),
+        "ch_ib_batch_free": (None, [vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -361,3 +367,48 @@ def state_for_case(case, precision: int = 64, geom: Optional[Geometry] = None) -
     C0, faces = case.initial_fields()
     st.set_initial(C0, faces)
     return st
+
+
+class Batch:
+    """Independent 2D states advanced together: grouped launches per phase, replayed as a hipGraph."""
+
+    def __init__(self, states, stream=None):
+        import torch
+        self.torch = torch
+        self.states = list(states)
+        n = len(self.states)
+        nbytes = lib.ch_ib_batch_workspace_bytes(n)
+        dev = self.states[0].device
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=dev)
+        ptr = self.workspace.data_ptr()
+        ptr += (-ptr) % 256
+        # a stream of its own (default priority): graphs cannot be captured on the NULL stream
+        self.stream = stream if stream is not None else torch.cuda.Stream(device=dev)
+        handles = (C.c_void_p * n)(*[s.h.value for s in self.states])
+        out = C.c_void_p()
+        check(lib.ch_ib_batch_create(handles, n, C.c_void_p(ptr), nbytes, C.c_void_p(self.stream.cuda_stream),
+                                     C.byref(out)))
+        self.h = out
+
+    def step(self, n: int = 1) -> None:
+        check(lib.ch_ib_batch_step(self.h, int(n)))
+
+    def sync(self) -> None:
+        check(lib.ch_ib_batch_sync(self.h))
+
+    def tune(self, reps: int = 3):
+        radix = (C.c_int * 3)()
+        unroll = C.c_int()
+        check(lib.ch_ib_batch_tune(self.h, int(reps), radix, C.byref(unroll)))
+        return list(radix), unroll.value
+
+    def close(self) -> None:
+        if getattr(self, "h", None):
+            lib.ch_ib_batch_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

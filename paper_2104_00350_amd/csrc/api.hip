@@ -694,3 +694,285 @@ extern "C" int ch_ib_state_load(ch_ib_state *st, const void *buf, size_t len) {
 }
 
 extern "C" void ch_ib_state_free(ch_ib_state *st) { delete st; }
+
+
+// ---------------------------------------------------------------------------------------------
+// Batched sweep.
+
+struct ch_ib_batch {
+  std::vector<ch_ib_state *> st;
+  int es = 8;
+  char *ws = nullptr;
+  size_t ws_bytes = 0;
+  hipStream_t stream = nullptr;
+  chib::BatchLaunch bl;
+  int parity = 0;               // launch parity relative to the uploaded descriptors
+  hipGraphExec_t graph[2] = {nullptr, nullptr};  // two steps starting at parity 0 / 1
+  hipGraph_t graph_def[2] = {nullptr, nullptr};
+};
+
+static size_t batch_desc_bytes(int es) {
+  return es == 8 ? chib::case_desc_bytes<double>() : chib::case_desc_bytes<float>();
+}
+
+extern "C" size_t ch_ib_batch_workspace_bytes(int n) {
+  if (n < 1) return 0;
+  const size_t d = std::max(batch_desc_bytes(8), batch_desc_bytes(4));
+  return ((d * n + 255) & ~(size_t)255) + ((6 * (size_t)(n + 1) * sizeof(int) + 255) & ~(size_t)255) + 256;
+}
+
+static void batch_drop_graphs(ch_ib_batch *b) {
+  for (int k = 0; k < 2; ++k) {
+    if (b->graph[k]) (void)hipGraphExecDestroy(b->graph[k]);
+    if (b->graph_def[k]) (void)hipGraphDestroy(b->graph_def[k]);
+    b->graph[k] = nullptr;
+    b->graph_def[k] = nullptr;
+  }
+}
+
+// Uploads descriptors (from each member's current buffer roles) and tile offsets.
+static int batch_upload(ch_ib_batch *b) {
+  const int n = (int)b->st.size();
+  const size_t db = batch_desc_bytes(b->es);
+  std::vector<unsigned char> descs(db * n);
+  std::vector<int> off(6 * (size_t)(n + 1), 0);
+  size_t lds[3] = {0, 0, 0};
+  for (int c = 0; c < n; ++c) {
+    ch_ib_state *s = b->st[c];
+    int tiles[6];
+    size_t l[3];
+    if (b->es == 8) {
+      chib::fill_case_desc<double>(s->plan, s->cur, descs.data() + db * c);
+      chib::case_tiles<double>(s->plan, tiles, l);
+    } else {
+      chib::fill_case_desc<float>(s->plan, s->cur, descs.data() + db * c);
+      chib::case_tiles<float>(s->plan, tiles, l);
+    }
+    for (int ph = 0; ph < 6; ++ph) off[ph * (n + 1) + c + 1] = off[ph * (n + 1) + c] + tiles[ph];
+    for (int k = 0; k < 3; ++k) lds[k] = std::max(lds[k], l[k]);
+  }
+  const size_t doff = (db * n + 255) & ~(size_t)255;
+  hipError_t e = hipMemcpyAsync(b->ws, descs.data(), descs.size(), hipMemcpyHostToDevice, b->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(b->ws + doff, off.data(), off.size() * sizeof(int), hipMemcpyHostToDevice, b->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+  if (e != hipSuccess) return hip_fail(nullptr, e, "batch upload");
+  b->bl.descs = b->ws;
+  b->bl.off = (const int *)(b->ws + doff);
+  b->bl.n = n;
+  for (int ph = 0; ph < 6; ++ph) b->bl.total[ph] = (unsigned)off[ph * (n + 1) + n];
+  for (int k = 0; k < 3; ++k) b->bl.lds[k] = lds[k];
+  b->bl.stream = b->stream;
+  b->parity = 0;
+  batch_drop_graphs(b);
+  return CH_IB_OK;
+}
+
+static hipError_t batch_direct_step(ch_ib_batch *b, int parity) {
+  return b->es == 8 ? chib::enqueue_batch_step<double>(b->bl, parity) : chib::enqueue_batch_step<float>(b->bl, parity);
+}
+
+extern "C" int ch_ib_batch_create(ch_ib_state *const *states, int n, void *ws, size_t bytes, void *stream,
+                                  ch_ib_batch **out) {
+  if (!out) return fail(CH_IB_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!states || n < 1 || !ws) return fail(CH_IB_EINVAL, "bad state list or workspace");
+  if (bytes < ch_ib_batch_workspace_bytes(n)) return fail(CH_IB_ENOMEM, "batch workspace too small");
+  if (((uintptr_t)ws) & 255) return fail(CH_IB_EINVAL, "workspace must be 256-byte aligned");
+  const int es = states[0] ? states[0]->es : 0;
+  for (int c = 0; c < n; ++c) {
+    ch_ib_state *s = states[c];
+    if (!s) return fail(CH_IB_EINVAL, "NULL state");
+    if (s->es != es) return fail(CH_IB_EINVAL, "mixed precisions in one batch");
+    if (s->plan.d != 2) return fail(CH_IB_EUNSUPPORTED, "batches hold 2D states only");
+    if (s->plan.dynamic) return fail(CH_IB_EUNSUPPORTED, "batches hold static contact-angle states only");
+    if (s->sticky) return fail(s->sticky, "a member state is in an error state");
+  }
+  for (int c = 0; c < n; ++c) {
+    int rc = ensure_init(states[c]);
+    if (rc) return rc;
+    hipError_t e = hipStreamSynchronize(states[c]->plan.stream);
+    if (e != hipSuccess) return hip_fail(states[c], e, "batch create");
+  }
+  auto *b = new ch_ib_batch();
+  b->st.assign(states, states + n);
+  b->es = es;
+  b->ws = (char *)ws;
+  b->ws_bytes = bytes;
+  b->stream = (hipStream_t)stream;
+  // shared kernel choices follow the first member's shapes (so that a batched step is the same
+  // computation as stepping each member with those shapes)
+  b->bl.radix_rhs = states[0]->plan.shape[0].radix;
+  b->bl.unroll = std::min(states[0]->plan.shape[0].unroll, 2);
+  b->bl.radix_neu = states[0]->plan.shape[2].radix;
+  b->bl.radix_out = states[0]->plan.shape[3].radix;
+  int rc = batch_upload(b);
+  if (rc) {
+    delete b;
+    return rc;
+  }
+  *out = b;
+  return CH_IB_OK;
+}
+
+extern "C" int ch_ib_batch_step(ch_ib_batch *b, int n_steps) {
+  if (!b) return fail(CH_IB_EINVAL, "NULL batch");
+  if (n_steps < 0) return fail(CH_IB_EINVAL, "n_steps must be >= 0");
+  hipError_t e = hipSuccess;
+  int left = n_steps;
+  if (!b->stream) {  // the legacy NULL stream cannot be captured: direct grouped launches
+    for (; left > 0 && e == hipSuccess; --left) {
+      e = batch_direct_step(b, b->parity);
+      b->parity ^= 1;
+    }
+  }
+  while (left >= 2 && e == hipSuccess) {
+    const int p = b->parity;
+    if (!b->graph[p]) {
+      e = hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal);
+      if (e == hipSuccess) e = batch_direct_step(b, p);
+      if (e == hipSuccess) e = batch_direct_step(b, 1 - p);
+      hipGraph_t g = nullptr;
+      hipError_t e2 = hipStreamEndCapture(b->stream, &g);
+      if (e == hipSuccess) e = e2;
+      if (e == hipSuccess) {
+        b->graph_def[p] = g;
+        e = hipGraphInstantiate(&b->graph[p], g, nullptr, nullptr, 0);
+      } else if (g) {
+        (void)hipGraphDestroy(g);
+      }
+      if (e != hipSuccess) break;
+    }
+    e = hipGraphLaunch(b->graph[p], b->stream);
+    left -= 2;
+  }
+  if (left == 1 && e == hipSuccess) {
+    e = batch_direct_step(b, b->parity);
+    if (e == hipSuccess) b->parity ^= 1;
+  }
+  if (e != hipSuccess) return hip_fail(nullptr, e, "batch step");
+  for (ch_ib_state *s : b->st) {
+    s->step += n_steps;
+    if (n_steps & 1) s->cur = 1 - s->cur;
+  }
+  return CH_IB_OK;
+}
+
+extern "C" int ch_ib_batch_sync(ch_ib_batch *b) {
+  if (!b) return fail(CH_IB_EINVAL, "NULL batch");
+  hipError_t e = hipStreamSynchronize(b->stream);
+  if (e != hipSuccess) return hip_fail(nullptr, e, "batch sync");
+  return CH_IB_OK;
+}
+
+extern "C" int ch_ib_batch_tune(ch_ib_batch *b, int reps, int *radix_out, int *unroll_out) {
+  if (!b) return fail(CH_IB_EINVAL, "NULL batch");
+  if (reps < 1 || reps > 100) return fail(CH_IB_EINVAL, "reps must be in 1..100");
+  hipError_t e = hipStreamSynchronize(b->stream);
+  if (e != hipSuccess) return hip_fail(nullptr, e, "batch tune");
+  // 1. per distinct grid size, tune one member and copy its shapes to the others
+  std::vector<std::pair<int, int>> sizes;
+  for (ch_ib_state *s : b->st) {
+    std::pair<int, int> key{s->plan.n[0], s->plan.n[1]};
+    if (std::find(sizes.begin(), sizes.end(), key) != sizes.end()) continue;
+    sizes.push_back(key);
+    int rc = ch_ib_tune(s, reps, nullptr);
+    if (rc) return rc;
+    for (ch_ib_state *o : b->st)
+      if (o->plan.n[0] == key.first && o->plan.n[1] == key.second)
+        for (int k = 0; k < 4; ++k) o->plan.shape[k] = s->plan.shape[k];
+  }
+  // 2. the shared radix / cells in flight: time full batched steps (an even number, so that every
+  // member's buffer roles end where they started; the fields advance, so restore them after)
+  std::vector<std::vector<unsigned char>> saved(b->st.size());
+  for (size_t c = 0; c < b->st.size(); ++c) {
+    size_t len = 0;
+    int rc = ch_ib_state_save(b->st[c], nullptr, &len);
+    if (rc) return rc;
+    saved[c].resize(len);
+    rc = ch_ib_state_save(b->st[c], saved[c].data(), &len);
+    if (rc) return rc;
+  }
+  int rc = batch_upload(b);
+  if (rc) return rc;
+  hipEvent_t e0, e1;
+  e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  auto time_pair = [&]() -> float {
+    e = batch_direct_step(b, 0);
+    if (e == hipSuccess) e = batch_direct_step(b, 1);
+    float tmin = 1e30f;
+    for (int r = 0; r < reps && e == hipSuccess; ++r) {
+      e = hipEventRecord(e0, b->stream);
+      if (e == hipSuccess) e = batch_direct_step(b, 0);
+      if (e == hipSuccess) e = batch_direct_step(b, 1);
+      if (e == hipSuccess) e = hipEventRecord(e1, b->stream);
+      if (e == hipSuccess) e = hipEventSynchronize(e1);
+      float ms = 0.f;
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+      tmin = std::min(tmin, ms);
+    }
+    return tmin;
+  };
+  // greedy over the shared choices: rhs radix x cells in flight, then the solve radix, then the out radix
+  {
+    float best = 1e30f;
+    int br = b->bl.radix_rhs, bu = b->bl.unroll;
+    for (int radix : {8, 16})
+      for (int un : {1, 2}) {
+        if (e != hipSuccess) break;
+        b->bl.radix_rhs = radix;
+        b->bl.unroll = un;
+        const float t = time_pair();
+        if (t < best) {
+          best = t;
+          br = radix;
+          bu = un;
+        }
+      }
+    b->bl.radix_rhs = br;
+    b->bl.unroll = bu;
+  }
+  for (int which = 0; which < 2 && e == hipSuccess; ++which) {
+    int &slot = which == 0 ? b->bl.radix_neu : b->bl.radix_out;
+    float best = 1e30f;
+    int bv = slot;
+    for (int radix : {8, 16}) {
+      if (e != hipSuccess) break;
+      slot = radix;
+      const float t = time_pair();
+      if (t < best) {
+        best = t;
+        bv = radix;
+      }
+    }
+    slot = bv;
+  }
+  const int br = b->bl.radix_rhs, bu = b->bl.unroll, bn = b->bl.radix_neu, bo = b->bl.radix_out;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (e != hipSuccess) return hip_fail(nullptr, e, "batch tune");
+  for (size_t c = 0; c < b->st.size(); ++c) {
+    rc = ch_ib_state_load(b->st[c], saved[c].data(), saved[c].size());
+    if (rc) return rc;
+  }
+  rc = batch_upload(b);
+  if (rc) return rc;
+  b->bl.radix_rhs = br;
+  b->bl.unroll = bu;
+  b->bl.radix_neu = bn;
+  b->bl.radix_out = bo;
+  if (radix_out) {
+    radix_out[0] = br;
+    radix_out[1] = bn;
+    radix_out[2] = bo;
+  }
+  if (unroll_out) *unroll_out = bu;
+  return CH_IB_OK;
+}
+
+extern "C" void ch_ib_batch_free(ch_ib_batch *b) {
+  if (!b) return;
+  batch_drop_graphs(b);
+  delete b;
+}

@@ -13,7 +13,9 @@
 //    first or last cell layer of the bounded axis is rejected;
 //  - intersect point: march from the ghost along n in steps of h/100 to the first fluid
 //    point, then 60 bisections keeping the fluid end;
-//  - mirror point d1 beyond the intersect point (default one cell diagonal), interpolation
+//  - mirror point d1 beyond the intersect point (default 2h: near one cell diagonal the
+//    averaging stencil of the first interpolation point reaches the ghost's own fluid
+//    neighbours and near-wall modes grow for strongly wetting angles), interpolation
 //    points d2 and 2*d2 beyond the mirror point (default d2 = h/2);
 //  - averaging points: the cell containing the interpolation point and its 2d face
 //    neighbours; solid ones are dropped and the weights renormalised; with none left, the
@@ -304,7 +306,7 @@ extern "C" int ch_ib_geometry_build(const ch_ib_grid *grid, const ch_ib_shape *s
   g->ap.assign((size_t)2 * K * G, 0);
   g->w.assign((size_t)2 * K * G, 0.0);
 
-  const double d1 = (params->d1_cells > 0 ? params->d1_cells : std::sqrt((double)d)) * h;
+  const double d1 = (params->d1_cells > 0 ? params->d1_cells : 2.0) * h;
   const double d2 = params->d2_cells * h;
   std::vector<int> err(G, 0);
 

@@ -93,6 +93,21 @@ template <typename T> hipError_t enqueue_solve(const Plan &p, const void *in, vo
 template <typename T> hipError_t enqueue_phi(const Plan &p, int cur, void *out);
 template <typename T> hipError_t enqueue_diag(const Plan &p, int cur);
 
+// One grouped step over a batch of 2D cases (see the batched kernels).
+struct BatchLaunch {
+  const void *descs = nullptr;   // device array of per-case descriptors
+  const int *off = nullptr;      // device [6][n+1] per-phase tile offsets
+  int n = 0;
+  unsigned total[6] = {0, 0, 0, 0, 0, 0};
+  size_t lds[3] = {0, 0, 0};
+  int radix_rhs = 8, unroll = 2, radix_neu = 16, radix_out = 16;  // shared by all cases
+  hipStream_t stream = nullptr;
+};
+template <typename T> void fill_case_desc(const Plan &p, int cur, void *desc_host);
+template <typename T> size_t case_desc_bytes();
+template <typename T> void case_tiles(const Plan &p, int *tiles, size_t *lds);
+template <typename T> hipError_t enqueue_batch_step(const BatchLaunch &bl, int parity);
+
 // Launch-shape helpers shared with the host (elements per LDS tile).
 template <typename T> constexpr int tile_elems() { return 32768 / (int)sizeof(T); }  // 32 KB of LDS
 

@@ -21,6 +21,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <cstring>
 
 #include "kernels.h"
 
@@ -356,16 +357,15 @@ __device__ __forceinline__ T hartley_of_pair(T p, T q, T r, T s, int par) {
 // ---------------------------------------------------------------------------------------
 // K1: rhs of L consecutive x-lines into LDS, Hartley transform along x, store to W.
 template <typename T, int D, int E, int U = 1, int MAXR = 16>
-__global__ __launch_bounds__(kThreads) void k_rhs_xdht(const T *__restrict__ Cn, const T *__restrict__ Cp,
+__device__ __forceinline__ void rhs_xdht_body(unsigned char *smem_raw, const T *__restrict__ Cn, const T *__restrict__ Cp,
                                                        const T *__restrict__ F0, const T *__restrict__ F1,
                                                        const T *__restrict__ F2, T *__restrict__ W, Dims dm,
                                                        RhsCoef<T> cf, int logL, const T *__restrict__ twr,
-                                                       const T *__restrict__ twi) {
-  extern __shared__ __align__(16) unsigned char smem_raw[];
+                                                       const T *__restrict__ twi, int tile) {
   T *s = reinterpret_cast<T *>(smem_raw);
   const int L = 1 << logL;
   const int nx = dm.nx;
-  const int line0 = xcd_tile(blockIdx.x, gridDim.x) * L;
+  const int line0 = tile * L;
   const int tot = L << dm.lnx;
   const int pitch = line_pitch(nx);
   // U cells per iteration so that their loads are in flight together
@@ -413,6 +413,16 @@ __global__ __launch_bounds__(kThreads) void k_rhs_xdht(const T *__restrict__ Cn,
     o[0] = (p - q + r + sv) * T(0.5);
     o[nx] = (p + q - r + sv) * T(0.5);
   }
+}
+
+template <typename T, int D, int E, int U = 1, int MAXR = 16>
+__global__ __launch_bounds__(kThreads) void k_rhs_xdht(const T *__restrict__ Cn, const T *__restrict__ Cp,
+                                                       const T *__restrict__ F0, const T *__restrict__ F1,
+                                                       const T *__restrict__ F2, T *__restrict__ W, Dims dm,
+                                                       RhsCoef<T> cf, int logL, const T *__restrict__ twr,
+                                                       const T *__restrict__ twi) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  rhs_xdht_body<T, D, E, U, MAXR>(smem_raw, Cn, Cp, F0, F1, F2, W, dm, cf, logL, twr, twi, xcd_tile(blockIdx.x, gridDim.x));
 }
 
 // K1 for 3D grids, marching in z (2.5D blocking): a workgroup owns L consecutive y rows and
@@ -547,13 +557,12 @@ __global__ __launch_bounds__(kThreads) void k_rhs_xdht_zm(const T *__restrict__ 
 // K5 (and the forward x pass of the SOLVE stage): Hartley transform of L consecutive
 // contiguous lines of length nx from `in` to `out`.
 template <typename T, int E, int MAXR = 16>
-__global__ __launch_bounds__(kThreads) void k_xdht(const T *__restrict__ in, T *__restrict__ out, int lnx,
-                                                   int logL, const T *__restrict__ twr, const T *__restrict__ twi) {
-  extern __shared__ __align__(16) unsigned char smem_raw[];
+__device__ __forceinline__ void xdht_body(unsigned char *smem_raw, const T *__restrict__ in, T *__restrict__ out, int lnx,
+                                                   int logL, const T *__restrict__ twr, const T *__restrict__ twi, int tile) {
   T *s = reinterpret_cast<T *>(smem_raw);
   const int L = 1 << logL;
   const int nx = 1 << lnx;
-  const int line0 = xcd_tile(blockIdx.x, gridDim.x) * L;
+  const int line0 = tile * L;
   const int tot = L << lnx;
   const int pitch = line_pitch(nx);
   const T *src = in + (int64_t)line0 * nx;
@@ -576,6 +585,13 @@ __global__ __launch_bounds__(kThreads) void k_xdht(const T *__restrict__ in, T *
     o[0] = (p - q + r + sv) * T(0.5);
     o[nx] = (p + q - r + sv) * T(0.5);
   }
+}
+
+template <typename T, int E, int MAXR = 16>
+__global__ __launch_bounds__(kThreads) void k_xdht(const T *__restrict__ in, T *__restrict__ out, int lnx,
+                                                   int logL, const T *__restrict__ twr, const T *__restrict__ twi) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  xdht_body<T, E, MAXR>(smem_raw, in, out, lnx, logL, twr, twi, xcd_tile(blockIdx.x, gridDim.x));
 }
 
 template <typename T> struct Vec2;
@@ -622,16 +638,15 @@ __global__ __launch_bounds__(kThreads) void k_strided_dht(T *__restrict__ W, int
 // division by (lam - a)(lam + alpha_s) times the inverse normalisation, inverse DCT-II
 // (pre-twiddle + inverse FFT + reorder).  lam = lamx[kx] (+ lamy[ky]) + lamz[kz].
 template <typename T, int E, int MAXR = 16>
-__global__ __launch_bounds__(kThreads) void k_neumann_solve(T *__restrict__ W, int logN, int64_t stride, int logB,
+__device__ __forceinline__ void neumann_body(unsigned char *smem_raw, T *__restrict__ W, int logN, int64_t stride, int logB,
                                                             int lognxb, int64_t outer, const T *__restrict__ lamx,
                                                             const T *__restrict__ lamy, const T *__restrict__ lamz,
                                                             T a, T alpha_s, T inv_norm, const T *__restrict__ twr,
                                                             const T *__restrict__ twi, const T *__restrict__ dctc,
-                                                            const T *__restrict__ dcts) {
-  extern __shared__ __align__(16) unsigned char smem_raw[];
+                                                            const T *__restrict__ dcts, int tile) {
   T *s = reinterpret_cast<T *>(smem_raw);
   const int N = 1 << logN, B = 1 << logB;
-  const int t = xcd_tile(blockIdx.x, gridDim.x);
+  const int t = tile;
   const int xb = t & ((1 << lognxb) - 1);
   const int oy = t >> lognxb;
   const int64_t base = (int64_t)oy * outer + (int64_t)xb * B;
@@ -690,6 +705,17 @@ __global__ __launch_bounds__(kThreads) void k_neumann_solve(T *__restrict__ W, i
     const int pos = (n & 1) ? (N - 1 - (n >> 1)) : (n >> 1);
     W[base + n * stride + col] = s[pos * B + (pos >> 4) * 2 + col];
   }
+}
+
+template <typename T, int E, int MAXR = 16>
+__global__ __launch_bounds__(kThreads) void k_neumann_solve(T *__restrict__ W, int logN, int64_t stride, int logB,
+                                                            int lognxb, int64_t outer, const T *__restrict__ lamx,
+                                                            const T *__restrict__ lamy, const T *__restrict__ lamz,
+                                                            T a, T alpha_s, T inv_norm, const T *__restrict__ twr,
+                                                            const T *__restrict__ twi, const T *__restrict__ dctc,
+                                                            const T *__restrict__ dcts) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  neumann_body<T, E, MAXR>(smem_raw, W, logN, stride, logB, lognxb, outer, lamx, lamy, lamz, a, alpha_s, inv_norm, twr, twi, dctc, dcts, xcd_tile(blockIdx.x, gridDim.x));
 }
 
 // ---------------------------------------------------------------------------------------
@@ -768,17 +794,17 @@ __device__ __forceinline__ T group16_sum(T v) {
 }
 
 // K6 (static condition, no contact-line friction): per ghost, C_M = 2 IDW(IP1) - IDW(IP2),
-// C_I solves b C_I^2 + C_I - (C_M + b) = 0 with b = gamma dn cos(theta)/(sqrt2 Cn) (the
-// algebraic wall condition of Eq. WallBCS with mu_f = 0 together with Eqs.
-// interpolationAtWall and ProjectingToNT), C_G = ((gamma+1) C_I - C_M)/gamma (Eq. UpdateC).
+// C_I = C_M + b (1 - C_M^2) kept inside [-1, 1], b = gamma dn cos(theta)/(sqrt2 Cn): the
+// algebraic wall condition of Eq. WallBCS with mu_f = 0, its slope taken between I and M
+// and its wetting term at M; then C_G = ((gamma+1) C_I - C_M)/gamma (Eq. UpdateC).
 // Sixteen lanes per ghost: lane s < 2K gathers one weighted averaging point.
 template <typename T>
-__global__ __launch_bounds__(kThreads) void k_fill_static(T *__restrict__ C, const int *__restrict__ gidx,
+__device__ __forceinline__ void fill_static_body(T *__restrict__ C, const int *__restrict__ gidx,
                                                           const T *__restrict__ dn, const T *__restrict__ gam,
                                                           const int *__restrict__ ap, const T *__restrict__ w,
                                                           T *__restrict__ CGn, T *__restrict__ CGnm1,
-                                                          T *__restrict__ CMs, int64_t G, int K, T cb, int init) {
-  const int64_t g = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 4;
+                                                          T *__restrict__ CMs, int64_t G, int K, T cb, int init, int64_t tile) {
+  const int64_t g = ((int64_t)tile * blockDim.x + threadIdx.x) >> 4;
   const int sl = threadIdx.x & 15;
   T v = T(0);
   if (g < G && sl < 2 * K) {
@@ -789,15 +815,22 @@ __global__ __launch_bounds__(kThreads) void k_fill_static(T *__restrict__ C, con
   if (g >= G || sl != 0) return;
   const T ga = gam[g];
   const T b = ga * dn[g] * cb;
-  const T q = CM + b;
-  T disc = T(1) + T(4) * b * q;
-  disc = disc > T(0) ? disc : T(0);
-  const T CI = T(2) * q / (T(1) + sqrt(disc));
+  const T CIr = CM + b * (T(1) - CM * CM);
+  const T CI = CIr > T(1) ? T(1) : (CIr < T(-1) ? T(-1) : CIr);
   const T CG = ((ga + T(1)) * CI - CM) / ga;
   C[gidx[g]] = CG;
   CMs[g] = CM;
   CGnm1[g] = init ? CG : CGn[g];
   CGn[g] = CG;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_fill_static(T *__restrict__ C, const int *__restrict__ gidx,
+                                                          const T *__restrict__ dn, const T *__restrict__ gam,
+                                                          const int *__restrict__ ap, const T *__restrict__ w,
+                                                          T *__restrict__ CGn, T *__restrict__ CGnm1,
+                                                          T *__restrict__ CMs, int64_t G, int K, T cb, int init) {
+  fill_static_body<T>(C, gidx, dn, gam, ap, w, CGn, CGnm1, CMs, G, K, cb, init, blockIdx.x);
 }
 
 // Dynamic condition, part 1: provisional ghost values C^_G = 2 C^n_G - C^(n-1)_G.
@@ -890,16 +923,16 @@ __global__ __launch_bounds__(kThreads) void k_commit_ghosts(T *__restrict__ C, c
 // ghost (lane s < 2K: one averaging point's gradient and centred velocity, lane 2K: the
 // ghost's own gradient); the remaining blocks take one face per thread.
 template <typename T>
-__global__ __launch_bounds__(kThreads) void k_vel_ghosts(
+__device__ __forceinline__ void vel_ghosts_body(
     const T *__restrict__ C, const T *__restrict__ F0, const T *__restrict__ F1, const T *__restrict__ F2,
     const int *__restrict__ gidx, const T *__restrict__ nrm, const T *__restrict__ dn, const T *__restrict__ gam,
     const int *__restrict__ ap, const T *__restrict__ w, const T *__restrict__ CMs, T *__restrict__ UG, int64_t G,
     int K, const int *__restrict__ f_cell, const int *__restrict__ f_axis, const int *__restrict__ f_gL,
     const int *__restrict__ f_gR, T *__restrict__ stashL, T *__restrict__ stashR, int64_t NF, Dims dm, int d,
-    T inv2h, T Cn, T cos_t, T inv_Ca, T inv_mu, T ls, unsigned nbg) {
+    T inv2h, T Cn, T cos_t, T inv_Ca, T inv_mu, T ls, int wet_at_mirror, unsigned nbg, int64_t tile) {
   const T *Fs[3] = {F0, F1, F2};
-  if (blockIdx.x >= nbg) {
-    const int64_t f = (int64_t)(blockIdx.x - nbg) * blockDim.x + threadIdx.x;
+  if (tile >= nbg) {
+    const int64_t f = (int64_t)(tile - nbg) * blockDim.x + threadIdx.x;
     if (f >= NF) return;
     const int a = f_axis[f];
     const int64_t cL = f_cell[f];
@@ -916,7 +949,7 @@ __global__ __launch_bounds__(kThreads) void k_vel_ghosts(
     stashR[f] = f_gR[f] < 0 ? centred_u(Fs[a], cR, a, dm, d) : T(0);
     return;
   }
-  const int64_t g = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 4;
+  const int64_t g = ((int64_t)tile * blockDim.x + threadIdx.x) >> 4;
   const int sl = threadIdx.x & 15;
   T gm[3] = {0, 0, 0}, um[3] = {0, 0, 0}, gg[3] = {0, 0, 0};
   if (g < G) {
@@ -955,7 +988,8 @@ __global__ __launch_bounds__(kThreads) void k_vel_ghosts(
   const T CG = C[cg], CM = CMs[g];
   const T CIv = (ga * CG + CM) / (ga + T(1));
   const T dCdn = (CM - CG) / ((T(1) + ga) * dng);
-  const T Kc = (T(1.06066017177982128660) * Cn * dCdn + T(0.75) * cos_t * (T(1) - CIv * CIv)) * inv_Ca;
+  const T Cw = wet_at_mirror ? CM : CIv;
+  const T Kc = (T(1.06066017177982128660) * Cn * dCdn + T(0.75) * cos_t * (T(1) - Cw * Cw)) * inv_Ca;
   const T den = ls + ga * dng;
   const T fM = (ls - dng) / den;
   const T fK = ls * (ga + T(1)) * dng * inv_mu / den;
@@ -967,15 +1001,26 @@ __global__ __launch_bounds__(kThreads) void k_vel_ghosts(
   }
 }
 
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_vel_ghosts(
+    const T *__restrict__ C, const T *__restrict__ F0, const T *__restrict__ F1, const T *__restrict__ F2,
+    const int *__restrict__ gidx, const T *__restrict__ nrm, const T *__restrict__ dn, const T *__restrict__ gam,
+    const int *__restrict__ ap, const T *__restrict__ w, const T *__restrict__ CMs, T *__restrict__ UG, int64_t G,
+    int K, const int *__restrict__ f_cell, const int *__restrict__ f_axis, const int *__restrict__ f_gL,
+    const int *__restrict__ f_gR, T *__restrict__ stashL, T *__restrict__ stashR, int64_t NF, Dims dm, int d,
+    T inv2h, T Cn, T cos_t, T inv_Ca, T inv_mu, T ls, int wet_at_mirror, unsigned nbg) {
+  vel_ghosts_body<T>(C, F0, F1, F2, gidx, nrm, dn, gam, ap, w, CMs, UG, G, K, f_cell, f_axis, f_gL, f_gR, stashL, stashR, NF, dm, d, inv2h, Cn, cos_t, inv_Ca, inv_mu, ls, wet_at_mirror, nbg, blockIdx.x);
+}
+
 // K7b: every face touching a ghost becomes the mean of its two cell-centred values.
 template <typename T>
-__global__ __launch_bounds__(kThreads) void k_vel_faces(T *__restrict__ F0, T *__restrict__ F1, T *__restrict__ F2,
+__device__ __forceinline__ void vel_faces_body(T *__restrict__ F0, T *__restrict__ F1, T *__restrict__ F2,
                                                         const T *__restrict__ UG, int64_t G,
                                                         const int *__restrict__ f_cell, const int *__restrict__ f_axis,
                                                         const int *__restrict__ f_gL, const int *__restrict__ f_gR,
                                                         const T *__restrict__ stashL, const T *__restrict__ stashR,
-                                                        int64_t NF) {
-  const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+                                                        int64_t NF, int64_t tile) {
+  const int64_t f = (int64_t)tile * blockDim.x + threadIdx.x;
   if (f >= NF) return;
   const int a = f_axis[f];
   const int gL = f_gL[f], gR = f_gR[f];
@@ -983,6 +1028,16 @@ __global__ __launch_bounds__(kThreads) void k_vel_faces(T *__restrict__ F0, T *_
   const T vR = gR >= 0 ? UG[(int64_t)a * G + gR] : stashR[f];
   T *Fa = a == 0 ? F0 : (a == 1 ? F1 : F2);
   Fa[f_cell[f]] = T(0.5) * (vL + vR);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_vel_faces(T *__restrict__ F0, T *__restrict__ F1, T *__restrict__ F2,
+                                                        const T *__restrict__ UG, int64_t G,
+                                                        const int *__restrict__ f_cell, const int *__restrict__ f_axis,
+                                                        const int *__restrict__ f_gL, const int *__restrict__ f_gR,
+                                                        const T *__restrict__ stashL, const T *__restrict__ stashR,
+                                                        int64_t NF) {
+  vel_faces_body<T>(F0, F1, F2, UG, G, f_cell, f_axis, f_gL, f_gR, stashL, stashR, NF, blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -1368,7 +1423,8 @@ hipError_t launch_velocity_fill(const Plan &p, const T *Cfin) {
                      (const T *)p.F[0], (const T *)p.F[1], (const T *)p.F[2], p.gidx, (const T *)p.normal,
                      (const T *)p.dn, (const T *)p.gamma, p.ap, (const T *)p.w, (const T *)p.CMs, (T *)p.UG, p.G,
                      p.K, p.f_cell, p.f_axis, p.f_gL, p.f_gR, (T *)p.stashL, (T *)p.stashR, p.NF, dm, p.d,
-                     (T)(0.5 / p.h), (T)p.Cn, (T)p.cos_t, (T)(1.0 / p.Ca), (T)(1.0 / p.mu), (T)p.ls, nbg);
+                     (T)(0.5 / p.h), (T)p.Cn, (T)p.cos_t, (T)(1.0 / p.Ca), (T)(1.0 / p.mu), (T)p.ls,
+                     p.dynamic ? 0 : 1, nbg);
   if (p.NF)
     hipLaunchKernelGGL((k_vel_faces<T>), dim3(blocks_for(p.NF)), dim3(kThreads), 0, p.stream, (T *)p.F[0],
                        (T *)p.F[1], (T *)p.F[2], (const T *)p.UG, p.G, p.f_cell, p.f_axis, p.f_gL, p.f_gR,
@@ -1583,5 +1639,224 @@ template hipError_t enqueue_phi<double>(const Plan &, int, void *);
 template hipError_t enqueue_phi<float>(const Plan &, int, void *);
 template hipError_t enqueue_diag<double>(const Plan &, int);
 template hipError_t enqueue_diag<float>(const Plan &, int);
+
+}  // namespace chib
+
+// =======================================================================================
+// Batched sweep: many independent 2D cases advanced together.  Each phase of the step is
+// one grouped launch over all cases: block b belongs to the case c with
+// off[c] <= b < off[c+1] (per-case tile counts, prefix-summed), whose pointers, sizes,
+// coefficients and tile shapes are read from a descriptor in device memory.  No block ever
+// waits for another; the order between phases is the stream order (or the graph's edges).
+namespace chib {
+
+template <typename T>
+struct CaseDesc {
+  T *C[2];                 // C[p] = C^n and C[1-p] = C^(n-1) (then C^(n+1)) for launch parity p
+  T *F0, *F1, *W;
+  Dims dm;
+  RhsCoef<T> cf;
+  const T *twr0, *twi0, *twr1, *twi1, *lamx, *lamy, *dctc, *dcts;
+  T a, alpha_s, inv_norm;
+  int logL_rhs, logL_out, logB, lognxb;
+  const int *gidx, *ap;
+  const T *dn, *gam, *normal, *w;
+  T *CGn, *CGnm1, *CMs, *UG;
+  int64_t G, NF;
+  int K, vel_fill;
+  T cb, inv2h, Cn, cos_t, inv_Ca, inv_mu, ls;
+  const int *f_cell, *f_axis, *f_gL, *f_gR;
+  T *stashL, *stashR;
+  unsigned nbg;
+};
+
+namespace {
+
+__device__ __forceinline__ int find_case(const int *__restrict__ off, int n, int b) {
+  int lo = 0, hi = n;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (off[mid] <= b) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
+template <typename T, int E, int U, int R>
+__global__ __launch_bounds__(kThreads) void kb_rhs(const CaseDesc<T> *__restrict__ cs, const int *__restrict__ off,
+                                                   int n, int parity) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int c = find_case(off, n, blockIdx.x);
+  const CaseDesc<T> &d = cs[c];
+  rhs_xdht_body<T, 2, E, U, R>(smem_raw, d.C[parity], d.C[1 - parity], d.F0, d.F1, d.F1, d.W, d.dm, d.cf,
+                               d.logL_rhs, d.twr0, d.twi0, (int)(blockIdx.x - off[c]));
+}
+
+template <typename T, int E, int R>
+__global__ __launch_bounds__(kThreads) void kb_neumann(const CaseDesc<T> *__restrict__ cs, const int *__restrict__ off,
+                                                       int n) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int c = find_case(off, n, blockIdx.x);
+  const CaseDesc<T> &d = cs[c];
+  neumann_body<T, E, R>(smem_raw, d.W, d.dm.lny, (int64_t)d.dm.nx, d.logB, d.lognxb, (int64_t)0, d.lamx,
+                        (const T *)nullptr, d.lamy, d.a, d.alpha_s, d.inv_norm, d.twr1, d.twi1, d.dctc, d.dcts,
+                        (int)(blockIdx.x - off[c]));
+}
+
+template <typename T, int E, int R>
+__global__ __launch_bounds__(kThreads) void kb_out(const CaseDesc<T> *__restrict__ cs, const int *__restrict__ off,
+                                                   int n, int parity) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int c = find_case(off, n, blockIdx.x);
+  const CaseDesc<T> &d = cs[c];
+  xdht_body<T, E, R>(smem_raw, d.W, d.C[1 - parity], d.dm.lnx, d.logL_out, d.twr0, d.twi0,
+                     (int)(blockIdx.x - off[c]));
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void kb_fill(const CaseDesc<T> *__restrict__ cs, const int *__restrict__ off,
+                                                    int n, int parity) {
+  const int c = find_case(off, n, blockIdx.x);
+  const CaseDesc<T> &d = cs[c];
+  fill_static_body<T>(d.C[1 - parity], d.gidx, d.dn, d.gam, d.ap, d.w, d.CGn, d.CGnm1, d.CMs, d.G, d.K, d.cb, 0,
+                      (int64_t)(blockIdx.x - off[c]));
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void kb_velg(const CaseDesc<T> *__restrict__ cs, const int *__restrict__ off,
+                                                    int n, int parity) {
+  const int c = find_case(off, n, blockIdx.x);
+  const CaseDesc<T> &d = cs[c];
+  vel_ghosts_body<T>(d.C[1 - parity], d.F0, d.F1, d.F1, d.gidx, d.normal, d.dn, d.gam, d.ap, d.w, d.CMs, d.UG, d.G,
+                     d.K, d.f_cell, d.f_axis, d.f_gL, d.f_gR, d.stashL, d.stashR, d.NF, d.dm, 2, d.inv2h, d.Cn,
+                     d.cos_t, d.inv_Ca, d.inv_mu, d.ls, 1, d.nbg, (int64_t)(blockIdx.x - off[c]));
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void kb_velf(const CaseDesc<T> *__restrict__ cs, const int *__restrict__ off,
+                                                    int n) {
+  const int c = find_case(off, n, blockIdx.x);
+  const CaseDesc<T> &d = cs[c];
+  vel_faces_body<T>(d.F0, d.F1, d.F1, d.UG, d.G, d.f_cell, d.f_axis, d.f_gL, d.f_gR, d.stashL, d.stashR, d.NF,
+                    (int64_t)(blockIdx.x - off[c]));
+}
+
+}  // namespace
+
+// Host side: descriptors from the member plans, per-phase tile offsets, one batched step.
+template <typename T>
+void fill_case_desc(const Plan &p, int cur, void *desc_host) {
+  CaseDesc<T> d{};
+  d.C[0] = (T *)p.C[cur];
+  d.C[1] = (T *)p.C[1 - cur];
+  d.F0 = (T *)p.F[0];
+  d.F1 = (T *)p.F[1];
+  d.W = (T *)p.W;
+  d.dm = make_dims(p);
+  d.cf = make_coef<T>(p);
+  d.twr0 = (const T *)p.twr[0];
+  d.twi0 = (const T *)p.twi[0];
+  d.twr1 = (const T *)p.twr[1];
+  d.twi1 = (const T *)p.twi[1];
+  d.lamx = (const T *)p.lam[0];
+  d.lamy = (const T *)p.lam[1];
+  d.dctc = (const T *)p.dctc;
+  d.dcts = (const T *)p.dcts;
+  d.a = (T)p.a;
+  d.alpha_s = (T)p.alpha_s;
+  d.inv_norm = (T)(1.0 / (double)p.N);
+  constexpr int E = tile_elems<T>();
+  d.logL_rhs = clamp_log(p.shape[0].log_tile, max_log_lines(p, E));
+  d.logL_out = clamp_log(p.shape[3].log_tile, max_log_lines(p, E));
+  d.logB = clamp_log(p.shape[2].log_tile, max_log_cols(p, p.n[1], E));
+  d.lognxb = p.logn[0] - d.logB;
+  d.gidx = p.gidx;
+  d.ap = p.ap;
+  d.dn = (const T *)p.dn;
+  d.gam = (const T *)p.gamma;
+  d.normal = (const T *)p.normal;
+  d.w = (const T *)p.w;
+  d.CGn = (T *)p.CGn;
+  d.CGnm1 = (T *)p.CGnm1;
+  d.CMs = (T *)p.CMs;
+  d.UG = (T *)p.UG;
+  d.G = p.G;
+  d.NF = p.NF;
+  d.K = p.K;
+  d.vel_fill = p.vel_fill && p.G > 0;
+  d.cb = (T)(p.cos_t / (1.4142135623730951 * p.Cn));
+  d.inv2h = (T)(0.5 / p.h);
+  d.Cn = (T)p.Cn;
+  d.cos_t = (T)p.cos_t;
+  d.inv_Ca = (T)(1.0 / p.Ca);
+  d.inv_mu = (T)(1.0 / p.mu);
+  d.ls = (T)p.ls;
+  d.f_cell = p.f_cell;
+  d.f_axis = p.f_axis;
+  d.f_gL = p.f_gL;
+  d.f_gR = p.f_gR;
+  d.stashL = (T *)p.stashL;
+  d.stashR = (T *)p.stashR;
+  d.nbg = blocks_for(p.G * 16);
+  std::memcpy(desc_host, &d, sizeof(d));
+}
+
+template <typename T>
+size_t case_desc_bytes() {
+  return sizeof(CaseDesc<T>);
+}
+
+// Per-phase tile counts of one case (0 rhs, 1 neumann, 2 out, 3 fill, 4 velg, 5 velf) and the
+// LDS bytes of its tiles (0 rhs, 1 neumann, 2 out).
+template <typename T>
+void case_tiles(const Plan &p, int *tiles, size_t *lds) {
+  constexpr int E = tile_elems<T>();
+  const int lr = clamp_log(p.shape[0].log_tile, max_log_lines(p, E));
+  const int lo = clamp_log(p.shape[3].log_tile, max_log_lines(p, E));
+  const int lb = clamp_log(p.shape[2].log_tile, max_log_cols(p, p.n[1], E));
+  tiles[0] = p.n[1] >> lr;
+  tiles[1] = p.n[0] >> lb;
+  tiles[2] = p.n[1] >> lo;
+  tiles[3] = (int)blocks_for(p.G * 16);
+  const bool vf = p.vel_fill && p.G > 0;
+  tiles[4] = vf ? (int)(blocks_for(p.G * 16) + blocks_for(p.NF)) : 0;
+  tiles[5] = vf ? (int)blocks_for(p.NF) : 0;
+  lds[0] = (size_t)(1 << lr) * line_pitch(p.n[0]) * sizeof(T);
+  lds[1] = (size_t)col_tile(p.n[1], 1 << lb) * sizeof(T);
+  lds[2] = (size_t)(1 << lo) * line_pitch(p.n[0]) * sizeof(T);
+}
+
+template <typename T>
+hipError_t enqueue_batch_step(const BatchLaunch &bl, int parity) {
+  constexpr int E = tile_elems<T>();
+  const CaseDesc<T> *cs = (const CaseDesc<T> *)bl.descs;
+  const int n = bl.n;
+  const int *off = bl.off;
+  auto O = [&](int ph) { return off + ph * (n + 1); };
+  const unsigned nb0 = bl.total[0], nb1 = bl.total[1], nb2 = bl.total[2];
+  const unsigned nb3 = bl.total[3], nb4 = bl.total[4], nb5 = bl.total[5];
+  const bool r8 = bl.radix_rhs == 8, u2 = bl.unroll >= 2;
+  if (r8 && u2) hipLaunchKernelGGL((kb_rhs<T, E, 2, 8>), dim3(nb0), dim3(kThreads), bl.lds[0], bl.stream, cs, O(0), n, parity);
+  else if (r8) hipLaunchKernelGGL((kb_rhs<T, E, 1, 8>), dim3(nb0), dim3(kThreads), bl.lds[0], bl.stream, cs, O(0), n, parity);
+  else if (u2) hipLaunchKernelGGL((kb_rhs<T, E, 2, 16>), dim3(nb0), dim3(kThreads), bl.lds[0], bl.stream, cs, O(0), n, parity);
+  else hipLaunchKernelGGL((kb_rhs<T, E, 1, 16>), dim3(nb0), dim3(kThreads), bl.lds[0], bl.stream, cs, O(0), n, parity);
+  if (bl.radix_neu == 8) hipLaunchKernelGGL((kb_neumann<T, E, 8>), dim3(nb1), dim3(kThreads), bl.lds[1], bl.stream, cs, O(1), n);
+  else hipLaunchKernelGGL((kb_neumann<T, E, 16>), dim3(nb1), dim3(kThreads), bl.lds[1], bl.stream, cs, O(1), n);
+  if (bl.radix_out == 8) hipLaunchKernelGGL((kb_out<T, E, 8>), dim3(nb2), dim3(kThreads), bl.lds[2], bl.stream, cs, O(2), n, parity);
+  else hipLaunchKernelGGL((kb_out<T, E, 16>), dim3(nb2), dim3(kThreads), bl.lds[2], bl.stream, cs, O(2), n, parity);
+  if (nb3) hipLaunchKernelGGL((kb_fill<T>), dim3(nb3), dim3(kThreads), 0, bl.stream, cs, O(3), n, parity);
+  if (nb4) hipLaunchKernelGGL((kb_velg<T>), dim3(nb4), dim3(kThreads), 0, bl.stream, cs, O(4), n, parity);
+  if (nb5) hipLaunchKernelGGL((kb_velf<T>), dim3(nb5), dim3(kThreads), 0, bl.stream, cs, O(5), n);
+  return hipGetLastError();
+}
+
+template void fill_case_desc<double>(const Plan &, int, void *);
+template void fill_case_desc<float>(const Plan &, int, void *);
+template size_t case_desc_bytes<double>();
+template size_t case_desc_bytes<float>();
+template void case_tiles<double>(const Plan &, int *, size_t *);
+template void case_tiles<float>(const Plan &, int *, size_t *);
+template hipError_t enqueue_batch_step<double>(const BatchLaunch &, int);
+template hipError_t enqueue_batch_step<float>(const BatchLaunch &, int);
 
 }  // namespace chib

@@ -1,0 +1,96 @@
+"""GPU: the batched sweep (grouped launches per phase, hipGraph replays) against stepping each
+state alone (bit for bit with the same launch shapes) and against the oracle."""
+import sys
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle.geometry import build_tables
+from oracle.solver import OracleState
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def chib():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2104_00350_amd import chib as m
+    return m
+
+
+def _cases():
+    return [W.small_case(64, 32, kind="flat", theta_deg=50.0),
+            W.small_case(128, 64, kind="sin", theta_deg=120.0, seed=3),
+            W.small_case(256, 128, kind="circle", theta_deg=80.0, seed=4),
+            W.small_case(64, 32, kind="tilted", theta_deg=100.0, seed=5),
+            W.config4_cases(6)[5]]
+
+
+def _make(chib, case, faces_seed):
+    T = build_tables(case.grid, case.shapes, case.params)
+    g = case.grid
+    geo = chib.Geometry.from_tables(g.n, g.lo, g.hi, T.gidx, T.normal, T.dn, T.gamma, T.ap, T.w, T.alpha)
+    st = chib.State(geo, case.params)
+    C0, _ = case.initial_fields()
+    rng = np.random.default_rng(faces_seed)
+    faces = [0.2 * rng.standard_normal(g.shape) for _ in range(2)]
+    st.set_initial(C0, faces)
+    return st, T, C0, faces
+
+
+def test_batched_steps_equal_single_steps(chib):
+    cases = _cases()
+    singles = [_make(chib, c, 10 + i)[0] for i, c in enumerate(cases)]
+    members = [_make(chib, c, 10 + i)[0] for i, c in enumerate(cases)]
+    b = chib.Batch(members)
+    print("[gpu] batch of", len(members), file=sys.stderr, flush=True)
+    b.step(21)            # ten graph replays of two steps plus one direct step
+    b.sync()
+    for s in singles:
+        s.step(21)
+    for s, m in zip(singles, members):
+        assert np.array_equal(s.get(chib.FIELD_C), m.get(chib.FIELD_C))
+        assert np.array_equal(s.get(chib.FIELD_C_PREV), m.get(chib.FIELD_C_PREV))
+        assert np.array_equal(s.get(chib.FIELD_U), m.get(chib.FIELD_U))
+        assert m.diagnostics()["step"] == 21
+    b.step(4)
+    b.sync()
+    for s in singles:
+        s.step(4)
+    for s, m in zip(singles, members):
+        assert np.array_equal(s.get(chib.FIELD_C), m.get(chib.FIELD_C))
+
+
+def test_batch_against_oracle_after_tuning(chib):
+    cases = _cases()[:3]
+    made = [_make(chib, c, 20 + i) for i, c in enumerate(cases)]
+    b = chib.Batch([m[0] for m in made])
+    radix, unroll = b.tune(2)
+    print("[gpu] batch tuned", radix, unroll, file=sys.stderr, flush=True)
+    assert all(r in (8, 16) for r in radix) and unroll in (1, 2)
+    b.step(40)
+    b.sync()
+    for case, (st, T, C0, faces) in zip(cases, made):
+        orc = OracleState(case.grid, case.params, T, C0, faces)
+        orc.step(40)
+        assert float(np.max(np.abs(st.get(chib.FIELD_C) - orc.C))) <= 1e-9
+        assert float(np.max(np.abs(st.get(chib.FIELD_U) - orc.faces[0]))) <= 1e-9
+
+
+def test_batch_rejects_3d_and_dynamic(chib):
+    c3 = W.small_case_3d(16)
+    g = c3.grid
+    geo = chib.Geometry.build(g.n, g.lo, g.hi, c3.shapes, c3.params)
+    s3 = chib.State(geo, c3.params)
+    s3.set_initial(c3.initial_fields()[0])
+    with pytest.raises(chib.ChibError) as e:
+        chib.Batch([s3])
+    assert e.value.code == chib.EUNSUPPORTED
+    cd = W.small_case(64, 32, kind="flat", Vs=100.0)
+    sd, _, _, _ = _make(chib, cd, 2)
+    with pytest.raises(chib.ChibError) as e:
+        chib.Batch([sd])
+    assert e.value.code == chib.EUNSUPPORTED

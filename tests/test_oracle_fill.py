@@ -2,7 +2,7 @@
 
 CPU only.  The pins are special cases with known answers (constant and linear
 fields, the exact tanh wedge that satisfies the continuous contact-angle
-condition, the static limit of the dynamic condition, the no-slip and free-slip
+condition, the wall balance reached by the dynamic condition, the no-slip and free-slip
 limits of the Navier condition) and the discrete mass identity of the
 semi-implicit step.
 """
@@ -50,7 +50,10 @@ def test_linear_field_mirror_value_exact_for_on_centre_interpolation_points():
 
 
 @pytest.mark.parametrize("kind,theta", [("flat", 60.0), ("sin", 45.0), ("circle", 135.0), ("tilted", 120.0)])
-def test_static_condition_holds_at_the_intersect_point(kind, theta):
+def test_static_condition_holds_between_mirror_and_intersect(kind, theta):
+    """The ghost value makes the wall balance hold with the slope taken from G to M and the
+    wetting term at the mirror point; where that would put C_I outside [-1, 1] it sits on the
+    bound instead."""
     case = W.small_case(64, 32, kind=kind, theta_deg=theta)
     st, T = _state(case)
     P = st.C.copy()
@@ -59,8 +62,15 @@ def test_static_condition_holds_at_the_intersect_point(kind, theta):
     g = T.gamma
     CI = (g * CG + CM) / (g + 1)
     dCdn = (CM - CG) / ((1 + g) * T.dn)
-    res = (3 / (2 * SQ2)) * case.params.Cn * dCdn + math.cos(math.radians(theta)) * 0.75 * (1 - CI * CI)
-    assert np.max(np.abs(res)) <= 1e-12
+    res = (3 / (2 * SQ2)) * case.params.Cn * dCdn + math.cos(math.radians(theta)) * 0.75 * (1 - CM * CM)
+    b = T.gamma * T.dn * math.cos(math.radians(theta)) / (SQ2 * case.params.Cn)
+    raw = CM + b * (1 - CM * CM)
+    free = np.abs(raw) < 1
+    assert np.count_nonzero(free & (np.abs(CM) < 0.9)) >= 4      # interface ghosts are checked
+    assert np.max(np.abs(res[free])) <= 1e-12
+    # elsewhere (bulk ghosts, where noise puts |C_M| just above 1) C_I sits on the bound
+    # on the side that the unclipped value overshoots
+    assert np.max(np.abs(CI[~free] - np.sign(raw[~free])), initial=0.0) <= 1e-12
 
 
 @pytest.mark.parametrize("theta", [50.0, 120.0])
@@ -88,9 +98,15 @@ def test_tanh_wedge_is_reproduced_under_refinement(theta):
     assert errs[2] < 0.05
 
 
-def test_dynamic_condition_relaxes_to_the_static_one():
-    """With the fluid frozen, repeated dynamic updates converge to the static ghost values."""
+def test_dynamic_condition_relaxes_to_the_wall_balance():
+    """With the fluid frozen, repeated dynamic updates converge to ghost values at which the
+    wall equation holds with zero time derivative, g' taken at C_I (Eq. WallBCS_recast).
+
+    The frozen-fluid iteration contracts when the diffusive part Cn/d1 of the linearised wall
+    equation outweighs the wetting part sqrt2 cos(theta) |C_I|; d1 = 1.5 cells keeps this case
+    in that regime."""
     case = W.small_case(64, 32, kind="sin", theta_deg=60.0, Vs=2000.0)   # Vs dt = 0.2
+    case.params.d1_cells = 1.5
     st, T = _state(case)
     st.faces = [np.zeros(case.grid.shape) for _ in range(2)]   # no wall advection term
     P = st.C.copy()
@@ -101,11 +117,15 @@ def test_dynamic_condition_relaxes_to_the_static_one():
         Pf[T.gidx] = 2 * CG - CG_prev
         new = st.fill_C(P, initial=False)
         CG_prev, CG = CG, new
-    static = W.small_case(64, 32, kind="sin", theta_deg=60.0, Vs=0.0)
-    st2 = OracleState(static.grid, static.params, T, st.C)
     Pf[T.gidx] = CG
-    CGs = st2.fill_C(P, initial=False)
-    assert np.max(np.abs(CG - CGs)) <= 1e-10
+    CM = mirror_value(Pf, T)
+    g = T.gamma
+    CI = (g * CG + CM) / (g + 1)
+    dCdn = (CM - CG) / ((1 + g) * T.dn)
+    res = case.params.Cn * dCdn + math.cos(math.radians(60.0)) * (1 - CI * CI) / SQ2
+    assert np.max(np.abs(CG - CG_prev)) <= 1e-12
+    assert np.max(np.abs(res)) <= 1e-10
+    assert np.max(np.abs(st.CI - CI)) <= 1e-10
 
 
 def _random_faces(grid, seed, amp=0.05):
@@ -117,7 +137,7 @@ def _random_faces(grid, seed, amp=0.05):
 def test_velocity_fill_limits(ls, kind):
     """No penetration at I always; no slip (ls = 0) gives zero tangential velocity at I;
     ls -> infinity gives zero normal derivative of the tangential velocity (the capillary
-    bracket vanishes because the static condition holds exactly)."""
+    bracket vanishes wherever the static fill was not clipped)."""
     case = W.small_case(64, 32, kind=kind, theta_deg=70.0, slip_length=ls)
     st, T = _state(case)
     st.faces = _random_faces(case.grid, 3)
@@ -135,7 +155,12 @@ def test_velocity_fill_limits(ls, kind):
     if ls == 0.0:
         assert np.max(np.abs(g * VtG + VtM)) <= 1e-13
     else:
-        assert np.max(np.abs(VtG - VtM)) <= 1e-9
+        Cf = st.C.reshape(-1)
+        CM = mirror_value(Cf, T)
+        b = T.gamma * T.dn * math.cos(math.radians(70.0)) / (SQ2 * case.params.Cn)
+        free = np.abs(CM + b * (1 - CM * CM)) < 1
+        assert np.count_nonzero(free & (np.abs(CM) < 0.9)) >= 4
+        assert np.max(np.abs(VtG - VtM)[:, free]) <= 1e-9
     # faces touching a ghost hold the mean of the two adjacent centred values; others unchanged
     ghost = np.zeros(case.grid.cells, bool)
     ghost[T.gidx] = True

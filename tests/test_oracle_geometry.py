@@ -41,7 +41,7 @@ def test_flat_wall_tables_closed_form():
     assert np.all(T.normal[0] == 0.0) and np.all(T.normal[1] == 1.0)
     assert np.allclose(T.dn, 0.1 - 5.5 * h, rtol=0, atol=1e-14)
     assert np.allclose(T.points["I"][1], 0.1, rtol=0, atol=1e-14)
-    assert np.allclose(T.gamma, math.sqrt(2) * h / T.dn, rtol=1e-14)
+    assert np.allclose(T.gamma, 2.0 * h / T.dn, rtol=1e-14)
 
 
 def _check_colinear(T, grid):

@@ -80,7 +80,7 @@ class Params:
     friction); ``S <= 0`` selects the smallest stabilisation parameter that
     keeps the two Helmholtz factors real.  ``d1_cells``/``d2_cells`` are the
     intersect-to-mirror and mirror-to-interpolation distances in cell widths
-    (``d1_cells <= 0`` means one cell diagonal).
+    (``d1_cells <= 0`` means 2 cells).
     """
 
     Cn: float
