@@ -95,7 +95,7 @@ typedef struct {
   double dt;
   double S;                   /* stabilisation of Appendix A.1; <= 0 selects Cn sqrt(6 Pe/dt) */
   double d1_cells;            /* intersect-to-mirror distance in cells; <= 0 selects 2 */
-  double d2_cells;            /* mirror-to-interpolation-point spacing in cells (0.5 recommended) */
+  double d2_cells;            /* mirror-to-interpolation-point spacing in cells; <= 0 selects 1.5 */
   int subgrid;                /* subgrid points per direction for the volume fraction; 0: 100 (2D) / 20 (3D) */
   int precision;              /* 64 (FP64) or 32 (FP32) arithmetic on the device */
   int flags;                  /* CH_IB_FLAG_* */

@@ -22,13 +22,12 @@ Readings of silent or garbled passages (each is also listed in the design doc):
 * the intersect point is found by marching from the ghost along n in steps of
   h/100 to the first fluid point, then bisecting 60 times (the kept end is the
   fluid one);
-* d1 (intersect to mirror) defaults to 2h and d2 to h/2; the interpolation
-  points lie beyond the mirror point: IP1 = M + d2 n, IP2 = M + 2 d2 n.  The
-  paper only asks for d1 above half a cell diagonal; with d1 near one diagonal
-  the averaging stencil of IP1 reaches the ghost's own fluid neighbours and the
-  linearised step has growing near-wall modes for wetting angles below about
-  60 degrees at Cn/h ~ 1.3 (spectral radius up to 1.06 per step); 2h removes
-  them together with the explicit static condition of the solver;
+* d1 (intersect to mirror) defaults to 2h and d2 to 1.5h (d2 < d1 as the
+  paper asks); the interpolation points lie beyond the mirror point:
+  IP1 = M + d2 n, IP2 = M + 2 d2 n.  The paper only asks for d1 above half a
+  cell diagonal; with d1 near one diagonal and d2 = h/2 the averaging stencil
+  of IP1 reaches the ghost's own fluid neighbours and near-wall modes grow for
+  strongly wetting angles at Cn/h ~ 1.3;
 * the averaging points of an interpolation point are the cell containing it
   and that cell's 2d face neighbours (5 in 2D, 7 in 3D); averaging points whose
   centre is solid are dropped and the remaining weights renormalised; if none
@@ -333,7 +332,7 @@ def build_tables(grid: Grid, shapes: Sequence[Shape], params: Params) -> GhostTa
     dn = np.sqrt(((Ip - Gp) ** 2).sum(axis=0))
 
     d1 = (params.d1_cells if params.d1_cells > 0 else 2.0) * h
-    d2 = params.d2_cells * h
+    d2 = (params.d2_cells if params.d2_cells > 0 else 1.5) * h
     Mp = Ip + d1 * n
     IP1 = Mp + d2 * n
     IP2 = Mp + (2.0 * d2) * n

@@ -266,13 +266,18 @@ class OracleState:
         reads come from P (Jacobi sweep), so the result is order independent.
         Static condition (no contact-line friction, mu_f = 0): Eq. WallBCS loses
         its time derivative and reads (3/(2 sqrt2)) Cn dC/dn + cos(theta) g'(C) = 0,
-        g'(C) = 3(1 - C^2)/4, i.e. dC/dn = -cos(theta)(1 - C^2)/(sqrt2 Cn) along the
-        wall normal.  One explicit step of that relation from M back to I gives
-        C_I = C_M + b (1 - C_M^2), b = d1 cos(theta)/(sqrt2 Cn) = gamma dn cos(theta)/(sqrt2 Cn),
-        kept inside [-1, 1]; C_G then follows from Eq. UpdateC.  (Taking g' at C_I
-        and solving for it instead gives the ghost a gain 1/(1 - 2b) on the mirror
-        value against 1 + 2b here, and the step then has growing near-wall modes
-        for wetting angles below about 60 degrees at Cn/h ~ 1.3.)
+        g'(C) = 3(1 - C^2)/4, i.e. dC/dn = -cos(theta)(1 - C^2)/(sqrt2 Cn) with n
+        pointing into the fluid.  That relation also holds at every point of the
+        normal through a straight interface meeting the wall at theta (the
+        equilibrium tanh profile), so it is integrated exactly from M back to I:
+        artanh C_I = artanh C_M + b, b = d1 cos(theta)/(sqrt2 Cn) = gamma dn cos(theta)/(sqrt2 Cn),
+        i.e. C_I = (C_M + t)/(1 + t C_M), t = tanh b, with C_M taken inside [-1, 1]
+        (continued smoothly beyond +-1 the map has slope e^(2b) there and the ghost
+        feedback diverges at these resolutions; the clip keeps it bounded).  C_G then
+        follows from Eq. UpdateC.  (The one-sided slope over d1 with g'
+        at C_I or at C_M instead has spurious wall-film steady states and, for
+        wetting angles below about 60 degrees at Cn/h ~ 1.3, growing near-wall
+        modes.)
         Dynamic condition: C_I advanced by one forward step of
         DC/Dt = Vs [Cn dC/dn + cos(theta)(1 - C_I^2)/sqrt2] (Eq. WallBCS_recast),
         then C_G = ((gamma+1) C_I - C_M)/gamma (Eq. UpdateC).
@@ -285,8 +290,9 @@ class OracleState:
         CM = mirror_value(Pf, T)
         CIs = (gam * PG + CM) / (gam + 1.0)
         if prm.Vs <= 0.0:
-            b = gam * T.dn * self.cos_theta / (SQRT2 * prm.Cn)
-            CI = np.clip(CM + b * (1.0 - CM * CM), -1.0, 1.0)
+            t = np.tanh(gam * T.dn * self.cos_theta / (SQRT2 * prm.Cn))
+            Mc = np.clip(CM, -1.0, 1.0)
+            CI = (Mc + t) / (1.0 + t * Mc)
             return ((gam + 1.0) * CI - CM) / gam
         if initial:
             self.CI = CIs.copy()
@@ -311,10 +317,9 @@ class OracleState:
 
         V_nG = -V_nM/gamma (Eq. NoPenetration);
         V_tG = V_tM (ls - dn)/(ls + gamma dn) - Kc grad_t C_I ls (gamma+1) dn / (mu (ls + gamma dn))
-        (Eq. UpdateVtan), Kc = [(3/(2 sqrt2)) Cn dC/dn + cos(theta) g'(C_w)]/Ca with
-        C_w = C_I for the dynamic condition and C_w = C_M for the static one (the
-        same discrete balance as the static fill, so Kc vanishes wherever that fill
-        was not clipped); the ghost velocity is V_nG n + V_tG (vector form of Eq. UpdateVandW, with the
+        (Eq. UpdateVtan), Kc = [(3/(2 sqrt2)) Cn dC/dn + cos(theta) g'(C_I)]/Ca for the
+        dynamic condition; with mu_f = 0 the wall equation itself sets that bracket
+        to zero, so Kc = 0 for the static condition; the ghost velocity is V_nG n + V_tG (vector form of Eq. UpdateVandW, with the
         back-transform sign read so that it inverts Eq. CoordinateTransformation).
         Every face with a ghost on either side becomes the mean of its two
         cell-centred values, taken from the faces as they were before this fill.
@@ -337,8 +342,10 @@ class OracleState:
         gM = _mirror_grad(Cf, grid, T)
         gI = (gam * gG + gM) / (gam + 1.0)
         gt = gI - (gI * n).sum(axis=0) * n
-        Cw = CM if prm.Vs <= 0.0 else CI
-        Kc = ((3.0 / (2.0 * SQRT2)) * prm.Cn * dCdn + 0.75 * self.cos_theta * (1.0 - Cw * Cw)) / prm.Ca
+        if prm.Vs <= 0.0:
+            Kc = np.zeros_like(CI)
+        else:
+            Kc = ((3.0 / (2.0 * SQRT2)) * prm.Cn * dCdn + 0.75 * self.cos_theta * (1.0 - CI * CI)) / prm.Ca
         ls = prm.slip_length
         VtG = VtM * ((ls - dn) / (ls + gam * dn)) - Kc * gt * (ls * (gam + 1.0) * dn / (prm.mu * (ls + gam * dn)))
         uG = VnG * n + VtG

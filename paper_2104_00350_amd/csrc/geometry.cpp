@@ -16,7 +16,7 @@
 //  - mirror point d1 beyond the intersect point (default 2h: near one cell diagonal the
 //    averaging stencil of the first interpolation point reaches the ghost's own fluid
 //    neighbours and near-wall modes grow for strongly wetting angles), interpolation
-//    points d2 and 2*d2 beyond the mirror point (default d2 = h/2);
+//    points d2 and 2*d2 beyond the mirror point (default d2 = 1.5h);
 //  - averaging points: the cell containing the interpolation point and its 2d face
 //    neighbours; solid ones are dropped and the weights renormalised; with none left, the
 //    nearest fluid centre within 2h takes the whole weight.
@@ -307,7 +307,7 @@ extern "C" int ch_ib_geometry_build(const ch_ib_grid *grid, const ch_ib_shape *s
   g->w.assign((size_t)2 * K * G, 0.0);
 
   const double d1 = (params->d1_cells > 0 ? params->d1_cells : 2.0) * h;
-  const double d2 = params->d2_cells * h;
+  const double d2 = (params->d2_cells > 0 ? params->d2_cells : 1.5) * h;
   std::vector<int> err(G, 0);
 
   parallel_for(G, [&](int64_t gi) {

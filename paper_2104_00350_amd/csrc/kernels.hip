@@ -794,9 +794,10 @@ __device__ __forceinline__ T group16_sum(T v) {
 }
 
 // K6 (static condition, no contact-line friction): per ghost, C_M = 2 IDW(IP1) - IDW(IP2),
-// C_I = C_M + b (1 - C_M^2) kept inside [-1, 1], b = gamma dn cos(theta)/(sqrt2 Cn): the
-// algebraic wall condition of Eq. WallBCS with mu_f = 0, its slope taken between I and M
-// and its wetting term at M; then C_G = ((gamma+1) C_I - C_M)/gamma (Eq. UpdateC).
+// then the wall relation of Eq. WallBCS with mu_f = 0, dC/dn = -cos(theta)(1 - C^2)/(sqrt2 Cn),
+// integrated exactly from M back to I: C_I = (C_M + t)/(1 + t C_M), t = tanh(b),
+// b = gamma dn cos(theta)/(sqrt2 Cn), C_M taken inside [-1, 1]; C_G = ((gamma+1) C_I - C_M)/gamma
+// (Eq. UpdateC).
 // Sixteen lanes per ghost: lane s < 2K gathers one weighted averaging point.
 template <typename T>
 __device__ __forceinline__ void fill_static_body(T *__restrict__ C, const int *__restrict__ gidx,
@@ -814,9 +815,9 @@ __device__ __forceinline__ void fill_static_body(T *__restrict__ C, const int *_
   const T CM = group16_sum(v);
   if (g >= G || sl != 0) return;
   const T ga = gam[g];
-  const T b = ga * dn[g] * cb;
-  const T CIr = CM + b * (T(1) - CM * CM);
-  const T CI = CIr > T(1) ? T(1) : (CIr < T(-1) ? T(-1) : CIr);
+  const T t = tanh(ga * dn[g] * cb);
+  const T Mc = CM > T(1) ? T(1) : (CM < T(-1) ? T(-1) : CM);
+  const T CI = (Mc + t) / (T(1) + t * Mc);
   const T CG = ((ga + T(1)) * CI - CM) / ga;
   C[gidx[g]] = CG;
   CMs[g] = CM;
@@ -921,7 +922,9 @@ __global__ __launch_bounds__(kThreads) void k_commit_ghosts(T *__restrict__ C, c
 // for the faces touching ghosts, the cell-centred velocity of their non-ghost side, all
 // from the faces as they are before this fill.  Blocks [0, nbg) take sixteen lanes per
 // ghost (lane s < 2K: one averaging point's gradient and centred velocity, lane 2K: the
-// ghost's own gradient); the remaining blocks take one face per thread.
+// ghost's own gradient); the remaining blocks take one face per thread.  With the static
+// condition (capillary = 0) the wall equation makes the bracket Kc of Eq. UpdateVtan zero,
+// and no gradient of C is gathered.
 template <typename T>
 __device__ __forceinline__ void vel_ghosts_body(
     const T *__restrict__ C, const T *__restrict__ F0, const T *__restrict__ F1, const T *__restrict__ F2,
@@ -929,7 +932,7 @@ __device__ __forceinline__ void vel_ghosts_body(
     const int *__restrict__ ap, const T *__restrict__ w, const T *__restrict__ CMs, T *__restrict__ UG, int64_t G,
     int K, const int *__restrict__ f_cell, const int *__restrict__ f_axis, const int *__restrict__ f_gL,
     const int *__restrict__ f_gR, T *__restrict__ stashL, T *__restrict__ stashR, int64_t NF, Dims dm, int d,
-    T inv2h, T Cn, T cos_t, T inv_Ca, T inv_mu, T ls, int wet_at_mirror, unsigned nbg, int64_t tile) {
+    T inv2h, T Cn, T cos_t, T inv_Ca, T inv_mu, T ls, int capillary, unsigned nbg, int64_t tile) {
   const T *Fs[3] = {F0, F1, F2};
   if (tile >= nbg) {
     const int64_t f = (int64_t)(tile - nbg) * blockDim.x + threadIdx.x;
@@ -958,12 +961,12 @@ __device__ __forceinline__ void vel_ghosts_body(
       const T cw = (sl < K ? T(2) : T(-1)) * w[i];
       const int64_t c = ap[i];
       T gk[3] = {0, 0, 0};
-      grad_at(C, c, dm, d, inv2h, gk);
+      if (capillary) grad_at(C, c, dm, d, inv2h, gk);
       for (int a = 0; a < d; ++a) {
         gm[a] = cw * gk[a];
         um[a] = cw * centred_u(Fs[a], c, a, dm, d);
       }
-    } else if (sl == 2 * K) {
+    } else if (sl == 2 * K && capillary) {
       grad_at(C, (int64_t)gidx[g], dm, d, inv2h, gg);
     }
   }
@@ -988,8 +991,8 @@ __device__ __forceinline__ void vel_ghosts_body(
   const T CG = C[cg], CM = CMs[g];
   const T CIv = (ga * CG + CM) / (ga + T(1));
   const T dCdn = (CM - CG) / ((T(1) + ga) * dng);
-  const T Cw = wet_at_mirror ? CM : CIv;
-  const T Kc = (T(1.06066017177982128660) * Cn * dCdn + T(0.75) * cos_t * (T(1) - Cw * Cw)) * inv_Ca;
+  const T Kc = capillary ? (T(1.06066017177982128660) * Cn * dCdn + T(0.75) * cos_t * (T(1) - CIv * CIv)) * inv_Ca
+                         : T(0);
   const T den = ls + ga * dng;
   const T fM = (ls - dng) / den;
   const T fK = ls * (ga + T(1)) * dng * inv_mu / den;
@@ -1008,8 +1011,8 @@ __global__ __launch_bounds__(kThreads) void k_vel_ghosts(
     const int *__restrict__ ap, const T *__restrict__ w, const T *__restrict__ CMs, T *__restrict__ UG, int64_t G,
     int K, const int *__restrict__ f_cell, const int *__restrict__ f_axis, const int *__restrict__ f_gL,
     const int *__restrict__ f_gR, T *__restrict__ stashL, T *__restrict__ stashR, int64_t NF, Dims dm, int d,
-    T inv2h, T Cn, T cos_t, T inv_Ca, T inv_mu, T ls, int wet_at_mirror, unsigned nbg) {
-  vel_ghosts_body<T>(C, F0, F1, F2, gidx, nrm, dn, gam, ap, w, CMs, UG, G, K, f_cell, f_axis, f_gL, f_gR, stashL, stashR, NF, dm, d, inv2h, Cn, cos_t, inv_Ca, inv_mu, ls, wet_at_mirror, nbg, blockIdx.x);
+    T inv2h, T Cn, T cos_t, T inv_Ca, T inv_mu, T ls, int capillary, unsigned nbg) {
+  vel_ghosts_body<T>(C, F0, F1, F2, gidx, nrm, dn, gam, ap, w, CMs, UG, G, K, f_cell, f_axis, f_gL, f_gR, stashL, stashR, NF, dm, d, inv2h, Cn, cos_t, inv_Ca, inv_mu, ls, capillary, nbg, blockIdx.x);
 }
 
 // K7b: every face touching a ghost becomes the mean of its two cell-centred values.
@@ -1424,7 +1427,7 @@ hipError_t launch_velocity_fill(const Plan &p, const T *Cfin) {
                      (const T *)p.dn, (const T *)p.gamma, p.ap, (const T *)p.w, (const T *)p.CMs, (T *)p.UG, p.G,
                      p.K, p.f_cell, p.f_axis, p.f_gL, p.f_gR, (T *)p.stashL, (T *)p.stashR, p.NF, dm, p.d,
                      (T)(0.5 / p.h), (T)p.Cn, (T)p.cos_t, (T)(1.0 / p.Ca), (T)(1.0 / p.mu), (T)p.ls,
-                     p.dynamic ? 0 : 1, nbg);
+                     p.dynamic ? 1 : 0, nbg);
   if (p.NF)
     hipLaunchKernelGGL((k_vel_faces<T>), dim3(blocks_for(p.NF)), dim3(kThreads), 0, p.stream, (T *)p.F[0],
                        (T *)p.F[1], (T *)p.F[2], (const T *)p.UG, p.G, p.f_cell, p.f_axis, p.f_gL, p.f_gR,
@@ -1729,7 +1732,7 @@ __global__ __launch_bounds__(kThreads) void kb_velg(const CaseDesc<T> *__restric
   const CaseDesc<T> &d = cs[c];
   vel_ghosts_body<T>(d.C[1 - parity], d.F0, d.F1, d.F1, d.gidx, d.normal, d.dn, d.gam, d.ap, d.w, d.CMs, d.UG, d.G,
                      d.K, d.f_cell, d.f_axis, d.f_gL, d.f_gR, d.stashL, d.stashR, d.NF, d.dm, 2, d.inv2h, d.Cn,
-                     d.cos_t, d.inv_Ca, d.inv_mu, d.ls, 1, d.nbg, (int64_t)(blockIdx.x - off[c]));
+                     d.cos_t, d.inv_Ca, d.inv_mu, d.ls, 0, d.nbg, (int64_t)(blockIdx.x - off[c]));
 }
 
 template <typename T>

@@ -80,7 +80,7 @@ class Params:
     friction); ``S <= 0`` selects the smallest stabilisation parameter that
     keeps the two Helmholtz factors real.  ``d1_cells``/``d2_cells`` are the
     intersect-to-mirror and mirror-to-interpolation distances in cell widths
-    (``d1_cells <= 0`` means 2 cells).
+    (``d1_cells <= 0`` means 2 cells, ``d2_cells <= 0`` 1.5 cells).
     """
 
     Cn: float
@@ -94,7 +94,7 @@ class Params:
     dt: float = 1e-4
     S: float = 0.0
     d1_cells: float = 0.0
-    d2_cells: float = 0.5
+    d2_cells: float = 0.0
     subgrid: int = 0           # 0: 100 per direction in 2D, 20 in 3D
     velocity_fill: bool = True
 
@@ -235,8 +235,8 @@ def small_case(nx: int = 64, ny: int = 32, theta_deg: float = 60.0, kind: str = 
         shapes = [Shape(SINUSOID, (0.25, 0.06, 0.5, 0.0))]
         yc = 0.25 + 0.06 * math.sin(2.0 * math.pi * 1.0 / 0.5)
     elif kind == "circle":
-        shapes = [Shape(SPHERE, (1.0, 0.35, 0.0, 0.25))]
-        yc = 0.6
+        shapes = [Shape(SPHERE, (1.0, 0.42, 0.0, 0.22))]
+        yc = 0.64
     else:
         raise ValueError(kind)
     return Case(f"small_{kind}_{nx}x{ny}", g, shapes, prm, 50, (1.0, yc), 0.3, 1e-3, seed)
