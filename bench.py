@@ -26,11 +26,13 @@ HBM_PEAK_GBS = 8000.0
 METRIC = "CH+IB cell-updates/s at 256³; learned/plain speedup at ≤1° contact-angle err"
 
 
-def algorithmic_bytes(name: str, cells: int, d: int, es: int, G: int, NF: int) -> float:
+def algorithmic_bytes(name: str, cells: int, d: int, es: int, G: int, NF: int, dynamic: bool = False) -> float:
     """Bytes the method must move per launch of each kernel of a step.
 
     Field passes count each array they must read and write once; the ghost kernels count
-    their table entries, gathers and writes per ghost (and per re-interpolated face)."""
+    their table entries, gathers and writes per ghost (and per re-interpolated face).  The
+    velocity fill gathers the centred velocity at every averaging point (2 face values per
+    axis) and, with the dynamic condition only, the centred gradient of C as well."""
     K = 2 * d + 1
     if name == "rhs_xdht":
         return cells * es * (2 + d + 1)              # C^n, C^(n-1), d face arrays in; Q out
@@ -39,7 +41,7 @@ def algorithmic_bytes(name: str, cells: int, d: int, es: int, G: int, NF: int) -
     if name == "ghost_fill_C":
         return G * (4 + 8 * K + es * (7 + 4 * K))
     if name == "ghost_fill_u":
-        per_ghost = 4 + 8 * K + es * (3 * d + 4 + 2 * K + 2 * K * 4 * d)
+        per_ghost = 4 + 8 * K + es * (3 * d + 4 + 2 * K + 2 * K * (4 if dynamic else 2) * d)
         per_face = 16 + es * 4 + 16 + es * 3
         return G * per_ghost + NF * per_face
     return 0.0
@@ -242,7 +244,7 @@ def main() -> int:
 
     kernels = {}
     for name, t in ms.items():
-        b = algorithmic_bytes(name, cells, 3, es, st.G, NF)
+        b = algorithmic_bytes(name, cells, 3, es, st.G, NF, case.params.Vs > 0)
         kernels[name] = {"ms": round(t, 5), "alg_bytes": int(b), "GB_s": round(b / (t * 1e-3) / 1e9, 1)}
     dominant = max(ms, key=ms.get)
     dom = kernels[dominant]
