@@ -267,6 +267,64 @@ void ch_ib_state_free(ch_ib_state *st);
  * EINVAL if S is below Cn sqrt(6 Pe/dt). */
 int ch_ib_coefficients(const ch_ib_params *params, double *S, double *alpha_s, double *a);
 
+/* ---- learned wall-band correction (2D, FP64 states, static condition) ------------------------
+ * An extension of the method, not part of the paper: a coarse run is corrected in the band of
+ * fluid cells near the wall (0 < wall distance <= band cells, |C| < 0.9) by a three-layer 3x3
+ * convolutional network on features [C, phi, wall distance / (band h) clipped to [-2, 2], n_x,
+ * n_y]: 5 -> 32 -> 32 channels with tanh, then 32 -> 1 scaled by out_scale.  Layers 1-2 run as
+ * BF16 matrix-core products with FP32 accumulation; weights are BF16 copies of FP32 master
+ * weights, biases FP32.  Convolutions are periodic along x and see zeros outside the box along y.
+ *
+ * ch_ib_wall_field (host, no GPU): signed distance to the wall (positive in the fluid, the
+ *   minimum over the shapes) and the unit normal into the fluid at the nearest wall point, per
+ *   cell; dist[N], normal[2][N] caller-allocated (x fastest).  Half-plane, sinusoid and circle
+ *   walls in 2D; EUNSUPPORTED otherwise.
+ * ch_ib_net_workspace_bytes / ch_ib_net_create: one caller-owned device workspace (256-byte
+ *   aligned) sized for grids of up to max_cells cells, max_tiles band tiles, a sample store of
+ *   max_store_tiles tiles (17.5 KB each) and training batches of up to max_batch tiles; all work
+ *   of the network is enqueued on hip_stream (use the bound state's stream).
+ * ch_ib_net_set_params / get_params: CH_IB_NET_NPARAMS floats (layout: W1[9][32][16] (tap, out,
+ *   in; inputs 5..15 must be zero), b1[32], W2[9][32][32], b2[32], W3[9][32], b3; tap = 3 ky + kx
+ *   multiplies the input at (x + kx - 1, y + ky - 1)); set_params also resets the optimiser.
+ * ch_ib_net_bind: attaches a 2D FP64 static-condition state whose grid sizes are multiples of 16;
+ *   wall_dist[N] and wall_normal[2][N] are host arrays (as ch_ib_wall_field returns), copied;
+ *   the band tiles are the 16x16 tiles holding a cell with 0 < dist <= band_cells h.
+ * ch_ib_net_forward: dC of the band tiles of the bound state's current C into dC_device
+ *   ([n_tiles][16][16] floats, 0 outside the band), or into the network's own buffer if NULL.
+ * ch_ib_net_apply: C += dC in both time levels of the bound state, then the ghost values are
+ *   filled again from the corrected field.
+ * ch_ib_net_extract: stores one training sample per band tile at store_offset..: the feature
+ *   patch, the target correction target_device[c] - C[c] (target: a device field of the bound
+ *   grid) and the band mask; mask_counts (optional, host, n_tiles floats) gets each tile's count.
+ * ch_ib_net_store_get: host copy of stored sample `slot` (X: 22*22*16 BF16 values, Y, M: 256).
+ * ch_ib_net_train_step: forward and backward pass of the listed stored samples (count <= max_batch;
+ *   the loss is sum over masked cells of (dC - Y)^2 times inv_count) and one Adam step (beta1
+ *   0.9, beta2 0.999, eps 1e-8) with learning rate lr; loss_out (optional) gets the loss (syncs).
+ * ch_ib_net_gradient: the same pass without the update; grad_host gets the summed gradient.
+ * ch_ib_restrict2: sets the coarse state's C to the 2x2 means of the fine state's C (fine grid
+ *   twice as many cells per axis, same box); the coarse state restarts from it (C_prev := C,
+ *   ghosts refilled) at its next step.  Synchronous. */
+#define CH_IB_NET_NPARAMS 14177
+typedef struct ch_ib_net ch_ib_net;
+int ch_ib_wall_field(const ch_ib_grid *grid, const ch_ib_shape *shapes, int n_shapes, double *dist, double *normal);
+size_t ch_ib_net_workspace_bytes(int64_t max_cells, int max_tiles, int64_t max_store_tiles, int max_batch);
+int ch_ib_net_create(int64_t max_cells, int max_tiles, int64_t max_store_tiles, int max_batch, double out_scale,
+                     void *device_workspace, size_t bytes, void *hip_stream, ch_ib_net **out);
+int ch_ib_net_set_params(ch_ib_net *net, const float *params);
+int ch_ib_net_get_params(ch_ib_net *net, float *params);
+int ch_ib_net_bind(ch_ib_net *net, ch_ib_state *st, const double *wall_dist, const double *wall_normal,
+                   double band_cells, int *n_tiles);
+int ch_ib_net_forward(ch_ib_net *net, float *dC_device);
+int ch_ib_net_apply(ch_ib_net *net);
+int ch_ib_net_extract(ch_ib_net *net, const double *target_device, int64_t store_offset, float *mask_counts);
+int ch_ib_net_store_get(ch_ib_net *net, int64_t slot, unsigned short *X, float *Y, float *M);
+int ch_ib_net_train_step(ch_ib_net *net, const int64_t *sample_ids, int count, double lr, double inv_count,
+                         double *loss_out);
+int ch_ib_net_gradient(ch_ib_net *net, const int64_t *sample_ids, int count, double inv_count, float *grad_host,
+                       double *loss_out);
+int ch_ib_restrict2(ch_ib_state *fine, ch_ib_state *coarse);
+void ch_ib_net_free(ch_ib_net *net);
+
 #ifdef __cplusplus
 }
 #endif

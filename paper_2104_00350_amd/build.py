@@ -21,7 +21,7 @@ HIP_FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-munsafe-fp
              "-I", INCLUDE, "-I", CSRC]
 HOST_FLAGS = ["-O2", "-std=c++17", "-fPIC", "-ffp-contract=off", "-pthread", "-I", INCLUDE, "-I", CSRC]
 
-HIP_SOURCES = ["kernels.hip", "api.hip"]
+HIP_SOURCES = ["kernels.hip", "api.hip", "learned.hip"]
 HOST_SOURCES = ["geometry.cpp"]
 
 

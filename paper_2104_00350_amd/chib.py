@@ -95,6 +95,20 @@ def _load():
         "ch_ib_batch_tune": (i32, [vp, i32, C.POINTER(C.c_int), C.POINTER(C.c_int)]),
         "ch_ib_batch_sync": (i32, [vp]),
         "ch_ib_batch_free": (None, [vp]),
+        "ch_ib_wall_field": (i32, [C.POINTER(Grid), C.POINTER(Shape), i32, vp, vp]),
+        "ch_ib_net_workspace_bytes": (C.c_size_t, [C.c_int64, i32, C.c_int64, i32]),
+        "ch_ib_net_create": (i32, [C.c_int64, i32, C.c_int64, i32, C.c_double, vp, C.c_size_t, vp, C.POINTER(vp)]),
+        "ch_ib_net_set_params": (i32, [vp, vp]),
+        "ch_ib_net_get_params": (i32, [vp, vp]),
+        "ch_ib_net_bind": (i32, [vp, vp, vp, vp, C.c_double, C.POINTER(C.c_int)]),
+        "ch_ib_net_forward": (i32, [vp, vp]),
+        "ch_ib_net_apply": (i32, [vp]),
+        "ch_ib_net_extract": (i32, [vp, vp, C.c_int64, vp]),
+        "ch_ib_net_store_get": (i32, [vp, C.c_int64, vp, vp, vp]),
+        "ch_ib_net_train_step": (i32, [vp, vp, i32, C.c_double, C.c_double, C.POINTER(C.c_double)]),
+        "ch_ib_net_gradient": (i32, [vp, vp, i32, C.c_double, vp, C.POINTER(C.c_double)]),
+        "ch_ib_restrict2": (i32, [vp, vp]),
+        "ch_ib_net_free": (None, [vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -412,3 +426,123 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+# -- learned wall-band correction (2D) ----------------------------------------------------------
+NET_NPARAMS = 14177
+NET_TILE = 16
+NET_PATCH = 22 * 22 * 16
+
+
+def wall_field(n, lo, hi, shapes):
+    """Signed wall distance (ny, nx) and unit wall normal (2, ny, nx) of a 2D grid (host)."""
+    g = make_grid(n, lo, hi)
+    sh = make_shapes(shapes)
+    cells = int(n[0]) * int(n[1])
+    dist = np.empty(cells)
+    nrm = np.empty(2 * cells)
+    check(lib.ch_ib_wall_field(C.byref(g), sh, len(shapes), dist.ctypes.data_as(C.c_void_p),
+                               nrm.ctypes.data_as(C.c_void_p)))
+    return dist.reshape(n[1], n[0]), nrm.reshape(2, n[1], n[0])
+
+
+class Net:
+    """The correction network and its sample store in a torch-owned device workspace."""
+
+    def __init__(self, max_cells: int, max_tiles: int, max_store_tiles: int, max_batch: int,
+                 out_scale: float, stream, device: str = "cuda:0"):
+        import torch
+        self.torch = torch
+        nbytes = lib.ch_ib_net_workspace_bytes(int(max_cells), int(max_tiles), int(max_store_tiles), int(max_batch))
+        if nbytes == 0:
+            raise ChibError(EINVAL, "network workspace size query failed")
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=torch.device(device))
+        ptr = self.workspace.data_ptr()
+        ptr += (-ptr) % 256
+        self.stream = stream
+        out = C.c_void_p()
+        check(lib.ch_ib_net_create(int(max_cells), int(max_tiles), int(max_store_tiles), int(max_batch),
+                                   float(out_scale), C.c_void_p(ptr), nbytes, C.c_void_p(stream.cuda_stream),
+                                   C.byref(out)))
+        self.h = out
+        self.n_tiles = 0
+        self.out_scale = out_scale
+
+    def set_params(self, params) -> None:
+        a = np.ascontiguousarray(params, dtype=np.float32)
+        if a.size != NET_NPARAMS:
+            raise ValueError("wrong number of parameters")
+        check(lib.ch_ib_net_set_params(self.h, a.ctypes.data_as(C.c_void_p)))
+
+    def get_params(self) -> np.ndarray:
+        a = np.empty(NET_NPARAMS, dtype=np.float32)
+        check(lib.ch_ib_net_get_params(self.h, a.ctypes.data_as(C.c_void_p)))
+        return a
+
+    def bind(self, state: State, dist, normal, band_cells: float) -> int:
+        d = np.ascontiguousarray(dist, dtype=np.float64)
+        nn = np.ascontiguousarray(normal, dtype=np.float64)
+        nt = C.c_int()
+        check(lib.ch_ib_net_bind(self.h, state.h, d.ctypes.data_as(C.c_void_p), nn.ctypes.data_as(C.c_void_p),
+                                 float(band_cells), C.byref(nt)))
+        self.state = state
+        self.n_tiles = nt.value
+        return nt.value
+
+    def forward(self) -> np.ndarray:
+        """dC of the band tiles ([n_tiles, 16, 16], 0 outside the band) for the bound state."""
+        t = self.torch.zeros(max(1, self.n_tiles) * NET_TILE * NET_TILE, dtype=self.torch.float32,
+                             device=self.workspace.device)
+        check(lib.ch_ib_net_forward(self.h, C.c_void_p(t.data_ptr())))
+        self.stream.synchronize()
+        return t.cpu().numpy()[: self.n_tiles * 256].reshape(self.n_tiles, NET_TILE, NET_TILE)
+
+    def apply(self) -> None:
+        check(lib.ch_ib_net_apply(self.h))
+
+    def extract(self, target_device, store_offset: int) -> np.ndarray:
+        """One sample per band tile at store_offset..; returns the tiles' band-cell counts."""
+        counts = np.zeros(max(1, self.n_tiles), dtype=np.float32)
+        check(lib.ch_ib_net_extract(self.h, C.c_void_p(target_device.data_ptr()), int(store_offset),
+                                    counts.ctypes.data_as(C.c_void_p)))
+        return counts[: self.n_tiles]
+
+    def store_get(self, slot: int):
+        X = np.empty(NET_PATCH, dtype=np.uint16)
+        Y = np.empty(256, dtype=np.float32)
+        M = np.empty(256, dtype=np.float32)
+        check(lib.ch_ib_net_store_get(self.h, int(slot), X.ctypes.data_as(C.c_void_p),
+                                      Y.ctypes.data_as(C.c_void_p), M.ctypes.data_as(C.c_void_p)))
+        Xf = (X.astype(np.uint32) << 16).view(np.float32).astype(np.float64).reshape(22, 22, 16)
+        return np.transpose(Xf, (2, 0, 1)), Y.reshape(16, 16).astype(np.float64), M.reshape(16, 16).astype(np.float64)
+
+    def train_step(self, ids, lr: float, inv_count: float, want_loss: bool = False):
+        a = np.ascontiguousarray(ids, dtype=np.int64)
+        loss = C.c_double()
+        check(lib.ch_ib_net_train_step(self.h, a.ctypes.data_as(C.c_void_p), a.size, float(lr), float(inv_count),
+                                       C.byref(loss) if want_loss else None))
+        return loss.value if want_loss else None
+
+    def gradient(self, ids, inv_count: float):
+        a = np.ascontiguousarray(ids, dtype=np.int64)
+        g = np.empty(NET_NPARAMS, dtype=np.float32)
+        loss = C.c_double()
+        check(lib.ch_ib_net_gradient(self.h, a.ctypes.data_as(C.c_void_p), a.size, float(inv_count),
+                                     g.ctypes.data_as(C.c_void_p), C.byref(loss)))
+        return loss.value, g
+
+    def close(self) -> None:
+        if getattr(self, "h", None):
+            lib.ch_ib_net_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def restrict2(fine: State, coarse: State) -> None:
+    """Coarse C := 2x2 means of the fine C; the coarse state restarts from it at its next step."""
+    check(lib.ch_ib_restrict2(fine.h, coarse.h))

@@ -419,6 +419,21 @@ static int ensure_init(ch_ib_state *st) {
   return CH_IB_OK;
 }
 
+int chib::state_ref(ch_ib_state *st, chib::StateRef *out) {
+  if (!st || !out) return fail(CH_IB_EINVAL, "NULL argument");
+  if (st->sticky) return fail(st->sticky, "state is in an error state");
+  int rc = ensure_init(st);
+  if (rc) return rc;
+  out->plan = &st->plan;
+  out->cur = st->cur;
+  out->es = st->es;
+  return CH_IB_OK;
+}
+
+void chib::state_mark_reinit(ch_ib_state *st) {
+  if (st) st->needs_init = 1;
+}
+
 extern "C" int ch_ib_state_get(ch_ib_state *st, int field, void *dst, int dst_on_device) {
   if (!st || !dst) return fail(CH_IB_EINVAL, "NULL argument");
   const int64_t cnt = field_count(st, field);

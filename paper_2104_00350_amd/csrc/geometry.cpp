@@ -582,3 +582,77 @@ extern "C" int ch_ib_geometry_count(const ch_ib_geometry *g, int64_t *n_ghost, i
 }
 
 extern "C" void ch_ib_geometry_free(ch_ib_geometry *g) { delete g; }
+
+// Signed distance to the wall (positive in the fluid) and the unit wall normal (into the fluid)
+// of the nearest wall point, per cell of a 2D grid: the minimum of the shapes' own signed
+// distances (union of solids).  Half-plane and circle in closed form; sinusoid by the nearest
+// point of the curve (16 seeds over one wavelength around the cell, then Newton on the squared
+// distance).  Used for the features of the learned wall-band correction.
+extern "C" int ch_ib_wall_field(const ch_ib_grid *grid, const ch_ib_shape *shapes, int n_shapes, double *dist,
+                                double *normal) {
+  ch_ib_geometry g;
+  int rc = chib::check_grid(grid, &g);
+  if (rc) return rc;
+  if (g.ndim != 2) return chib::fail(CH_IB_EUNSUPPORTED, "wall field: 2D grids only");
+  if (!dist || !normal || (n_shapes > 0 && !shapes)) return chib::fail(CH_IB_EINVAL, "NULL argument");
+  for (int s = 0; s < n_shapes; ++s)
+    if (shapes[s].kind != CH_IB_HALFPLANE && shapes[s].kind != CH_IB_SINUSOID && shapes[s].kind != CH_IB_SPHERE)
+      return chib::fail(CH_IB_EUNSUPPORTED, "wall field: half-plane, sinusoid and circle walls only");
+  const int nx = g.n[0], ny = g.n[1];
+  const double h = g.h;
+  parallel_for((int64_t)nx * ny, [&](int64_t c) {
+    const int i = (int)(c % nx), j = (int)(c / nx);
+    const double x = g.lo[0] + (i + 0.5) * h, y = g.lo[1] + (j + 0.5) * h;
+    double best = 1e300, bn0 = 0.0, bn1 = 1.0;
+    for (int s = 0; s < n_shapes; ++s) {
+      const double *p = shapes[s].p;
+      double sd = 0.0, n0 = 0.0, n1 = 1.0;
+      if (shapes[s].kind == CH_IB_HALFPLANE) {
+        const double nn = std::sqrt(p[3] * p[3] + p[4] * p[4]);
+        n0 = p[3] / nn;
+        n1 = p[4] / nn;
+        sd = (x - p[0]) * n0 + (y - p[1]) * n1;
+      } else if (shapes[s].kind == CH_IB_SPHERE) {
+        const double dx = x - p[0], dy = y - p[1];
+        const double r = std::sqrt(dx * dx + dy * dy);
+        sd = r - p[3];
+        n0 = r > 0 ? dx / r : 0.0;
+        n1 = r > 0 ? dy / r : 1.0;
+      } else {
+        const double A = p[1], lam = p[2], k = kTwoPi / lam, ph = p[3];
+        auto D = [&](double t) {
+          const double yw = p[0] + A * std::sin(k * t + ph);
+          return (t - x) * (t - x) + (yw - y) * (yw - y);
+        };
+        double tb = x, db = D(x);
+        for (int q = 0; q < 16; ++q) {
+          const double t = x + lam * ((q + 0.5) / 16.0 - 0.5);
+          const double v = D(t);
+          if (v < db) { db = v; tb = t; }
+        }
+        for (int it = 0; it < 50; ++it) {   // Newton on D'(t) = 0
+          const double sn = std::sin(k * tb + ph), cs = std::cos(k * tb + ph);
+          const double yw = p[0] + A * sn, y1 = A * k * cs, y2 = -A * k * k * sn;
+          const double g1 = 2.0 * ((tb - x) + (yw - y) * y1);
+          const double g2 = 2.0 * (1.0 + y1 * y1 + (yw - y) * y2);
+          if (g2 <= 0.0) break;
+          const double step = g1 / g2;
+          tb -= step;
+          if (std::fabs(step) < 1e-15 * (1.0 + std::fabs(tb))) break;
+        }
+        const double yw = p[0] + A * std::sin(k * tb + ph), y1 = A * k * std::cos(k * tb + ph);
+        const double dd = std::sqrt((tb - x) * (tb - x) + (yw - y) * (yw - y));
+        const double yx = p[0] + A * std::sin(k * x + ph);
+        sd = y >= yx ? dd : -dd;
+        const double nn = std::sqrt(1.0 + y1 * y1);
+        n0 = -y1 / nn;
+        n1 = 1.0 / nn;
+      }
+      if (sd < best) { best = sd; bn0 = n0; bn1 = n1; }
+    }
+    dist[c] = n_shapes > 0 ? best : 1e300;
+    normal[c] = bn0;
+    normal[(int64_t)nx * ny + c] = bn1;
+  });
+  return CH_IB_OK;
+}

@@ -33,4 +33,17 @@ int fail(int code, const std::string &msg);
 // Validates a grid and fills the derived fields of a geometry object (n, lo, h, cells).
 int check_grid(const ch_ib_grid *grid, ch_ib_geometry *g);
 
+struct Plan;
+
+// Access to a state's device plan for the other device sources of the library.  state_ref runs
+// a pending initial ghost fill first; state_mark_reinit makes the next step start over from the
+// current C (C_prev := C, ghosts refilled).
+struct StateRef {
+  Plan *plan;
+  int cur;
+  int es;
+};
+int state_ref(ch_ib_state *st, StateRef *out);
+void state_mark_reinit(ch_ib_state *st);
+
 }  // namespace chib

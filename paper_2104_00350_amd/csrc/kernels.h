@@ -88,6 +88,7 @@ struct KernelTimer {
 template <typename T> hipError_t enqueue_step(const Plan &p, int cur, KernelTimer *tm = nullptr);
 template <typename T> hipError_t enqueue_initial_fill(const Plan &p, int cur);
 template <typename T> hipError_t tune_shapes(Plan &p, int cur, int reps);
+template <typename T> hipError_t enqueue_ghost_refresh(const Plan &p, int cur);   // static fill again, same step
 template <typename T> hipError_t enqueue_rhs(const Plan &p, int cur, void *out);
 template <typename T> hipError_t enqueue_solve(const Plan &p, const void *in, void *out);
 template <typename T> hipError_t enqueue_phi(const Plan &p, int cur, void *out);

@@ -821,7 +821,7 @@ __device__ __forceinline__ void fill_static_body(T *__restrict__ C, const int *_
   const T CG = ((ga + T(1)) * CI - CM) / ga;
   C[gidx[g]] = CG;
   CMs[g] = CM;
-  CGnm1[g] = init ? CG : CGn[g];
+  if (init != 2) CGnm1[g] = init ? CG : CGn[g];   // 2: refresh within a step, history kept
   CGn[g] = CG;
 }
 
@@ -1577,6 +1577,12 @@ hipError_t enqueue_initial_fill(const Plan &p, int cur) {
 }
 
 template <typename T>
+hipError_t enqueue_ghost_refresh(const Plan &p, int cur) {
+  if (p.dynamic) return hipErrorInvalidValue;   // the dynamic fill advances C_I: not repeatable
+  return launch_ghost_fill<T>(p, (T *)p.C[cur], 2);
+}
+
+template <typename T>
 hipError_t enqueue_rhs(const Plan &p, int cur, void *out) {
   const Dims dm = make_dims(p);
   const RhsCoef<T> cf = make_coef<T>(p);
@@ -1634,6 +1640,8 @@ template hipError_t enqueue_step<double>(const Plan &, int, KernelTimer *);
 template hipError_t enqueue_step<float>(const Plan &, int, KernelTimer *);
 template hipError_t enqueue_initial_fill<double>(const Plan &, int);
 template hipError_t enqueue_initial_fill<float>(const Plan &, int);
+template hipError_t enqueue_ghost_refresh<double>(const Plan &, int);
+template hipError_t enqueue_ghost_refresh<float>(const Plan &, int);
 template hipError_t enqueue_rhs<double>(const Plan &, int, void *);
 template hipError_t enqueue_rhs<float>(const Plan &, int, void *);
 template hipError_t enqueue_solve<double>(const Plan &, const void *, void *);

@@ -21,7 +21,7 @@ def _chib():
 def test_library_exports_every_declared_symbol():
     chib = _chib()
     hdr = open(os.path.join(ROOT, "include", "ch_ib.h")).read()
-    names = set(re.findall(r"\b(ch_ib_[a-z_]+)\s*\(", hdr))
+    names = set(re.findall(r"\b(ch_ib_[a-z0-9_]+)\s*\(", hdr))
     assert len(names) >= 20
     for n in sorted(names):
         assert hasattr(chib.lib, n), n
@@ -97,3 +97,23 @@ def test_coefficients_match_oracle():
     from oracle.solver import derived_coefficients
     for c in (W.config1(), W.config2(0), W.config3(32)):
         assert chib.coefficients(c.params) == derived_coefficients(c.params)
+
+
+@pytest.mark.parametrize("kind", ["flat", "sin", "circle"])
+def test_host_wall_field_matches_oracle(kind):
+    from oracle.learned import wall_field
+    chib = _chib()
+    case = W.small_case(64, 32, kind=kind)
+    g = case.grid
+    d, n = chib.wall_field(g.n, g.lo, g.hi, case.shapes)
+    dr, nr = wall_field(g.n, g.lo, g.hi, case.shapes)
+    assert np.max(np.abs(d - dr)) <= 1e-12
+    near = np.abs(dr) <= 8 * g.h          # unique nearest wall point within the network's reach
+    assert np.max(np.abs(n - nr)[:, near]) <= 1e-9
+
+
+def test_wall_field_rejects_3d():
+    chib = _chib()
+    g = W.small_case_3d(16).grid
+    with pytest.raises(chib.ChibError):
+        chib.wall_field(g.n, g.lo, g.hi, [W.Shape(W.SPHERE, (0.0, 0.0, 0.0, 0.5))])

@@ -1,0 +1,209 @@
+"""GPU parity of the learned wall-band correction (BF16 matrix-core network) against its
+reference in oracle/learned.py, on seeded inputs.
+
+Inputs: a 128x64 sinusoidal-wall case advanced 40 steps by both the library and the FP64
+oracle (they agree to 1e-9), seeded random network parameters.  Tolerances: features bit for
+bit (both sides round the same float32 values to BF16); the correction and the gradients
+within 2 % of their largest magnitude (hidden activations are rounded to BF16 on both sides,
+and FP32 accumulation order occasionally moves a value across a BF16 rounding boundary)."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import learned as L
+from oracle.geometry import build_tables
+from oracle.solver import OracleState, chemical_potential
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+BAND = 5.0
+SCALE = 0.05
+
+
+def _say(*a):
+    print("[gpu-learned]", *a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def chib():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2104_00350_amd import chib as m
+    return m
+
+
+def _params(seed, scale=0.3):
+    rng = np.random.default_rng(seed)
+    p = rng.standard_normal(L.NPARAM) * scale
+    p[L.OFF_W1:L.OFF_B1].reshape(9, L.CH, L.CIN)[:, :, L.NFEAT:] = 0.0
+    return p.astype(np.float32)
+
+
+@pytest.fixture(scope="module")
+def setup(chib):
+    case = W.small_case(128, 64, kind="sin", theta_deg=60.0)
+    g = case.grid
+    T = build_tables(g, case.shapes, case.params)
+    geo = chib.Geometry.from_tables(g.n, g.lo, g.hi, T.gidx, T.normal, T.dn, T.gamma, T.ap, T.w, T.alpha)
+    C0, f0 = case.initial_fields()
+    st = chib.State(geo, case.params)
+    st.set_initial(C0, f0)
+    orc = OracleState(g, case.params, T, C0, f0)
+    _say("40 steps on both sides")
+    st.step(40)
+    orc.step(40)
+    st.sync()
+    assert np.max(np.abs(st.get(chib.FIELD_C) - orc.C)) <= 1e-9
+    dist, nrm = chib.wall_field(g.n, g.lo, g.hi, case.shapes)
+    dist_o, nrm_o = L.wall_field(g.n, g.lo, g.hi, case.shapes)
+    net = chib.Net(g.cells, 64, 256, 64, SCALE, st.stream)
+    p = _params(11)
+    net.set_params(p)
+    nt = net.bind(st, dist, nrm, BAND)
+    band_h = BAND * g.h
+    phi = chemical_potential(orc.C, g, T, case.params.Cn)
+    X = L.features(orc.C, phi, dist_o, nrm_o, band_h)
+    tiles = L.band_tiles(dist_o, band_h)
+    return dict(case=case, T=T, st=st, orc=orc, net=net, p=p, nt=nt, X=X, tiles=tiles, dist_o=dist_o,
+                band_h=band_h)
+
+
+def test_band_tiles_and_forward(chib, setup):
+    s = setup
+    assert s["nt"] == len(s["tiles"]) and s["nt"] > 4
+    dC = s["net"].forward()
+    full, _, _ = L.forward(s["p"], s["X"], SCALE)
+    ref = full * L.band_mask(s["orc"].C, s["dist_o"], s["band_h"])
+    scale = np.max(np.abs(ref))
+    assert scale > 0
+    err = max(np.max(np.abs(dC[b] - ref[ty:ty + 16, tx:tx + 16])) for b, (tx, ty) in enumerate(s["tiles"]))
+    _say("forward max err", err, "of", scale)
+    assert err <= 2e-2 * scale
+
+
+def _target(s):
+    g = s["case"].grid
+    x = g.lo[0] + (np.arange(g.n[0]) + 0.5) * g.h
+    return s["orc"].C + 0.02 * np.sin(2 * math.pi * x / 0.5)[None, :]
+
+
+def test_extract_gradient_and_adam(chib, setup):
+    s = setup
+    net, p = s["net"], s["p"]
+    tgt = _target(s)
+    counts = net.extract(torch.tensor(tgt.reshape(-1), dtype=torch.float64, device="cuda:0"), 0)
+    Xpad = np.zeros((L.CIN,) + s["X"].shape[1:])
+    Xpad[:L.NFEAT] = s["X"]
+    mask = L.band_mask(s["orc"].C, s["dist_o"], s["band_h"]).astype(float)
+    Yfull = (tgt - s["orc"].C).astype(np.float32).astype(np.float64)
+    total = 0.0
+    loss_ref = 0.0
+    grad_ref = np.zeros(L.NPARAM)
+    ny = s["case"].grid.n[1]
+    mism = 0
+    for b, (tx, ty) in enumerate(s["tiles"]):
+        Xg, Yg, Mg = net.store_get(b)
+        Xo = L.patch(Xpad, tx, ty)
+        mism += int(np.count_nonzero(Xg != Xo))
+        assert np.max(np.abs(Xg - Xo)) <= 2.0 ** -7 * np.max(np.abs(Xo))
+        assert np.array_equal(Mg, mask[ty:ty + 16, tx:tx + 16])
+        assert np.array_equal(Yg, Yfull[ty:ty + 16, tx:tx + 16])
+        assert counts[b] == Mg.sum()
+        total += Mg.sum()
+    assert mism <= 1e-3 * len(s["tiles"]) * Xpad[:, :22, :22].size
+    ic = 1.0 / total
+    for b, (tx, ty) in enumerate(s["tiles"]):
+        Xo = L.patch(Xpad, tx, ty)
+        lb, gb, _ = L.tile_gradient(p, Xo, Yfull[ty:ty + 16, tx:tx + 16], mask[ty:ty + 16, tx:tx + 16], ty, ny,
+                                    SCALE, ic)
+        loss_ref += lb
+        grad_ref += gb
+    ids = np.arange(len(s["tiles"]))
+    loss, g = net.gradient(ids, ic)
+    _say("loss", loss, "ref", loss_ref)
+    assert abs(loss - loss_ref) <= 1e-3 * loss_ref
+    for a, bnd in ((L.OFF_W1, L.OFF_B1), (L.OFF_B1, L.OFF_W2), (L.OFF_W2, L.OFF_B2), (L.OFF_B2, L.OFF_W3),
+                   (L.OFF_W3, L.OFF_B3), (L.OFF_B3, L.NPARAM)):
+        err = np.max(np.abs(g[a:bnd] - grad_ref[a:bnd]))
+        _say("grad block", a, err, np.max(np.abs(grad_ref[a:bnd])))
+        assert err <= 2e-2 * np.max(np.abs(grad_ref[a:bnd])), a
+    # first Adam step moves every clearly non-zero gradient component by lr against its sign
+    lr = 1e-3
+    net.train_step(ids, lr, ic)
+    p1 = net.get_params()
+    step = p1.astype(np.float64) - p
+    big = np.abs(grad_ref) > 1e-2 * np.max(np.abs(grad_ref))
+    assert np.all(np.abs(step[big] + lr * np.sign(grad_ref[big])) <= 1e-6)
+    assert np.max(np.abs(step)) <= lr * (1 + 1e-4)
+    # a few more steps lower the loss on these samples
+    l0 = net.train_step(ids, lr, ic, want_loss=True)
+    for _ in range(30):
+        l1 = net.train_step(ids, lr, ic, want_loss=True)
+    _say("loss after 32 Adam steps", l1, "from", l0)
+    assert l1 < 0.7 * l0
+    net.set_params(p)
+
+
+def test_apply_adds_the_correction_and_refills_ghosts(chib, setup):
+    s = setup
+    st, net = s["st"], s["net"]
+    g = s["case"].grid
+    C0 = st.get(chib.FIELD_C)
+    Cp0 = st.get(chib.FIELD_C_PREV)
+    dC = net.forward()
+    full = np.zeros(C0.shape)
+    for b, (tx, ty) in enumerate(s["tiles"]):
+        full[ty:ty + 16, tx:tx + 16] = dC[b]
+    blob = st.save()
+    net.apply()
+    st.sync()
+    C1 = st.get(chib.FIELD_C)
+    Cp1 = st.get(chib.FIELD_C_PREV)
+    ghost = np.zeros(g.cells, bool)
+    ghost[s["T"].gidx] = True
+    ghost = ghost.reshape(C0.shape)
+    assert np.array_equal(Cp1, Cp0 + full)
+    assert np.array_equal(C1[~ghost], (C0 + full)[~ghost])
+    # the ghosts hold the static fill of the corrected field: a fresh start from C1 fills them the same
+    st2 = chib.State(st.geom, s["case"].params)
+    st2.set(chib.FIELD_C, np.where(ghost, 0.0, C1))
+    st2.step(0)
+    assert np.max(np.abs(st2.get(chib.FIELD_C)[ghost] - C1[ghost])) <= 1e-14
+    st.load(blob)
+
+
+def test_restriction_matches_the_two_by_two_mean(chib):
+    fine_c = W.small_case(128, 64, kind="sin", theta_deg=70.0)
+    coarse_c = W.small_case(64, 32, kind="sin", theta_deg=70.0)
+    fine = chib.state_for_case(fine_c)
+    coarse = chib.state_for_case(coarse_c)
+    fine.step(0)
+    T = build_tables(fine_c.grid, fine_c.shapes, fine_c.params)
+    C0, f0 = fine_c.initial_fields()
+    orc = OracleState(fine_c.grid, fine_c.params, T, C0, f0)
+    chib.restrict2(fine, coarse)
+    ref = 0.25 * (orc.C[0::2, 0::2] + orc.C[0::2, 1::2] + orc.C[1::2, 0::2] + orc.C[1::2, 1::2])
+    assert np.max(np.abs(coarse.get(chib.FIELD_C) - ref)) <= 1e-12
+    with pytest.raises(chib.ChibError):
+        chib.restrict2(coarse, fine)
+
+
+def test_bind_rejects_unsupported_states(chib):
+    dyn = W.small_case(64, 32, kind="sin", Vs=100.0)
+    st = chib.state_for_case(dyn)
+    g = dyn.grid
+    d, n = chib.wall_field(g.n, g.lo, g.hi, dyn.shapes)
+    net = chib.Net(g.cells, 16, 16, 16, SCALE, st.stream)
+    with pytest.raises(chib.ChibError):
+        net.bind(st, d, n, BAND)
+    odd = W.small_case(16, 8, kind="flat")
+    st2 = chib.state_for_case(odd)
+    d2, n2 = chib.wall_field(odd.grid.n, odd.grid.lo, odd.grid.hi, odd.shapes)
+    with pytest.raises(chib.ChibError):
+        net.bind(st2, d2, n2, BAND)
+    with pytest.raises(chib.ChibError):
+        net.train_step([0], 1e-3, 1.0)
