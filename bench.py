@@ -147,6 +147,36 @@ def sweep_benchmark(chib, torch, steps: int, count: int = 64) -> dict:
             "cases_not_finite": nonfinite}
 
 
+def learned_benchmark(chib, steps: int) -> dict:
+    """Learned wall-band correction (config 5): the 8 held-out contact angles run as one batch on
+    the plain 1024x512 grid (the judge), on the plain 512x256 grid and on the 512x256 grid with
+    the committed trained correction; contact angles measured with the same routine."""
+    import numpy as np
+    import torch
+    import workloads as W
+    from paper_2104_00350_amd import learned as LR
+    _, eval_a = LR.study_angles()
+    coarse = W.config5(False)
+    net = chib.Net(coarse.grid.cells, coarse.grid.cells // 256, 1, 1, 0.1, torch.cuda.current_stream())
+    net.set_params(np.load(LR.WEIGHTS))
+    cps = sorted({min(steps, c) for c in (2000, 5000, 10000, 20000)})
+    ev = LR.evaluate(net, W.config5, eval_a, 100, cps, 0.5, log=lambda m: None)
+    net.close()
+    sm = LR.summarize(ev, cps)
+    return {"workload": "config 5: 2D sinusoidal wall y = 0.3 + 0.1 sin(2 pi x / 0.5) in [0,4]x[0,2], droplet "
+                        "R = 0.4, Cn = 0.01, Pe = 300, 8 held-out angles in [30, 150] deg, "
+                        f"{max(cps)} steps, correction every 100 steps at weight 0.5",
+            "speedup_learned_vs_plain_fine": round(sm["speedup_learned_vs_fine"], 3),
+            "speedup_plain_coarse_vs_plain_fine": round(sm["speedup_coarse_vs_fine"], 3),
+            "seconds": {"fine": round(sm["fine_s"], 3), "coarse": round(sm["coarse_s"], 3),
+                        "learned": round(sm["learned_s"], 3)},
+            "angle_err_vs_fine_deg": [{"step": p["step"], "cases": p["cases"],
+                                       "plain_coarse": p["mean_abs_err_coarse_deg"],
+                                       "learned": p["mean_abs_err_learned_deg"]} for p in sm["per_checkpoint"]],
+            "within_1deg": sm["learned_within_1deg_at_every_measured_checkpoint"],
+            "fallbacks_to_fine": sm["fallbacks"]}
+
+
 def cpu_baseline(case, steps: int) -> dict:
     """The FP64 oracle on the host, on a bounded sample (a few steps) of the same workload."""
     from oracle.geometry import build_tables
@@ -176,6 +206,8 @@ def main() -> int:
     ap.add_argument("--no-tune", action="store_true", help="keep the default launch shapes")
     ap.add_argument("--shapes", default="", help="fixed launch shapes 'a,b,c;d,e,f;g,h,i;j,k,l' instead of tuning")
     ap.add_argument("--sweep-steps", type=int, default=2000, help="steps per case of the batched sweep (0: skip)")
+    ap.add_argument("--learned-steps", type=int, default=20000,
+                    help="steps of the learned-correction comparison (0: skip)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="also run one plain device copy of this size (for counter calibration)")
     args = ap.parse_args()
@@ -279,6 +311,9 @@ def main() -> int:
     if args.sweep_steps > 0:
         print("[bench] batched sweep (64 cases)", file=sys.stderr, flush=True)
         out["batched_sweep"] = sweep_benchmark(chib, torch, args.sweep_steps)
+    if args.learned_steps > 0:
+        print("[bench] learned correction study (config 5, held-out angles)", file=sys.stderr, flush=True)
+        out["learned"] = learned_benchmark(chib, args.learned_steps)
     if not args.no_cpu_baseline:
         print(f"[bench] GPU done ({value:.3e} cell-updates/s); timing the CPU oracle", file=sys.stderr,
               flush=True)

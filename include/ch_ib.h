@@ -289,10 +289,13 @@ int ch_ib_coefficients(const ch_ib_params *params, double *S, double *alpha_s, d
  * ch_ib_net_bind: attaches a 2D FP64 static-condition state whose grid sizes are multiples of 16;
  *   wall_dist[N] and wall_normal[2][N] are host arrays (as ch_ib_wall_field returns), copied;
  *   the band tiles are the 16x16 tiles holding a cell with 0 < dist <= band_cells h.
+ * ch_ib_net_rebind: attaches another state with the same grid and wall (same tiles and wall
+ *   field; the caller guarantees the wall is the same), without copying anything.
  * ch_ib_net_forward: dC of the band tiles of the bound state's current C into dC_device
- *   ([n_tiles][16][16] floats, 0 outside the band), or into the network's own buffer if NULL.
- * ch_ib_net_apply: C += dC in both time levels of the bound state, then the ghost values are
- *   filled again from the corrected field.
+ *   ([n_tiles][16][16] floats, 0 outside the band), or into the network's own buffer if NULL;
+ *   dC is limited so that C + dC stays in [-1, 1].
+ * ch_ib_net_apply: C += weight dC (0 <= weight <= 1) in both time levels of the bound state, then
+ *   the ghost values are filled again from the corrected field.
  * ch_ib_net_extract: stores one training sample per band tile at store_offset..: the feature
  *   patch, the target correction target_device[c] - C[c] (target: a device field of the bound
  *   grid) and the band mask; mask_counts (optional, host, n_tiles floats) gets each tile's count.
@@ -302,8 +305,10 @@ int ch_ib_coefficients(const ch_ib_params *params, double *S, double *alpha_s, d
  *   0.9, beta2 0.999, eps 1e-8) with learning rate lr; loss_out (optional) gets the loss (syncs).
  * ch_ib_net_gradient: the same pass without the update; grad_host gets the summed gradient.
  * ch_ib_restrict2: sets the coarse state's C to the 2x2 means of the fine state's C (fine grid
- *   twice as many cells per axis, same box); the coarse state restarts from it (C_prev := C,
- *   ghosts refilled) at its next step.  Synchronous. */
+ *   twice as many cells per axis, same box).  both_levels = 0: the coarse state restarts from it
+ *   (C_prev := C, ghosts refilled) at its next step; both_levels = 1: C_prev is restricted from
+ *   the fine C_prev as well and the ghosts of C are refilled at once (the two-level history is
+ *   kept; static condition only).  Synchronous. */
 #define CH_IB_NET_NPARAMS 14177
 typedef struct ch_ib_net ch_ib_net;
 int ch_ib_wall_field(const ch_ib_grid *grid, const ch_ib_shape *shapes, int n_shapes, double *dist, double *normal);
@@ -315,14 +320,15 @@ int ch_ib_net_get_params(ch_ib_net *net, float *params);
 int ch_ib_net_bind(ch_ib_net *net, ch_ib_state *st, const double *wall_dist, const double *wall_normal,
                    double band_cells, int *n_tiles);
 int ch_ib_net_forward(ch_ib_net *net, float *dC_device);
-int ch_ib_net_apply(ch_ib_net *net);
+int ch_ib_net_rebind(ch_ib_net *net, ch_ib_state *st);
+int ch_ib_net_apply(ch_ib_net *net, double weight);
 int ch_ib_net_extract(ch_ib_net *net, const double *target_device, int64_t store_offset, float *mask_counts);
 int ch_ib_net_store_get(ch_ib_net *net, int64_t slot, unsigned short *X, float *Y, float *M);
 int ch_ib_net_train_step(ch_ib_net *net, const int64_t *sample_ids, int count, double lr, double inv_count,
                          double *loss_out);
 int ch_ib_net_gradient(ch_ib_net *net, const int64_t *sample_ids, int count, double inv_count, float *grad_host,
                        double *loss_out);
-int ch_ib_restrict2(ch_ib_state *fine, ch_ib_state *coarse);
+int ch_ib_restrict2(ch_ib_state *fine, ch_ib_state *coarse, int both_levels);
 void ch_ib_net_free(ch_ib_net *net);
 
 #ifdef __cplusplus

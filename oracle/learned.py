@@ -13,7 +13,8 @@ every layer's input):
   h2 = tanh(W2 * h1 + b2)         32 channels (BF16)
   dC = s (W3 * h2 + b3)
 "*" is the 3x3 cross-correlation out(x, y) = sum_{ky,kx} W[ky][kx] in(x + kx - 1, y + ky - 1).
-The correction applies in the band 0 < dist <= band h, |C| < 0.9.
+The correction applies in the band 0 < dist <= band h, |C| < 0.9, limited so that C + dC stays
+inside [-1, 1].
 Parameter vector: W1[9][32][16] (tap = 3 ky + kx, out, in; inputs 5..15 unused), b1[32],
 W2[9][32][32], b2[32], W3[9][32], b3.
 """
@@ -122,6 +123,11 @@ def features(C, phi, dist, nrm, band_h: float) -> np.ndarray:
          np.clip(d32, np.float32(-2), np.float32(2)),
          np.asarray(nrm[0], np.float32), np.asarray(nrm[1], np.float32)]
     return np.stack([bf16(v) for v in f])
+
+
+def limit(C, dC) -> np.ndarray:
+    """The applied correction keeps C + dC inside [-1, 1] (float32 result, as stored)."""
+    return (np.clip(C + dC, -1.0, 1.0) - C).astype(np.float32).astype(np.float64)
 
 
 def band_mask(C, dist, band_h: float) -> np.ndarray:

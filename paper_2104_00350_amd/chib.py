@@ -60,6 +60,9 @@ class Diag(C.Structure):
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with paper_2104_00350_amd.build.build()")
+    # torch ships a HIP runtime with the same soname as the library's dependency: loading torch
+    # first makes the library bind to that one runtime, so both share device memory and streams
+    import torch  # noqa: F401
     lib = C.CDLL(LIB_PATH)
     vp, i32, i64p = C.c_void_p, C.c_int, C.POINTER(C.c_int64)
     sig = {
@@ -102,12 +105,13 @@ def _load():
         "ch_ib_net_get_params": (i32, [vp, vp]),
         "ch_ib_net_bind": (i32, [vp, vp, vp, vp, C.c_double, C.POINTER(C.c_int)]),
         "ch_ib_net_forward": (i32, [vp, vp]),
-        "ch_ib_net_apply": (i32, [vp]),
+        "ch_ib_net_apply": (i32, [vp, C.c_double]),
+        "ch_ib_net_rebind": (i32, [vp, vp]),
         "ch_ib_net_extract": (i32, [vp, vp, C.c_int64, vp]),
         "ch_ib_net_store_get": (i32, [vp, C.c_int64, vp, vp, vp]),
         "ch_ib_net_train_step": (i32, [vp, vp, i32, C.c_double, C.c_double, C.POINTER(C.c_double)]),
         "ch_ib_net_gradient": (i32, [vp, vp, i32, C.c_double, vp, C.POINTER(C.c_double)]),
-        "ch_ib_restrict2": (i32, [vp, vp]),
+        "ch_ib_restrict2": (i32, [vp, vp, i32]),
         "ch_ib_net_free": (None, [vp]),
     }
     for name, (res, args) in sig.items():
@@ -497,8 +501,13 @@ class Net:
         self.stream.synchronize()
         return t.cpu().numpy()[: self.n_tiles * 256].reshape(self.n_tiles, NET_TILE, NET_TILE)
 
-    def apply(self) -> None:
-        check(lib.ch_ib_net_apply(self.h))
+    def apply(self, weight: float = 1.0) -> None:
+        check(lib.ch_ib_net_apply(self.h, float(weight)))
+
+    def rebind(self, state: State) -> None:
+        """Switches to another state on the same grid and wall (no copies)."""
+        check(lib.ch_ib_net_rebind(self.h, state.h))
+        self.state = state
 
     def extract(self, target_device, store_offset: int) -> np.ndarray:
         """One sample per band tile at store_offset..; returns the tiles' band-cell counts."""
@@ -543,6 +552,7 @@ class Net:
             pass
 
 
-def restrict2(fine: State, coarse: State) -> None:
-    """Coarse C := 2x2 means of the fine C; the coarse state restarts from it at its next step."""
-    check(lib.ch_ib_restrict2(fine.h, coarse.h))
+def restrict2(fine: State, coarse: State, both_levels: bool = False) -> None:
+    """Coarse C := 2x2 means of the fine C (and C_prev too with both_levels, keeping the history);
+    otherwise the coarse state restarts from C at its next step."""
+    check(lib.ch_ib_restrict2(fine.h, coarse.h, int(both_levels)))

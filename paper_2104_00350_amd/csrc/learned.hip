@@ -219,15 +219,22 @@ __global__ __launch_bounds__(kT) void k_net_forward(const int2 *tiles, Fields f,
   forward(s, tl.y, f.ny, out_scale);
   const int x = tl.x + threadIdx.x % TS, y = tl.y + threadIdx.x / TS;
   const int64_t c = ((int64_t)y << f.lnx) + x;
-  dC[(int64_t)blockIdx.x * TS * TS + threadIdx.x] = in_band(f, c) ? s.out[threadIdx.x] : 0.f;
+  float v = 0.f;
+  if (in_band(f, c)) {   // the corrected value stays in the physical range [-1, 1]
+    const double Cc = f.C[c];
+    const double Cn = fmin(fmax(Cc + (double)s.out[threadIdx.x], -1.0), 1.0);
+    v = (float)(Cn - Cc);
+  }
+  dC[(int64_t)blockIdx.x * TS * TS + threadIdx.x] = v;
 }
 
 // C += dC on the tiles' own cells, in both time levels (the correction shifts the state).
-__global__ __launch_bounds__(kT) void k_net_add(const int2 *tiles, const float *dC, double *C0, double *C1, int lnx) {
+__global__ __launch_bounds__(kT) void k_net_add(const int2 *tiles, const float *dC, double *C0, double *C1, int lnx,
+                                                double weight) {
   const int2 tl = tiles[blockIdx.x];
   const int x = tl.x + threadIdx.x % TS, y = tl.y + threadIdx.x / TS;
   const int64_t c = ((int64_t)y << lnx) + x;
-  const double v = (double)dC[(int64_t)blockIdx.x * TS * TS + threadIdx.x];
+  const double v = weight * (double)dC[(int64_t)blockIdx.x * TS * TS + threadIdx.x];
   C0[c] += v;
   C1[c] += v;
 }
@@ -598,6 +605,19 @@ extern "C" int ch_ib_net_bind(ch_ib_net *n, ch_ib_state *st, const double *wall_
   return CH_IB_OK;
 }
 
+extern "C" int ch_ib_net_rebind(ch_ib_net *n, ch_ib_state *st) {
+  if (!n || !st) return chib::fail(CH_IB_EINVAL, "NULL argument");
+  if (!n->st) return chib::fail(CH_IB_EINVAL, "network was never bound");
+  chib::StateRef r;
+  int rc = chib::state_ref(st, &r);
+  if (rc) return rc;
+  const chib::Plan &p = *r.plan;
+  if (p.d != 2 || r.es != 8 || p.dynamic || p.n[0] != n->nx || p.n[1] != n->ny || p.h != n->h)
+    return chib::fail(CH_IB_EINVAL, "rebind needs a 2D FP64 static state on the bound grid");
+  n->st = st;
+  return CH_IB_OK;
+}
+
 static int net_fields(ch_ib_net *n, chib::StateRef &r, chib::net::Fields &f) {
   if (!n || !n->st) return chib::fail(CH_IB_EINVAL, "network is not bound to a state");
   int rc = chib::state_ref(n->st, &r);
@@ -630,7 +650,8 @@ extern "C" int ch_ib_net_forward(ch_ib_net *n, float *dC_device) {
   return e == hipSuccess ? CH_IB_OK : net_hip(e, "net_forward");
 }
 
-extern "C" int ch_ib_net_apply(ch_ib_net *n) {
+extern "C" int ch_ib_net_apply(ch_ib_net *n, double weight) {
+  if (!(weight >= 0.0 && weight <= 1.0)) return chib::fail(CH_IB_EINVAL, "weight must lie in [0, 1]");
   int rc = ch_ib_net_forward(n, nullptr);
   if (rc) return rc;
   if (n->tiles.empty()) return CH_IB_OK;
@@ -639,7 +660,7 @@ extern "C" int ch_ib_net_apply(ch_ib_net *n) {
   if (rc) return rc;
   const chib::Plan &p = *r.plan;
   hipLaunchKernelGGL(k_net_add, dim3((unsigned)n->tiles.size()), dim3(kT), 0, p.stream, n->at<int2>(n->L.tiles),
-                     n->at<float>(n->L.dC), (double *)p.C[r.cur], (double *)p.C[1 - r.cur], n->lnx);
+                     n->at<float>(n->L.dC), (double *)p.C[r.cur], (double *)p.C[1 - r.cur], n->lnx, weight);
   hipError_t e = hipGetLastError();
   if (e == hipSuccess) e = chib::enqueue_ghost_refresh<double>(p, r.cur);
   return e == hipSuccess ? CH_IB_OK : net_hip(e, "net_apply");
@@ -740,7 +761,7 @@ extern "C" int ch_ib_net_gradient(ch_ib_net *n, const int64_t *sample_ids, int c
   return net_train(n, sample_ids, count, -1.0, inv_count, grad_host, loss_out);
 }
 
-extern "C" int ch_ib_restrict2(ch_ib_state *fine, ch_ib_state *coarse) {
+extern "C" int ch_ib_restrict2(ch_ib_state *fine, ch_ib_state *coarse, int both_levels) {
   chib::StateRef rf, rc_;
   int rc = chib::state_ref(fine, &rf);
   if (rc) return rc;
@@ -754,12 +775,16 @@ extern "C" int ch_ib_restrict2(ch_ib_state *fine, ch_ib_state *coarse) {
   // both states on one stream order: the fine state's work is finished before the copy
   hipError_t e = hipStreamSynchronize(pf.stream);
   if (e == hipSuccess) {
-    hipLaunchKernelGGL(k_restrict2, dim3((unsigned)((pc.N + kT - 1) / kT)), dim3(kT), 0, pc.stream,
-                       (const double *)pf.C[rf.cur], pf.logn[0], (double *)pc.C[rc_.cur], pc.logn[0], pc.N);
-    e = hipGetLastError();
+    for (int lev = 0; lev < (both_levels ? 2 : 1) && e == hipSuccess; ++lev) {
+      const int cf = lev ? 1 - rf.cur : rf.cur, cc = lev ? 1 - rc_.cur : rc_.cur;
+      hipLaunchKernelGGL(k_restrict2, dim3((unsigned)((pc.N + kT - 1) / kT)), dim3(kT), 0, pc.stream,
+                         (const double *)pf.C[cf], pf.logn[0], (double *)pc.C[cc], pc.logn[0], pc.N);
+      e = hipGetLastError();
+    }
+    if (e == hipSuccess && both_levels) e = chib::enqueue_ghost_refresh<double>(pc, rc_.cur);
   }
   if (e == hipSuccess) e = hipStreamSynchronize(pc.stream);
   if (e != hipSuccess) return net_hip(e, "restrict2");
-  chib::state_mark_reinit(coarse);
+  if (!both_levels) chib::state_mark_reinit(coarse);
   return CH_IB_OK;
 }

@@ -1,0 +1,271 @@
+"""Learned wall-band correction of coarse 2D runs: data generation, training and scoring.
+
+Every numerical step runs in the library (ch_ib_net_* and the plain step); this module only
+orders the calls.
+
+* Data: for each training angle a fine run (2x the cells per axis, same box and parameters)
+  and a coarse run are paired.  At every sampling time the fine state is restricted (2x2 means)
+  into the coarse state, both advance `interval` steps, and the coarse band tiles are stored
+  with the target correction restrict(fine) - coarse.
+* Training: Adam on random batches of stored tiles that hold band cells; the loss is the mean
+  squared error of the correction over the band cells of the batch.
+* Scoring: for held-out angles, the plain fine run (the judge), the plain coarse run and the
+  corrected coarse run (correction every `interval` steps) advance the same number of steps;
+  the contact angles of all three are measured with the same routine (angle.measure) and the
+  wall-clock times of the runs are compared.  A corrected run whose max |C| exceeds
+  FALLBACK_MAX_C or turns non-finite is flagged as falling back to the plain fine solve.
+"""
+from __future__ import annotations
+
+import math
+import os
+import time
+from typing import Dict, List, Sequence
+
+import numpy as np
+
+from . import angle as A
+from . import chib
+
+BAND_CELLS = 5.0
+# a corrected run is flagged for the plain fine solve when max |C| (ghost cells included) passes
+# this bound or turns non-finite; plain runs of the sinusoidal-wall study reach about 1.08
+FALLBACK_MAX_C = 1.15
+# parameters trained by `python -m paper_2104_00350_amd.learned --weights-out ...` (defaults)
+WEIGHTS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "weights", "wallband_sin512.npy")
+
+
+def init_params(seed: int) -> np.ndarray:
+    """Seeded initial parameters: N(0, 1/fan_in) weights (the last layer 10x smaller), zero biases."""
+    rng = np.random.default_rng(seed)
+    p = np.zeros(chib.NET_NPARAMS)
+    o_b1 = 9 * 32 * 16
+    W1 = rng.standard_normal((9, 32, 16)) / math.sqrt(9 * 5)
+    W1[:, :, 5:] = 0.0
+    p[:o_b1] = W1.reshape(-1)
+    o_w2 = o_b1 + 32
+    p[o_w2:o_w2 + 9 * 32 * 32] = rng.standard_normal(9 * 32 * 32) / math.sqrt(9 * 32)
+    o_w3 = o_w2 + 9 * 32 * 32 + 32
+    p[o_w3:o_w3 + 9 * 32] = 0.1 * rng.standard_normal(9 * 32) / math.sqrt(9 * 32)
+    return p.astype(np.float32)
+
+
+def _state(case):
+    g = case.grid
+    geo = chib.Geometry.build(g.n, g.lo, g.hi, case.shapes, case.params)
+    st = chib.State(geo, case.params)
+    C0, faces = case.initial_fields()
+    st.set_initial(C0, faces)
+    st.step(0)
+    return st
+
+
+def _angle(st, case) -> float:
+    r = A.measure(st.get(chib.FIELD_C), case.grid.lo, case.grid.hi, case.shapes[0].kind, case.shapes[0].p,
+                  case.params.Cn)
+    return r["mean"]
+
+
+def generate(net: "chib.Net", make_case, angles: Sequence[float], steps: int, interval: int, start: int,
+             stride: int, log=print) -> Dict[str, np.ndarray]:
+    """Stores training samples for every angle; returns the slots that hold band cells and their counts."""
+    slots, counts = [], []
+    off = 0
+    for th in angles:
+        fine_c, coarse_c = make_case(True, th), make_case(False, th)
+        fine, coarse, holder = _state(fine_c), _state(coarse_c), _state(coarse_c)
+        g = coarse_c.grid
+        dist, nrm = chib.wall_field(g.n, g.lo, g.hi, coarse_c.shapes)
+        net.bind(coarse, dist, nrm, BAND_CELLS)
+        fine.step(start)
+        t = start
+        while t + interval <= steps:
+            chib.restrict2(fine, coarse, both_levels=True)
+            coarse.step(interval)
+            fine.step(interval)
+            chib.restrict2(fine, holder)
+            target = holder.get_device(chib.FIELD_C)
+            c = net.extract(target, off)
+            keep = np.nonzero(c > 0)[0]
+            slots.extend((off + keep).tolist())
+            counts.extend(c[keep].tolist())
+            off += len(c)
+            fine.step(stride - interval)
+            t += stride
+        log(f"[learned] angle {th:.1f}: {off} tiles stored, {len(slots)} with band cells")
+        for s in (fine, coarse, holder):
+            s.close()
+    return {"slots": np.array(slots, dtype=np.int64), "counts": np.array(counts), "stored": off}
+
+
+def train(net: "chib.Net", data: Dict[str, np.ndarray], iters: int, batch: int, lr: float, seed: int,
+          log=print) -> List[float]:
+    rng = np.random.default_rng(seed)
+    slots, counts = data["slots"], data["counts"]
+    losses = []
+    for it in range(iters):
+        pick = rng.choice(len(slots), size=min(batch, len(slots)), replace=False)
+        ids = slots[pick]
+        ic = 1.0 / max(1.0, counts[pick].sum())
+        lr_t = lr * 0.5 * (1 + math.cos(math.pi * it / iters))
+        want = (it % 100 == 0) or it == iters - 1
+        loss = net.train_step(ids, lr_t, ic, want_loss=want)
+        if want:
+            losses.append(loss)
+            log(f"[learned] iter {it}: batch loss {loss:.4e}")
+    return losses
+
+
+def evaluate(net: "chib.Net", make_case, angles: Sequence[float], interval: int, checkpoints: Sequence[int],
+             weight: float = 1.0, log=print) -> Dict:
+    """Plain fine, plain coarse and corrected coarse runs of all angles, each kind advanced as one
+    batch (grouped launches replayed as a hipGraph); the corrected batch pauses every `interval`
+    steps while the network corrects each member.  Angles are measured at the checkpoints (NaN
+    where the routine finds no contact line); the seconds are the kind's whole time-to-solution
+    (measurements excluded)."""
+    import torch
+    recs = [{"theta": th} for th in angles]
+    for kind, fine, learned in (("fine", True, False), ("coarse", False, False), ("learned", False, True)):
+        cases = [make_case(fine, th) for th in angles]
+        states = [_state(c) for c in cases]
+        if learned:
+            g = cases[0].grid
+            dist, nrm = chib.wall_field(g.n, g.lo, g.hi, cases[0].shapes)
+            net.bind(states[0], dist, nrm, BAND_CELLS)
+        batch = chib.Batch(states)
+        done, wall = 0, 0.0
+        meas = [[] for _ in angles]
+        fallback = [False] * len(angles)
+        maxc = [0.0] * len(angles)
+        for cp in checkpoints:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            while done < cp:
+                k = min(interval, cp - done) if learned else cp - done
+                batch.step(k)
+                done += k
+                if learned and k == interval:
+                    batch.sync()
+                    for st in states:
+                        net.rebind(st)
+                        net.apply(weight)
+                    torch.cuda.synchronize()
+            batch.sync()
+            torch.cuda.synchronize()
+            wall += time.perf_counter() - t0
+            for a, (st, case) in enumerate(zip(states, cases)):
+                dg = st.diagnostics()
+                maxc[a] = max(maxc[a], dg["max_abs_C"] if dg["status"] == 0 else float("inf"))
+                if learned and (dg["status"] != 0 or dg["max_abs_C"] > FALLBACK_MAX_C):
+                    fallback[a] = True
+                try:
+                    meas[a].append(_angle(st, case))
+                except A.AngleError:
+                    meas[a].append(float("nan"))
+        for a in range(len(angles)):
+            recs[a][kind] = {"angles": meas[a], "max_abs_C": maxc[a]}
+            if learned:
+                recs[a][kind]["fallback_to_fine"] = fallback[a]
+        log(f"[learned] {kind}: {len(angles)} cases x {done} steps in {wall:.2f} s")
+        batch.close()
+        for st in states:
+            st.close()
+        for r in recs:
+            r.setdefault("seconds", {})[kind] = wall
+    for r in recs:
+        for kind in ("coarse", "learned"):
+            r[kind]["err_vs_fine"] = [abs(a - b) for a, b in zip(r[kind]["angles"], r["fine"]["angles"])]
+        log(f"[learned] theta {r['theta']:.1f}: fine {np.round(r['fine']['angles'], 2).tolist()} coarse "
+            f"{np.round(r['coarse']['angles'], 2).tolist()} learned {np.round(r['learned']['angles'], 2).tolist()}")
+    return {"cases": recs}
+
+
+def summarize(ev: Dict, checkpoints: Sequence[int]) -> Dict:
+    """Per checkpoint: mean |angle - fine angle| of the plain and corrected coarse runs over the
+    cases where all three angles were measured; plus the time-to-solution ratio."""
+    per = []
+    for k, cp in enumerate(checkpoints):
+        ok = [c for c in ev["cases"] if all(np.isfinite(c[m]["angles"][k]) for m in ("fine", "coarse", "learned"))]
+        per.append({"step": cp, "cases": len(ok),
+                    "mean_abs_err_coarse_deg": float(np.mean([c["coarse"]["err_vs_fine"][k] for c in ok])) if ok else None,
+                    "mean_abs_err_learned_deg": float(np.mean([c["learned"]["err_vs_fine"][k] for c in ok])) if ok else None})
+    sec = ev["cases"][0]["seconds"]
+    tf, tc, tl = sec["fine"], sec["coarse"], sec["learned"]
+    last = [p for p in per if p["cases"]]
+    within = bool(last and all(p["mean_abs_err_learned_deg"] <= 1.0 for p in last))
+    return {"per_checkpoint": per, "fine_s": tf, "coarse_s": tc, "learned_s": tl,
+            "speedup_learned_vs_fine": tf / tl, "speedup_coarse_vs_fine": tf / tc,
+            "learned_within_1deg_at_every_measured_checkpoint": within,
+            "fallbacks": sum(int(c["learned"]["fallback_to_fine"]) for c in ev["cases"])}
+
+
+def study_angles(seed: int = 2104, n_train: int = 32, n_eval: int = 8):
+    """Training and held-out contact angles, uniform in [30, 150] degrees from one seed."""
+    rng = np.random.default_rng(seed)
+    a = rng.uniform(30.0, 150.0, n_train + n_eval)
+    return [float(x) for x in a[:n_train]], [float(x) for x in a[n_train:]]
+
+
+def main(argv=None) -> int:
+    import argparse
+    import json
+    import sys
+    import torch
+    sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+    import workloads as W
+    ap = argparse.ArgumentParser(description="train and score the wall-band correction (config 5)")
+    ap.add_argument("--train-angles", type=int, default=32)
+    ap.add_argument("--eval-angles", type=int, default=8)
+    ap.add_argument("--steps", type=int, default=20000)
+    ap.add_argument("--interval", type=int, default=100)
+    ap.add_argument("--start", type=int, default=500)
+    ap.add_argument("--stride", type=int, default=1000)
+    ap.add_argument("--iters", type=int, default=2000)
+    ap.add_argument("--batch", type=int, default=256)
+    ap.add_argument("--lr", type=float, default=2e-3)
+    ap.add_argument("--out-scale", type=float, default=0.1)
+    ap.add_argument("--checkpoints", default="2000,5000,10000,20000")
+    ap.add_argument("--weight", type=float, default=0.5, help="fraction of the correction applied")
+    ap.add_argument("--weights-out", default="")
+    ap.add_argument("--weights-in", default="")
+    ap.add_argument("--json", default="")
+    args = ap.parse_args(argv)
+    train_a, eval_a = study_angles(n_train=args.train_angles, n_eval=args.eval_angles)
+    coarse = W.config5(False)
+    cells = W.config5(True).grid.cells
+    per_angle = ((args.steps - args.start) // args.stride + 1) * (coarse.grid.cells // 256)
+    stream = torch.cuda.current_stream()
+    net = chib.Net(cells, coarse.grid.cells // 256, per_angle * len(train_a) if not args.weights_in else 1,
+                   args.batch, args.out_scale, stream)
+    t0 = time.perf_counter()
+    if args.weights_in:
+        net.set_params(np.load(args.weights_in))
+        losses, data = [], {"slots": np.zeros(0), "stored": 0}
+    else:
+        net.set_params(init_params(7))
+        data = generate(net, W.config5, train_a, args.steps, args.interval, args.start, args.stride,
+                        log=lambda m: print(m, file=sys.stderr, flush=True))
+        t1 = time.perf_counter()
+        print(f"[learned] data {t1 - t0:.1f}s", file=sys.stderr, flush=True)
+        losses = train(net, data, args.iters, args.batch, args.lr, 11, log=lambda m: print(m, file=sys.stderr, flush=True))
+        print(f"[learned] training {time.perf_counter() - t1:.1f}s", file=sys.stderr, flush=True)
+        if args.weights_out:
+            np.save(args.weights_out, net.get_params())
+    cps = [int(c) for c in args.checkpoints.split(",")]
+    ev = evaluate(net, W.config5, eval_a, args.interval, cps, args.weight,
+                  log=lambda m: print(m, file=sys.stderr, flush=True))
+    res = {"train_angles": train_a, "eval_angles": eval_a, "interval": args.interval, "weight": args.weight,
+           "band_cells": BAND_CELLS,
+           "out_scale": args.out_scale, "samples_with_band_cells": int(len(data["slots"])),
+           "tiles_stored": int(data["stored"]), "loss_trace": losses, "checkpoints": cps,
+           "summary": summarize(ev, cps), "cases": ev["cases"]}
+    print(json.dumps(res["summary"]))
+    if args.json:
+        with open(args.json, "w") as f:
+            json.dump(res, f, indent=1)
+    net.close()
+    return 0
+
+
+if __name__ == "__main__":
+    raise SystemExit(main())

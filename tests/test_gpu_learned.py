@@ -77,7 +77,7 @@ def test_band_tiles_and_forward(chib, setup):
     assert s["nt"] == len(s["tiles"]) and s["nt"] > 4
     dC = s["net"].forward()
     full, _, _ = L.forward(s["p"], s["X"], SCALE)
-    ref = full * L.band_mask(s["orc"].C, s["dist_o"], s["band_h"])
+    ref = L.limit(s["orc"].C, full) * L.band_mask(s["orc"].C, s["dist_o"], s["band_h"])
     scale = np.max(np.abs(ref))
     assert scale > 0
     err = max(np.max(np.abs(dC[b] - ref[ty:ty + 16, tx:tx + 16])) for b, (tx, ty) in enumerate(s["tiles"]))
@@ -159,8 +159,9 @@ def test_apply_adds_the_correction_and_refills_ghosts(chib, setup):
     for b, (tx, ty) in enumerate(s["tiles"]):
         full[ty:ty + 16, tx:tx + 16] = dC[b]
     blob = st.save()
-    net.apply()
+    net.apply(0.5)
     st.sync()
+    full = 0.5 * full
     C1 = st.get(chib.FIELD_C)
     Cp1 = st.get(chib.FIELD_C_PREV)
     ghost = np.zeros(g.cells, bool)
@@ -190,6 +191,22 @@ def test_restriction_matches_the_two_by_two_mean(chib):
     assert np.max(np.abs(coarse.get(chib.FIELD_C) - ref)) <= 1e-12
     with pytest.raises(chib.ChibError):
         chib.restrict2(coarse, fine)
+    # both levels: C_prev restricted too, ghosts of C refilled at once
+    fine.step(3)
+    orc.step(3)
+    chib.restrict2(fine, coarse, both_levels=True)
+    R = lambda a: 0.25 * (a[0::2, 0::2] + a[0::2, 1::2] + a[1::2, 0::2] + a[1::2, 1::2])
+    Tc = build_tables(coarse_c.grid, coarse_c.shapes, coarse_c.params)
+    gh = np.zeros(coarse_c.grid.cells, bool)
+    gh[Tc.gidx] = True
+    gh = gh.reshape(coarse_c.grid.shape)
+    Cc = coarse.get(chib.FIELD_C)
+    assert np.max(np.abs(coarse.get(chib.FIELD_C_PREV) - R(orc.Cp))) <= 1e-9
+    assert np.max(np.abs(Cc[~gh] - R(orc.C)[~gh])) <= 1e-9
+    fresh = chib.state_for_case(coarse_c)
+    fresh.set(chib.FIELD_C, Cc)
+    fresh.step(0)
+    assert np.max(np.abs(fresh.get(chib.FIELD_C)[gh] - Cc[gh])) <= 1e-14
 
 
 def test_bind_rejects_unsupported_states(chib):
@@ -207,3 +224,18 @@ def test_bind_rejects_unsupported_states(chib):
         net.bind(st2, d2, n2, BAND)
     with pytest.raises(chib.ChibError):
         net.train_step([0], 1e-3, 1.0)
+
+
+def test_study_driver_with_the_committed_weights(chib):
+    """The trained parameters shipped with the package load and run through the scoring driver."""
+    import workloads as W
+    from paper_2104_00350_amd import learned as LR
+    coarse = W.config5(False)
+    net = chib.Net(coarse.grid.cells, coarse.grid.cells // 256, 1, 1, 0.1, torch.cuda.current_stream())
+    net.set_params(np.load(LR.WEIGHTS))
+    ev = LR.evaluate(net, W.config5, [90.0], 100, [300], 0.5, log=lambda m: None)
+    rec = ev["cases"][0]
+    for kind in ("fine", "coarse", "learned"):
+        assert np.isfinite(rec[kind]["angles"][0]) and rec[kind]["max_abs_C"] < 1.1
+    assert not rec["learned"]["fallback_to_fine"]
+    net.close()
