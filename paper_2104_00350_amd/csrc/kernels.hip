@@ -198,9 +198,17 @@ __device__ __forceinline__ void twiddle_powers(T w1r, T w1i, T *wr, T *wi) {
 
 // One Stockham stage of radix R over `np` sequences of length N in LDS.  p = 2^lp is the
 // product of the radices of the previous stages.  Inputs are staged in registers.
-template <typename T, int R, int IT, bool INV>
+template <typename T> struct Pair2;
+template <> struct Pair2<double> { using type = double2; };
+template <> struct Pair2<float> { using type = float2; };
+
+// PAIRED: the imaginary part sits right after the real part (io == 1), and both move as one
+// 2-element LDS access; with the sequence index fastest across lanes (bfast) the lanes served
+// together then touch distinct bank groups, where two separate accesses would collide.
+template <typename T, int R, int IT, bool INV, bool PAIRED = false>
 __device__ __forceinline__ void fft_stage(T *__restrict__ s, int logN, int lognp, int ps, int ns, int io, int padw,
                                           bool bfast, int lp, const T *__restrict__ twr, const T *__restrict__ twi) {
+  using P2 = typename Pair2<T>::type;
   constexpr int LR = ilog2c(R);
   const int nt = blockDim.x;
   const int tid = threadIdx.x;
@@ -225,8 +233,14 @@ __device__ __forceinline__ void fft_stage(T *__restrict__ s, int logN, int lognp
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         const int a = lds_at(b, i + (r << lq), ps, ns, padw);
-        xr[it][r] = s[a];
-        xi[it][r] = s[a + io];
+        if constexpr (PAIRED) {
+          const P2 v = *reinterpret_cast<const P2 *>(s + a);
+          xr[it][r] = v.x;
+          xi[it][r] = v.y;
+        } else {
+          xr[it][r] = s[a];
+          xi[it][r] = s[a + io];
+        }
       }
     }
   }
@@ -260,8 +274,15 @@ __device__ __forceinline__ void fft_stage(T *__restrict__ s, int logN, int lognp
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         const int a = lds_at(b, j + r * p, ps, ns, padw);
-        s[a] = xr[it][r];
-        s[a + io] = xi[it][r];
+        if constexpr (PAIRED) {
+          P2 v;
+          v.x = xr[it][r];
+          v.y = xi[it][r];
+          *reinterpret_cast<P2 *>(s + a) = v;
+        } else {
+          s[a] = xr[it][r];
+          s[a + io] = xi[it][r];
+        }
       }
     }
   }
@@ -272,7 +293,7 @@ __device__ __forceinline__ void fft_stage(T *__restrict__ s, int logN, int lognp
 // Stockham autosort with register-resident radix-16 butterflies (then 8, 4 or 2 for the
 // remaining factor).  E bounds the tile (elements of T) so that every thread holds at most
 // 16 complex values per stage.  No 1/N scaling.
-template <typename T, int E, bool INV, int MAXR = 16, int NT = 256>
+template <typename T, int E, bool INV, int MAXR = 16, int NT = 256, bool PAIRED = false>
 __device__ __forceinline__ void lds_fft(T *__restrict__ s, int logN, int lognp, int ps, int ns, int io, int padw,
                                         bool bfast, const T *__restrict__ twr, const T *__restrict__ twi) {
   constexpr int IT16 = (E / 2 / 16 + NT - 1) / NT;
@@ -283,20 +304,20 @@ __device__ __forceinline__ void lds_fft(T *__restrict__ s, int logN, int lognp, 
   int rem = logN;
   if constexpr (MAXR >= 16) {
     while (rem >= 4) {
-      fft_stage<T, 16, IT16, INV>(s, logN, lognp, ps, ns, io, padw, bfast, lp, twr, twi);
+      fft_stage<T, 16, IT16, INV, PAIRED>(s, logN, lognp, ps, ns, io, padw, bfast, lp, twr, twi);
       lp += 4;
       rem -= 4;
     }
   } else {
     while (rem >= 3) {
-      fft_stage<T, 8, IT8, INV>(s, logN, lognp, ps, ns, io, padw, bfast, lp, twr, twi);
+      fft_stage<T, 8, IT8, INV, PAIRED>(s, logN, lognp, ps, ns, io, padw, bfast, lp, twr, twi);
       lp += 3;
       rem -= 3;
     }
   }
-  if (rem == 3) fft_stage<T, 8, IT8, INV>(s, logN, lognp, ps, ns, io, padw, bfast, lp, twr, twi);
-  else if (rem == 2) fft_stage<T, 4, IT4, INV>(s, logN, lognp, ps, ns, io, padw, bfast, lp, twr, twi);
-  else if (rem == 1) fft_stage<T, 2, IT2, INV>(s, logN, lognp, ps, ns, io, padw, bfast, lp, twr, twi);
+  if (rem == 3) fft_stage<T, 8, IT8, INV, PAIRED>(s, logN, lognp, ps, ns, io, padw, bfast, lp, twr, twi);
+  else if (rem == 2) fft_stage<T, 4, IT4, INV, PAIRED>(s, logN, lognp, ps, ns, io, padw, bfast, lp, twr, twi);
+  else if (rem == 1) fft_stage<T, 2, IT2, INV, PAIRED>(s, logN, lognp, ps, ns, io, padw, bfast, lp, twr, twi);
 }
 
 // Padded LDS pitch of a contiguous line of n elements (one pad element per 16).
@@ -618,15 +639,16 @@ __global__ __launch_bounds__(kThreads) void k_strided_dht(T *__restrict__ W, int
     s[n * B + (n >> 4) * 2 + col] = W[base + n * stride + col];
   }
   __syncthreads();
-  lds_fft<T, E, false, MAXR>(s, logN, logB - 1, 2, B, 1, 2, true, twr, twi);
+  lds_fft<T, E, false, MAXR, 256, true>(s, logN, logB - 1, 2, B, 1, 2, true, twr, twi);
   const int lp = logB - 1;
   const int half = tot >> 1;
   for (int e = threadIdx.x; e < half; e += blockDim.x) {
     const int b = e & ((1 << lp) - 1), n = e >> lp;
     const int nn = (N - n) & (N - 1);
     const int a0 = n * B + (n >> 4) * 2 + 2 * b, a1 = nn * B + (nn >> 4) * 2 + 2 * b;
-    const T p = s[a0], q = s[a0 + 1];
-    const T r = s[a1], sv = s[a1 + 1];
+    const V2 u0 = *reinterpret_cast<const V2 *>(s + a0), u1 = *reinterpret_cast<const V2 *>(s + a1);
+    const T p = u0.x, q = u0.y;
+    const T r = u1.x, sv = u1.y;
     V2 v;
     v.x = (p - q + r + sv) * T(0.5);
     v.y = (p + q - r + sv) * T(0.5);
@@ -657,7 +679,7 @@ __device__ __forceinline__ void neumann_body(unsigned char *smem_raw, T *__restr
     s[pos * B + (pos >> 4) * 2 + col] = W[base + n * stride + col];
   }
   __syncthreads();
-  lds_fft<T, E, false, MAXR>(s, logN, logB - 1, 2, B, 1, 2, true, twr, twi);
+  lds_fft<T, E, false, MAXR, 256, true>(s, logN, logB - 1, 2, B, 1, 2, true, twr, twi);
   const int half = N >> 1;
   const int npairs = B >> 1;
   const int items = npairs * (half + 1);
@@ -666,9 +688,11 @@ __device__ __forceinline__ void neumann_body(unsigned char *smem_raw, T *__restr
     const int b = e % npairs;
     const int k = e / npairs;
     const int kk = (N - k) & (N - 1);
+    using V2 = typename Pair2<T>::type;
     T *zk = s + k * B + (k >> 4) * 2 + 2 * b;
     T *zn = s + kk * B + (kk >> 4) * 2 + 2 * b;
-    const T p = zk[0], q = zk[1], r = zn[0], sv = zn[1];
+    const V2 uk = *reinterpret_cast<const V2 *>(zk), un = *reinterpret_cast<const V2 *>(zn);
+    const T p = uk.x, q = uk.y, r = un.x, sv = un.y;
     const T var = (p + r) * T(0.5), vai = (q - sv) * T(0.5);
     const T vbr = (q + sv) * T(0.5), vbi = (r - p) * T(0.5);
     const T c = dctc[k], sn = dcts[k];
@@ -691,15 +715,19 @@ __device__ __forceinline__ void neumann_body(unsigned char *smem_raw, T *__restr
     // back to the reordered-sequence spectrum: V'[k] = e^{i pi k/2N} (X[k] - i X[N-k]) / 2
     const T a1 = (c * xa1 + sn * xa2) * T(0.5), a2 = (sn * xa1 - c * xa2) * T(0.5);
     const T b1 = (c * xb1 + sn * xb2) * T(0.5), b2 = (sn * xb1 - c * xb2) * T(0.5);
-    zk[0] = a1 - b2;
-    zk[1] = a2 + b1;
+    V2 ok;
+    ok.x = a1 - b2;
+    ok.y = a2 + b1;
+    *reinterpret_cast<V2 *>(zk) = ok;
     if (k != 0 && k != half) {
-      zn[0] = a1 + b2;
-      zn[1] = b1 - a2;
+      V2 on;
+      on.x = a1 + b2;
+      on.y = b1 - a2;
+      *reinterpret_cast<V2 *>(zn) = on;
     }
   }
   __syncthreads();
-  lds_fft<T, E, true, MAXR>(s, logN, logB - 1, 2, B, 1, 2, true, twr, twi);
+  lds_fft<T, E, true, MAXR, 256, true>(s, logN, logB - 1, 2, B, 1, 2, true, twr, twi);
   for (int e = threadIdx.x; e < tot; e += blockDim.x) {
     const int n = e >> logB, col = e & (B - 1);
     const int pos = (n & 1) ? (N - 1 - (n >> 1)) : (n >> 1);
