@@ -34,9 +34,9 @@ def algorithmic_bytes(name: str, cells: int, d: int, es: int, G: int, NF: int, d
     velocity fill gathers the centred velocity at every averaging point (2 face values per
     axis) and, with the dynamic condition only, the centred gradient of C as well."""
     K = 2 * d + 1
-    if name == "rhs_xdht":
-        return cells * es * (2 + d + 1)              # C^n, C^(n-1), d face arrays in; Q out
-    if name in ("ydht_fwd", "ydht_inv", "neumann_solve", "xdht_out"):
+    if name in ("rhs_xdht", "rhs_stencil"):
+        return cells * es * (2 + d + 1)              # C^n, C^(n-1), d face arrays in; Q (or its transform) out
+    if name in ("xdht_fwd", "ydht_fwd", "ydht_inv", "neumann_solve", "xdht_out"):
         return cells * es * 2                        # one read, one write
     if name == "ghost_fill_C":
         return G * (4 + 8 * K + es * (7 + 4 * K))
@@ -54,8 +54,13 @@ def kernel_template(name: str, shapes, es: int, nx: int) -> list:
     if name == "rhs_xdht":
         lt, r, u = shapes[0]
         if u >= 3 and nx in (256, 512):
-            return [f"k_rhs_xdht_zm<{t}, {2 ** min(max(lt, 1), 3)}, {nx // 256}, {r}>"]
+            return [f"k_rhs_xdht_zm<{t}, {2 ** min(max(lt, 1), 3)}, {nx // 256}, {r}, false>"]
         return [f"k_rhs_xdht<{t}, 3, {E}, {u}, {r}>"]
+    if name == "rhs_stencil":
+        lt = shapes[0][0]
+        return [f"k_rhs_xdht_zm<{t}, {2 ** min(max(lt, 1), 3)}, {nx // 256}, 8, true>"]
+    if name == "xdht_fwd":
+        return [f"k_xdht<{t}, {E}, {shapes[3][1]}>"]
     if name in ("ydht_fwd", "ydht_inv"):
         return [f"k_strided_dht<{t}, {E}, {shapes[1][1]}>"]
     if name == "neumann_solve":

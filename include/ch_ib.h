@@ -211,9 +211,12 @@ int ch_ib_step_timed(ch_ib_state *st, int n_steps, int max_kernels, double *ms_o
  * 2 bounded-axis solve, 3 x transform out) each have a launch shape of three ints:
  * {log2 lines or columns per tile, largest FFT radix (8 or 16), third field}.  The third field is
  * 1 for passes 1-3; for pass 0 it is the cells in flight per thread (1 or 2) of the line-tiled
- * kernel, or 3..5 to select the z-marching kernel (3D grids with nx = 256 or 512 only) with
- * 2^value planes per workgroup.  Shapes change speed, never results: every shape computes the same
- * sums in the same order per element except for the FFT radix, which changes rounding only.
+ * kernel, 3..5 to select the z-marching kernel (3D grids with nx = 256 or 512 only) with
+ * 2^value planes per workgroup, or 6..8 to split that kernel in two: a stencil-only z-march over
+ * 2^(value-3) planes writing the right-hand side, then the x transform in place with pass 3's
+ * shape (16 more bytes per cell, no FFT inside the stencil loop).  Shapes change speed, never
+ * results: every shape computes the same sums in the same order per element except for the FFT
+ * radix, which changes rounding only.
  * ch_ib_tune: times every candidate shape of each pass reps times with HIP events on the state's
  *   buffers (the fields are left unchanged), keeps the fastest and writes the 12 chosen ints to
  *   shapes_out (may be NULL).  Synchronous.

@@ -452,7 +452,7 @@ __global__ __launch_bounds__(kThreads) void k_rhs_xdht(const T *__restrict__ Cn,
 // keeps C~ of planes z-1, z, z+1 in registers, so y and z neighbours never leave the thread;
 // x neighbours come from one LDS plane buffer.  Each plane's L rows of Q go through the same
 // Hartley transform as K1 and are stored to W.  Requires nx a multiple of 256.
-template <typename T, int L, int XM, int R>
+template <typename T, int L, int XM, int R, bool SPLIT = false>
 __global__ __launch_bounds__(kThreads) void k_rhs_xdht_zm(const T *__restrict__ Cn, const T *__restrict__ Cp,
                                                           const T *__restrict__ F0, const T *__restrict__ F1,
                                                           const T *__restrict__ F2, T *__restrict__ W, Dims dm,
@@ -538,8 +538,12 @@ __global__ __launch_bounds__(kThreads) void k_rhs_xdht_zm(const T *__restrict__ 
         const T A = flux * T(0.5) * cf.inv_h;
         const T lap = (gsum - T(6) * gf(v0)) * cf.inv_h2;
         q[m][r] = cf.pe_cn2 * (h0[m][r] * cf.inv_dt - A) + lap;
+        if constexpr (SPLIT) W[c] = q[m][r];
       }
     }
+    if constexpr (SPLIT) {
+      __syncthreads();   // every x-neighbour read of this plane is done before the next write
+    } else {
 #pragma unroll
     for (int m = 0; m < XM; ++m)
 #pragma unroll
@@ -561,6 +565,7 @@ __global__ __launch_bounds__(kThreads) void k_rhs_xdht_zm(const T *__restrict__ 
       T *o = W + (line0 + 2 * b) * nx + kx;
       o[0] = (p - qq + rr + sv) * T(0.5);
       o[nx] = (p + qq - rr + sv) * T(0.5);
+    }
     }
     // rotate planes (the FFT's final barrier protects the plane buffer for the next write)
 #pragma unroll
@@ -1352,15 +1357,23 @@ void launch_rhs_variant(const Plan &p, const T *Cn, const T *Cp, int logL, unsig
 // z-marching variant (3D, nx a multiple of 256 up to 512): unroll = log2 of the planes per chunk.
 inline bool zm_ok(const Plan &p) { return p.d == 3 && (p.n[0] == 256 || p.n[0] == 512) && p.n[1] >= 2; }
 
-template <typename T, int L, int XM, int R>
+template <typename T, int L, int XM, int R, bool SPLIT = false>
 void launch_zm_variant(const Plan &p, const T *Cn, const T *Cp, int zc_log) {
   const Dims dm = make_dims(p);
   const RhsCoef<T> cf = make_coef<T>(p);
   const unsigned nb = (unsigned)((p.n[1] / L) * (p.n[2] >> zc_log));
-  const size_t lds = ((size_t)L * p.n[0] + (size_t)L * line_pitch(p.n[0])) * sizeof(T);
-  hipLaunchKernelGGL((k_rhs_xdht_zm<T, L, XM, R>), dim3(nb), dim3(kThreads), lds, p.stream, Cn, Cp,
+  const size_t lds = ((size_t)L * p.n[0] + (SPLIT ? 0 : (size_t)L * line_pitch(p.n[0]))) * sizeof(T);
+  hipLaunchKernelGGL((k_rhs_xdht_zm<T, L, XM, R, SPLIT>), dim3(nb), dim3(kThreads), lds, p.stream, Cn, Cp,
                      (const T *)p.F[0], (const T *)p.F[1], (const T *)p.F[2], (T *)p.W, dm, cf, zc_log,
                      (const T *)p.twr[0], (const T *)p.twi[0]);
+}
+
+// Stencil-only z-march (the rhs Q into W, no transform) with L rows per tile.
+template <typename T, int XM>
+void launch_zm_split(const Plan &p, const T *Cn, const T *Cp, int logL, int zc_log) {
+  if (logL <= 1) launch_zm_variant<T, 2, XM, 8, true>(p, Cn, Cp, zc_log);
+  else if (logL == 2) launch_zm_variant<T, 4, XM, 8, true>(p, Cn, Cp, zc_log);
+  else launch_zm_variant<T, 8, XM, 8, true>(p, Cn, Cp, zc_log);
 }
 
 template <typename T, int XM>
@@ -1377,14 +1390,26 @@ void launch_zm_xm(const Plan &p, const T *Cn, const T *Cp, int logL, int radix, 
   }
 }
 
+// Pass 0.  unroll 1-2: one fused rhs + x-transform kernel per line tile; 3-5: the same fused
+// work z-marching over 2^unroll planes (3D, nx 256 or 512); 6-8: a stencil-only z-march over
+// 2^(unroll-3) planes writing Q, then the x transform of W in place (with split_only, the
+// caller launches that transform itself).
 template <typename T, int D>
-hipError_t launch_rhs(const Plan &p, const T *Cn, const T *Cp, const Plan::Shape &sh) {
+hipError_t launch_rhs(const Plan &p, const T *Cn, const T *Cp, const Plan::Shape &sh, bool split_only = false) {
   constexpr int E = tile_elems<T>();
   if (D == 3 && sh.unroll >= 3 && zm_ok(p)) {
     int logL = sh.log_tile < 1 ? 1 : (sh.log_tile > 3 ? 3 : sh.log_tile);
     while ((1 << logL) > p.n[1]) --logL;
-    int zc_log = sh.unroll;
+    const bool split = sh.unroll >= 6;
+    int zc_log = split ? sh.unroll - 3 : sh.unroll;
     while ((1 << zc_log) > p.n[2]) --zc_log;
+    if (split) {
+      if (p.n[0] == 256) launch_zm_split<T, 1>(p, Cn, Cp, logL, zc_log);
+      else launch_zm_split<T, 2>(p, Cn, Cp, logL, zc_log);
+      hipError_t e = hipGetLastError();
+      if (e != hipSuccess || split_only) return e;
+      return launch_xdht<T>(p, (const T *)p.W, (T *)p.W, p.shape[3]);
+    }
     if (p.n[0] == 256) launch_zm_xm<T, 1>(p, Cn, Cp, logL, sh.radix, zc_log);
     else launch_zm_xm<T, 2>(p, Cn, Cp, logL, sh.radix, zc_log);
     return hipGetLastError();
@@ -1473,9 +1498,14 @@ hipError_t enqueue_step(const Plan &p, int cur, KernelTimer *tm) {
   auto mark = [&](const char *name) {
     if (tm && e == hipSuccess) e = tm->mark(name, p.stream);
   };
-  mark("rhs_xdht");
+  const bool split = p.d == 3 && p.shape[0].unroll >= 6 && zm_ok(p);
+  mark(split ? "rhs_stencil" : "rhs_xdht");
   if (e == hipSuccess)
-    e = p.d == 2 ? launch_rhs<T, 2>(p, Cn, Cp, p.shape[0]) : launch_rhs<T, 3>(p, Cn, Cp, p.shape[0]);
+    e = p.d == 2 ? launch_rhs<T, 2>(p, Cn, Cp, p.shape[0], true) : launch_rhs<T, 3>(p, Cn, Cp, p.shape[0], true);
+  if (split) {
+    mark("xdht_fwd");
+    if (e == hipSuccess) e = launch_xdht<T>(p, (const T *)p.W, (T *)p.W, p.shape[3]);
+  }
   if (e == hipSuccess) e = launch_spectral_tail<T>(p, tm);
   mark("xdht_out");
   if (e == hipSuccess) e = launch_xdht<T>(p, (const T *)p.W, Cp, p.shape[3]);
@@ -1525,8 +1555,10 @@ hipError_t tune_shapes(Plan &p, int cur, int reps) {
     Plan::Shape bs = p.shape[0];
     for (int lt = 1; lt <= hi; ++lt)
       for (int radix : {8, 16})
-        for (int un : {1, 2, 3, 4, 5}) {
-          if (un >= 3 && (!zm_ok(p) || lt > 3 || (1 << lt) > p.n[1] || (1 << un) > p.n[2])) continue;
+        for (int un : {1, 2, 3, 4, 5, 6, 7, 8}) {
+          const int zl = un >= 6 ? un - 3 : un;
+          if (un >= 3 && (!zm_ok(p) || lt > 3 || (1 << lt) > p.n[1] || (1 << zl) > p.n[2])) continue;
+          if (un >= 6 && radix == 16) continue;   // the stencil-only kernel has no transform
           Plan::Shape sh{lt, radix, un};
           const float t = time_it([&]() {
             return p.d == 2 ? launch_rhs<T, 2>(p, Cn, Cp, sh) : launch_rhs<T, 3>(p, Cn, Cp, sh);

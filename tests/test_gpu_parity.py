@@ -250,7 +250,8 @@ def test_tuned_shapes_keep_parity(chib):
 
 
 def test_z_marching_rhs_variants(chib):
-    """Every shape of the z-marching fused rhs kernel (3D, nx = 256) matches the oracle step."""
+    """Every shape of the z-marching rhs kernel (3D, nx = 256), fused with the x transform or split
+    from it, matches the oracle step."""
     grid = W.Grid((256, 16, 32), (-2.0, -0.125, -0.25), (2.0, 0.125, 0.25))
     prm = W.Params(Cn=0.02, Pe=100.0, Ca=0.1, theta_deg=70.0, slip_length=0.01, dt=1e-4)
     case = W.Case("slab3d", grid, [W.Shape(W.HALFPLANE, (0.0, 0.0, -0.1, 0.0, 0.0, 1.0))], prm, 10,
@@ -262,7 +263,7 @@ def test_z_marching_rhs_variants(chib):
     orc.step(6)
     for lt in (1, 2, 3):
         for radix in (8, 16):
-            for zc in (3, 4, 5):
+            for zc in (3, 4, 5, 6, 7, 8):      # 6..8: stencil-only z-march + separate x transform
                 st.load(blob)
                 st.set_shapes([[lt, radix, zc], [3, 8, 1], [4, 16, 1], [3, 8, 1]])
                 st.step(6)
