@@ -269,3 +269,29 @@ def test_z_marching_rhs_variants(chib):
                 st.step(6)
                 err = _linf(st.get(chib.FIELD_C), orc.C)
                 assert err <= 1e-11, (lt, radix, zc, err)
+
+
+@pytest.mark.parametrize("i", range(6))
+def test_config2_full_length_5000_steps(chib, i):
+    """Config 2 at its full length.  Over 5000 steps rounding differences are amplified while
+    contact lines jump between crests, so the bound is derived from the arithmetic: a second GPU
+    run that differs only in its FFT radices (another correct FP64 summation order) measures how
+    far two correct orderings drift apart; the oracle must stay within 1e-9 or within five times
+    that spread of the GPU result.  The factor is empirical: the two GPU orderings share their
+    transform and stencil structure while the oracle sums its FFTs in a different order, and the
+    measured oracle/spread ratios over the six cases are 1.0 to 3.7."""
+    case = W.config2(i)
+    st, orc, T = _pair(chib, case)
+    st2, _, _ = _pair(chib, case)
+    st.set_shapes([[4, 8, 1], [3, 8, 1], [3, 8, 1], [3, 8, 1]])
+    st2.set_shapes([[4, 16, 1], [3, 16, 1], [3, 16, 1], [3, 16, 1]])
+    _say("config2 full length", case.name)
+    st.step(5000)
+    st2.step(5000)
+    orc.step(5000)
+    C1 = st.get(chib.FIELD_C)
+    err = _linf(C1, orc.C)
+    spread = _linf(C1, st2.get(chib.FIELD_C))
+    _say("config2", case.name, "Linf vs oracle", err, "radix-8 vs radix-16 spread", spread)
+    assert np.all(np.isfinite(C1))
+    assert err <= max(1e-9, 5.0 * spread)
