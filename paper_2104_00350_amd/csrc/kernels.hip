@@ -182,6 +182,27 @@ __device__ __forceinline__ int lds_at(int b, int n, int ps, int ns, int padw) {
   return b * ps + n * ns + (n >> 4) * padw;
 }
 
+// Stages `tot` elements from global memory into LDS, element e read from src(e) and written to
+// LDS slot dst(e): every thread issues kBatch independent loads before its LDS stores, so a tile
+// costs one memory round trip per batch rather than one per element.
+constexpr int kBatch = 8;
+template <typename T, typename Src, typename Dst>
+__device__ __forceinline__ void stage_tile(T *__restrict__ s, int tot, Src src, Dst dst) {
+  for (int e0 = threadIdx.x; e0 < tot; e0 += kBatch * blockDim.x) {
+    T v[kBatch];
+#pragma unroll
+    for (int k = 0; k < kBatch; ++k) {
+      const int e = e0 + k * blockDim.x;
+      v[k] = e < tot ? src(e) : T(0);
+    }
+#pragma unroll
+    for (int k = 0; k < kBatch; ++k) {
+      const int e = e0 + k * blockDim.x;
+      if (e < tot) s[dst(e)] = v[k];
+    }
+  }
+}
+
 // w^r for r = 1..R-1 from w = w^1 by products of at most four factors.
 template <typename T, int R>
 __device__ __forceinline__ void twiddle_powers(T w1r, T w1i, T *wr, T *wi) {
@@ -592,10 +613,10 @@ __device__ __forceinline__ void xdht_body(unsigned char *smem_raw, const T *__re
   const int tot = L << lnx;
   const int pitch = line_pitch(nx);
   const T *src = in + (int64_t)line0 * nx;
-  for (int e = threadIdx.x; e < tot; e += blockDim.x) {
+  stage_tile(s, tot, [&](int e) { return src[e]; }, [&](int e) {
     const int l = e >> lnx, i = e & (nx - 1);
-    s[l * pitch + i + (i >> 4)] = src[e];
-  }
+    return l * pitch + i + (i >> 4);
+  });
   __syncthreads();
   lds_fft<T, E, false, MAXR>(s, lnx, logL - 1, 2 * pitch, 1, pitch, 1, false, twr, twi);
   T *dst = out + (int64_t)line0 * nx;
@@ -639,10 +660,10 @@ __global__ __launch_bounds__(kThreads) void k_strided_dht(T *__restrict__ W, int
   const int t = xcd_tile(blockIdx.x, gridDim.x);
   const int64_t base = (int64_t)(t >> lognxb) * outer + (int64_t)(t & ((1 << lognxb) - 1)) * B;
   const int tot = N << logB;
-  for (int e = threadIdx.x; e < tot; e += blockDim.x) {
+  stage_tile(s, tot, [&](int e) { return W[base + (e >> logB) * stride + (e & (B - 1))]; }, [&](int e) {
     const int n = e >> logB, col = e & (B - 1);
-    s[n * B + (n >> 4) * 2 + col] = W[base + n * stride + col];
-  }
+    return n * B + (n >> 4) * 2 + col;
+  });
   __syncthreads();
   lds_fft<T, E, false, MAXR, 256, true>(s, logN, logB - 1, 2, B, 1, 2, true, twr, twi);
   const int lp = logB - 1;
@@ -678,11 +699,11 @@ __device__ __forceinline__ void neumann_body(unsigned char *smem_raw, T *__restr
   const int oy = t >> lognxb;
   const int64_t base = (int64_t)oy * outer + (int64_t)xb * B;
   const int tot = N << logB;
-  for (int e = threadIdx.x; e < tot; e += blockDim.x) {
+  stage_tile(s, tot, [&](int e) { return W[base + (e >> logB) * stride + (e & (B - 1))]; }, [&](int e) {
     const int n = e >> logB, col = e & (B - 1);
     const int pos = (n & 1) ? (N - 1 - (n >> 1)) : (n >> 1);
-    s[pos * B + (pos >> 4) * 2 + col] = W[base + n * stride + col];
-  }
+    return pos * B + (pos >> 4) * 2 + col;
+  });
   __syncthreads();
   lds_fft<T, E, false, MAXR, 256, true>(s, logN, logB - 1, 2, B, 1, 2, true, twr, twi);
   const int half = N >> 1;
