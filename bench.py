@@ -44,6 +44,9 @@ def algorithmic_bytes(name: str, cells: int, d: int, es: int, G: int, NF: int, d
         per_ghost = 4 + 8 * K + es * (3 * d + 4 + 2 * K + 2 * K * (4 if dynamic else 2) * d)
         per_face = 16 + es * 4 + 16 + es * 3
         return G * per_ghost + NF * per_face
+    if name == "ghost_fills":                        # static: both fills, one launch plus the faces
+        return (algorithmic_bytes("ghost_fill_C", cells, d, es, G, NF, dynamic)
+                + algorithmic_bytes("ghost_fill_u", cells, d, es, G, NF, dynamic))
     return 0.0
 
 
@@ -71,6 +74,8 @@ def kernel_template(name: str, shapes, es: int, nx: int) -> list:
         return [f"k_fill_static<{t}>"]
     if name == "ghost_fill_u":
         return [f"k_vel_ghosts<{t}>", f"k_vel_faces<{t}>"]
+    if name == "ghost_fills":
+        return [f"k_fill_static_vel<{t}>", f"k_vel_faces<{t}>"]
     return []
 
 

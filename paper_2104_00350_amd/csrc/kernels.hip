@@ -1042,11 +1042,13 @@ __device__ __forceinline__ void vel_ghosts_body(
     gIn += gI[a] * n[a];
   }
   const T VnG = -VnM / ga;
-  const T CG = C[cg], CM = CMs[g];
-  const T CIv = (ga * CG + CM) / (ga + T(1));
-  const T dCdn = (CM - CG) / ((T(1) + ga) * dng);
-  const T Kc = capillary ? (T(1.06066017177982128660) * Cn * dCdn + T(0.75) * cos_t * (T(1) - CIv * CIv)) * inv_Ca
-                         : T(0);
+  T Kc = T(0);
+  if (capillary) {   // only then are C and C_M read (the static fill may be writing them meanwhile)
+    const T CG = C[cg], CM = CMs[g];
+    const T CIv = (ga * CG + CM) / (ga + T(1));
+    const T dCdn = (CM - CG) / ((T(1) + ga) * dng);
+    Kc = (T(1.06066017177982128660) * Cn * dCdn + T(0.75) * cos_t * (T(1) - CIv * CIv)) * inv_Ca;
+  }
   const T den = ls + ga * dng;
   const T fM = (ls - dng) / den;
   const T fK = ls * (ga + T(1)) * dng * inv_mu / den;
@@ -1067,6 +1069,25 @@ __global__ __launch_bounds__(kThreads) void k_vel_ghosts(
     const int *__restrict__ f_gR, T *__restrict__ stashL, T *__restrict__ stashR, int64_t NF, Dims dm, int d,
     T inv2h, T Cn, T cos_t, T inv_Ca, T inv_mu, T ls, int capillary, unsigned nbg) {
   vel_ghosts_body<T>(C, F0, F1, F2, gidx, nrm, dn, gam, ap, w, CMs, UG, G, K, f_cell, f_axis, f_gL, f_gR, stashL, stashR, NF, dm, d, inv2h, Cn, cos_t, inv_Ca, inv_mu, ls, capillary, nbg, blockIdx.x);
+}
+
+// K6 + K7a in one launch for the static condition, where the velocity fill does not read C:
+// blocks [0, nbc) fill the C ghosts, the others compute the ghost velocities and face stashes.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_fill_static_vel(
+    T *__restrict__ C, const int *__restrict__ gidx, const T *__restrict__ dn, const T *__restrict__ gam,
+    const int *__restrict__ ap, const T *__restrict__ w, T *__restrict__ CGn, T *__restrict__ CGnm1,
+    T *__restrict__ CMs, int64_t G, int K, T cb, const T *__restrict__ F0, const T *__restrict__ F1,
+    const T *__restrict__ F2, const T *__restrict__ nrm, T *__restrict__ UG, const int *__restrict__ f_cell,
+    const int *__restrict__ f_axis, const int *__restrict__ f_gL, const int *__restrict__ f_gR, T *__restrict__ stashL,
+    T *__restrict__ stashR, int64_t NF, Dims dm, int d, T inv2h, T Cn, T cos_t, T inv_Ca, T inv_mu, T ls,
+    unsigned nbc, unsigned nbg) {
+  if (blockIdx.x < nbc) {
+    fill_static_body<T>(C, gidx, dn, gam, ap, w, CGn, CGnm1, CMs, G, K, cb, 0, blockIdx.x);
+    return;
+  }
+  vel_ghosts_body<T>(C, F0, F1, F2, gidx, nrm, dn, gam, ap, w, CMs, UG, G, K, f_cell, f_axis, f_gL, f_gR, stashL,
+                     stashR, NF, dm, d, inv2h, Cn, cos_t, inv_Ca, inv_mu, ls, 0, nbg, blockIdx.x - nbc);
 }
 
 // K7b: every face touching a ghost becomes the mean of its two cell-centred values.
@@ -1492,6 +1513,31 @@ hipError_t launch_ghost_fill(const Plan &p, T *Cout, int init) {
 }
 
 template <typename T>
+hipError_t launch_velocity_faces(const Plan &p) {
+  if (p.NF)
+    hipLaunchKernelGGL((k_vel_faces<T>), dim3(blocks_for(p.NF)), dim3(kThreads), 0, p.stream, (T *)p.F[0],
+                       (T *)p.F[1], (T *)p.F[2], (const T *)p.UG, p.G, p.f_cell, p.f_axis, p.f_gL, p.f_gR,
+                       (const T *)p.stashL, (const T *)p.stashR, p.NF);
+  return hipGetLastError();
+}
+
+// Static condition with the velocity fill: C ghosts and ghost velocities in one launch, then the faces.
+template <typename T>
+hipError_t launch_static_fills(const Plan &p, T *Cout) {
+  const Dims dm = make_dims(p);
+  const unsigned nbc = blocks_for(p.G * 16), nbg = blocks_for(p.G * 16);
+  const T cb = (T)(p.cos_t / (1.4142135623730951 * p.Cn));
+  hipLaunchKernelGGL((k_fill_static_vel<T>), dim3(nbc + nbg + blocks_for(p.NF)), dim3(kThreads), 0, p.stream, Cout,
+                     p.gidx, (const T *)p.dn, (const T *)p.gamma, p.ap, (const T *)p.w, (T *)p.CGn, (T *)p.CGnm1,
+                     (T *)p.CMs, p.G, p.K, cb, (const T *)p.F[0], (const T *)p.F[1], (const T *)p.F[2],
+                     (const T *)p.normal, (T *)p.UG, p.f_cell, p.f_axis, p.f_gL, p.f_gR, (T *)p.stashL,
+                     (T *)p.stashR, p.NF, dm, p.d, (T)(0.5 / p.h), (T)p.Cn, (T)p.cos_t, (T)(1.0 / p.Ca),
+                     (T)(1.0 / p.mu), (T)p.ls, nbc, nbg);
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? launch_velocity_faces<T>(p) : e;
+}
+
+template <typename T>
 hipError_t launch_velocity_fill(const Plan &p, const T *Cfin) {
   if (!p.vel_fill || p.G == 0) return hipSuccess;
   const Dims dm = make_dims(p);
@@ -1530,10 +1576,15 @@ hipError_t enqueue_step(const Plan &p, int cur, KernelTimer *tm) {
   if (e == hipSuccess) e = launch_spectral_tail<T>(p, tm);
   mark("xdht_out");
   if (e == hipSuccess) e = launch_xdht<T>(p, (const T *)p.W, Cp, p.shape[3]);
-  mark("ghost_fill_C");
-  if (e == hipSuccess) e = launch_ghost_fill<T>(p, Cp, 0);
-  if (p.vel_fill && p.G) mark("ghost_fill_u");
-  if (e == hipSuccess) e = launch_velocity_fill<T>(p, Cp);
+  if (!p.dynamic && p.vel_fill && p.G) {
+    mark("ghost_fills");
+    if (e == hipSuccess) e = launch_static_fills<T>(p, Cp);
+  } else {
+    mark("ghost_fill_C");
+    if (e == hipSuccess) e = launch_ghost_fill<T>(p, Cp, 0);
+    if (p.vel_fill && p.G) mark("ghost_fill_u");
+    if (e == hipSuccess) e = launch_velocity_fill<T>(p, Cp);
+  }
   if (tm && e == hipSuccess) e = tm->end(p.stream);
   return e;
 }
@@ -1805,23 +1856,22 @@ __global__ __launch_bounds__(kThreads) void kb_out(const CaseDesc<T> *__restrict
                      (int)(blockIdx.x - off[c]));
 }
 
+// Static C fill and (with the velocity fill) the ghost velocities of every case in one launch:
+// per case, the first blocks fill C, the following ones compute ghost velocities and face stashes.
 template <typename T>
 __global__ __launch_bounds__(kThreads) void kb_fill(const CaseDesc<T> *__restrict__ cs, const int *__restrict__ off,
                                                     int n, int parity) {
   const int c = find_case(off, n, blockIdx.x);
   const CaseDesc<T> &d = cs[c];
-  fill_static_body<T>(d.C[1 - parity], d.gidx, d.dn, d.gam, d.ap, d.w, d.CGn, d.CGnm1, d.CMs, d.G, d.K, d.cb, 0,
-                      (int64_t)(blockIdx.x - off[c]));
-}
-
-template <typename T>
-__global__ __launch_bounds__(kThreads) void kb_velg(const CaseDesc<T> *__restrict__ cs, const int *__restrict__ off,
-                                                    int n, int parity) {
-  const int c = find_case(off, n, blockIdx.x);
-  const CaseDesc<T> &d = cs[c];
+  const int64_t t = (int64_t)(blockIdx.x - off[c]);
+  const int64_t nbc = (d.G * 16 + kThreads - 1) / kThreads;
+  if (t < nbc) {
+    fill_static_body<T>(d.C[1 - parity], d.gidx, d.dn, d.gam, d.ap, d.w, d.CGn, d.CGnm1, d.CMs, d.G, d.K, d.cb, 0, t);
+    return;
+  }
   vel_ghosts_body<T>(d.C[1 - parity], d.F0, d.F1, d.F1, d.gidx, d.normal, d.dn, d.gam, d.ap, d.w, d.CMs, d.UG, d.G,
                      d.K, d.f_cell, d.f_axis, d.f_gL, d.f_gR, d.stashL, d.stashR, d.NF, d.dm, 2, d.inv2h, d.Cn,
-                     d.cos_t, d.inv_Ca, d.inv_mu, d.ls, 0, d.nbg, (int64_t)(blockIdx.x - off[c]));
+                     d.cos_t, d.inv_Ca, d.inv_mu, d.ls, 0, d.nbg, t - nbc);
 }
 
 template <typename T>
@@ -1909,9 +1959,9 @@ void case_tiles(const Plan &p, int *tiles, size_t *lds) {
   tiles[0] = p.n[1] >> lr;
   tiles[1] = p.n[0] >> lb;
   tiles[2] = p.n[1] >> lo;
-  tiles[3] = (int)blocks_for(p.G * 16);
   const bool vf = p.vel_fill && p.G > 0;
-  tiles[4] = vf ? (int)(blocks_for(p.G * 16) + blocks_for(p.NF)) : 0;
+  tiles[3] = (int)blocks_for(p.G * 16) + (vf ? (int)(blocks_for(p.G * 16) + blocks_for(p.NF)) : 0);
+  tiles[4] = 0;   // the ghost velocities run inside phase 3 (kb_fill)
   tiles[5] = vf ? (int)blocks_for(p.NF) : 0;
   lds[0] = (size_t)(1 << lr) * line_pitch(p.n[0]) * sizeof(T);
   lds[1] = (size_t)col_tile(p.n[1], 1 << lb) * sizeof(T);
@@ -1937,7 +1987,7 @@ hipError_t enqueue_batch_step(const BatchLaunch &bl, int parity) {
   if (bl.radix_out == 8) hipLaunchKernelGGL((kb_out<T, E, 8>), dim3(nb2), dim3(kThreads), bl.lds[2], bl.stream, cs, O(2), n, parity);
   else hipLaunchKernelGGL((kb_out<T, E, 16>), dim3(nb2), dim3(kThreads), bl.lds[2], bl.stream, cs, O(2), n, parity);
   if (nb3) hipLaunchKernelGGL((kb_fill<T>), dim3(nb3), dim3(kThreads), 0, bl.stream, cs, O(3), n, parity);
-  if (nb4) hipLaunchKernelGGL((kb_velg<T>), dim3(nb4), dim3(kThreads), 0, bl.stream, cs, O(4), n, parity);
+  (void)nb4;
   if (nb5) hipLaunchKernelGGL((kb_velf<T>), dim3(nb5), dim3(kThreads), 0, bl.stream, cs, O(5), n);
   return hipGetLastError();
 }
