@@ -180,10 +180,21 @@ def learned_benchmark(chib, steps: int) -> dict:
             "speedup_plain_coarse_vs_plain_fine": round(sm["speedup_coarse_vs_fine"], 3),
             "seconds": {"fine": round(sm["fine_s"], 3), "coarse": round(sm["coarse_s"], 3),
                         "learned": round(sm["learned_s"], 3)},
+            "angle_measure": "circular-cap fit beyond 3 Cn from the wall (equilibrium angle); near-wall local "
+                             "fit alongside",
             "angle_err_vs_fine_deg": [{"step": p["step"], "cases": p["cases"],
                                        "plain_coarse": p["mean_abs_err_coarse_deg"],
-                                       "learned": p["mean_abs_err_learned_deg"]} for p in sm["per_checkpoint"]],
-            "within_1deg": sm["learned_within_1deg_at_every_measured_checkpoint"],
+                                       "learned": p["mean_abs_err_learned_deg"],
+                                       "fine_vs_prescribed": p["mean_abs_fine_minus_theta_deg"],
+                                       "local_fit": {"cases": p["cases_local"],
+                                                     "plain_coarse": p["mean_abs_err_coarse_deg_local"],
+                                                     "learned": p["mean_abs_err_learned_deg_local"]}}
+                                      for p in sm["per_checkpoint"]],
+            "within_1deg": {"cap_fit_vs_fine": sm["learned_within_1deg_cap_fit"],
+                            "local_fit_vs_fine": sm["learned_within_1deg_local_fit"],
+                            "fine_at_equilibrium": sm["fine_at_equilibrium"],
+                            "equilibrium_target_met": bool(sm["learned_within_1deg_cap_fit"]
+                                                           and sm["fine_at_equilibrium"])},
             "fallbacks_to_fine": sm["fallbacks"]}
 
 

@@ -17,6 +17,15 @@ measured the same way:
   (measured through the C > 0 phase, so cos(theta) > 0 means the C > 0 phase wets).
 
 Returns the two angles in degrees and their mean.
+
+`measure_cap` is the equilibrium measurement: at rest the 2D interface away from the wall's
+diffuse layer is a circular arc (uniform pressure jump), so the droplet's C = 0 crossings
+farther than a few interface widths from the wall are fitted by one circle, which is then
+followed down to its first intersections with the wall curve on each side.  There the angle
+through the droplet between wall and interface satisfies cos(theta) = n_w . (P - c) / R,
+with n_w the wall normal into the fluid, c and R the circle's centre and radius.  It does not
+look at the region near the wall, so the wall's curvature within a few interface widths of the
+contact line cannot fold the sampling curves.
 """
 from __future__ import annotations
 
@@ -164,4 +173,161 @@ def measure(C: np.ndarray, lo: Sequence[float], hi: Sequence[float], shape_kind:
         out[side] = math.degrees(math.acos(max(-1.0, min(1.0, float(tw @ ti)))))
         out[side + "_x"] = float(s0)
     out["mean"] = 0.5 * (out["left"] + out["right"])
+    return out
+
+
+def _wall_distance(shape_kind: int, p: Sequence[float], x, y):
+    """Unsigned distance from points (x, y) above the wall to the wall curve (Newton on the
+    nearest-point condition from three seeds, smallest result)."""
+    x = np.asarray(x, dtype=np.float64)
+    y = np.asarray(y, dtype=np.float64)
+    if shape_kind == HALFPLANE:
+        return np.abs(y - p[1])
+    mean, amp, lam, ph = p[0], p[1], p[2], p[3]
+    k = 2.0 * math.pi / lam
+    best = np.full(x.shape, np.inf)
+    for seed in (0.0, -0.25 * lam, 0.25 * lam):
+        s = x + seed
+        for _ in range(20):
+            yw = mean + amp * np.sin(k * s + ph)
+            d1 = amp * k * np.cos(k * s + ph)
+            d2 = -amp * k * k * np.sin(k * s + ph)
+            f = (s - x) + (yw - y) * d1
+            fp = 1.0 + d1 * d1 + (yw - y) * d2
+            fp = np.where(fp > 0.1, fp, 0.1)
+            s = s - np.clip(f / fp, -0.1 * lam, 0.1 * lam)
+        best = np.minimum(best, np.hypot(s - x, mean + amp * np.sin(k * s + ph) - y))
+    return best
+
+
+def _fit_circle(P: np.ndarray):
+    """Least-squares circle through points P (m, 2): algebraic fit, then Gauss-Newton on the
+    geometric residuals |p - c| - R."""
+    A_ = np.column_stack([P[:, 0], P[:, 1], np.ones(len(P))])
+    sol, *_ = np.linalg.lstsq(A_, -(P[:, 0] ** 2 + P[:, 1] ** 2), rcond=None)
+    c = np.array([-0.5 * sol[0], -0.5 * sol[1]])
+    R = math.sqrt(max(c @ c - sol[2], 1e-300))
+    for _ in range(20):
+        d = P - c
+        r = np.hypot(d[:, 0], d[:, 1])
+        res = r - R
+        J = np.column_stack([-d[:, 0] / r, -d[:, 1] / r, -np.ones(len(P))])
+        step, *_ = np.linalg.lstsq(J, -res, rcond=None)
+        c = c + step[:2]
+        R = R + step[2]
+        if np.max(np.abs(step)) < 1e-14 * max(1.0, R):
+            break
+    res = np.hypot(P[:, 0] - c[0], P[:, 1] - c[1]) - R
+    return c, R, res
+
+
+def measure_cap(C: np.ndarray, lo: Sequence[float], hi: Sequence[float], shape_kind: int,
+                shape_p: Sequence[float], Cn: float, min_dist: float = 3.0, rays: int = 720) -> Dict[str, float]:
+    """Equilibrium contact angles (degrees) of the C > 0 droplet from a circular-cap fit.
+
+    Crossings C = 0 are found along `rays` rays from the droplet's centre of mass (bisection of
+    the bilinearly interpolated C; a ray that enters the solid first has none), and those closer
+    than min_dist * Cn to the wall are dropped.  Points farther than 3 median deviations (and two
+    cells) from the fitted circle are trimmed and the circle refitted (up to three times), so
+    liquid left in a groove does not bend the fit.  Returns left, right, mean, the contact
+    abscissas and the rms fit residual over the cell size (`fit_rms_cells`)."""
+    C = np.asarray(C, dtype=np.float64)
+    ny, nx = C.shape
+    h = (hi[0] - lo[0]) / nx
+    yw, dyw = _wall(shape_kind, shape_p)
+    xs = lo[0] + (np.arange(nx) + 0.5) * h
+    ys = lo[1] + (np.arange(ny) + 0.5) * h
+    fluid = ys[:, None] > yw(xs)[None, :]
+    wgt = np.where(fluid & (C > 0), C, 0.0)
+    if wgt.sum() <= 0:
+        raise AngleError("no droplet (C > 0) above the wall")
+    xc = float((wgt.sum(axis=0) * xs).sum() / wgt.sum())
+    yc = float((wgt.sum(axis=1) * ys).sum() / wgt.sum())
+    if _bilinear(C, lo, h, xc, yc) <= 0:
+        raise AngleError("droplet centre of mass is not inside C > 0")
+    dmin = min_dist * Cn
+    phi = np.linspace(0.0, 2.0 * math.pi, rays, endpoint=False)
+    ux, uy = np.cos(phi), np.sin(phi)
+    step = 0.25 * h
+    rmax = 0.5 * (hi[0] - lo[0])
+    alive = np.ones(rays, dtype=bool)
+    r_in = np.zeros(rays)
+    r_out = np.full(rays, np.nan)
+    r = 0.0
+    while alive.any() and r < rmax:
+        r += step
+        px, py = xc + r * ux, yc + r * uy
+        out_box = (py <= lo[1]) | (py >= hi[1])
+        solid = np.zeros(rays, dtype=bool)
+        idx = np.nonzero(alive & ~out_box)[0]
+        solid[idx] = py[idx] <= yw(px[idx])
+        alive &= ~(out_box | solid)
+        idx = np.nonzero(alive)[0]
+        neg = _bilinear(C, lo, h, px[idx], py[idx]) <= 0
+        hit = idx[neg]
+        r_out[hit] = r
+        r_in[hit] = r - step
+        alive[hit] = False
+    ok = np.isfinite(r_out)
+    a, b = r_in[ok], r_out[ok]
+    for _ in range(40):
+        m = 0.5 * (a + b)
+        pos = _bilinear(C, lo, h, xc + m * ux[ok], yc + m * uy[ok]) > 0
+        a = np.where(pos, m, a)
+        b = np.where(pos, b, m)
+    rm = 0.5 * (a + b)
+    P = np.column_stack([xc + rm * ux[ok], yc + rm * uy[ok]])
+    P = P[_wall_distance(shape_kind, shape_p, P[:, 0], P[:, 1]) >= dmin]
+    if len(P) < 12:
+        raise AngleError("too few interface points away from the wall")
+    keep = np.ones(len(P), dtype=bool)
+    for _ in range(3):
+        c, R, res = _fit_circle(P[keep])
+        res_all = np.hypot(P[:, 0] - c[0], P[:, 1] - c[1]) - R
+        mad = np.median(np.abs(res_all[keep] - np.median(res_all[keep])))
+        new = np.abs(res_all) <= max(3.0 * 1.4826 * mad, 2.0 * h)
+        if new.sum() < 12 or np.array_equal(new, keep):
+            break
+        keep = new
+    c, R, res = _fit_circle(P[keep])
+    # follow the circle from the ends of the fitted arc down to the wall on each side
+    v = (P[keep] - c) / R
+    mid = v.mean(axis=0)
+    psi_mid = math.atan2(mid[1], mid[0])
+    dpsi = np.angle(np.exp(1j * (np.arctan2(v[:, 1], v[:, 0]) - psi_mid)))
+
+    def below(ps):
+        x, y = c[0] + R * math.cos(ps), c[1] + R * math.sin(ps)
+        return y - float(yw(x)) <= 0
+
+    out = {}
+    dstep = 0.25 * h / R
+    for side, start, sgn in (("left", dpsi.max(), 1.0), ("right", dpsi.min(), -1.0)):
+        d_in = start
+        d_out = None
+        d = start
+        while abs(d) < math.pi:
+            d += sgn * dstep
+            if below(psi_mid + d):
+                d_out = d
+                break
+            d_in = d
+        if d_out is None:
+            raise AngleError("fitted circle does not meet the wall on the " + side)
+        for _ in range(60):
+            m = 0.5 * (d_in + d_out)
+            if below(psi_mid + m):
+                d_out = m
+            else:
+                d_in = m
+        ps = psi_mid + 0.5 * (d_in + d_out)
+        Px, Py = c[0] + R * math.cos(ps), c[1] + R * math.sin(ps)
+        t = float(dyw(Px))
+        nw = np.array([-t, 1.0]) / math.sqrt(1.0 + t * t)
+        cos_t = float(nw @ ((np.array([Px, Py]) - c) / R))
+        out[side] = math.degrees(math.acos(max(-1.0, min(1.0, cos_t))))
+        out[side + "_x"] = Px
+    out["mean"] = 0.5 * (out["left"] + out["right"])
+    out["fit_rms_cells"] = float(np.sqrt(np.mean(res ** 2)) / h)
+    out["points"] = int(keep.sum())
     return out
