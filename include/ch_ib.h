@@ -211,12 +211,14 @@ int ch_ib_step_timed(ch_ib_state *st, int n_steps, int max_kernels, double *ms_o
  * 2 bounded-axis solve, 3 x transform out) each have a launch shape of three ints:
  * {log2 lines or columns per tile, largest FFT radix (8 or 16), third field}.  The third field is
  * 1 for passes 1-3; for pass 0 it is the cells in flight per thread (1 or 2) of the line-tiled
- * kernel, 3..5 to select the z-marching kernel (3D grids with nx = 256 or 512 only) with
- * 2^value planes per workgroup, or 6..8 to split that kernel in two: a stencil-only z-march over
- * 2^(value-3) planes writing the right-hand side, then the x transform in place with pass 3's
- * shape (16 more bytes per cell, no FFT inside the stencil loop).  Shapes change speed, never
- * results: every shape computes the same sums in the same order per element except for the FFT
- * radix, which changes rounding only.
+ * kernel; for 2D grids with nx <= 1024, 3 selects the y-marching kernel (rows y-1..y+1 held per
+ * thread, each value loaded and combined once); for 3D grids, 3..5 select the z-marching kernel
+ * (nx = 256 or 512 only) with 2^value planes per workgroup, or 6..8 split that kernel in two: a
+ * stencil-only z-march over 2^(value-3) planes writing the right-hand side, then the x transform
+ * in place with pass 3's shape (16 more bytes per cell, no FFT inside the stencil loop).  Shapes
+ * change speed, never results, apart from rounding: every shape computes the same sums in the
+ * same order per element except for the FFT radix and the y-marching kernel (which evaluates the
+ * bulk-energy derivative once per value and scales it by 1/Cn^2 inside the Laplacian factor).
  * ch_ib_tune: times every candidate shape of each pass reps times with HIP events on the state's
  *   buffers (the fields are left unchanged), keeps the fastest and writes the 12 chosen ints to
  *   shapes_out (may be NULL).  Synchronous.
@@ -243,9 +245,11 @@ int ch_ib_set_shapes(ch_ib_state *st, const int *shapes);
  *   launches only); the members' step counters and buffer roles are updated.
  * ch_ib_batch_tune: tunes the launch shapes of one member per distinct grid size
  *   (ch_ib_tune), applies them to all members of that size, then times full batched steps for
- *   the choices shared by the grouped kernels (greedy: rhs radix and cells in flight, then the
- *   solve radix, then the output radix); radix_out[0..2] (rhs, solve, out) and *unroll_out
- *   (either may be NULL) receive them.  Leaves the fields unchanged.  Synchronous.
+ *   the choices shared by the grouped kernels and the tile heights (greedy: rhs radix and rhs
+ *   kernel, then per grid size the rhs, solve and output tile heights, written to the members'
+ *   shapes, then the solve radix, then the output radix); radix_out[0..2] (rhs, solve, out) and
+ *   *unroll_out (either may be NULL) receive the shared choices.  Leaves the fields unchanged.
+ *   Synchronous.
  * ch_ib_batch_sync: waits for the batch's stream.  ch_ib_batch_free: releases the graphs and the
  *   host object (not the states). */
 typedef struct ch_ib_batch ch_ib_batch;

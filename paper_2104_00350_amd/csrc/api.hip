@@ -751,11 +751,12 @@ static int batch_upload(ch_ib_batch *b) {
   const size_t db = batch_desc_bytes(b->es);
   std::vector<unsigned char> descs(db * n);
   std::vector<int> off(6 * (size_t)(n + 1), 0);
-  size_t lds[3] = {0, 0, 0};
+  size_t lds[4] = {0, 0, 0, 0};
+  bool ym_all = true;
   for (int c = 0; c < n; ++c) {
     ch_ib_state *s = b->st[c];
     int tiles[6];
-    size_t l[3];
+    size_t l[4];
     if (b->es == 8) {
       chib::fill_case_desc<double>(s->plan, s->cur, descs.data() + db * c);
       chib::case_tiles<double>(s->plan, tiles, l);
@@ -764,8 +765,10 @@ static int batch_upload(ch_ib_batch *b) {
       chib::case_tiles<float>(s->plan, tiles, l);
     }
     for (int ph = 0; ph < 6; ++ph) off[ph * (n + 1) + c + 1] = off[ph * (n + 1) + c] + tiles[ph];
-    for (int k = 0; k < 3; ++k) lds[k] = std::max(lds[k], l[k]);
+    for (int k = 0; k < 4; ++k) lds[k] = std::max(lds[k], l[k]);
+    ym_all = ym_all && l[3] > 0;
   }
+  if (!ym_all) lds[3] = 0;
   const size_t doff = (db * n + 255) & ~(size_t)255;
   hipError_t e = hipMemcpyAsync(b->ws, descs.data(), descs.size(), hipMemcpyHostToDevice, b->stream);
   if (e == hipSuccess)
@@ -776,7 +779,7 @@ static int batch_upload(ch_ib_batch *b) {
   b->bl.off = (const int *)(b->ws + doff);
   b->bl.n = n;
   for (int ph = 0; ph < 6; ++ph) b->bl.total[ph] = (unsigned)off[ph * (n + 1) + n];
-  for (int k = 0; k < 3; ++k) b->bl.lds[k] = lds[k];
+  for (int k = 0; k < 4; ++k) b->bl.lds[k] = lds[k];
   b->bl.stream = b->stream;
   b->parity = 0;
   batch_drop_graphs(b);
@@ -818,7 +821,10 @@ extern "C" int ch_ib_batch_create(ch_ib_state *const *states, int n, void *ws, s
   // shared kernel choices follow the first member's shapes (so that a batched step is the same
   // computation as stepping each member with those shapes)
   b->bl.radix_rhs = states[0]->plan.shape[0].radix;
-  b->bl.unroll = std::min(states[0]->plan.shape[0].unroll, 2);
+  {
+    const int u = states[0]->plan.shape[0].unroll;   // 3: y-march where every case allows it
+    b->bl.unroll = u == 3 ? 3 : std::min(u, 2);
+  }
   b->bl.radix_neu = states[0]->plan.shape[2].radix;
   b->bl.radix_out = states[0]->plan.shape[3].radix;
   int rc = batch_upload(b);
@@ -934,8 +940,9 @@ extern "C" int ch_ib_batch_tune(ch_ib_batch *b, int reps, int *radix_out, int *u
     float best = 1e30f;
     int br = b->bl.radix_rhs, bu = b->bl.unroll;
     for (int radix : {8, 16})
-      for (int un : {1, 2}) {
+      for (int un : {1, 2, 3}) {
         if (e != hipSuccess) break;
+        if (un == 3 && !b->bl.lds[3]) continue;
         b->bl.radix_rhs = radix;
         b->bl.unroll = un;
         const float t = time_pair();
@@ -947,6 +954,33 @@ extern "C" int ch_ib_batch_tune(ch_ib_batch *b, int reps, int *radix_out, int *u
       }
     b->bl.radix_rhs = br;
     b->bl.unroll = bu;
+  }
+  // tile heights per distinct grid size (rhs lines, solve columns, out lines), timed on the whole
+  // batch: a case that runs alone wants small tiles to fill the GPU, a batch has parallelism to spare
+  for (int pass : {0, 2, 3}) {
+    for (const auto &key : sizes) {
+      if (e != hipSuccess) break;
+      std::vector<ch_ib_state *> grp;
+      for (ch_ib_state *s : b->st)
+        if (s->plan.n[0] == key.first && s->plan.n[1] == key.second) grp.push_back(s);
+      const int hi = b->es == 8 ? chib::max_log_tile<double>(grp[0]->plan, pass)
+                                : chib::max_log_tile<float>(grp[0]->plan, pass);
+      int best_lt = grp[0]->plan.shape[pass].log_tile;
+      float best = 1e30f;
+      for (int lt = 1; lt <= hi && e == hipSuccess; ++lt) {
+        for (ch_ib_state *s : grp) s->plan.shape[pass].log_tile = lt;
+        rc = batch_upload(b);
+        if (rc) return rc;
+        const float t = time_pair();
+        if (t < best) {
+          best = t;
+          best_lt = lt;
+        }
+      }
+      for (ch_ib_state *s : grp) s->plan.shape[pass].log_tile = best_lt;
+      rc = batch_upload(b);
+      if (rc) return rc;
+    }
   }
   for (int which = 0; which < 2 && e == hipSuccess; ++which) {
     int &slot = which == 0 ? b->bl.radix_neu : b->bl.radix_out;

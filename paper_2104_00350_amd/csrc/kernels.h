@@ -88,6 +88,8 @@ struct KernelTimer {
 template <typename T> hipError_t enqueue_step(const Plan &p, int cur, KernelTimer *tm = nullptr);
 template <typename T> hipError_t enqueue_initial_fill(const Plan &p, int cur);
 template <typename T> hipError_t tune_shapes(Plan &p, int cur, int reps);
+// Largest log2 tile height (passes 0 and 3: lines; 1 and 2: columns) a pass allows on this grid.
+template <typename T> int max_log_tile(const Plan &p, int pass);
 template <typename T> hipError_t enqueue_ghost_refresh(const Plan &p, int cur);   // static fill again, same step
 template <typename T> hipError_t enqueue_rhs(const Plan &p, int cur, void *out);
 template <typename T> hipError_t enqueue_solve(const Plan &p, const void *in, void *out);
@@ -100,8 +102,8 @@ struct BatchLaunch {
   const int *off = nullptr;      // device [6][n+1] per-phase tile offsets
   int n = 0;
   unsigned total[6] = {0, 0, 0, 0, 0, 0};
-  size_t lds[3] = {0, 0, 0};
-  int radix_rhs = 8, unroll = 2, radix_neu = 16, radix_out = 16;  // shared by all cases
+  size_t lds[4] = {0, 0, 0, 0};  // rhs, solve, out; y-marching rhs (0 unless every case allows it)
+  int radix_rhs = 8, unroll = 2, radix_neu = 16, radix_out = 16;  // shared by all cases (unroll 3: y-march)
   hipStream_t stream = nullptr;
 };
 template <typename T> void fill_case_desc(const Plan &p, int cur, void *desc_host);

@@ -467,6 +467,122 @@ __global__ __launch_bounds__(kThreads) void k_rhs_xdht(const T *__restrict__ Cn,
   rhs_xdht_body<T, D, E, U, MAXR>(smem_raw, Cn, Cp, F0, F1, F2, W, dm, cf, logL, twr, twi, xcd_tile(blockIdx.x, gridDim.x));
 }
 
+// Extra LDS of the y-marching K1 (two rows of C~ for the x neighbours) over the line tile.
+__host__ __device__ __forceinline__ int ym_extra(int nx) { return 2 * nx; }
+
+// K1 for 2D grids, marching in y: the workgroup owns the L rows of its tile across the whole x
+// range, thread t the columns x = t + 256 m (m < XM, nx <= 256 XM).  C~ = 2C^n - C^(n-1) of row
+// y-1 and the raw C^n, C^(n-1) of rows y and y+1 stay in registers, so every value is loaded
+// once and y neighbours never leave the thread (C~, C^ = 2C^n - C^(n-1)/2 and g(C~) =
+// C~^3 - (1 + S) C~ are formed from them as needed); the raw values of row y+2 are requested
+// while row y is computed.  x neighbours come from a two-row
+// ring of C~ in LDS (one barrier per row); each Q row goes straight into the line tile, which
+// then goes through the same x transform as the line-tiled K1.  1/Cn^2 scales the Laplacian.
+template <typename T, int XM, int R>
+__device__ __forceinline__ void rhs_ym_body(unsigned char *smem_raw, const T *__restrict__ Cn,
+                                            const T *__restrict__ Cp, const T *__restrict__ F0,
+                                            const T *__restrict__ F1, T *__restrict__ W, Dims dm, RhsCoef<T> cf,
+                                            int logL, const T *__restrict__ twr, const T *__restrict__ twi,
+                                            int tile) {
+  const int nx = dm.nx, ny = dm.ny;
+  const int L = 1 << logL;
+  const int pitch = line_pitch(nx);
+  T *fb = reinterpret_cast<T *>(smem_raw);           // L rows x pitch: Q, then its transform
+  T *xr = fb + L * pitch;                             // 2 rows x nx: C~ of the current row
+  const int y0 = tile * L;
+  const int tid = threadIdx.x;
+  const T s1 = T(1) + cf.S;
+  const T klap = cf.inv_h2 * cf.inv_cn2;
+  auto g = [&](T v) { return v * (v * v - s1); };
+  auto rowp = [&](const T *__restrict__ a, int y) { return a + (int64_t)(y < 0 ? 0 : (y >= ny ? ny - 1 : y)) * nx; };
+  // per column: C~ of row y-1, the raw C^n, C^(n-1) of rows y, y+1 and y+2 (in flight), F1 of row y-1
+  T cm[XM], a0[XM], b0[XM], a1[XM], b1[XM], an[XM], bn[XM], f1m[XM];
+#pragma unroll
+  for (int m = 0; m < XM; ++m) {
+    const int i = tid + 256 * m;
+    if (i < nx) {
+      const T a_m = rowp(Cn, y0 - 1)[i], b_m = rowp(Cp, y0 - 1)[i];
+      a0[m] = rowp(Cn, y0)[i];
+      b0[m] = rowp(Cp, y0)[i];
+      a1[m] = rowp(Cn, y0 + 1)[i];
+      b1[m] = rowp(Cp, y0 + 1)[i];
+      f1m[m] = rowp(F1, y0 - 1)[i];
+      an[m] = rowp(Cn, y0 + 2)[i];
+      bn[m] = rowp(Cp, y0 + 2)[i];
+      cm[m] = T(2) * a_m - b_m;
+    }
+  }
+  for (int r = 0; r < L; ++r) {
+    const int y = y0 + r;
+    const bool top = y == ny - 1, bot = y == 0;
+    T *xb = xr + (r & 1) * nx;
+    T f0[XM], f0m[XM], f1[XM];
+#pragma unroll
+    for (int m = 0; m < XM; ++m) {
+      const int i = tid + 256 * m;
+      if (i < nx) {
+        const T *r0 = rowp(F0, y), *r1 = rowp(F1, y);
+        f0[m] = r0[i];
+        f0m[m] = r0[(i - 1) & (nx - 1)];
+        f1[m] = r1[i];
+        xb[i] = T(2) * a0[m] - b0[m];
+      }
+    }
+    __syncthreads();   // the row is in LDS; the ring slot written next row was last read two rows ago
+#pragma unroll
+    for (int m = 0; m < XM; ++m) {
+      const int i = tid + 256 * m;
+      if (i < nx) {
+        const T v0 = T(2) * a0[m] - b0[m];
+        const T cxp = xb[(i + 1) & (nx - 1)], cxm = xb[(i - 1) & (nx - 1)];
+        const T cyp = top ? v0 : T(2) * a1[m] - b1[m], cym = bot ? v0 : cm[m];
+        T flux = f0[m] * (v0 + cxp) - f0m[m] * (cxm + v0);
+        flux += (top ? T(0) : f1[m] * (v0 + cyp)) - (bot ? T(0) : f1m[m] * (cym + v0));
+        const T g0 = g(v0);
+        const T gsum = g(cxp) + g(cxm) + (top ? g0 : g(cyp)) + (bot ? g0 : g(cym));
+        const T A = flux * T(0.5) * cf.inv_h;
+        const T lap = (gsum - T(4) * g0) * klap;
+        const T h0 = T(2) * a0[m] - T(0.5) * b0[m];
+        fb[r * pitch + i + (i >> 4)] = cf.pe_cn2 * (h0 * cf.inv_dt - A) + lap;
+        // slide the window down one row and request the row after next
+        cm[m] = v0;
+        a0[m] = a1[m];
+        b0[m] = b1[m];
+        a1[m] = an[m];
+        b1[m] = bn[m];
+        f1m[m] = f1[m];
+        if (r + 1 < L) {
+          an[m] = rowp(Cn, y + 3)[i];
+          bn[m] = rowp(Cp, y + 3)[i];
+        }
+      }
+    }
+  }
+  __syncthreads();
+  lds_fft<T, tile_elems<T>(), false, R>(fb, dm.lnx, logL - 1, 2 * pitch, 1, pitch, 1, false, twr, twi);
+  const int half = (L * nx) >> 1;
+  for (int e = tid; e < half; e += blockDim.x) {
+    const int b = e >> dm.lnx;
+    const int kx = e & (nx - 1);
+    const int kk = (nx - kx) & (nx - 1);
+    const T *pb = fb + b * 2 * pitch;
+    const int ak = kx + (kx >> 4), a2 = kk + (kk >> 4);
+    const T p = pb[ak], q = pb[pitch + ak], rr = pb[a2], sv = pb[pitch + a2];
+    T *o = W + (int64_t)(y0 + 2 * b) * nx + kx;
+    o[0] = (p - q + rr + sv) * T(0.5);
+    o[nx] = (p + q - rr + sv) * T(0.5);
+  }
+}
+
+template <typename T, int XM, int R>
+__global__ __launch_bounds__(kThreads, R == 8 ? 4 : 3) void k_rhs_xdht_ym(const T *__restrict__ Cn, const T *__restrict__ Cp,
+                                                          const T *__restrict__ F0, const T *__restrict__ F1,
+                                                          T *__restrict__ W, Dims dm, RhsCoef<T> cf, int logL,
+                                                          const T *__restrict__ twr, const T *__restrict__ twi) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  rhs_ym_body<T, XM, R>(smem_raw, Cn, Cp, F0, F1, W, dm, cf, logL, twr, twi, xcd_tile(blockIdx.x, gridDim.x));
+}
+
 // K1 for 3D grids, marching in z (2.5D blocking): a workgroup owns L consecutive y rows and
 // a chunk of ZC planes.  Thread t owns the x positions x = t + 256 m (m < nx/256, nx >= 256)
 // of rows -1..L of the tile, i.e. whole column segments including the two halo rows, and
@@ -1396,6 +1512,27 @@ void launch_rhs_variant(const Plan &p, const T *Cn, const T *Cp, int logL, unsig
                      logL, (const T *)p.twr[0], (const T *)p.twi[0]);
 }
 
+// y-marching variant (2D, nx up to 1024): unroll = 3.
+inline bool ym_ok(const Plan &p) { return p.d == 2 && p.n[0] <= 1024; }
+
+template <typename T, int XM, int R>
+void launch_ym_variant(const Plan &p, const T *Cn, const T *Cp, int logL) {
+  const Dims dm = make_dims(p);
+  const RhsCoef<T> cf = make_coef<T>(p);
+  const unsigned nb = (unsigned)(p.n[1] >> logL);
+  const size_t lds = ((size_t)(1 << logL) * line_pitch(p.n[0]) + ym_extra(p.n[0])) * sizeof(T);
+  hipLaunchKernelGGL((k_rhs_xdht_ym<T, XM, R>), dim3(nb), dim3(kThreads), lds, p.stream, Cn, Cp,
+                     (const T *)p.F[0], (const T *)p.F[1], (T *)p.W, dm, cf, logL, (const T *)p.twr[0],
+                     (const T *)p.twi[0]);
+}
+
+template <typename T, int R>
+void launch_ym(const Plan &p, const T *Cn, const T *Cp, int logL) {
+  if (p.n[0] <= 256) launch_ym_variant<T, 1, R>(p, Cn, Cp, logL);
+  else if (p.n[0] <= 512) launch_ym_variant<T, 2, R>(p, Cn, Cp, logL);
+  else launch_ym_variant<T, 4, R>(p, Cn, Cp, logL);
+}
+
 // z-marching variant (3D, nx a multiple of 256 up to 512): unroll = log2 of the planes per chunk.
 inline bool zm_ok(const Plan &p) { return p.d == 3 && (p.n[0] == 256 || p.n[0] == 512) && p.n[1] >= 2; }
 
@@ -1432,7 +1569,8 @@ void launch_zm_xm(const Plan &p, const T *Cn, const T *Cp, int logL, int radix, 
   }
 }
 
-// Pass 0.  unroll 1-2: one fused rhs + x-transform kernel per line tile; 3-5: the same fused
+// Pass 0.  unroll 1-2: one fused rhs + x-transform kernel per line tile; 2D, 3: the y-marching
+// form of it (nx up to 1024); 3D, 3-5: the same fused
 // work z-marching over 2^unroll planes (3D, nx 256 or 512); 6-8: a stencil-only z-march over
 // 2^(unroll-3) planes writing Q, then the x transform of W in place (with split_only, the
 // caller launches that transform itself).
@@ -1457,6 +1595,11 @@ hipError_t launch_rhs(const Plan &p, const T *Cn, const T *Cp, const Plan::Shape
     return hipGetLastError();
   }
   const int logL = clamp_log(sh.log_tile, max_log_lines(p, E));
+  if (D == 2 && sh.unroll == 3 && ym_ok(p)) {
+    if (sh.radix == 8) launch_ym<T, 8>(p, Cn, Cp, logL);
+    else launch_ym<T, 16>(p, Cn, Cp, logL);
+    return hipGetLastError();
+  }
   const int lines = p.d == 3 ? p.n[1] * p.n[2] : p.n[1];
   const unsigned nb = (unsigned)(lines >> logL);
   const size_t lds = (size_t)(1 << logL) * line_pitch(p.n[0]) * sizeof(T);
@@ -1629,7 +1772,8 @@ hipError_t tune_shapes(Plan &p, int cur, int reps) {
       for (int radix : {8, 16})
         for (int un : {1, 2, 3, 4, 5, 6, 7, 8}) {
           const int zl = un >= 6 ? un - 3 : un;
-          if (un >= 3 && (!zm_ok(p) || lt > 3 || (1 << lt) > p.n[1] || (1 << zl) > p.n[2])) continue;
+          if (un >= 3 && p.d == 2 && (un != 3 || !ym_ok(p))) continue;
+          if (un >= 3 && p.d == 3 && (!zm_ok(p) || lt > 3 || (1 << lt) > p.n[1] || (1 << zl) > p.n[2])) continue;
           if (un >= 6 && radix == 16) continue;   // the stencil-only kernel has no transform
           Plan::Shape sh{lt, radix, un};
           const float t = time_it([&]() {
@@ -1766,6 +1910,15 @@ hipError_t enqueue_diag(const Plan &p, int cur) {
   return hipGetLastError();
 }
 
+template <typename T>
+int max_log_tile(const Plan &p, int pass) {
+  constexpr int E = tile_elems<T>();
+  if (pass == 0 || pass == 3) return max_log_lines(p, E);
+  return max_log_cols(p, p.n[pass == 1 ? 1 : p.d - 1], E);
+}
+
+template int max_log_tile<double>(const Plan &, int);
+template int max_log_tile<float>(const Plan &, int);
 template hipError_t tune_shapes<double>(Plan &, int, int);
 template hipError_t tune_shapes<float>(Plan &, int, int);
 template hipError_t enqueue_step<double>(const Plan &, int, KernelTimer *);
@@ -1833,6 +1986,22 @@ __global__ __launch_bounds__(kThreads) void kb_rhs(const CaseDesc<T> *__restrict
   const CaseDesc<T> &d = cs[c];
   rhs_xdht_body<T, 2, E, U, R>(smem_raw, d.C[parity], d.C[1 - parity], d.F0, d.F1, d.F1, d.W, d.dm, d.cf,
                                d.logL_rhs, d.twr0, d.twi0, (int)(blockIdx.x - off[c]));
+}
+
+template <typename T, int R>
+__global__ __launch_bounds__(kThreads, R == 8 ? 4 : 3) void kb_rhs_ym(const CaseDesc<T> *__restrict__ cs,
+                                                      const int *__restrict__ off, int n, int parity) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int c = find_case(off, n, blockIdx.x);
+  const CaseDesc<T> &d = cs[c];
+  const int t = (int)(blockIdx.x - off[c]);
+  // the same instantiation as the single-state launch for this width, so results match bit for bit
+  if (d.dm.nx <= 256)
+    rhs_ym_body<T, 1, R>(smem_raw, d.C[parity], d.C[1 - parity], d.F0, d.F1, d.W, d.dm, d.cf, d.logL_rhs, d.twr0, d.twi0, t);
+  else if (d.dm.nx <= 512)
+    rhs_ym_body<T, 2, R>(smem_raw, d.C[parity], d.C[1 - parity], d.F0, d.F1, d.W, d.dm, d.cf, d.logL_rhs, d.twr0, d.twi0, t);
+  else
+    rhs_ym_body<T, 4, R>(smem_raw, d.C[parity], d.C[1 - parity], d.F0, d.F1, d.W, d.dm, d.cf, d.logL_rhs, d.twr0, d.twi0, t);
 }
 
 template <typename T, int E, int R>
@@ -1966,6 +2135,7 @@ void case_tiles(const Plan &p, int *tiles, size_t *lds) {
   lds[0] = (size_t)(1 << lr) * line_pitch(p.n[0]) * sizeof(T);
   lds[1] = (size_t)col_tile(p.n[1], 1 << lb) * sizeof(T);
   lds[2] = (size_t)(1 << lo) * line_pitch(p.n[0]) * sizeof(T);
+  lds[3] = ym_ok(p) ? lds[0] + (size_t)ym_extra(p.n[0]) * sizeof(T) : 0;   // 0: no y-march
 }
 
 template <typename T>
@@ -1978,7 +2148,10 @@ hipError_t enqueue_batch_step(const BatchLaunch &bl, int parity) {
   const unsigned nb0 = bl.total[0], nb1 = bl.total[1], nb2 = bl.total[2];
   const unsigned nb3 = bl.total[3], nb4 = bl.total[4], nb5 = bl.total[5];
   const bool r8 = bl.radix_rhs == 8, u2 = bl.unroll >= 2;
-  if (r8 && u2) hipLaunchKernelGGL((kb_rhs<T, E, 2, 8>), dim3(nb0), dim3(kThreads), bl.lds[0], bl.stream, cs, O(0), n, parity);
+  if (bl.unroll == 3 && bl.lds[3]) {
+    if (r8) hipLaunchKernelGGL((kb_rhs_ym<T, 8>), dim3(nb0), dim3(kThreads), bl.lds[3], bl.stream, cs, O(0), n, parity);
+    else hipLaunchKernelGGL((kb_rhs_ym<T, 16>), dim3(nb0), dim3(kThreads), bl.lds[3], bl.stream, cs, O(0), n, parity);
+  } else if (r8 && u2) hipLaunchKernelGGL((kb_rhs<T, E, 2, 8>), dim3(nb0), dim3(kThreads), bl.lds[0], bl.stream, cs, O(0), n, parity);
   else if (r8) hipLaunchKernelGGL((kb_rhs<T, E, 1, 8>), dim3(nb0), dim3(kThreads), bl.lds[0], bl.stream, cs, O(0), n, parity);
   else if (u2) hipLaunchKernelGGL((kb_rhs<T, E, 2, 16>), dim3(nb0), dim3(kThreads), bl.lds[0], bl.stream, cs, O(0), n, parity);
   else hipLaunchKernelGGL((kb_rhs<T, E, 1, 16>), dim3(nb0), dim3(kThreads), bl.lds[0], bl.stream, cs, O(0), n, parity);

@@ -41,10 +41,18 @@ def _make(chib, case, faces_seed):
     return st, T, C0, faces
 
 
-def test_batched_steps_equal_single_steps(chib):
+def _with_rhs_kernel(st, unroll):
+    sh = st.shapes()
+    sh[0][2] = unroll
+    st.set_shapes(sh)
+    return st
+
+
+@pytest.mark.parametrize("unroll", [1, 3])      # line-tiled and y-marching rhs
+def test_batched_steps_equal_single_steps(chib, unroll):
     cases = _cases()
-    singles = [_make(chib, c, 10 + i)[0] for i, c in enumerate(cases)]
-    members = [_make(chib, c, 10 + i)[0] for i, c in enumerate(cases)]
+    singles = [_with_rhs_kernel(_make(chib, c, 10 + i)[0], unroll) for i, c in enumerate(cases)]
+    members = [_with_rhs_kernel(_make(chib, c, 10 + i)[0], unroll) for i, c in enumerate(cases)]
     b = chib.Batch(members)
     print("[gpu] batch of", len(members), file=sys.stderr, flush=True)
     b.step(21)            # ten graph replays of two steps plus one direct step
@@ -70,7 +78,7 @@ def test_batch_against_oracle_after_tuning(chib):
     b = chib.Batch([m[0] for m in made])
     radix, unroll = b.tune(2)
     print("[gpu] batch tuned", radix, unroll, file=sys.stderr, flush=True)
-    assert all(r in (8, 16) for r in radix) and unroll in (1, 2)
+    assert all(r in (8, 16) for r in radix) and unroll in (1, 2, 3)
     b.step(40)
     b.sync()
     for case, (st, T, C0, faces) in zip(cases, made):

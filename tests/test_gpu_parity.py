@@ -271,6 +271,29 @@ def test_z_marching_rhs_variants(chib):
                 assert err <= 1e-11, (lt, radix, zc, err)
 
 
+@pytest.mark.parametrize("maker,steps", [(lambda: W.small_case(128, 64, kind="sin", theta_deg=50.0), 60),
+                                         (lambda: W.config2(1), 20), (lambda: W.config5(True, 120.0), 6)])
+def test_y_marching_rhs_2d(chib, maker, steps):
+    """The y-marching rhs kernel (2D, one, two and four columns per thread at nx = 128, 512 and
+    1024) with both FFT radices and every tile height matches the oracle step with flow."""
+    case = maker()
+    faces = _random_faces(case.grid, 9, 0.3)
+    st, orc, _ = _pair(chib, case, faces)
+    st.step(0)
+    blob = st.save()
+    orc.step(steps)
+    hi = {128: 5, 512: 3, 1024: 2}[case.grid.n[0]]
+    for lt in range(1, hi + 1):
+        for radix in (8, 16):
+            st.load(blob)
+            st.set_shapes([[lt, radix, 3], [3, 8, 1], [3, 8, 1], [3, 8, 1]])
+            assert st.shapes()[0] == [lt, radix, 3]
+            _say("y-march", case.name, lt, radix)
+            st.step(steps)
+            err = _linf(st.get(chib.FIELD_C), orc.C)
+            assert err <= 1e-11, (lt, radix, err)
+
+
 @pytest.mark.parametrize("i", range(6))
 def test_config2_full_length_5000_steps(chib, i):
     """Config 2 at its full length.  Over 5000 steps rounding differences are amplified while
