@@ -254,6 +254,7 @@ class OracleState:
             [np.array(f, dtype=np.float64, copy=True) for f in faces]
         self.CI = np.zeros(tables.n_ghost)
         self.step_count = 0
+        self.Rh = None          # rate of the previous explicit step
         self.initial_fill()
         self.Cp = self.C.copy()
 
@@ -390,9 +391,32 @@ class OracleState:
         """Helmholtz solution C* of this step on every cell, before any ghost overwrite."""
         return spectral_solve(self.rhs(), self.grid, self.alpha_s, self.a)
 
+    def explicit_rate(self) -> np.ndarray:
+        """Rate R^n of the explicit scheme (Eq. ExpCH, non-dimensional).
+
+        dC/dt = -div(u C) + (1/Pe) lap(phi) with phi the chemical potential of
+        Eq. Chemical-Potential (ghosts take the mirror value, dphi/dn = 0, as at the end
+        of section 4.2.2).  The advection is the conservative central form of the
+        semi-implicit path (equal to u . grad C for the divergence-free flows the paper
+        considers) evaluated on C^n; the mobility term is the paper's
+        (3/(2 sqrt2)) div(M grad phi) in the units of the non-dimensional equation.
+        """
+        prm = self.params
+        phi = chemical_potential(self.C, self.grid, self.T, prm.Cn)
+        return -advection(self.C, self.faces, self.grid) + laplacian(phi, self.grid) / prm.Pe
+
+    def explicit_provisional(self) -> np.ndarray:
+        """C^(n+1) = C^n + dt (3/2 R^n - 1/2 R^(n-1)) on every cell (second-order
+        Adams-Bashforth); the first step has no R^(n-1) and is a forward Euler step.
+        Records R^n for the next step."""
+        R = self.explicit_rate()
+        Rp = R if self.Rh is None else self.Rh
+        self.Rh = R
+        return self.C + self.params.dt * (1.5 * R - 0.5 * Rp)
+
     def step(self, nsteps: int = 1) -> None:
         for _ in range(nsteps):
-            P = self.provisional()
+            P = self.explicit_provisional() if self.params.explicit else self.provisional()
             Pf = P.reshape(-1)
             Pf[self.T.gidx] = 2.0 * self.C.reshape(-1)[self.T.gidx] - self.Cp.reshape(-1)[self.T.gidx]
             CG = self.fill_C(P, initial=False)

@@ -97,6 +97,7 @@ class Params:
     d2_cells: float = 0.0
     subgrid: int = 0           # 0: 100 per direction in 2D, 20 in 3D
     velocity_fill: bool = True
+    explicit: bool = False     # explicit Adams-Bashforth step instead of the semi-implicit one
 
 
 @dataclasses.dataclass
