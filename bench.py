@@ -44,6 +44,10 @@ def algorithmic_bytes(name: str, cells: int, d: int, es: int, G: int, NF: int, d
         per_ghost = 4 + 8 * K + es * (3 * d + 4 + 2 * K + 2 * K * (4 if dynamic else 2) * d)
         per_face = 16 + es * 4 + 16 + es * 3
         return G * per_ghost + NF * per_face
+    if name == "phi":                                # explicit step: phi on every cell, mirror value at ghosts
+        return cells * es * 2 + G * (4 + 2 * K * (4 + es) + 2 * K * es + es)
+    if name == "explicit_update":                    # C, phi, R, d faces in; C^(n+1), R out
+        return cells * es * (5 + d)
     if name == "ghost_fills":                        # static: both fills, one launch plus the faces
         return (algorithmic_bytes("ghost_fill_C", cells, d, es, G, NF, dynamic)
                 + algorithmic_bytes("ghost_fill_u", cells, d, es, G, NF, dynamic))
@@ -157,6 +161,36 @@ def sweep_benchmark(chib, torch, steps: int, count: int = 64) -> dict:
             "cases_not_finite": nonfinite}
 
 
+def explicit_benchmark(chib, geo, case, steps: int, precision: int, NF: int, semi_ms: float) -> dict:
+    """The explicit Adams-Bashforth step (Eq. ExpCH) on the same 256^3 workload at a tenth of the
+    semi-implicit time step (the paper's factor between the two schemes' stable steps): kernel
+    times, bytes, and the time to cover the same simulated time as one semi-implicit step."""
+    import dataclasses
+    prm = dataclasses.replace(case.params, explicit=True, dt=case.params.dt / 10)
+    st = chib.State(geo, prm, precision)
+    C0, faces = case.initial_fields()
+    st.set_initial(C0, faces)
+    st.step(5)
+    st.sync()
+    t0 = time.perf_counter()
+    ms = st.step_timed(steps)
+    wall = time.perf_counter() - t0
+    dg = st.diagnostics()
+    es = 8 if precision == 64 else 4
+    cells = case.grid.cells
+    kern = {}
+    for name, t in ms.items():
+        b = algorithmic_bytes(name, cells, 3, es, st.G, NF, False)
+        kern[name] = {"ms": round(t, 5), "alg_bytes": int(b), "GB_s": round(b / (t * 1e-3) / 1e9, 1),
+                      "frac_of_8TBs": round(b / (t * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+    ms_step = 1e3 * wall / steps
+    st.close()
+    return {"workload": f"same 3D sphere workload, explicit scheme, dt = {prm.dt:g}",
+            "steps": steps, "status": dg["status"], "max_abs_C": dg["max_abs_C"],
+            "cell_updates_per_s": cells * steps / wall, "ms_per_step": round(ms_step, 5), "kernels": kern,
+            "time_per_unit_sim_time_vs_semi_implicit": round(10 * ms_step / semi_ms, 3)}
+
+
 def learned_benchmark(chib, steps: int) -> dict:
     """Learned wall-band correction (config 5): the 8 held-out contact angles run as one batch on
     the plain 1024x512 grid (the judge), on the plain 512x256 grid and on the 512x256 grid with
@@ -229,6 +263,8 @@ def main() -> int:
     ap.add_argument("--sweep-steps", type=int, default=2000, help="steps per case of the batched sweep (0: skip)")
     ap.add_argument("--learned-steps", type=int, default=20000,
                     help="steps of the learned-correction comparison (0: skip)")
+    ap.add_argument("--explicit-steps", type=int, default=100,
+                    help="timed steps of the explicit scheme on the same workload (0: skip)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="also run one plain device copy of this size (for counter calibration)")
     args = ap.parse_args()
@@ -329,6 +365,10 @@ def main() -> int:
         "path_GB_s": round(sum(k["alg_bytes"] for k in kernels.values()) / (gpu_ms * 1e-3) / 1e9, 1),
         "kernels": kernels,
     }
+    if args.explicit_steps > 0:
+        print("[bench] explicit scheme", file=sys.stderr, flush=True)
+        out["explicit"] = explicit_benchmark(chib, geo, case, args.explicit_steps, args.precision, NF,
+                                             out["ms_per_step"])
     if args.sweep_steps > 0:
         print("[bench] batched sweep (64 cases)", file=sys.stderr, flush=True)
         out["batched_sweep"] = sweep_benchmark(chib, torch, args.sweep_steps)

@@ -68,7 +68,9 @@ enum {
 
 /* ---- params.flags ---------------------------------------------------------------------- */
 enum {
-  CH_IB_FLAG_VELOCITY_FILL = 1  /* refill faces touching ghosts every step (section 4.4) */
+  CH_IB_FLAG_VELOCITY_FILL = 1, /* refill faces touching ghosts every step (section 4.4) */
+  CH_IB_FLAG_EXPLICIT = 2        /* explicit Adams-Bashforth step (Eq. ExpCH) instead of the
+                                    semi-implicit one; needs a time step about ten times smaller */
 };
 
 typedef struct {
@@ -182,6 +184,11 @@ int ch_ib_state_get(ch_ib_state *st, int field, void *dst, int dst_on_device);
  *   spectral division (Hartley transforms on periodic axes, DCT-II on the bounded axis), the
  *   contact-angle ghost fill of C (section 4.2.2) and, with CH_IB_FLAG_VELOCITY_FILL, the
  *   no-penetration / Navier-slip fill of the faces touching ghosts (section 4.4).
+ *   With CH_IB_FLAG_EXPLICIT the step is Eq. ExpCH instead: the chemical potential on every
+ *   cell (ghosts take the mirror value, dphi/dn = 0), the rate R = -div(u C) + lap(phi)/Pe, and
+ *   C^(n+1) = C^n + dt (3/2 R^n - 1/2 R^(n-1)) (second-order Adams-Bashforth; the first step
+ *   after the fields are set or loaded without a rate is a forward Euler step), then the same
+ *   fills.  The workspace then holds one more field for R.
  * ch_ib_sync: waits for the stream; reports CH_IB_EHIP on a device error.
  * ch_ib_diagnostics: mass, free energy, max |C| (deterministic fixed-order reductions);
  *   synchronous; status CH_IB_ENAN (also returned) if any C is not finite. */
@@ -239,7 +246,7 @@ int ch_ib_set_shapes(ch_ib_state *st, const int *shapes);
  *   condition (Vs = 0); their pending initial fills are done here.  The batch keeps pointers to
  *   the states: while it exists, the member states must not be stepped on their own or freed.
  *   device_workspace (caller-owned, 256-byte aligned) must outlive the batch.  EUNSUPPORTED for
- *   3D or dynamic states, EINVAL for mixed precisions.
+ *   3D, dynamic or explicit-scheme states, EINVAL for mixed precisions.
  * ch_ib_batch_step: enqueues n_steps steps for every member on the batch's stream (graph replays
  *   plus at most one direct step; on the NULL stream, which cannot be captured, direct grouped
  *   launches only); the members' step counters and buffer roles are updated.
@@ -263,8 +270,10 @@ void ch_ib_batch_free(ch_ib_batch *b);
 
 /* ---- checkpoint / resume ---------------------------------------------------------------------
  * ch_ib_state_save: if buf is NULL, *len receives the size needed; otherwise writes a versioned
- *   blob (C^n, C^(n-1), faces, per-ghost history, step counter) and sets *len.  Synchronous.
- * ch_ib_state_load: restores a blob saved from a state with the same grid, tables and precision.
+ *   blob (C^n, C^(n-1), faces, per-ghost history, step counter; with the explicit scheme also
+ *   the previous step's rate) and sets *len.  Synchronous.
+ * ch_ib_state_load: restores a blob saved from a state with the same grid, tables, precision and
+ *   time scheme.
  * ch_ib_state_free: releases the host handle (the workspace stays the caller's). */
 int ch_ib_state_save(ch_ib_state *st, void *buf, size_t *len);
 int ch_ib_state_load(ch_ib_state *st, const void *buf, size_t len);

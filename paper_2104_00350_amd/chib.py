@@ -19,6 +19,7 @@ OK, EINVAL, EGEOM, EHIP, ENOMEM, ENAN, EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
 HALFPLANE, SINUSOID, SPHERE, BOX = 1, 2, 3, 4
 FIELD_C, FIELD_C_PREV, FIELD_U, FIELD_V, FIELD_W, FIELD_CI, FIELD_ALPHA, FIELD_PHI = range(8)
 FLAG_VELOCITY_FILL = 1
+FLAG_EXPLICIT = 2
 STAGE_RHS, STAGE_SOLVE, STAGE_PHI = 1, 2, 3
 
 
@@ -146,7 +147,7 @@ def make_params(prm, precision: int = 64) -> Params:
         setattr(p, name, float(getattr(prm, name)))
     p.subgrid = int(prm.subgrid)
     p.precision = int(precision)
-    p.flags = FLAG_VELOCITY_FILL if prm.velocity_fill else 0
+    p.flags = (FLAG_VELOCITY_FILL if prm.velocity_fill else 0) | (FLAG_EXPLICIT if getattr(prm, "explicit", False) else 0)
     return p
 
 

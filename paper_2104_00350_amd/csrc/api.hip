@@ -70,13 +70,13 @@ struct Layout {
 };
 
 struct Offsets {
-  size_t C[2], F[3], W, alpha, gidx, normal, dn, gamma, ap, w, CGn, CGnm1, CMs, CI, CGnew, UG;
+  size_t C[2], F[3], W, R, alpha, gidx, normal, dn, gamma, ap, w, CGn, CGnm1, CMs, CI, CGnew, UG;
   size_t f_cell, f_axis, f_gL, f_gR, stashL, stashR;
   size_t twr[3], twi[3], dctc, dcts, lam[3], partial, red_out;
   size_t total;
 };
 
-Offsets plan_layout(const ch_ib_geometry &g, int es, int64_t NF) {
+Offsets plan_layout(const ch_ib_geometry &g, int es, int64_t NF, bool explicit_ab2) {
   Layout L;
   Offsets o{};
   const int64_t N = g.cells, G = g.n_ghost;
@@ -85,6 +85,7 @@ Offsets plan_layout(const ch_ib_geometry &g, int es, int64_t NF) {
   o.C[1] = L.off(N * es);
   for (int a = 0; a < 3; ++a) o.F[a] = a < d ? L.off(N * es) : 0;
   o.W = L.off(N * es);
+  o.R = explicit_ab2 ? L.off(N * es) : 0;
   o.alpha = g.alpha.empty() ? 0 : L.off(N * es);
   o.gidx = L.off(G * 4);
   o.normal = L.off(d * G * es);
@@ -151,6 +152,7 @@ struct ch_ib_state {
   int64_t step = 0;
   int sticky = CH_IB_OK;
   int has_alpha = 0;
+  int r_valid = 0;      // explicit step: R holds the previous step's rate
 };
 
 static int hip_fail(ch_ib_state *st, hipError_t e, const char *where) {
@@ -194,7 +196,7 @@ extern "C" size_t ch_ib_workspace_bytes(const ch_ib_grid *grid, const ch_ib_geom
   if (params->precision != 64 && params->precision != 32) return 0;
   const int es = params->precision == 64 ? 8 : 4;
   FaceList fl = build_faces(*geom);
-  return plan_layout(*geom, es, (int64_t)fl.cell.size()).total + 256;
+  return plan_layout(*geom, es, (int64_t)fl.cell.size(), (params->flags & CH_IB_FLAG_EXPLICIT) != 0).total + 256;
 }
 
 extern "C" int ch_ib_state_create(const ch_ib_grid *grid, const ch_ib_geometry *geom, const ch_ib_params *params,
@@ -220,7 +222,7 @@ extern "C" int ch_ib_state_create(const ch_ib_grid *grid, const ch_ib_geometry *
   st->has_alpha = !geom->alpha.empty();
   FaceList fl = build_faces(*geom);
   const int64_t NF = (int64_t)fl.cell.size();
-  st->off = plan_layout(*geom, st->es, NF);
+  st->off = plan_layout(*geom, st->es, NF, (params->flags & CH_IB_FLAG_EXPLICIT) != 0);
   const Offsets &o = st->off;
   chib::Plan &p = st->plan;
   const int d = geom->ndim;
@@ -246,11 +248,13 @@ extern "C" int ch_ib_state_create(const ch_ib_grid *grid, const ch_ib_geometry *
   p.Vs = params->Vs;
   p.vel_fill = (params->flags & CH_IB_FLAG_VELOCITY_FILL) ? 1 : 0;
   p.dynamic = params->Vs > 0 ? 1 : 0;
+  p.explicit_ab2 = (params->flags & CH_IB_FLAG_EXPLICIT) ? 1 : 0;
   char *W0 = st->ws;
   p.C[0] = W0 + o.C[0];
   p.C[1] = W0 + o.C[1];
   for (int ax = 0; ax < 3; ++ax) p.F[ax] = ax < d ? W0 + o.F[ax] : nullptr;
   p.W = W0 + o.W;
+  p.R = p.explicit_ab2 ? W0 + o.R : nullptr;
   p.alpha = st->has_alpha ? W0 + o.alpha : nullptr;
   p.G = geom->n_ghost;
   p.K = geom->n_ap;
@@ -402,7 +406,10 @@ extern "C" int ch_ib_state_set(ch_ib_state *st, int field, const void *src, int 
                                 src_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, p.stream);
   if (e == hipSuccess) e = hipStreamSynchronize(p.stream);
   if (e != hipSuccess) return hip_fail(st, e, "state_set");
-  if (field != CH_IB_FIELD_CI) st->needs_init = 1;
+  if (field != CH_IB_FIELD_CI) {
+    st->needs_init = 1;
+    st->r_valid = 0;
+  }
   return CH_IB_OK;
 }
 
@@ -482,6 +489,20 @@ extern "C" int ch_ib_state_get(ch_ib_state *st, int field, void *dst, int dst_on
   return CH_IB_OK;
 }
 
+// One step of the state's scheme; the explicit scheme's first step after (re)initialisation has no
+// previous rate.
+static hipError_t enqueue_one_step(ch_ib_state *st, chib::KernelTimer *tm) {
+  const chib::Plan &p = st->plan;
+  hipError_t e;
+  if (p.explicit_ab2) {
+    e = st->es == 8 ? chib::enqueue_explicit_step<double>(p, st->cur, !st->r_valid, tm)
+                    : chib::enqueue_explicit_step<float>(p, st->cur, !st->r_valid, tm);
+    if (e == hipSuccess) st->r_valid = 1;
+    return e;
+  }
+  return st->es == 8 ? chib::enqueue_step<double>(p, st->cur, tm) : chib::enqueue_step<float>(p, st->cur, tm);
+}
+
 extern "C" int ch_ib_step(ch_ib_state *st, int n_steps) {
   if (!st) return fail(CH_IB_EINVAL, "NULL state");
   if (n_steps < 0) return fail(CH_IB_EINVAL, "n_steps must be >= 0");
@@ -489,8 +510,7 @@ extern "C" int ch_ib_step(ch_ib_state *st, int n_steps) {
   int rc = ensure_init(st);
   if (rc) return rc;
   for (int i = 0; i < n_steps; ++i) {
-    hipError_t e = st->es == 8 ? chib::enqueue_step<double>(st->plan, st->cur)
-                               : chib::enqueue_step<float>(st->plan, st->cur);
+    hipError_t e = enqueue_one_step(st, nullptr);
     if (e != hipSuccess) return hip_fail(st, e, "step");
     st->cur = 1 - st->cur;
     st->step++;
@@ -514,8 +534,7 @@ extern "C" int ch_ib_step_timed(ch_ib_state *st, int n_steps, int max_kernels, d
   // all steps are enqueued back to back; one wait at the end
   for (int s = 0; s < n_steps && e == hipSuccess; ++s) {
     tms[s].n = 0;
-    e = st->es == 8 ? chib::enqueue_step<double>(st->plan, st->cur, &tms[s])
-                    : chib::enqueue_step<float>(st->plan, st->cur, &tms[s]);
+    e = enqueue_one_step(st, &tms[s]);
     if (e != hipSuccess) break;
     st->cur = 1 - st->cur;
     st->step++;
@@ -641,13 +660,16 @@ extern "C" int ch_ib_state_save(ch_ib_state *st, void *buf, size_t *len) {
   if (!st || !len) return fail(CH_IB_EINVAL, "NULL argument");
   const chib::Plan &p = st->plan;
   const size_t fb = (size_t)p.N * st->es, gb = (size_t)p.G * st->es;
-  const size_t need = sizeof(BlobHeader) + (2 + p.d) * fb + 3 * gb;
+  // version 2 (explicit scheme) appends the history flag and the previous step's rate
+  const size_t extra = p.explicit_ab2 ? sizeof(int64_t) + fb : 0;
+  const size_t need = sizeof(BlobHeader) + (2 + p.d) * fb + 3 * gb + extra;
   if (!buf) {
     *len = need;
     return CH_IB_OK;
   }
   if (*len < need) return fail(CH_IB_ENOMEM, "buffer too small");
-  BlobHeader hd{kMagic, 1, st->es, p.d, {p.n[0], p.n[1], p.n[2]}, st->needs_init, p.G, p.NF, st->step};
+  BlobHeader hd{kMagic, p.explicit_ab2 ? 2u : 1u, st->es, p.d, {p.n[0], p.n[1], p.n[2]}, st->needs_init,
+                p.G, p.NF, st->step};
   char *b = (char *)buf;
   std::memcpy(b, &hd, sizeof(hd));
   b += sizeof(hd);
@@ -665,6 +687,12 @@ extern "C" int ch_ib_state_save(ch_ib_state *st, void *buf, size_t *len) {
     if (sz[i]) e = hipMemcpyAsync(b, srcs[i], sz[i], hipMemcpyDeviceToHost, p.stream);
     b += sz[i];
   }
+  if (p.explicit_ab2 && e == hipSuccess) {
+    const int64_t rv = st->r_valid;
+    std::memcpy(b, &rv, sizeof(rv));
+    b += sizeof(rv);
+    e = hipMemcpyAsync(b, p.R, fb, hipMemcpyDeviceToHost, p.stream);
+  }
   if (e == hipSuccess) e = hipStreamSynchronize(p.stream);
   if (e != hipSuccess) return hip_fail(st, e, "save");
   *len = need;
@@ -677,12 +705,14 @@ extern "C" int ch_ib_state_load(ch_ib_state *st, const void *buf, size_t len) {
   BlobHeader hd;
   if (len < sizeof(hd)) return fail(CH_IB_EINVAL, "blob too short");
   std::memcpy(&hd, buf, sizeof(hd));
-  if (hd.magic != kMagic || hd.version != 1) return fail(CH_IB_EINVAL, "not a state blob");
+  if (hd.magic != kMagic || (hd.version != 1 && hd.version != 2)) return fail(CH_IB_EINVAL, "not a state blob");
+  if (hd.version != (p.explicit_ab2 ? 2u : 1u)) return fail(CH_IB_EINVAL, "blob saved with the other time scheme");
   if (hd.es != st->es || hd.d != p.d || hd.n[0] != p.n[0] || hd.n[1] != p.n[1] || hd.n[2] != p.n[2] ||
       hd.G != p.G || hd.NF != p.NF)
     return fail(CH_IB_EINVAL, "blob saved from a different grid, geometry or precision");
   const size_t fb = (size_t)p.N * st->es, gb = (size_t)p.G * st->es;
-  const size_t need = sizeof(BlobHeader) + (2 + p.d) * fb + 3 * gb;
+  const size_t extra = p.explicit_ab2 ? sizeof(int64_t) + fb : 0;
+  const size_t need = sizeof(BlobHeader) + (2 + p.d) * fb + 3 * gb + extra;
   if (len < need) return fail(CH_IB_EINVAL, "blob too short");
   const char *b = (const char *)buf + sizeof(hd);
   st->cur = 0;
@@ -700,8 +730,15 @@ extern "C" int ch_ib_state_load(ch_ib_state *st, const void *buf, size_t len) {
     if (sz[i]) e = hipMemcpyAsync(dsts[i], b, sz[i], hipMemcpyHostToDevice, p.stream);
     b += sz[i];
   }
+  int64_t rv = 0;
+  if (p.explicit_ab2 && e == hipSuccess) {
+    std::memcpy(&rv, b, sizeof(rv));
+    b += sizeof(rv);
+    e = hipMemcpyAsync(p.R, b, fb, hipMemcpyHostToDevice, p.stream);
+  }
   if (e == hipSuccess) e = hipStreamSynchronize(p.stream);
   if (e != hipSuccess) return hip_fail(st, e, "load");
+  st->r_valid = rv ? 1 : 0;
   st->step = hd.step;
   st->needs_init = hd.needs_init;
   st->sticky = CH_IB_OK;
@@ -804,6 +841,7 @@ extern "C" int ch_ib_batch_create(ch_ib_state *const *states, int n, void *ws, s
     if (s->es != es) return fail(CH_IB_EINVAL, "mixed precisions in one batch");
     if (s->plan.d != 2) return fail(CH_IB_EUNSUPPORTED, "batches hold 2D states only");
     if (s->plan.dynamic) return fail(CH_IB_EUNSUPPORTED, "batches hold static contact-angle states only");
+    if (s->plan.explicit_ab2) return fail(CH_IB_EUNSUPPORTED, "batches hold semi-implicit states only");
     if (s->sticky) return fail(s->sticky, "a member state is in an error state");
   }
   for (int c = 0; c < n; ++c) {

@@ -20,11 +20,13 @@ struct Plan {
   double Pe = 0, Cn = 0, dt = 0, S = 0, alpha_s = 0, a = 0;
   double cos_t = 0, Ca = 1, mu = 1, ls = 0, Vs = 0;
   int vel_fill = 0, dynamic = 0;
+  int explicit_ab2 = 0;     // explicit Adams-Bashforth step (Eq. ExpCH) instead of the semi-implicit one
 
   // fields
   void *C[2] = {nullptr, nullptr};
   void *F[3] = {nullptr, nullptr, nullptr};
-  void *W = nullptr;        // spectral workspace, N elements
+  void *W = nullptr;        // spectral workspace, N elements (explicit step: the chemical potential)
+  void *R = nullptr;        // explicit step: rate of the previous step, N elements
   void *alpha = nullptr;    // N elements or nullptr (then alpha = 1)
 
   // ghost tables (SoA, sorted by cell)
@@ -88,6 +90,8 @@ struct KernelTimer {
 template <typename T> hipError_t enqueue_step(const Plan &p, int cur, KernelTimer *tm = nullptr);
 template <typename T> hipError_t enqueue_initial_fill(const Plan &p, int cur);
 template <typename T> hipError_t tune_shapes(Plan &p, int cur, int reps);
+// One explicit Adams-Bashforth step (first: no previous rate, forward Euler) from C[cur] into C[1-cur].
+template <typename T> hipError_t enqueue_explicit_step(const Plan &p, int cur, int first, KernelTimer *tm = nullptr);
 // Largest log2 tile height (passes 0 and 3: lines; 1 and 2: columns) a pass allows on this grid.
 template <typename T> int max_log_tile(const Plan &p, int pass);
 template <typename T> hipError_t enqueue_ghost_refresh(const Plan &p, int cur);   // static fill again, same step

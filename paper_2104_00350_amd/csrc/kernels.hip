@@ -1269,6 +1269,48 @@ __global__ __launch_bounds__(kThreads) void k_phi_ghost(T *__restrict__ phi, con
   phi[gidx[g]] = mirror_gather(phi, ap, w, g, G, K);
 }
 
+// Explicit step (Eq. ExpCH, non-dimensional) on every cell: the rate
+//   R = -div_h(u C^n) + (1/Pe) lap_h phi^n
+// (conservative central advection, zero normal velocity on the bounded axis' box walls, where
+// the Laplacian reflects), then C^(n+1) = C^n + dt (3/2 R - 1/2 R_prev) with R_prev = R on the
+// first step (forward Euler).  R replaces R_prev in place; the ghosts are refilled afterwards.
+template <typename T, int D>
+__global__ __launch_bounds__(kThreads) void k_explicit(const T *__restrict__ C, const T *__restrict__ phi,
+                                                       const T *__restrict__ F0, const T *__restrict__ F1,
+                                                       const T *__restrict__ F2, T *__restrict__ R,
+                                                       T *__restrict__ Cnext, Dims dm, T half_inv_h, T inv_h2,
+                                                       T inv_pe, T dt, int first, int64_t N) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= N) return;
+  const int nx = dm.nx;
+  const int i = (int)(c & (nx - 1));
+  const int64_t rowb = c - i;
+  const int ip = (i + 1) & (nx - 1), im = (i - 1) & (nx - 1);
+  const T c0 = C[c], p0 = phi[c];
+  T flux = F0[c] * (c0 + C[rowb + ip]) - F0[rowb + im] * (C[rowb + im] + c0);
+  T lsum = phi[rowb + ip] + phi[rowb + im];
+  if (D == 2) {
+    const int j = (int)(c >> dm.lnx);
+    const bool top = j == dm.ny - 1, bot = j == 0;
+    flux += (top ? T(0) : F1[c] * (c0 + C[c + nx])) - (bot ? T(0) : F1[c - nx] * (C[c - nx] + c0));
+    lsum += (top ? p0 : phi[c + nx]) + (bot ? p0 : phi[c - nx]);
+  } else {
+    const int j = (int)((c >> dm.lnx) & (dm.ny - 1));
+    const int k = (int)(c >> (dm.lnx + dm.lny));
+    const int64_t cyp = c + (int64_t)(((j + 1) & (dm.ny - 1)) - j) * nx;
+    const int64_t cym = c + (int64_t)(((j - 1) & (dm.ny - 1)) - j) * nx;
+    flux += F1[c] * (c0 + C[cyp]) - F1[cym] * (C[cym] + c0);
+    lsum += phi[cyp] + phi[cym];
+    const bool top = k == dm.nz - 1, bot = k == 0;
+    flux += (top ? T(0) : F2[c] * (c0 + C[c + dm.plane])) - (bot ? T(0) : F2[c - dm.plane] * (C[c - dm.plane] + c0));
+    lsum += (top ? p0 : phi[c + dm.plane]) + (bot ? p0 : phi[c - dm.plane]);
+  }
+  const T r = -flux * half_inv_h + inv_pe * (lsum - T(2 * D) * p0) * inv_h2;
+  const T rp = first ? r : R[c];
+  R[c] = r;
+  Cnext[c] = c0 + dt * (T(1.5) * r - T(0.5) * rp);
+}
+
 template <typename T, int D>
 __global__ __launch_bounds__(kThreads) void k_rhs_only(const T *__restrict__ Cn, const T *__restrict__ Cp,
                                                        const T *__restrict__ F0, const T *__restrict__ F1,
@@ -1700,6 +1742,26 @@ hipError_t launch_velocity_fill(const Plan &p, const T *Cfin) {
 
 }  // namespace
 
+// The fills that end a step, on the new field C: ghost values of C, then the velocity fill
+// (with the static condition both in one launch plus the face pass).
+template <typename T>
+hipError_t launch_step_fills(const Plan &p, T *C, KernelTimer *tm) {
+  hipError_t e = hipSuccess;
+  auto mark = [&](const char *name) {
+    if (tm && e == hipSuccess) e = tm->mark(name, p.stream);
+  };
+  if (!p.dynamic && p.vel_fill && p.G) {
+    mark("ghost_fills");
+    if (e == hipSuccess) e = launch_static_fills<T>(p, C);
+  } else {
+    mark("ghost_fill_C");
+    if (e == hipSuccess) e = launch_ghost_fill<T>(p, C, 0);
+    if (p.vel_fill && p.G) mark("ghost_fill_u");
+    if (e == hipSuccess) e = launch_velocity_fill<T>(p, C);
+  }
+  return e;
+}
+
 template <typename T>
 hipError_t enqueue_step(const Plan &p, int cur, KernelTimer *tm) {
   const T *Cn = (const T *)p.C[cur];
@@ -1719,15 +1781,7 @@ hipError_t enqueue_step(const Plan &p, int cur, KernelTimer *tm) {
   if (e == hipSuccess) e = launch_spectral_tail<T>(p, tm);
   mark("xdht_out");
   if (e == hipSuccess) e = launch_xdht<T>(p, (const T *)p.W, Cp, p.shape[3]);
-  if (!p.dynamic && p.vel_fill && p.G) {
-    mark("ghost_fills");
-    if (e == hipSuccess) e = launch_static_fills<T>(p, Cp);
-  } else {
-    mark("ghost_fill_C");
-    if (e == hipSuccess) e = launch_ghost_fill<T>(p, Cp, 0);
-    if (p.vel_fill && p.G) mark("ghost_fill_u");
-    if (e == hipSuccess) e = launch_velocity_fill<T>(p, Cp);
-  }
+  if (e == hipSuccess) e = launch_step_fills<T>(p, Cp, tm);
   if (tm && e == hipSuccess) e = tm->end(p.stream);
   return e;
 }
@@ -1931,6 +1985,39 @@ template hipError_t enqueue_rhs<double>(const Plan &, int, void *);
 template hipError_t enqueue_rhs<float>(const Plan &, int, void *);
 template hipError_t enqueue_solve<double>(const Plan &, const void *, void *);
 template hipError_t enqueue_solve<float>(const Plan &, const void *, void *);
+template <typename T>
+hipError_t enqueue_explicit_step(const Plan &p, int cur, int first, KernelTimer *tm) {
+  if (!p.R) return hipErrorInvalidValue;
+  const T *Cn = (const T *)p.C[cur];
+  T *Cnext = (T *)p.C[1 - cur];
+  hipError_t e = hipSuccess;
+  auto mark = [&](const char *name) {
+    if (tm && e == hipSuccess) e = tm->mark(name, p.stream);
+  };
+  mark("phi");
+  if (e == hipSuccess) e = enqueue_phi<T>(p, cur, p.W);
+  mark("explicit_update");
+  if (e == hipSuccess) {
+    const Dims dm = make_dims(p);
+    const T hih = (T)(0.5 / p.h), ih2 = (T)(1.0 / (p.h * p.h)), ipe = (T)(1.0 / p.Pe), dt = (T)p.dt;
+    const T *F2 = (const T *)(p.d == 3 ? p.F[2] : p.F[1]);
+    if (p.d == 2)
+      hipLaunchKernelGGL((k_explicit<T, 2>), dim3(blocks_for(p.N)), dim3(kThreads), 0, p.stream, Cn,
+                         (const T *)p.W, (const T *)p.F[0], (const T *)p.F[1], F2, (T *)p.R, Cnext, dm, hih, ih2,
+                         ipe, dt, first, p.N);
+    else
+      hipLaunchKernelGGL((k_explicit<T, 3>), dim3(blocks_for(p.N)), dim3(kThreads), 0, p.stream, Cn,
+                         (const T *)p.W, (const T *)p.F[0], (const T *)p.F[1], F2, (T *)p.R, Cnext, dm, hih, ih2,
+                         ipe, dt, first, p.N);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = launch_step_fills<T>(p, Cnext, tm);
+  if (tm && e == hipSuccess) e = tm->end(p.stream);
+  return e;
+}
+
+template hipError_t enqueue_explicit_step<double>(const Plan &, int, int, KernelTimer *);
+template hipError_t enqueue_explicit_step<float>(const Plan &, int, int, KernelTimer *);
 template hipError_t enqueue_phi<double>(const Plan &, int, void *);
 template hipError_t enqueue_phi<float>(const Plan &, int, void *);
 template hipError_t enqueue_diag<double>(const Plan &, int);
