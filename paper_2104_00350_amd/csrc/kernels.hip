@@ -1311,6 +1311,164 @@ __global__ __launch_bounds__(kThreads) void k_explicit(const T *__restrict__ C, 
   Cnext[c] = c0 + dt * (T(1.5) * r - T(0.5) * rp);
 }
 
+// 3D z-marching forms of k_phi and k_explicit (2.5D blocking): a workgroup owns a 64 x 4 tile of
+// (x, y) columns and a chunk of 2^zc_log planes; each thread keeps the values of planes z-1, z,
+// z+1 of its own column in registers and the tile's plane z (with its one-cell x/y halo) sits in
+// LDS, so every plane is read from memory once instead of three times.  Same sums in the same
+// order as the one-cell-per-thread kernels.  Requires nx % 64 == 0 and ny % 4 == 0.
+constexpr int kZmTx = 64, kZmTy = 4;
+
+// Halo value of plane base zb that thread (tx, ty) supplies to the tile (x, then y neighbours);
+// threads inside the tile supply none (returns their own cell, unused).
+template <typename T>
+__device__ __forceinline__ T zm_halo(const T *__restrict__ f, int64_t zb, int x, int y, int tx, int ty,
+                                     const Dims &dm) {
+  const int nx = dm.nx, ny = dm.ny;
+  if (tx == 0) return f[zb + ((x - 1) & (nx - 1)) + (int64_t)nx * y];
+  if (tx == kZmTx - 1) return f[zb + ((x + 1) & (nx - 1)) + (int64_t)nx * y];
+  return T(0);
+}
+template <typename T>
+__device__ __forceinline__ T zm_halo_y(const T *__restrict__ f, int64_t zb, int x, int y, int ty, const Dims &dm) {
+  const int nx = dm.nx, ny = dm.ny;
+  if (ty == 0) return f[zb + x + (int64_t)nx * ((y - 1) & (ny - 1))];
+  if (ty == kZmTy - 1) return f[zb + x + (int64_t)nx * ((y + 1) & (ny - 1))];
+  return T(0);
+}
+template <typename T>
+__device__ __forceinline__ void zm_tile_store(T (*s)[kZmTx + 2], int tx, int ty, T own, T hx, T hy) {
+  s[ty + 1][tx + 1] = own;
+  if (tx == 0) s[ty + 1][0] = hx;
+  if (tx == kZmTx - 1) s[ty + 1][kZmTx + 1] = hx;
+  if (ty == 0) s[0][tx + 1] = hy;
+  if (ty == kZmTy - 1) s[kZmTy + 1][tx + 1] = hy;
+}
+
+// Planes are taken kZmU at a time: their loads (own column and halo) are issued together, so a
+// thread has kZmU requests in flight per field instead of one.
+constexpr int kZmU = 4;
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_phi_zm(const T *__restrict__ C, T *__restrict__ phi, Dims dm, T cn2,
+                                                     T inv_h2, int zc_log) {
+  __shared__ T s[2][kZmTy + 2][kZmTx + 2];
+  const int nbx = dm.nx / kZmTx, nby = dm.ny / kZmTy;
+  const int t = blockIdx.x;
+  const int bx = t % nbx, by = (t / nbx) % nby, bz = t / (nbx * nby);
+  const int tx = threadIdx.x & (kZmTx - 1), ty = threadIdx.x / kZmTx;
+  const int x = bx * kZmTx + tx, y = by * kZmTy + ty;
+  const int z0 = bz << zc_log;
+  const int64_t col = x + (int64_t)dm.nx * y;
+  auto zb = [&](int z) { return (int64_t)(z < 0 ? 0 : (z >= dm.nz ? dm.nz - 1 : z)) * dm.plane; };
+  T cm = C[zb(z0 - 1) + col], c0 = C[zb(z0) + col];
+  for (int zg = 0; zg < (1 << zc_log); zg += kZmU) {
+    const int zs = z0 + zg;
+    T cz[kZmU], hx[kZmU], hy[kZmU];
+#pragma unroll
+    for (int u = 0; u < kZmU; ++u) {
+      cz[u] = C[zb(zs + u + 1) + col];
+      hx[u] = zm_halo(C, zb(zs + u), x, y, tx, ty, dm);
+      hy[u] = zm_halo_y(C, zb(zs + u), x, y, ty, dm);
+    }
+#pragma unroll
+    for (int u = 0; u < kZmU; ++u) {
+      const int z = zs + u;
+      const T cp = cz[u];
+      T (*sb)[kZmTx + 2] = s[u & 1];
+      zm_tile_store(sb, tx, ty, c0, hx[u], hy[u]);
+      __syncthreads();   // this slot was last read two planes ago, before the previous barrier
+      T sum = sb[ty + 1][tx + 2] + sb[ty + 1][tx];
+      sum += sb[ty + 2][tx + 1] + sb[ty][tx + 1];
+      sum += (z < dm.nz - 1 ? cp : c0) + (z > 0 ? cm : c0);
+      const T lap = (sum - T(6) * c0) * inv_h2;
+      phi[zb(z) + col] = c0 * c0 * c0 - c0 - cn2 * lap;
+      cm = c0;
+      c0 = cp;
+    }
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_explicit_zm(const T *__restrict__ C, const T *__restrict__ phi,
+                                                          const T *__restrict__ F0, const T *__restrict__ F1,
+                                                          const T *__restrict__ F2, T *__restrict__ R,
+                                                          T *__restrict__ Cnext, Dims dm, T half_inv_h, T inv_h2,
+                                                          T inv_pe, T dt, int first, int zc_log) {
+  __shared__ T sc[2][kZmTy + 2][kZmTx + 2], sp[2][kZmTy + 2][kZmTx + 2];
+  const int nx = dm.nx, ny = dm.ny;
+  const int nbx = nx / kZmTx, nby = ny / kZmTy;
+  const int t = blockIdx.x;
+  const int bx = t % nbx, by = (t / nbx) % nby, bz = t / (nbx * nby);
+  const int tx = threadIdx.x & (kZmTx - 1), ty = threadIdx.x / kZmTx;
+  const int x = bx * kZmTx + tx, y = by * kZmTy + ty;
+  const int z0 = bz << zc_log;
+  const int64_t col = x + (int64_t)nx * y;
+  const int64_t colxm = ((x - 1) & (nx - 1)) + (int64_t)nx * y;
+  const int64_t colym = x + (int64_t)nx * ((y - 1) & (ny - 1));
+  auto zb = [&](int z) { return (int64_t)(z < 0 ? 0 : (z >= dm.nz ? dm.nz - 1 : z)) * dm.plane; };
+  T cm = C[zb(z0 - 1) + col], c0 = C[zb(z0) + col];
+  T pm = phi[zb(z0 - 1) + col], p0 = phi[zb(z0) + col];
+  T f2m = F2[zb(z0 - 1) + col];   // the face below plane z0 (unused at the bottom wall)
+  for (int zg = 0; zg < (1 << zc_log); zg += kZmU) {
+    const int zs = z0 + zg;
+    T cz[kZmU], pz[kZmU], hcx[kZmU], hcy[kZmU], hpx[kZmU], hpy[kZmU];
+    T f0z[kZmU], f0mz[kZmU], f1z[kZmU], f1mz[kZmU], f2z[kZmU], rz[kZmU];
+#pragma unroll
+    for (int u = 0; u < kZmU; ++u) {
+      const int64_t b = zb(zs + u), b1 = zb(zs + u + 1);
+      cz[u] = C[b1 + col];
+      pz[u] = phi[b1 + col];
+      f0z[u] = F0[b + col];
+      f0mz[u] = F0[b + colxm];
+      f1z[u] = F1[b + col];
+      f1mz[u] = F1[b + colym];
+      f2z[u] = F2[b + col];
+      rz[u] = R[b + col];
+      hcx[u] = zm_halo(C, b, x, y, tx, ty, dm);
+      hcy[u] = zm_halo_y(C, b, x, y, ty, dm);
+      hpx[u] = zm_halo(phi, b, x, y, tx, ty, dm);
+      hpy[u] = zm_halo_y(phi, b, x, y, ty, dm);
+    }
+#pragma unroll
+    for (int u = 0; u < kZmU; ++u) {
+      const int z = zs + u;
+      const int64_t c = zb(z) + col;
+      const T cp = cz[u], pp = pz[u];
+      const T f0 = f0z[u], f0m = f0mz[u], f1 = f1z[u], f1m = f1mz[u], f2 = f2z[u];
+      const T rprev = rz[u];
+      T (*sbc)[kZmTx + 2] = sc[u & 1];
+      T (*sbp)[kZmTx + 2] = sp[u & 1];
+      zm_tile_store(sbc, tx, ty, c0, hcx[u], hcy[u]);
+      zm_tile_store(sbp, tx, ty, p0, hpx[u], hpy[u]);
+      __syncthreads();   // these slots were last read two planes ago, before the previous barrier
+      const bool top = z == dm.nz - 1, bot = z == 0;
+      T flux = f0 * (c0 + sbc[ty + 1][tx + 2]) - f0m * (sbc[ty + 1][tx] + c0);
+      T lsum = sbp[ty + 1][tx + 2] + sbp[ty + 1][tx];
+      flux += f1 * (c0 + sbc[ty + 2][tx + 1]) - f1m * (sbc[ty][tx + 1] + c0);
+      lsum += sbp[ty + 2][tx + 1] + sbp[ty][tx + 1];
+      flux += (top ? T(0) : f2 * (c0 + cp)) - (bot ? T(0) : f2m * (cm + c0));
+      lsum += (top ? p0 : pp) + (bot ? p0 : pm);
+      const T r = -flux * half_inv_h + inv_pe * (lsum - T(6) * p0) * inv_h2;
+      const T rp = first ? r : rprev;
+      R[c] = r;
+      Cnext[c] = c0 + dt * (T(1.5) * r - T(0.5) * rp);
+      cm = c0;
+      c0 = cp;
+      pm = p0;
+      p0 = pp;
+      f2m = f2;
+    }
+  }
+}
+
+inline bool stencil_zm_ok(const Plan &p) {
+  return p.d == 3 && p.n[0] % kZmTx == 0 && p.n[1] % kZmTy == 0 && p.n[2] >= 16;   // chunks of 16 planes
+}
+inline int stencil_zm_log(const Plan &p) { return p.logn[2] < 4 ? p.logn[2] : 4; }   // >= log2(kZmU) below
+inline unsigned stencil_zm_blocks(const Plan &p) {
+  return (unsigned)((p.n[0] / kZmTx) * (p.n[1] / kZmTy) * (p.n[2] >> stencil_zm_log(p)));
+}
+
 template <typename T, int D>
 __global__ __launch_bounds__(kThreads) void k_rhs_only(const T *__restrict__ Cn, const T *__restrict__ Cp,
                                                        const T *__restrict__ F0, const T *__restrict__ F1,
@@ -1941,6 +2099,9 @@ hipError_t enqueue_phi(const Plan &p, int cur, void *out) {
   if (p.d == 2)
     hipLaunchKernelGGL((k_phi<T, 2>), dim3(blocks_for(p.N)), dim3(kThreads), 0, p.stream, (const T *)p.C[cur],
                        (T *)out, dm, cn2, ih2, p.N);
+  else if (stencil_zm_ok(p))
+    hipLaunchKernelGGL((k_phi_zm<T>), dim3(stencil_zm_blocks(p)), dim3(kThreads), 0, p.stream, (const T *)p.C[cur],
+                       (T *)out, dm, cn2, ih2, stencil_zm_log(p));
   else
     hipLaunchKernelGGL((k_phi<T, 3>), dim3(blocks_for(p.N)), dim3(kThreads), 0, p.stream, (const T *)p.C[cur],
                        (T *)out, dm, cn2, ih2, p.N);
@@ -2005,6 +2166,10 @@ hipError_t enqueue_explicit_step(const Plan &p, int cur, int first, KernelTimer 
       hipLaunchKernelGGL((k_explicit<T, 2>), dim3(blocks_for(p.N)), dim3(kThreads), 0, p.stream, Cn,
                          (const T *)p.W, (const T *)p.F[0], (const T *)p.F[1], F2, (T *)p.R, Cnext, dm, hih, ih2,
                          ipe, dt, first, p.N);
+    else if (stencil_zm_ok(p))
+      hipLaunchKernelGGL((k_explicit_zm<T>), dim3(stencil_zm_blocks(p)), dim3(kThreads), 0, p.stream, Cn,
+                         (const T *)p.W, (const T *)p.F[0], (const T *)p.F[1], F2, (T *)p.R, Cnext, dm, hih, ih2,
+                         ipe, dt, first, stencil_zm_log(p));
     else
       hipLaunchKernelGGL((k_explicit<T, 3>), dim3(blocks_for(p.N)), dim3(kThreads), 0, p.stream, Cn,
                          (const T *)p.W, (const T *)p.F[0], (const T *)p.F[1], F2, (T *)p.R, Cnext, dm, hih, ih2,

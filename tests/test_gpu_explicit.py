@@ -86,6 +86,20 @@ def test_explicit_3d(chib):
     assert _linf(st.get(chib.FIELD_C), orc.C) <= 1e-9
 
 
+def test_explicit_3d_z_marching_kernels(chib):
+    """At nx a multiple of 64 the 3D phi and update kernels march in z over 64 x 4 tiles."""
+    from oracle.solver import chemical_potential
+    case = _explicit(W.small_case_3d(64), 1e-5)
+    st, orc = _pair(chib, case, _faces(case.grid, 4, 0.2))
+    phi = st.stage(chib.STAGE_PHI)
+    ref = chemical_potential(orc.C, case.grid, orc.T, case.params.Cn)
+    assert _linf(phi, ref) <= 1e-11 * np.max(np.abs(ref))
+    _say("explicit 3d 64^3")
+    st.step(20)
+    orc.step(20)
+    assert _linf(st.get(chib.FIELD_C), orc.C) <= 1e-9
+
+
 def test_explicit_fp32_tracks_the_fp64_oracle(chib):
     case = _explicit(W.config1(), 2e-5)
     st, orc = _pair(chib, case, precision=32)
