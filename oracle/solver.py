@@ -432,6 +432,29 @@ class OracleState:
         return diagnostics(self.grid, self.params, self.T.alpha, self.C)
 
 
+def fill_scalar(f: np.ndarray, T: GhostTables, a: float, b: float, g) -> np.ndarray:
+    """Ghost values of any scalar field from the mixed condition a f + b df/dn = g at the wall.
+
+    The ghost-cell procedure of section 4.2.2 applied to a general boundary condition (the
+    abstract and the conclusions note that it imposes Dirichlet, Neumann or mixed conditions on
+    any field).  With the wall value and the normal derivative taken from the ghost G and the
+    mirror point M as in Eq. interpolationAtWall and Eq. ProjectingToNT,
+        f_I = (gamma f_G + f_M) / (gamma + 1),   (df/dn)_I = (f_M - f_G) / ((1 + gamma) dn),
+    the condition is linear in f_G:
+        f_G = ((gamma + 1) g - f_M (a + b/dn)) / (a gamma - b/dn).
+    b = 0 is Dirichlet (f_G = ((gamma+1) g - f_M)/gamma, Eq. UpdateC with f_I = g); a = 0 is
+    Neumann (f_G = f_M - (gamma+1) dn g; g = 0 gives the mirror value used for phi).  g is a
+    scalar or one value per ghost.  Returns a copy of f with the ghosts replaced.
+    """
+    out = np.array(f, dtype=np.float64, copy=True)
+    of = out.reshape(-1)
+    fM = mirror_value(np.asarray(f, dtype=np.float64).reshape(-1), T)
+    gam, dn = T.gamma, T.dn
+    g = np.broadcast_to(np.asarray(g, dtype=np.float64), fM.shape)
+    of[T.gidx] = ((gam + 1.0) * g - fM * (a + b / dn)) / (a * gam - b / dn)
+    return out
+
+
 def chemical_potential(C: np.ndarray, grid: Grid, T: GhostTables, Cn: float) -> np.ndarray:
     """phi = C^3 - C - Cn^2 lap_h C on all cells; at ghosts the mirror value (dphi/dn = 0).
 

@@ -204,3 +204,66 @@ def test_mass_identity_before_ghost_overwrite(kind):
         ref = (4.0 / 3.0) * st.C.sum() - (1.0 / 3.0) * st.Cp.sum()
         assert abs(Cs.sum() - ref) <= 1e-11 * np.abs(st.C).sum()
         st.step(1)
+
+
+# ---- general mixed boundary condition for any scalar ----------------------------------------
+
+def _flat_on_centre_tables():
+    """Wall on a cell face with d1 = 1.5h, d2 = 1h: M, IP1 and IP2 fall on cell centres, so the
+    mirror value of a linear field is exact (pinned above)."""
+    g = W.Grid((32, 16), (0.0, 0.0), (2.0, 1.0))
+    h = g.h
+    prm = W.Params(Cn=0.05, Pe=10.0, d1_cells=1.5, d2_cells=1.0)
+    T = build_tables(g, [W.Shape(W.HALFPLANE, (0.0, 4 * h, 0.0, 0.0, 1.0, 0.0))], prm)
+    y = (np.arange(16) + 0.5) * h
+    x = (np.arange(32) + 0.5) * h
+    return g, T, x, y
+
+
+@pytest.mark.parametrize("a,b", [(1.0, 0.0), (0.0, 1.0), (-2.5, 1.0), (0.7, -0.3)])
+def test_mixed_condition_reproduces_a_linear_field(a, b):
+    """For f = 0.3 + 1.7 y - 0.4 x the wall value and normal derivative are known in closed form;
+    the ghost value that imposes a f_I + b df/dn = g with that g is the field's own value at G."""
+    from oracle.solver import fill_scalar
+    g_, T, x, y = _flat_on_centre_tables()
+    f = 0.3 + 1.7 * y[:, None] - 0.4 * x[None, :]
+    Ix, Iy = T.points["I"]
+    Gx, Gy = T.points["G"]
+    nx_, ny_ = T.normal
+    fI = 0.3 + 1.7 * Iy - 0.4 * Ix
+    dfdn = -0.4 * nx_ + 1.7 * ny_
+    wrong = f.copy()
+    wrong.reshape(-1)[T.gidx] = 99.0                    # the ghosts' previous values play no role
+    out = fill_scalar(wrong, T, a, b, a * fI + b * dfdn)
+    assert np.max(np.abs(out.reshape(-1)[T.gidx] - (0.3 + 1.7 * Gy - 0.4 * Gx))) <= 1e-12
+    keep = np.ones(g_.cells, dtype=bool)
+    keep[T.gidx] = False
+    assert np.array_equal(out.reshape(-1)[keep], wrong.reshape(-1)[keep])
+
+
+@pytest.mark.parametrize("kind", ["sin", "circle"])
+def test_mixed_condition_holds_at_the_wall_on_curved_walls(kind):
+    """On curved walls the filled ghost and the mirror value satisfy the condition at I exactly,
+    with I's value and derivative formed from G and M by the two-point formulas."""
+    from oracle.solver import fill_scalar
+    case = W.small_case(64, 32, kind=kind)
+    T = build_tables(case.grid, case.shapes, case.params)
+    rng = np.random.default_rng(4)
+    f = rng.standard_normal(case.grid.shape)
+    gv = rng.standard_normal(T.n_ghost)
+    for a, b in ((1.0, 0.0), (0.0, 1.0), (-3.0, 0.5)):
+        out = fill_scalar(f, T, a, b, gv)
+        fG = out.reshape(-1)[T.gidx]
+        fM = mirror_value(f.reshape(-1), T)
+        fI = (T.gamma * fG + fM) / (T.gamma + 1.0)
+        dfdn = (fM - fG) / ((1.0 + T.gamma) * T.dn)
+        assert np.max(np.abs(a * fI + b * dfdn - gv)) <= 1e-9 * (1.0 + np.max(np.abs(b / T.dn)))
+
+
+def test_neumann_zero_is_the_mirror_value():
+    from oracle.solver import fill_scalar
+    case = W.small_case(64, 32, kind="sin")
+    T = build_tables(case.grid, case.shapes, case.params)
+    f = np.random.default_rng(2).standard_normal(case.grid.shape)
+    out = fill_scalar(f, T, 0.0, 1.0, 0.0)
+    assert np.max(np.abs(out.reshape(-1)[T.gidx] - mirror_value(f.reshape(-1), T))) <= 1e-14
