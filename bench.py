@@ -191,6 +191,34 @@ def explicit_benchmark(chib, geo, case, steps: int, precision: int, NF: int, sem
             "time_per_unit_sim_time_vs_semi_implicit": round(10 * ms_step / semi_ms, 3)}
 
 
+def scalar_fill_benchmark(chib, st, case, reps: int = 50) -> dict:
+    """Mixed-condition ghost fill of an arbitrary scalar (Robin, per-ghost g) on the 256^3 ghost set,
+    timed with HIP events on the stream it is enqueued on."""
+    import ctypes
+    import numpy as np
+    import torch
+    f = torch.tensor(np.random.default_rng(1).standard_normal(case.grid.cells), dtype=torch.float64, device="cuda")
+    gv = torch.zeros(st.G, dtype=torch.float64, device="cuda")
+    lib = chib.lib
+    call = lambda: chib.check(lib.ch_ib_scalar_fill(st.h, ctypes.c_void_p(f.data_ptr()), -2.5, 1.0, 0.0,
+                                                    ctypes.c_void_p(gv.data_ptr())))
+    call()
+    st.sync()
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        call()
+    e1.record(stream)
+    e1.synchronize()
+    us = e0.elapsed_time(e1) * 1e3 / reps
+    K = 7
+    per_ghost = 4 + 2 * K * (4 + 8) + 2 * K * 8 + 2 * 8 + 8 + 8   # tables, gathers, dn, gamma, g, write
+    b = st.G * per_ghost
+    return {"what": "ghost fill of a scalar under a f + b df/dn = g (Robin, per-ghost g), host checks included",
+            "ghosts": st.G, "us_per_call": round(us, 2), "alg_bytes": b, "GB_s": round(b / (us * 1e-6) / 1e9, 1)}
+
+
 def learned_benchmark(chib, steps: int) -> dict:
     """Learned wall-band correction (config 5): the 8 held-out contact angles run as one batch on
     the plain 1024x512 grid (the judge), on the plain 512x256 grid and on the 512x256 grid with
@@ -365,6 +393,7 @@ def main() -> int:
         "path_GB_s": round(sum(k["alg_bytes"] for k in kernels.values()) / (gpu_ms * 1e-3) / 1e9, 1),
         "kernels": kernels,
     }
+    out["scalar_fill"] = scalar_fill_benchmark(chib, st, case)
     if args.explicit_steps > 0:
         print("[bench] explicit scheme", file=sys.stderr, flush=True)
         out["explicit"] = explicit_benchmark(chib, geo, case, args.explicit_steps, args.precision, NF,

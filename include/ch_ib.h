@@ -204,6 +204,24 @@ int ch_ib_diagnostics(ch_ib_state *st, ch_ib_diag *out);
 enum { CH_IB_STAGE_RHS = 1, CH_IB_STAGE_SOLVE = 2, CH_IB_STAGE_PHI = 3 };
 int ch_ib_stage(ch_ib_state *st, int stage, const void *in_device, void *out_device);
 
+/* ---- ghost fill of any scalar under a mixed wall condition ------------------------------------
+ * The ghost-cell procedure of section 4.2.2 applied to a general boundary condition, as the
+ * abstract and the conclusions propose (Dirichlet, Neumann or mixed conditions on any field):
+ * for a field f on the state's grid, every ghost value is set so that
+ *     a f_I + b (df/dn)_I = g     at the wall,
+ * with f_I = (gamma f_G + f_M)/(gamma + 1) and (df/dn)_I = (f_M - f_G)/((1 + gamma) dn) formed from
+ * the ghost and its mirror value (Eqs. extrapolation, interpolationAtWall, ProjectingToNT; n into
+ * the fluid), i.e. f_G = ((gamma + 1) g - f_M (a + b/dn)) / (a gamma - b/dn).  b = 0: Dirichlet;
+ * a = 0: Neumann (g = 0 gives the mirror value).
+ * field_device: the state's element type, one value per cell, x fastest; only the ghost cells are
+ *   written (the averaging points are fluid cells, never ghosts).  Caller-owned.
+ * g_ghost_device: NULL for the uniform g, else one value of g per ghost in the ghost order of the
+ *   geometry (ch_ib_geometry_export), the state's element type.
+ * Enqueued on the state's stream; returns without waiting.  EINVAL if field_device is NULL, a, b or
+ * g is not finite, or a gamma - b/dn vanishes at some ghost (the condition does not fix it there). */
+int ch_ib_scalar_fill(ch_ib_state *st, void *field_device, double a, double b, double g,
+                      const void *g_ghost_device);
+
 /* ---- measurement ------------------------------------------------------------------------------
  * ch_ib_step_timed: enqueues n_steps (1..4096) steps exactly as ch_ib_step does, with a HIP event
  *   recorded on the state's stream between consecutive kernels, then waits once.  ms_out[k]

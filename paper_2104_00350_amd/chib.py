@@ -88,6 +88,7 @@ def _load():
         "ch_ib_get_shapes": (i32, [vp, C.POINTER(C.c_int)]),
         "ch_ib_set_shapes": (i32, [vp, C.POINTER(C.c_int)]),
         "ch_ib_stage": (i32, [vp, i32, vp, vp]),
+        "ch_ib_scalar_fill": (i32, [vp, vp, C.c_double, C.c_double, C.c_double, vp]),
         "ch_ib_state_save": (i32, [vp, vp, C.POINTER(C.c_size_t)]),
         "ch_ib_state_load": (i32, [vp, vp, C.c_size_t]),
         "ch_ib_state_free": (None, [vp]),
@@ -354,6 +355,28 @@ class State:
             ip = C.c_void_p(t.data_ptr())
         check(lib.ch_ib_stage(self.h, stage, ip, C.c_void_p(out.data_ptr())))
         return out.cpu().numpy().reshape(tuple(reversed(self.n)))
+
+    def scalar_fill(self, field, a: float, b: float, g: float = 0.0, g_ghost=None):
+        """Ghost values of `field` (one value per cell) under a f + b df/dn = g at the wall (uniform g,
+        or one value per ghost in `g_ghost`).  A device tensor of the state's dtype is filled in place
+        and returned; anything else is copied to the device, filled and returned as a numpy array."""
+        torch = self.torch
+        in_place = isinstance(field, torch.Tensor) and field.device.type == "cuda" and field.dtype == self.torch_dtype \
+            and field.is_contiguous() and field.numel() == self.cells
+        t = field if in_place else torch.as_tensor(np.ascontiguousarray(field, dtype=np.float64).reshape(-1)).to(
+            device=self.device, dtype=self.torch_dtype).contiguous()
+        gp = None
+        if g_ghost is not None:
+            gt = torch.as_tensor(np.ascontiguousarray(g_ghost, dtype=np.float64).reshape(-1)).to(
+                device=self.device, dtype=self.torch_dtype).contiguous()
+            if gt.numel() != self.G:
+                raise ChibError(EINVAL, "g_ghost needs one value per ghost")
+            gp = C.c_void_p(gt.data_ptr())
+        check(lib.ch_ib_scalar_fill(self.h, C.c_void_p(t.data_ptr()), float(a), float(b), float(g), gp))
+        check(lib.ch_ib_sync(self.h))
+        if in_place:
+            return field
+        return t.cpu().numpy().astype(np.float64).reshape(tuple(reversed(self.n)))
 
     def save(self) -> bytes:
         n = C.c_size_t()

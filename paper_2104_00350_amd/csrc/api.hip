@@ -648,6 +648,24 @@ extern "C" int ch_ib_stage(ch_ib_state *st, int stage, const void *in_device, vo
   return CH_IB_OK;
 }
 
+extern "C" int ch_ib_scalar_fill(ch_ib_state *st, void *field_device, double a, double b, double g,
+                                 const void *g_ghost_device) {
+  if (!st || !field_device) return fail(CH_IB_EINVAL, "NULL state or field");
+  if (!std::isfinite(a) || !std::isfinite(b) || !std::isfinite(g)) return fail(CH_IB_EINVAL, "non-finite a, b or g");
+  const chib::Plan &p = st->plan;
+  // the condition fixes f_G only where a gamma - b/dn does not vanish
+  for (int64_t i = 0; i < p.G; ++i) {
+    const double dn = st->geom.dn[i], gm = st->geom.gamma[i];
+    const double den = a * gm - b / dn, scale = std::fabs(a) * gm + std::fabs(b) / dn;
+    if (!(scale > 0) || std::fabs(den) <= 1e-12 * scale)
+      return fail(CH_IB_EINVAL, "a gamma - b/dn vanishes at ghost " + std::to_string(i) + ": the condition does not fix it");
+  }
+  hipError_t e = st->es == 8 ? chib::enqueue_scalar_fill<double>(p, field_device, a, b, g, g_ghost_device)
+                             : chib::enqueue_scalar_fill<float>(p, field_device, a, b, g, g_ghost_device);
+  if (e != hipSuccess) return hip_fail(st, e, "scalar_fill");
+  return CH_IB_OK;
+}
+
 namespace {
 struct BlobHeader {
   uint32_t magic, version;

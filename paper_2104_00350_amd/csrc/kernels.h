@@ -98,6 +98,9 @@ template <typename T> hipError_t enqueue_ghost_refresh(const Plan &p, int cur); 
 template <typename T> hipError_t enqueue_rhs(const Plan &p, int cur, void *out);
 template <typename T> hipError_t enqueue_solve(const Plan &p, const void *in, void *out);
 template <typename T> hipError_t enqueue_phi(const Plan &p, int cur, void *out);
+// Ghost values of the scalar field f (N elements) under a f + b df/dn = g (g_ghost: G values or null).
+template <typename T>
+hipError_t enqueue_scalar_fill(const Plan &p, void *f, double a, double b, double g, const void *g_ghost);
 template <typename T> hipError_t enqueue_diag(const Plan &p, int cur);
 
 // One grouped step over a batch of 2D cases (see the batched kernels).

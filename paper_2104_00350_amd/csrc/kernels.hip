@@ -1269,6 +1269,24 @@ __global__ __launch_bounds__(kThreads) void k_phi_ghost(T *__restrict__ phi, con
   phi[gidx[g]] = mirror_gather(phi, ap, w, g, G, K);
 }
 
+// Ghost fill of any scalar under the mixed condition a f + b df/dn = g at the wall: the ghost-cell
+// procedure of section 4.2.2 with a general boundary condition.  With f_I and (df/dn)_I formed
+// from the ghost and the mirror value as for C, f_G = ((gamma+1) g - f_M (a + b/dn)) / (a gamma - b/dn).
+// The averaging points are fluid cells, never ghosts, so reads and writes do not overlap.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_scalar_fill(T *__restrict__ f, const int *__restrict__ gidx,
+                                                          const int *__restrict__ ap, const T *__restrict__ w,
+                                                          const T *__restrict__ dn, const T *__restrict__ gam,
+                                                          const T *__restrict__ gv, T g0, T a, T b, int64_t G,
+                                                          int K) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= G) return;
+  const T fM = mirror_gather(f, ap, w, g, G, K);
+  const T gg = gv ? gv[g] : g0;
+  const T d = dn[g], gm = gam[g];
+  f[gidx[g]] = ((gm + T(1)) * gg - fM * (a + b / d)) / (a * gm - b / d);
+}
+
 // Explicit step (Eq. ExpCH, non-dimensional) on every cell: the rate
 //   R = -div_h(u C^n) + (1/Pe) lap_h phi^n
 // (conservative central advection, zero normal velocity on the bounded axis' box walls, where
@@ -2181,6 +2199,17 @@ hipError_t enqueue_explicit_step(const Plan &p, int cur, int first, KernelTimer 
   return e;
 }
 
+template <typename T>
+hipError_t enqueue_scalar_fill(const Plan &p, void *f, double a, double b, double g, const void *g_ghost) {
+  if (!p.G) return hipSuccess;
+  hipLaunchKernelGGL((k_scalar_fill<T>), dim3(blocks_for(p.G)), dim3(kThreads), 0, p.stream, (T *)f, p.gidx, p.ap,
+                     (const T *)p.w, (const T *)p.dn, (const T *)p.gamma, (const T *)g_ghost, (T)g, (T)a, (T)b, p.G,
+                     p.K);
+  return hipGetLastError();
+}
+
+template hipError_t enqueue_scalar_fill<double>(const Plan &, void *, double, double, double, const void *);
+template hipError_t enqueue_scalar_fill<float>(const Plan &, void *, double, double, double, const void *);
 template hipError_t enqueue_explicit_step<double>(const Plan &, int, int, KernelTimer *);
 template hipError_t enqueue_explicit_step<float>(const Plan &, int, int, KernelTimer *);
 template hipError_t enqueue_phi<double>(const Plan &, int, void *);

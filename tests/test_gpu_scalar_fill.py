@@ -1,0 +1,71 @@
+"""GPU parity of the mixed-condition ghost fill of any scalar (ch_ib_scalar_fill) against the FP64
+oracle's fill_scalar: one operation on the same seeded field, held to 1e-12 relative (FP64)."""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle.geometry import build_tables
+from oracle.solver import fill_scalar
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def chib():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2104_00350_amd import chib as m
+    return m
+
+
+def _state(chib, case, precision=64):
+    T = build_tables(case.grid, case.shapes, case.params)
+    g = case.grid
+    geo = chib.Geometry.from_tables(g.n, g.lo, g.hi, T.gidx, T.normal, T.dn, T.gamma, T.ap, T.w, T.alpha)
+    st = chib.State(geo, case.params, precision)
+    st.set_initial(case.initial_fields()[0])
+    return st, T
+
+
+@pytest.mark.parametrize("maker", [lambda: W.small_case(64, 32, kind="sin"), lambda: W.small_case(64, 32, kind="circle"),
+                                   lambda: W.small_case(64, 32, kind="tilted"), lambda: W.small_case_3d(32)])
+@pytest.mark.parametrize("a,b", [(1.0, 0.0), (0.0, 1.0), (-2.5, 1.0)])
+def test_scalar_fill_matches_the_oracle(chib, maker, a, b):
+    case = maker()
+    st, T = _state(chib, case)
+    rng = np.random.default_rng(7)
+    f = rng.standard_normal(case.grid.shape)
+    gv = rng.standard_normal(T.n_ghost)
+    ref = fill_scalar(f, T, a, b, gv)
+    out = st.scalar_fill(f, a, b, g_ghost=gv)
+    assert np.max(np.abs(out - ref)) <= 1e-12 * np.max(np.abs(ref))
+    keep = np.ones(case.grid.cells, dtype=bool)
+    keep[T.gidx] = False
+    assert np.array_equal(out.reshape(-1)[keep], f.reshape(-1)[keep])
+    ref = fill_scalar(f, T, a, b, 0.25)                     # uniform g
+    assert np.max(np.abs(st.scalar_fill(f, a, b, 0.25) - ref)) <= 1e-12 * np.max(np.abs(ref))
+
+
+def test_scalar_fill_in_place_on_a_device_tensor_and_fp32(chib):
+    case = W.small_case(64, 32, kind="sin")
+    st, T = _state(chib, case)
+    f = np.random.default_rng(3).standard_normal(case.grid.shape)
+    t = torch.tensor(f.reshape(-1), dtype=torch.float64, device="cuda")
+    assert st.scalar_fill(t, 0.0, 1.0) is t
+    ref = fill_scalar(f, T, 0.0, 1.0, 0.0)
+    assert np.max(np.abs(t.cpu().numpy() - ref.reshape(-1))) <= 1e-12 * np.max(np.abs(ref))
+    s32, _ = _state(chib, case, precision=32)
+    out = s32.scalar_fill(f, -2.5, 1.0, 0.5)
+    ref = fill_scalar(f, T, -2.5, 1.0, 0.5)
+    assert np.max(np.abs(out - ref)) <= 1e-5 * np.max(np.abs(ref))
+
+
+def test_scalar_fill_rejects_conditions_that_fix_nothing(chib):
+    case = W.small_case(64, 32, kind="sin")
+    st, _ = _state(chib, case)
+    f = np.zeros(case.grid.shape)
+    for a, b in ((0.0, 0.0), (float("nan"), 1.0)):
+        with pytest.raises(chib.ChibError) as e:
+            st.scalar_fill(f, a, b)
+        assert e.value.code == chib.EINVAL
