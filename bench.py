@@ -301,6 +301,7 @@ def main() -> int:
         print(json.dumps({"error": "this build runs on exactly one GPU; multi-GPU runs are not part of it"}))
         return 2
 
+    import numpy as np
     import torch
     import workloads as W
     from paper_2104_00350_amd import chib
@@ -394,6 +395,15 @@ def main() -> int:
         "kernels": kernels,
     }
     out["scalar_fill"] = scalar_fill_benchmark(chib, st, case)
+    # geometry preprocessing (one-time, not in the step metric): host builder vs the device builder
+    chib.Geometry.build_device(g.n, g.lo, g.hi, case.shapes, case.params)      # loads its kernels
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    geo_dev = chib.Geometry.build_device(g.n, g.lo, g.hi, case.shapes, case.params)
+    t_dev = time.perf_counter() - t0
+    same = all(np.array_equal(a, b) for a, b in zip(geo_dev.export().values(), tabs.values()))
+    out["geometry"] = {"host_builder_s": round(t_geom, 4), "device_builder_s": round(t_dev, 4),
+                       "ghosts": st.G, "device_tables_equal_host": same}
     if args.explicit_steps > 0:
         print("[bench] explicit scheme", file=sys.stderr, flush=True)
         out["explicit"] = explicit_benchmark(chib, geo, case, args.explicit_steps, args.precision, NF,

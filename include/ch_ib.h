@@ -154,6 +154,22 @@ int ch_ib_geometry_build(const ch_ib_grid *grid, const ch_ib_shape *shapes, int 
                          const ch_ib_params *params, ch_ib_geometry **out);
 int ch_ib_geometry_import(const ch_ib_grid *grid, const ch_ib_ghost_tables *tables,
                           ch_ib_geometry **out);
+
+/* Geometry preprocessing on the GPU: the tables of ch_ib_geometry_build (same readings, same
+ * sequence of operations, no contraction of multiplies and adds), computed with one thread per
+ * cell for the volume fraction and the ghost list and one per ghost for the rest, returned as an
+ * ordinary host geometry object.  Integer tables and the doubles match the host builder bit for bit
+ * except where a sinusoid's sine from the device math library differs in its last bit.
+ * ch_ib_geometry_device_bytes: device scratch the builder needs for this grid (0 on a bad grid);
+ *   it holds per-ghost arrays for up to cells/8 + 1024 ghosts.
+ * ch_ib_geometry_build_device: device_scratch (caller-owned, 256-byte aligned, >= that many
+ *   bytes) is used on hip_stream (a hipStream_t; NULL = default stream) and free again on return;
+ *   synchronous.  At most 8 shapes.  Same errors as ch_ib_geometry_build, plus ENOMEM for a small
+ *   scratch or more ghosts than it holds and EHIP on a device error. */
+size_t ch_ib_geometry_device_bytes(const ch_ib_grid *grid);
+int ch_ib_geometry_build_device(const ch_ib_grid *grid, const ch_ib_shape *shapes, int n_shapes,
+                                const ch_ib_params *params, void *device_scratch, size_t bytes, void *hip_stream,
+                                ch_ib_geometry **out);
 int ch_ib_geometry_export(const ch_ib_geometry *geom, ch_ib_ghost_tables *dst);
 int ch_ib_geometry_count(const ch_ib_geometry *geom, int64_t *n_ghost, int *n_ap);
 void ch_ib_geometry_free(ch_ib_geometry *geom);
@@ -218,7 +234,8 @@ int ch_ib_stage(ch_ib_state *st, int stage, const void *in_device, void *out_dev
  * g_ghost_device: NULL for the uniform g, else one value of g per ghost in the ghost order of the
  *   geometry (ch_ib_geometry_export), the state's element type.
  * Enqueued on the state's stream; returns without waiting.  EINVAL if field_device is NULL, a, b or
- * g is not finite, or a gamma - b/dn vanishes at some ghost (the condition does not fix it there). */
+ * g is not finite, a = b = 0, or a gamma - b/dn = (a d1 - b)/dn vanishes (b/a within the range of
+ * d1 = gamma dn over the ghosts), where the condition does not fix the ghost value. */
 int ch_ib_scalar_fill(ch_ib_state *st, void *field_device, double a, double b, double g,
                       const void *g_ghost_device);
 

@@ -21,7 +21,9 @@ HIP_FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-munsafe-fp
              "-I", INCLUDE, "-I", CSRC]
 HOST_FLAGS = ["-O2", "-std=c++17", "-fPIC", "-ffp-contract=off", "-pthread", "-I", INCLUDE, "-I", CSRC]
 
-HIP_SOURCES = ["kernels.hip", "api.hip", "learned.hip"]
+HIP_SOURCES = ["kernels.hip", "api.hip", "learned.hip", "geometry_device.hip"]
+# the device geometry builder repeats the host builder's arithmetic operation for operation
+EXTRA_FLAGS = {"geometry_device.hip": ["-ffp-contract=off"]}
 HOST_SOURCES = ["geometry.cpp"]
 
 
@@ -39,7 +41,7 @@ def build(verbose: bool = False) -> str:
     for src in HIP_SOURCES:
         obj = os.path.join(BUILD, src + ".o")
         objs.append(obj)
-        jobs.append([HIPCC, *HIP_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj])
+        jobs.append([HIPCC, *HIP_FLAGS, *EXTRA_FLAGS.get(src, []), "-c", os.path.join(CSRC, src), "-o", obj])
     for src in HOST_SOURCES:
         obj = os.path.join(BUILD, src + ".o")
         objs.append(obj)

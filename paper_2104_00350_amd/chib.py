@@ -88,6 +88,8 @@ def _load():
         "ch_ib_get_shapes": (i32, [vp, C.POINTER(C.c_int)]),
         "ch_ib_set_shapes": (i32, [vp, C.POINTER(C.c_int)]),
         "ch_ib_stage": (i32, [vp, i32, vp, vp]),
+        "ch_ib_geometry_device_bytes": (C.c_size_t, [vp]),
+        "ch_ib_geometry_build_device": (i32, [vp, vp, i32, vp, vp, C.c_size_t, vp, C.POINTER(vp)]),
         "ch_ib_scalar_fill": (i32, [vp, vp, C.c_double, C.c_double, C.c_double, vp]),
         "ch_ib_state_save": (i32, [vp, vp, C.POINTER(C.c_size_t)]),
         "ch_ib_state_load": (i32, [vp, vp, C.c_size_t]),
@@ -182,6 +184,28 @@ class Geometry:
         p = make_params(prm)
         out = C.c_void_p()
         check(lib.ch_ib_geometry_build(C.byref(g), sh, len(shapes), C.byref(p), C.byref(out)))
+        return cls(out.value, g)
+
+    @classmethod
+    def build_device(cls, n, lo, hi, shapes, prm, device: str = "cuda:0", stream=None) -> "Geometry":
+        """The same tables computed on the GPU (ch_ib_geometry_build_device), in a torch-owned
+        scratch buffer that is released afterwards."""
+        import torch
+        g = make_grid(n, lo, hi)
+        sh = make_shapes(shapes)
+        p = make_params(prm)
+        nbytes = lib.ch_ib_geometry_device_bytes(C.byref(g))
+        if not nbytes:      # a bad grid: the builder itself reports why
+            check(lib.ch_ib_geometry_build_device(C.byref(g), sh, len(shapes), C.byref(p), None, 0, None,
+                                                  C.byref(C.c_void_p())))
+        buf = torch.empty(nbytes, dtype=torch.uint8, device=device)
+        ptr = (buf.data_ptr() + 255) // 256 * 256
+        st = stream if stream is not None else torch.cuda.current_stream(device)
+        out = C.c_void_p()
+        check(lib.ch_ib_geometry_build_device(C.byref(g), sh, len(shapes), C.byref(p), C.c_void_p(ptr),
+                                              nbytes - (ptr - buf.data_ptr()), C.c_void_p(st.cuda_stream),
+                                              C.byref(out)))
+        del buf
         return cls(out.value, g)
 
     @classmethod

@@ -153,6 +153,7 @@ struct ch_ib_state {
   int sticky = CH_IB_OK;
   int has_alpha = 0;
   int r_valid = 0;      // explicit step: R holds the previous step's rate
+  double d1_min = 0, d1_max = 0;   // range of gamma dn = d1 over the ghosts (mixed-condition checks)
 };
 
 static int hip_fail(ch_ib_state *st, hipError_t e, const char *where) {
@@ -369,6 +370,14 @@ extern "C" int ch_ib_state_create(const ch_ib_grid *grid, const ch_ib_geometry *
   }
   st->geom.alpha.clear();
   st->geom.alpha.shrink_to_fit();
+  if (G) {
+    st->d1_min = st->d1_max = geom->gamma[0] * geom->dn[0];
+    for (int64_t i = 1; i < G; ++i) {
+      const double v = geom->gamma[i] * geom->dn[i];
+      st->d1_min = std::min(st->d1_min, v);
+      st->d1_max = std::max(st->d1_max, v);
+    }
+  }
   *out = st;
   return CH_IB_OK;
 }
@@ -653,12 +662,13 @@ extern "C" int ch_ib_scalar_fill(ch_ib_state *st, void *field_device, double a, 
   if (!st || !field_device) return fail(CH_IB_EINVAL, "NULL state or field");
   if (!std::isfinite(a) || !std::isfinite(b) || !std::isfinite(g)) return fail(CH_IB_EINVAL, "non-finite a, b or g");
   const chib::Plan &p = st->plan;
-  // the condition fixes f_G only where a gamma - b/dn does not vanish
-  for (int64_t i = 0; i < p.G; ++i) {
-    const double dn = st->geom.dn[i], gm = st->geom.gamma[i];
-    const double den = a * gm - b / dn, scale = std::fabs(a) * gm + std::fabs(b) / dn;
-    if (!(scale > 0) || std::fabs(den) <= 1e-12 * scale)
-      return fail(CH_IB_EINVAL, "a gamma - b/dn vanishes at ghost " + std::to_string(i) + ": the condition does not fix it");
+  // the condition fixes f_G only where a gamma - b/dn = (a d1 - b)/dn does not vanish, with
+  // d1 = gamma dn the intersect-to-mirror distance (one value per geometry up to rounding)
+  if (a == 0.0 && b == 0.0) return fail(CH_IB_EINVAL, "a and b are both zero: the condition fixes nothing");
+  if (p.G && a != 0.0) {
+    const double r = b / a;
+    if (r >= st->d1_min * (1.0 - 1e-9) && r <= st->d1_max * (1.0 + 1e-9))
+      return fail(CH_IB_EINVAL, "a d1 = b: the condition does not fix the ghost values");
   }
   hipError_t e = st->es == 8 ? chib::enqueue_scalar_fill<double>(p, field_device, a, b, g, g_ghost_device)
                              : chib::enqueue_scalar_fill<float>(p, field_device, a, b, g, g_ghost_device);

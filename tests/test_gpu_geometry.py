@@ -1,0 +1,79 @@
+"""GPU geometry preprocessing (ch_ib_geometry_build_device) against the FP64 oracle's tables:
+integer tables (ghost list, averaging points) and the volume fraction bit for bit, normals,
+distances and weights within 1e-12; and against the host builder bit for bit on every table
+(the config-3 sphere at 256^3 included)."""
+import sys
+import time
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle.geometry import build_tables
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def chib():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2104_00350_amd import chib as m
+    return m
+
+
+CASES = [lambda: W.config1(), lambda: W.config2(0), lambda: W.config2(5),
+         lambda: W.small_case(64, 32, kind="circle"), lambda: W.small_case(64, 32, kind="tilted"),
+         lambda: W.small_case_3d(32), lambda: W.config4_cases(4)[3]]
+
+
+@pytest.mark.parametrize("maker", CASES)
+def test_device_geometry_matches_the_oracle_and_the_host_builder(chib, maker):
+    c = maker()
+    g = c.grid
+    print("[gpu] device geometry", c.name, file=sys.stderr, flush=True)
+    dev = chib.Geometry.build_device(g.n, g.lo, g.hi, c.shapes, c.params).export()
+    T = build_tables(g, c.shapes, c.params)
+    assert np.array_equal(dev["gidx"], T.gidx)
+    assert np.array_equal(dev["ap"], T.ap)
+    assert np.array_equal(dev["alpha"], T.alpha.reshape(-1))
+    for key, ref in (("normal", T.normal), ("dn", T.dn), ("gamma", T.gamma), ("w", T.w)):
+        assert np.max(np.abs(dev[key] - ref)) <= 1e-12 * max(1.0, np.max(np.abs(ref))), key
+    host = chib.Geometry.build(g.n, g.lo, g.hi, c.shapes, c.params).export()
+    for key in ("gidx", "ap", "alpha"):
+        assert np.array_equal(dev[key], host[key]), key
+    # the sine of a sinusoid comes from the device math library and may differ from the host's
+    # in its last bit, which moves the bisected intersect point by an ulp
+    sinusoid = any(sh.kind == W.SINUSOID for sh in c.shapes)
+    for key in ("normal", "dn", "gamma", "w"):
+        if sinusoid:
+            assert np.max(np.abs(dev[key] - host[key])) <= 1e-13 * max(1.0, np.max(np.abs(host[key]))), key
+        else:
+            assert np.array_equal(dev[key], host[key]), key
+
+
+def test_device_geometry_of_the_256_sphere_equals_the_host_builder(chib):
+    c = W.config3(256)
+    g = c.grid
+    t0 = time.perf_counter()
+    dev = chib.Geometry.build_device(g.n, g.lo, g.hi, c.shapes, c.params)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    host = chib.Geometry.build(g.n, g.lo, g.hi, c.shapes, c.params)
+    t2 = time.perf_counter()
+    print(f"[gpu] 256^3 sphere geometry: device {t1 - t0:.3f} s, host {t2 - t1:.3f} s", file=sys.stderr, flush=True)
+    a, b = dev.export(), host.export()
+    for key in ("gidx", "ap", "alpha", "normal", "dn", "gamma", "w"):
+        assert np.array_equal(a[key], b[key]), key
+
+
+def test_device_geometry_errors(chib):
+    g = W.Grid((16, 8), (0.0, 0.0), (1.0, 0.5))
+    prm = W.Params(Cn=0.05, Pe=10.0)
+    with pytest.raises(chib.ChibError) as e:      # a ghost in the first layer of the bounded axis
+        chib.Geometry.build_device(g.n, g.lo, g.hi, [W.Shape(W.HALFPLANE, (0.0, 0.05, 0.0, 0.0, 1.0, 0.0))], prm)
+    assert e.value.code == chib.EGEOM
+    with pytest.raises(chib.ChibError) as e:
+        chib.Geometry.build_device((12, 8), (0.0, 0.0), (1.5, 1.0), [], prm)
+    assert e.value.code == chib.EUNSUPPORTED

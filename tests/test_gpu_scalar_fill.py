@@ -65,7 +65,8 @@ def test_scalar_fill_rejects_conditions_that_fix_nothing(chib):
     case = W.small_case(64, 32, kind="sin")
     st, _ = _state(chib, case)
     f = np.zeros(case.grid.shape)
-    for a, b in ((0.0, 0.0), (float("nan"), 1.0)):
+    d1 = 2.0 * case.grid.h                                # the default intersect-to-mirror distance
+    for a, b in ((0.0, 0.0), (float("nan"), 1.0), (1.0, d1), (-2.0, -2.0 * d1)):
         with pytest.raises(chib.ChibError) as e:
             st.scalar_fill(f, a, b)
         assert e.value.code == chib.EINVAL
