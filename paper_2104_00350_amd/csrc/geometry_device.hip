@@ -145,9 +145,11 @@ __device__ int64_t lin_of(const DevShapes &S, const int *ijk) {
   return ijk[0] + (int64_t)S.n[0] * (ijk[1] + (int64_t)S.n[1] * ijk[2]);
 }
 
-// P1-P2: centre solid mask and volume fraction by counting subgrid points (cut cells only).
-__global__ __launch_bounds__(kGeomThreads) void k_gd_alpha(GeomArgs A, double *__restrict__ alpha,
-                                                           unsigned char *__restrict__ csolid) {
+// P1: centre solid mask; a cell no shape can cut gets its volume fraction (0 or 1) here, a cut
+// cell is flagged for the subgrid count.
+__global__ __launch_bounds__(kGeomThreads) void k_gd_classify(GeomArgs A, double *__restrict__ alpha,
+                                                              unsigned char *__restrict__ csolid,
+                                                              unsigned char *__restrict__ cutf) {
   const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= A.N) return;
   const DevShapes &S = A.S;
@@ -160,28 +162,50 @@ __global__ __launch_bounds__(kGeomThreads) void k_gd_alpha(GeomArgs A, double *_
   csolid[c] = cs ? 1 : 0;
   bool cut = false;
   for (int i = 0; i < S.n_shapes; ++i) cut = cut || may_cut(S, i, xc, A.h);
-  if (!cut) {
-    alpha[c] = cs ? 0.0 : 1.0;
-    return;
-  }
+  cutf[c] = cut ? 1 : 0;
+  if (!cut) alpha[c] = cs ? 0.0 : 1.0;
+}
+
+// P2: volume fraction of the cut cells by counting subgrid points, one 64-lane wave per cut cell
+// (the lanes share its sub^d points; the count is an integer, so its order does not matter).
+__global__ __launch_bounds__(kGeomThreads) void k_gd_subgrid(GeomArgs A, const int *__restrict__ cutlist,
+                                                             int64_t n_cut, double *__restrict__ alpha) {
+  const int lane = threadIdx.x & 63;
+  const int64_t item = (int64_t)blockIdx.x * (kGeomThreads / 64) + (threadIdx.x >> 6);
+  if (item >= n_cut) return;   // whole waves leave together
+  const DevShapes &S = A.S;
+  const int d = S.d;
+  const int64_t c = cutlist[item];
+  int ijk[3];
+  coords(S, c, ijk);
   double base[3] = {0, 0, 0};
   for (int a = 0; a < d; ++a) base[a] = S.lo[a] + (double)ijk[a] * A.h;
   const int sub = A.sub;
-  const int64_t per_cell = (int64_t)sub * sub * (d == 3 ? sub : 1);
-  int64_t fluid = 0;
-  double x[3] = {0, 0, 0};
-  const int s2 = d == 3 ? sub : 1;
-  for (int k = 0; k < s2; ++k) {
+  const int per_cell = sub * sub * (d == 3 ? sub : 1);   // sub <= 1000 (checked on the host)
+  // point q = i + sub (j + sub k); lane starts at q = lane and strides by 64, carried digit-wise
+  int i = lane % sub, j = (lane / sub) % sub, k = lane / (sub * sub);
+  const int di = 64 % sub, dj = (64 / sub) % sub, dk = 64 / (sub * sub);
+  int fluid = 0;
+  for (int q = lane; q < per_cell; q += 64) {
+    double x[3] = {0, 0, 0};
+    x[0] = base[0] + ((double)i + 0.5) * A.hs;
+    x[1] = base[1] + ((double)j + 0.5) * A.hs;
     if (d == 3) x[2] = base[2] + ((double)k + 0.5) * A.hs;
-    for (int j = 0; j < sub; ++j) {
-      x[1] = base[1] + ((double)j + 0.5) * A.hs;
-      for (int i = 0; i < sub; ++i) {
-        x[0] = base[0] + ((double)i + 0.5) * A.hs;
-        if (!solid(S, x)) ++fluid;
-      }
+    if (!solid(S, x)) ++fluid;
+    i += di;
+    if (i >= sub) {
+      i -= sub;
+      ++j;
     }
+    j += dj;
+    if (j >= sub) {
+      j -= sub;
+      ++k;
+    }
+    k += dk;
   }
-  alpha[c] = (double)fluid / (double)per_cell;
+  for (int off = 32; off > 0; off >>= 1) fluid += __shfl_down(fluid, off, 64);
+  if (lane == 0) alpha[c] = (double)fluid / (double)per_cell;
 }
 
 // Ghost: solid centre with a face neighbour whose centre is fluid.  Flags a ghost in the first
@@ -208,15 +232,18 @@ __device__ bool is_ghost(const DevShapes &S, const unsigned char *__restrict__ c
   return nb_fluid;
 }
 
-// Per-block ghost counts (phase 1) or the ghost list in cell order (phase 2, block offsets given):
-// a block-wide exclusive scan of the flags ranks the ghosts inside the block.
-__global__ __launch_bounds__(kGeomThreads) void k_gd_ghosts(GeomArgs A, const unsigned char *__restrict__ csolid,
-                                                            int *__restrict__ bcount, const int *__restrict__ boff,
-                                                            int *__restrict__ gidx, int *__restrict__ bad) {
+// Per-block counts (phase 1) or the list in cell order (phase 2, block offsets given) of the
+// ghosts (MODE 0, mask = centre solid mask) or of the cut cells (MODE 1, mask = cut flags): a
+// block-wide scan of the flags ranks them inside the block.
+template <int MODE>
+__global__ __launch_bounds__(kGeomThreads) void k_gd_list(GeomArgs A, const unsigned char *__restrict__ mask,
+                                                          int *__restrict__ bcount, const int *__restrict__ boff,
+                                                          int *__restrict__ list, int *__restrict__ bad) {
   __shared__ int s[kGeomThreads];
   const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   int b = 0;
-  const int flag = (c < A.N && is_ghost(A.S, csolid, c, &b)) ? 1 : 0;
+  int flag = 0;
+  if (c < A.N) flag = MODE == 0 ? (is_ghost(A.S, mask, c, &b) ? 1 : 0) : (mask[c] ? 1 : 0);
   if (b) *bad = 1;   // every writer stores the same value
   s[threadIdx.x] = flag;
   __syncthreads();
@@ -230,7 +257,7 @@ __global__ __launch_bounds__(kGeomThreads) void k_gd_ghosts(GeomArgs A, const un
     if (threadIdx.x == kGeomThreads - 1) bcount[blockIdx.x] = s[kGeomThreads - 1];
     return;
   }
-  if (flag) gidx[boff[blockIdx.x] + s[threadIdx.x] - 1] = (int)c;
+  if (flag) list[boff[blockIdx.x] + s[threadIdx.x] - 1] = (int)c;
 }
 
 // P3-P8 per ghost: normal from corner gradients of alpha, intersect point by marching along the
@@ -415,10 +442,11 @@ __global__ __launch_bounds__(kGeomThreads) void k_gd_tables(GeomArgs A, const do
   err[gi] = 0;
 }
 
-// Scratch layout (bytes, 256-aligned pieces): alpha N doubles, csolid N bytes, block counts and
-// offsets, the bad flag, then per-ghost arrays sized for max_ghosts(N).
+// Scratch layout (bytes, 256-aligned pieces): alpha N doubles, solid and cut masks N bytes each,
+// the cut-cell list N ints, block counts and offsets, the bad flag, then per-ghost arrays sized
+// for gmax ghosts.
 struct DevLayout {
-  size_t alpha, csolid, bcount, boff, bad, gidx, normal, dn, gam, ap, w, err, total;
+  size_t alpha, csolid, cutf, cutlist, bcount, boff, bad, gidx, normal, dn, gam, ap, w, err, total;
   int64_t gmax;
   int64_t nblocks;
 };
@@ -438,6 +466,8 @@ DevLayout dev_layout(int64_t N, int d) {
   };
   L.alpha = take(N * 8);
   L.csolid = take(N);
+  L.cutf = take(N);
+  L.cutlist = take(N * 4);
   L.bcount = take(L.nblocks * 4);
   L.boff = take(L.nblocks * 4);
   L.bad = take(4);
@@ -500,6 +530,7 @@ extern "C" int ch_ib_geometry_build_device(const ch_ib_grid *grid, const ch_ib_s
   }
   A.h = tmp.h;
   A.sub = params->subgrid > 0 ? params->subgrid : (d == 2 ? 100 : 20);
+  if (A.sub > 1000) return fail(CH_IB_EUNSUPPORTED, "at most 1000 subgrid points per direction on the device builder");
   A.hs = tmp.h / A.sub;
   A.d1 = (params->d1_cells > 0 ? params->d1_cells : 2.0) * tmp.h;
   A.d2 = (params->d2_cells > 0 ? params->d2_cells : 1.5) * tmp.h;
@@ -514,30 +545,51 @@ extern "C" int ch_ib_geometry_build_device(const ch_ib_grid *grid, const ch_ib_s
   hipStream_t s = (hipStream_t)hip_stream;
   const unsigned nb = (unsigned)L.nblocks;
 
+  unsigned char *cutf = (unsigned char *)(ws + L.cutf);
+  int *cutlist = (int *)(ws + L.cutlist);
+  std::vector<int> counts(nb), offs(nb);
+  // block counts -> exclusive block offsets (host prefix sum, uploaded); *total = sum of counts
+  auto offsets = [&](int64_t *total) {
+    hipError_t e2 = hipMemcpyAsync(counts.data(), bcount, (size_t)nb * 4, hipMemcpyDeviceToHost, s);
+    if (e2 == hipSuccess) e2 = hipStreamSynchronize(s);
+    if (e2 != hipSuccess) return e2;
+    int64_t t = 0;
+    for (unsigned b = 0; b < nb; ++b) {
+      offs[b] = (int)t;
+      t += counts[b];
+    }
+    *total = t;
+    return hipMemcpyAsync(boff, offs.data(), (size_t)nb * 4, hipMemcpyHostToDevice, s);
+  };
   int zero = 0;
+  int64_t n_cut = 0, G = 0;
   hipError_t e = hipMemcpyAsync(bad, &zero, 4, hipMemcpyHostToDevice, s);
   if (e == hipSuccess) {
-    hipLaunchKernelGGL(k_gd_alpha, dim3(nb), dim3(kGeomThreads), 0, s, A, alpha, csolid);
-    hipLaunchKernelGGL(k_gd_ghosts, dim3(nb), dim3(kGeomThreads), 0, s, A, (const unsigned char *)csolid, bcount,
+    hipLaunchKernelGGL(k_gd_classify, dim3(nb), dim3(kGeomThreads), 0, s, A, alpha, csolid, cutf);
+    hipLaunchKernelGGL(k_gd_list<1>, dim3(nb), dim3(kGeomThreads), 0, s, A, (const unsigned char *)cutf, bcount,
                        (const int *)nullptr, (int *)nullptr, bad);
     e = hipGetLastError();
   }
-  std::vector<int> counts(nb), offs(nb);
+  if (e == hipSuccess) e = offsets(&n_cut);
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(k_gd_list<1>, dim3(nb), dim3(kGeomThreads), 0, s, A, (const unsigned char *)cutf, bcount,
+                       (const int *)boff, cutlist, bad);
+    if (n_cut)
+      hipLaunchKernelGGL(k_gd_subgrid, dim3((unsigned)((n_cut + 3) / 4)), dim3(kGeomThreads), 0, s, A,
+                         (const int *)cutlist, n_cut, alpha);
+    hipLaunchKernelGGL(k_gd_list<0>, dim3(nb), dim3(kGeomThreads), 0, s, A, (const unsigned char *)csolid, bcount,
+                       (const int *)nullptr, (int *)nullptr, bad);
+    e = hipGetLastError();
+  }
   int hbad = 0;
-  if (e == hipSuccess) e = hipMemcpyAsync(counts.data(), bcount, (size_t)nb * 4, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = offsets(&G);
   if (e == hipSuccess) e = hipMemcpyAsync(&hbad, bad, 4, hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) return hip_error(e, "device geometry (volume fraction, ghosts)");
   if (hbad) return fail(CH_IB_EGEOM, "a ghost point touches the box wall of the bounded axis");
-  int64_t G = 0;
-  for (unsigned b = 0; b < nb; ++b) {
-    offs[b] = (int)G;
-    G += counts[b];
-  }
   if (G > L.gmax) return fail(CH_IB_ENOMEM, "more ghosts than the device builder holds (cells/8 + 1024)");
-  e = hipMemcpyAsync(boff, offs.data(), (size_t)nb * 4, hipMemcpyHostToDevice, s);
-  if (e == hipSuccess) {
-    hipLaunchKernelGGL(k_gd_ghosts, dim3(nb), dim3(kGeomThreads), 0, s, A, (const unsigned char *)csolid, bcount,
+  {
+    hipLaunchKernelGGL(k_gd_list<0>, dim3(nb), dim3(kGeomThreads), 0, s, A, (const unsigned char *)csolid, bcount,
                        (const int *)boff, gidx, bad);
     if (G)
       hipLaunchKernelGGL(k_gd_tables, dim3((unsigned)((G + kGeomThreads - 1) / kGeomThreads)), dim3(kGeomThreads), 0,

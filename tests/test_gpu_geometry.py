@@ -77,3 +77,6 @@ def test_device_geometry_errors(chib):
     with pytest.raises(chib.ChibError) as e:
         chib.Geometry.build_device((12, 8), (0.0, 0.0), (1.5, 1.0), [], prm)
     assert e.value.code == chib.EUNSUPPORTED
+    with pytest.raises(chib.ChibError) as e:      # subgrid counts above 1000 per direction
+        chib.Geometry.build_device(g.n, g.lo, g.hi, [], W.Params(Cn=0.05, Pe=10.0, subgrid=1001))
+    assert e.value.code == chib.EUNSUPPORTED
