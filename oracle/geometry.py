@@ -38,7 +38,7 @@ from __future__ import annotations
 import dataclasses
 import itertools
 import math
-from typing import List, Sequence
+from typing import List, Optional, Sequence
 
 import numpy as np
 
@@ -159,17 +159,24 @@ def centre_coords(grid: Grid, I: Sequence[np.ndarray]) -> List[np.ndarray]:
     return [grid.lo[a] + (I[a] + 0.5) * grid.h for a in range(grid.ndim)]
 
 
-def volume_fraction(grid: Grid, shapes: Sequence[Shape], subgrid: int):
+def volume_fraction(grid: Grid, shapes: Sequence[Shape], subgrid: int, face_axis: Optional[int] = None):
     """Fluid volume fraction alpha of every cell and the centre solid mask (section 4.1.1).
 
     alpha = (number of subgrid points outside the solid) / subgrid^d, counted
     in cells that the wall may cut; other cells are wholly solid or fluid and
-    take 0 or 1 from their centre.
+    take 0 or 1 from their centre.  With ``face_axis`` = a the control volumes
+    are the staggered cells of the faces normal to axis a (each cell shifted by
+    h/2 along a), the other three of the four volume fractions the section
+    asks for on a staggered grid.
     """
     d = grid.ndim
     h = grid.h
     I = cell_index_coords(grid)
     Xc = centre_coords(grid, I)
+    off = [0.0] * d
+    if face_axis is not None:
+        off[face_axis] = 0.5 * h
+        Xc = [Xc[a] + off[a] for a in range(d)]
     csolid = solid(grid, shapes, Xc)
     alpha = np.where(csolid, 0.0, 1.0)
     cut = np.zeros(grid.shape, dtype=bool)
@@ -187,7 +194,7 @@ def volume_fraction(grid: Grid, shapes: Sequence[Shape], subgrid: int):
         cells = flat_cut[c0:c0 + chunk]
         X = []
         for a in range(d):
-            base = grid.lo[a] + Iflat[a][cells].astype(np.float64) * h
+            base = grid.lo[a] + Iflat[a][cells].astype(np.float64) * h + off[a]
             shp = [1] * (d + 1)
             shp[1 + a] = n
             X.append(base.reshape((cells.size,) + (1,) * d) + sub.reshape(shp))
@@ -195,6 +202,13 @@ def volume_fraction(grid: Grid, shapes: Sequence[Shape], subgrid: int):
         fluid_count = (~inside).reshape(cells.size, -1).sum(axis=1)
         aflat[cells] = fluid_count / float(per_cell)
     return alpha, csolid
+
+
+def face_fractions(grid: Grid, shapes: Sequence[Shape], params: Params) -> List[np.ndarray]:
+    """Fluid volume fractions of the face-centred staggered cells, one field per axis
+    (entry c of field a belongs to the face between cell c and c + e_a)."""
+    n = default_subgrid(grid, params)
+    return [volume_fraction(grid, shapes, n, face_axis=a)[0] for a in range(grid.ndim)]
 
 
 @dataclasses.dataclass

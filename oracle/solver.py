@@ -243,7 +243,8 @@ class OracleState:
     """Order parameter, face velocities and per-ghost state of one run (FP64, host)."""
 
     def __init__(self, grid: Grid, params: Params, tables: GhostTables,
-                 C0: np.ndarray, faces: Optional[List[np.ndarray]] = None):
+                 C0: np.ndarray, faces: Optional[List[np.ndarray]] = None,
+                 face_alpha: Optional[List[np.ndarray]] = None):
         self.grid = grid
         self.params = params
         self.T = tables
@@ -255,8 +256,16 @@ class OracleState:
         self.CI = np.zeros(tables.n_ghost)
         self.step_count = 0
         self.Rh = None          # rate of the previous explicit step
+        if params.navier_stokes:
+            if face_alpha is None:
+                raise ParamError("the momentum step needs the staggered-cell volume fractions")
+            self.face_alpha = [np.array(f, dtype=np.float64) for f in face_alpha]
+            self.Nh = None      # convective term of the previous momentum step
+            self.p = np.zeros(grid.shape)
+            self.p_prev = np.zeros(grid.shape)
         self.initial_fill()
         self.Cp = self.C.copy()
+        self.u_prev = [f.copy() for f in self.faces]
 
     # -- ghost fill of C -------------------------------------------------------
     def fill_C(self, P: np.ndarray, initial: bool) -> np.ndarray:
@@ -383,7 +392,10 @@ class OracleState:
         Cn2 = prm.Cn * prm.Cn
         Ct = 2.0 * self.C - self.Cp
         Cc = 2.0 * self.C - 0.5 * self.Cp
-        A = advection(Ct, self.faces, grid)
+        # with the momentum step the advecting velocity is the extrapolation 2u^n - u^(n-1)
+        # (Appendix A.1, u~^(n+1)); with frozen faces both are the same field
+        uadv = [2.0 * u - up for u, up in zip(self.faces, self.u_prev)] if prm.navier_stokes else self.faces
+        A = advection(Ct, uadv, grid)
         g = (Ct * Ct * Ct - Ct - self.S * Ct) / Cn2
         return (prm.Pe / Cn2) * (Cc / prm.dt - A) + laplacian(g, grid)
 
@@ -423,9 +435,31 @@ class OracleState:
             Pf[self.T.gidx] = CG
             self.Cp = self.C
             self.C = P
-            if self.params.velocity_fill:
+            if self.params.navier_stokes:
+                self.momentum_step()
+            elif self.params.velocity_fill:
                 self.fill_velocity(self.C)
             self.step_count += 1
+
+    # -- momentum ---------------------------------------------------------------------
+    def momentum_step(self) -> None:
+        """Prediction, penalisation, velocity ghost fill, pressure and correction with the new C
+        (sections 3.3-3.5; the operators are in ``oracle.ns``)."""
+        from . import ns
+        grid = self.grid
+        prm = self.params
+        phi = chemical_potential(self.C, grid, self.T, prm.Cn)
+        us, self.Nh = ns.prediction(self.faces, self.C, phi, prm, grid, self.Nh)
+        u_old = self.faces
+        self.faces = [self.face_alpha[a] * us[a] for a in range(grid.ndim)]
+        self.fill_velocity(self.C)
+        u2 = self.faces
+        R = ns.pressure_rhs(u2, self.C, self.p, self.p_prev, prm, grid)
+        pn = ns.poisson_solve(R, grid)
+        self.faces = ns.correction(u2, self.C, pn, self.p, self.p_prev, prm, grid)
+        self.u_prev = u_old
+        self.p_prev = self.p
+        self.p = pn
 
     # -- diagnostics ------------------------------------------------------------------
     def diagnostics(self) -> dict:

@@ -81,6 +81,10 @@ class Params:
     keeps the two Helmholtz factors real.  ``d1_cells``/``d2_cells`` are the
     intersect-to-mirror and mirror-to-interpolation distances in cell widths
     (``d1_cells <= 0`` means 2 cells, ``d2_cells <= 0`` 1.5 cells).
+    With ``navier_stokes`` the face velocities follow the momentum equation
+    (Reynolds number ``Re``, capillary number ``Ca``, phase densities and
+    viscosities ``rho1``/``mu1`` for C = -1 and ``rho2``/``mu2`` for C = +1
+    relative to the reference fluid, ``body_force`` an acceleration).
     """
 
     Cn: float
@@ -98,6 +102,12 @@ class Params:
     subgrid: int = 0           # 0: 100 per direction in 2D, 20 in 3D
     velocity_fill: bool = True
     explicit: bool = False     # explicit Adams-Bashforth step instead of the semi-implicit one
+    navier_stokes: bool = False  # advance the face velocities with the momentum equation too
+    rho1: float = 1.0          # density of the C = -1 phase over the reference density
+    rho2: float = 1.0          # density of the C = +1 phase over the reference density
+    mu1: float = 1.0           # viscosity of the C = -1 phase over the reference viscosity
+    mu2: float = 1.0           # viscosity of the C = +1 phase over the reference viscosity
+    body_force: Tuple[float, ...] = (0.0, 0.0, 0.0)   # acceleration per axis (e.g. gravity)
 
 
 @dataclasses.dataclass
