@@ -63,14 +63,17 @@ enum {
   CH_IB_FIELD_W = 4,       /* face velocity along axis 2 (3D) */
   CH_IB_FIELD_CI = 5,      /* per-ghost wall value C_I of the dynamic condition (n_ghost values) */
   CH_IB_FIELD_ALPHA = 6,   /* fluid volume fraction (get only) */
-  CH_IB_FIELD_PHI = 7      /* chemical potential C^3 - C - Cn^2 lap C with mirror ghosts (get only) */
+  CH_IB_FIELD_PHI = 7,     /* chemical potential C^3 - C - Cn^2 lap C with mirror ghosts (get only) */
+  CH_IB_FIELD_P = 8        /* pressure p^n of the momentum step, zero mean (get only) */
 };
 
 /* ---- params.flags ---------------------------------------------------------------------- */
 enum {
   CH_IB_FLAG_VELOCITY_FILL = 1, /* refill faces touching ghosts every step (section 4.4) */
-  CH_IB_FLAG_EXPLICIT = 2        /* explicit Adams-Bashforth step (Eq. ExpCH) instead of the
+  CH_IB_FLAG_EXPLICIT = 2,       /* explicit Adams-Bashforth step (Eq. ExpCH) instead of the
                                     semi-implicit one; needs a time step about ten times smaller */
+  CH_IB_FLAG_NAVIER_STOKES = 4   /* advance the face velocities with the momentum equation too
+                                    (sections 2 and 3.3-3.5); implies the velocity fill */
 };
 
 typedef struct {
@@ -101,6 +104,11 @@ typedef struct {
   int subgrid;                /* subgrid points per direction for the volume fraction; 0: 100 (2D) / 20 (3D) */
   int precision;              /* 64 (FP64) or 32 (FP32) arithmetic on the device */
   int flags;                  /* CH_IB_FLAG_* */
+  /* momentum step (CH_IB_FLAG_NAVIER_STOKES only; all four must then be positive): densities and
+   * viscosities of the C = -1 (rho1, mu1) and C = +1 (rho2, mu2) phases relative to the reference
+   * fluid of Re; body_force is an acceleration per axis (e.g. gravity) */
+  double rho1, rho2, mu1, mu2;
+  double body_force[3];
 } ch_ib_params;
 
 /* Per-ghost tables (structure of arrays, sorted by ghost cell index), section 4.1.
@@ -155,6 +163,17 @@ int ch_ib_geometry_build(const ch_ib_grid *grid, const ch_ib_shape *shapes, int 
 int ch_ib_geometry_import(const ch_ib_grid *grid, const ch_ib_ghost_tables *tables,
                           ch_ib_geometry **out);
 
+/* Fluid fractions of the staggered (face-centred) cells, section 4.1.1's other three volume
+ * fractions: ndim fields of cells doubles, field a for the faces between cell c and c + e_a, each
+ * control volume the cell shifted by h/2 along a, counted with the same subgrid points.
+ * ch_ib_geometry_build computes them when params->flags has CH_IB_FLAG_NAVIER_STOKES.
+ * ch_ib_geometry_face_fractions: copies them to dst (ndim * cells doubles, caller-allocated);
+ *   EUNSUPPORTED if the geometry holds none (imported or built without the flag).
+ * ch_ib_geometry_set_face_fractions: replaces them with a copy of src (same layout; every value
+ *   in [0, 1], else EINVAL), e.g. for an imported geometry. */
+int ch_ib_geometry_face_fractions(const ch_ib_geometry *geom, double *dst);
+int ch_ib_geometry_set_face_fractions(ch_ib_geometry *geom, const double *src);
+
 /* Geometry preprocessing on the GPU: the tables of ch_ib_geometry_build (same readings, same
  * sequence of operations, no contraction of multiplies and adds), computed with one thread per
  * cell for the volume fraction and the ghost list and one per ghost for the rest, returned as an
@@ -205,6 +224,17 @@ int ch_ib_state_get(ch_ib_state *st, int field, void *dst, int dst_on_device);
  *   C^(n+1) = C^n + dt (3/2 R^n - 1/2 R^(n-1)) (second-order Adams-Bashforth; the first step
  *   after the fields are set or loaded without a rate is a forward Euler step), then the same
  *   fills.  The workspace then holds one more field for R.
+ *   With CH_IB_FLAG_NAVIER_STOKES the faces follow the momentum equation: after the order-parameter
+ *   step (semi-implicit: advected by 2u^n - u^(n-1), Appendix A.1; explicit: by u^n) comes the
+ *   momentum step of sections 3.3-3.5 on the staggered grid, with rho and mu linear in C^(n+1),
+ *   phi the chemical potential above and the capillary force 3/(2 sqrt2 Re Ca Cn) phi grad C:
+ *   Adams-Bashforth prediction (Eq. PredictionExp; the first step after the fields are set uses a
+ *   forward Euler convective term), penalisation u** = alpha_face u* (Eq. Penalization2), the
+ *   velocity ghost fill on u**, the pressure of Eq. PressurePoisson (rho0 = min(rho1, rho2),
+ *   p^ = 2p^n - p^(n-1), zero-mean, no flux through the box walls) by the same transforms, and
+ *   the correction of Eq. correction.  The box walls of the bounded axis are no-slip.  Needs a
+ *   geometry with staggered-cell fractions (EINVAL at state creation otherwise); not available to
+ *   batches or the learned correction.
  * ch_ib_sync: waits for the stream; reports CH_IB_EHIP on a device error.
  * ch_ib_diagnostics: mass, free energy, max |C| (deterministic fixed-order reductions);
  *   synchronous; status CH_IB_ENAN (also returned) if any C is not finite. */

@@ -382,7 +382,7 @@ class OracleState:
         Pf = P.reshape(-1)
         Pf[self.T.gidx] = CG
         self.C = P
-        if self.params.velocity_fill:
+        if self.params.velocity_fill or self.params.navier_stokes:
             self.fill_velocity(self.C)
 
     def rhs(self) -> np.ndarray:

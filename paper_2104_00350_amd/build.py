@@ -21,7 +21,7 @@ HIP_FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-munsafe-fp
              "-I", INCLUDE, "-I", CSRC]
 HOST_FLAGS = ["-O2", "-std=c++17", "-fPIC", "-ffp-contract=off", "-pthread", "-I", INCLUDE, "-I", CSRC]
 
-HIP_SOURCES = ["kernels.hip", "api.hip", "learned.hip", "geometry_device.hip"]
+HIP_SOURCES = ["kernels.hip", "api.hip", "learned.hip", "geometry_device.hip", "ns.hip"]
 # the device geometry builder repeats the host builder's arithmetic operation for operation
 EXTRA_FLAGS = {"geometry_device.hip": ["-ffp-contract=off"]}
 HOST_SOURCES = ["geometry.cpp"]

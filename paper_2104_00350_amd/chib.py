@@ -17,9 +17,10 @@ LIB_PATH = os.path.join(_PKG, "libchib.so")
 
 OK, EINVAL, EGEOM, EHIP, ENOMEM, ENAN, EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
 HALFPLANE, SINUSOID, SPHERE, BOX = 1, 2, 3, 4
-FIELD_C, FIELD_C_PREV, FIELD_U, FIELD_V, FIELD_W, FIELD_CI, FIELD_ALPHA, FIELD_PHI = range(8)
+FIELD_C, FIELD_C_PREV, FIELD_U, FIELD_V, FIELD_W, FIELD_CI, FIELD_ALPHA, FIELD_PHI, FIELD_P = range(9)
 FLAG_VELOCITY_FILL = 1
 FLAG_EXPLICIT = 2
+FLAG_NAVIER_STOKES = 4
 STAGE_RHS, STAGE_SOLVE, STAGE_PHI = 1, 2, 3
 
 
@@ -42,7 +43,9 @@ class Params(C.Structure):
                 ("mu", C.c_double), ("theta_deg", C.c_double), ("Vs", C.c_double),
                 ("slip_length", C.c_double), ("dt", C.c_double), ("S", C.c_double),
                 ("d1_cells", C.c_double), ("d2_cells", C.c_double), ("subgrid", C.c_int),
-                ("precision", C.c_int), ("flags", C.c_int)]
+                ("precision", C.c_int), ("flags", C.c_int),
+                ("rho1", C.c_double), ("rho2", C.c_double), ("mu1", C.c_double), ("mu2", C.c_double),
+                ("body_force", C.c_double * 3)]
 
 
 class GhostTables(C.Structure):
@@ -75,6 +78,8 @@ def _load():
         "ch_ib_geometry_export": (i32, [vp, C.POINTER(GhostTables)]),
         "ch_ib_geometry_count": (i32, [vp, i64p, C.POINTER(C.c_int)]),
         "ch_ib_geometry_free": (None, [vp]),
+        "ch_ib_geometry_face_fractions": (i32, [vp, vp]),
+        "ch_ib_geometry_set_face_fractions": (i32, [vp, vp]),
         "ch_ib_workspace_bytes": (C.c_size_t, [C.POINTER(Grid), vp, C.POINTER(Params)]),
         "ch_ib_state_create": (i32, [C.POINTER(Grid), vp, C.POINTER(Params), vp, C.c_size_t, vp, C.POINTER(vp)]),
         "ch_ib_state_set": (i32, [vp, i32, vp, i32]),
@@ -150,7 +155,14 @@ def make_params(prm, precision: int = 64) -> Params:
         setattr(p, name, float(getattr(prm, name)))
     p.subgrid = int(prm.subgrid)
     p.precision = int(precision)
-    p.flags = (FLAG_VELOCITY_FILL if prm.velocity_fill else 0) | (FLAG_EXPLICIT if getattr(prm, "explicit", False) else 0)
+    ns = bool(getattr(prm, "navier_stokes", False))
+    p.flags = ((FLAG_VELOCITY_FILL if prm.velocity_fill else 0) | (FLAG_EXPLICIT if getattr(prm, "explicit", False) else 0)
+               | (FLAG_NAVIER_STOKES if ns else 0))
+    for name in ("rho1", "rho2", "mu1", "mu2"):
+        setattr(p, name, float(getattr(prm, name, 1.0)))
+    bf = tuple(getattr(prm, "body_force", (0.0, 0.0, 0.0))) + (0.0, 0.0, 0.0)
+    for a in range(3):
+        p.body_force[a] = float(bf[a])
     return p
 
 
@@ -238,6 +250,19 @@ class Geometry:
         K = C.c_int()
         check(lib.ch_ib_geometry_count(self.h, C.byref(G), C.byref(K)))
         return G.value, K.value
+
+    def face_fractions(self) -> np.ndarray:
+        """Staggered-cell fluid fractions, shape (d,) + field shape (ch_ib_geometry_face_fractions)."""
+        d = self.grid.ndim
+        shape = tuple(self.grid.n[a] for a in reversed(range(d)))
+        out = np.zeros((d,) + shape)
+        check(lib.ch_ib_geometry_face_fractions(self.h, out.ctypes.data_as(C.c_void_p)))
+        return out
+
+    def set_face_fractions(self, fractions) -> None:
+        """Attach staggered-cell fractions (d fields), e.g. to an imported geometry."""
+        arr = np.ascontiguousarray(np.stack([np.asarray(f, dtype=np.float64) for f in fractions]))
+        check(lib.ch_ib_geometry_set_face_fractions(self.h, arr.ctypes.data_as(C.c_void_p)))
 
     def export(self) -> dict:
         G, K = self.count()

@@ -71,12 +71,13 @@ struct Layout {
 
 struct Offsets {
   size_t C[2], F[3], W, R, alpha, gidx, normal, dn, gamma, ap, w, CGn, CGnm1, CMs, CI, CGnew, UG;
+  size_t Us[3], Ut[3], Nh[3], Af[3], P[2];
   size_t f_cell, f_axis, f_gL, f_gR, stashL, stashR;
   size_t twr[3], twi[3], dctc, dcts, lam[3], partial, red_out;
   size_t total;
 };
 
-Offsets plan_layout(const ch_ib_geometry &g, int es, int64_t NF, bool explicit_ab2) {
+Offsets plan_layout(const ch_ib_geometry &g, int es, int64_t NF, bool explicit_ab2, bool ns) {
   Layout L;
   Offsets o{};
   const int64_t N = g.cells, G = g.n_ghost;
@@ -86,6 +87,15 @@ Offsets plan_layout(const ch_ib_geometry &g, int es, int64_t NF, bool explicit_a
   for (int a = 0; a < 3; ++a) o.F[a] = a < d ? L.off(N * es) : 0;
   o.W = L.off(N * es);
   o.R = explicit_ab2 ? L.off(N * es) : 0;
+  // momentum step: u**, the advecting 2u^n - u^(n-1) (semi-implicit only), the previous
+  // convective term, the staggered-cell fractions and two pressure levels
+  for (int a = 0; a < 3; ++a) {
+    o.Us[a] = ns && a < d ? L.off(N * es) : 0;
+    o.Ut[a] = ns && !explicit_ab2 && a < d ? L.off(N * es) : 0;
+    o.Nh[a] = ns && a < d ? L.off(N * es) : 0;
+    o.Af[a] = ns && a < d ? L.off(N * es) : 0;
+  }
+  for (int k = 0; k < 2; ++k) o.P[k] = ns ? L.off(N * es) : 0;
   o.alpha = g.alpha.empty() ? 0 : L.off(N * es);
   o.gidx = L.off(G * 4);
   o.normal = L.off(d * G * es);
@@ -123,8 +133,12 @@ int check_params(const ch_ib_params *p, double *S, double *alpha_s, double *a) {
   if (!(p->Cn > 0) || !(p->Pe > 0) || !(p->dt > 0)) return fail(CH_IB_EINVAL, "Cn, Pe and dt must be positive");
   if (p->precision != 64 && p->precision != 32) return fail(CH_IB_EINVAL, "precision must be 64 or 32");
   if (p->Vs < 0 || p->slip_length < 0) return fail(CH_IB_EINVAL, "Vs and slip_length must be >= 0");
-  if ((p->flags & CH_IB_FLAG_VELOCITY_FILL) && (!(p->Ca > 0) || !(p->mu > 0)))
+  if ((p->flags & (CH_IB_FLAG_VELOCITY_FILL | CH_IB_FLAG_NAVIER_STOKES)) && (!(p->Ca > 0) || !(p->mu > 0)))
     return fail(CH_IB_EINVAL, "Ca and mu must be positive for the velocity fill");
+  if ((p->flags & CH_IB_FLAG_NAVIER_STOKES) &&
+      (!(p->Re > 0) || !(p->rho1 > 0) || !(p->rho2 > 0) || !(p->mu1 > 0) || !(p->mu2 > 0) ||
+       !std::isfinite(p->body_force[0]) || !std::isfinite(p->body_force[1]) || !std::isfinite(p->body_force[2])))
+    return fail(CH_IB_EINVAL, "the momentum step needs positive Re, rho1, rho2, mu1, mu2 and a finite body force");
   const double Cn = p->Cn, Pe = p->Pe, dt = p->dt;
   const double Smin = Cn * std::sqrt(6.0 * Pe / dt);
   const double Sv = p->S > 0 ? p->S : Smin;
@@ -153,6 +167,8 @@ struct ch_ib_state {
   int sticky = CH_IB_OK;
   int has_alpha = 0;
   int r_valid = 0;      // explicit step: R holds the previous step's rate
+  int ns_first = 1;     // momentum step: no previous convective term yet
+  int ut_valid = 0;     // momentum step: Ut holds 2u^n - u^(n-1)
   double d1_min = 0, d1_max = 0;   // range of gamma dn = d1 over the ghosts (mixed-condition checks)
 };
 
@@ -197,7 +213,10 @@ extern "C" size_t ch_ib_workspace_bytes(const ch_ib_grid *grid, const ch_ib_geom
   if (params->precision != 64 && params->precision != 32) return 0;
   const int es = params->precision == 64 ? 8 : 4;
   FaceList fl = build_faces(*geom);
-  return plan_layout(*geom, es, (int64_t)fl.cell.size(), (params->flags & CH_IB_FLAG_EXPLICIT) != 0).total + 256;
+  return plan_layout(*geom, es, (int64_t)fl.cell.size(), (params->flags & CH_IB_FLAG_EXPLICIT) != 0,
+                     (params->flags & CH_IB_FLAG_NAVIER_STOKES) != 0)
+             .total +
+         256;
 }
 
 extern "C" int ch_ib_state_create(const ch_ib_grid *grid, const ch_ib_geometry *geom, const ch_ib_params *params,
@@ -215,6 +234,9 @@ extern "C" int ch_ib_state_create(const ch_ib_grid *grid, const ch_ib_geometry *
   if (bytes < need) return fail(CH_IB_ENOMEM, "workspace too small: need " + std::to_string(need) + " bytes");
   if (((uintptr_t)device_workspace) & 255) return fail(CH_IB_EINVAL, "workspace must be 256-byte aligned");
 
+  if ((params->flags & CH_IB_FLAG_NAVIER_STOKES) &&
+      geom->face_alpha.size() != (size_t)geom->ndim * (size_t)geom->cells)
+    return fail(CH_IB_EINVAL, "the momentum step needs a geometry with staggered-cell fractions");
   auto *st = new ch_ib_state();
   st->geom = *geom;
   st->prm = *params;
@@ -223,7 +245,8 @@ extern "C" int ch_ib_state_create(const ch_ib_grid *grid, const ch_ib_geometry *
   st->has_alpha = !geom->alpha.empty();
   FaceList fl = build_faces(*geom);
   const int64_t NF = (int64_t)fl.cell.size();
-  st->off = plan_layout(*geom, st->es, NF, (params->flags & CH_IB_FLAG_EXPLICIT) != 0);
+  const bool ns = (params->flags & CH_IB_FLAG_NAVIER_STOKES) != 0;
+  st->off = plan_layout(*geom, st->es, NF, (params->flags & CH_IB_FLAG_EXPLICIT) != 0, ns);
   const Offsets &o = st->off;
   chib::Plan &p = st->plan;
   const int d = geom->ndim;
@@ -250,12 +273,29 @@ extern "C" int ch_ib_state_create(const ch_ib_grid *grid, const ch_ib_geometry *
   p.vel_fill = (params->flags & CH_IB_FLAG_VELOCITY_FILL) ? 1 : 0;
   p.dynamic = params->Vs > 0 ? 1 : 0;
   p.explicit_ab2 = (params->flags & CH_IB_FLAG_EXPLICIT) ? 1 : 0;
+  if (ns) {
+    p.ns = 1;
+    p.vel_fill = 1;
+    p.Re = params->Re;
+    p.rho1 = params->rho1;
+    p.rho2 = params->rho2;
+    p.mu1 = params->mu1;
+    p.mu2 = params->mu2;
+    for (int a = 0; a < 3; ++a) p.g[a] = a < geom->ndim ? params->body_force[a] : 0.0;
+  }
   char *W0 = st->ws;
   p.C[0] = W0 + o.C[0];
   p.C[1] = W0 + o.C[1];
   for (int ax = 0; ax < 3; ++ax) p.F[ax] = ax < d ? W0 + o.F[ax] : nullptr;
   p.W = W0 + o.W;
   p.R = p.explicit_ab2 ? W0 + o.R : nullptr;
+  for (int a = 0; a < 3; ++a) {
+    p.Us[a] = ns && a < d ? W0 + o.Us[a] : nullptr;
+    p.Ut[a] = ns && !p.explicit_ab2 && a < d ? W0 + o.Ut[a] : nullptr;
+    p.Nh[a] = ns && a < d ? W0 + o.Nh[a] : nullptr;
+    p.Af[a] = ns && a < d ? W0 + o.Af[a] : nullptr;
+  }
+  for (int k = 0; k < 2; ++k) p.P[k] = ns ? W0 + o.P[k] : nullptr;
   p.alpha = st->has_alpha ? W0 + o.alpha : nullptr;
   p.G = geom->n_ghost;
   p.K = geom->n_ap;
@@ -357,10 +397,24 @@ extern "C" int ch_ib_state_create(const ch_ib_grid *grid, const ch_ib_geometry *
   up(dctc, (void *)p.dctc);
   up(dcts, (void *)p.dcts);
   if (st->has_alpha) up(geom->alpha, p.alpha);
+  if (ns) {
+    std::vector<double> fa((size_t)p.N);
+    for (int a = 0; a < d; ++a) {
+      std::copy(geom->face_alpha.begin() + (size_t)a * p.N, geom->face_alpha.begin() + (size_t)(a + 1) * p.N,
+                fa.begin());
+      up(fa, p.Af[a]);
+    }
+  }
   // fields start at zero
   if (e == hipSuccess) e = hipMemsetAsync(p.C[0], 0, (size_t)p.N * st->es, s);
   if (e == hipSuccess) e = hipMemsetAsync(p.C[1], 0, (size_t)p.N * st->es, s);
   for (int ax = 0; ax < d && e == hipSuccess; ++ax) e = hipMemsetAsync(p.F[ax], 0, (size_t)p.N * st->es, s);
+  for (int ax = 0; ns && ax < d && e == hipSuccess; ++ax) {
+    e = hipMemsetAsync(p.Us[ax], 0, (size_t)p.N * st->es, s);
+    if (e == hipSuccess) e = hipMemsetAsync(p.Nh[ax], 0, (size_t)p.N * st->es, s);
+    if (e == hipSuccess && p.Ut[ax]) e = hipMemsetAsync(p.Ut[ax], 0, (size_t)p.N * st->es, s);
+  }
+  for (int k = 0; ns && k < 2 && e == hipSuccess; ++k) e = hipMemsetAsync(p.P[k], 0, (size_t)p.N * st->es, s);
   if (G && e == hipSuccess) e = hipMemsetAsync(p.CI, 0, (size_t)G * st->es, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e == hipSuccess) e = hipGetLastError();
@@ -370,6 +424,8 @@ extern "C" int ch_ib_state_create(const ch_ib_grid *grid, const ch_ib_geometry *
   }
   st->geom.alpha.clear();
   st->geom.alpha.shrink_to_fit();
+  st->geom.face_alpha.clear();
+  st->geom.face_alpha.shrink_to_fit();
   if (G) {
     st->d1_min = st->d1_max = geom->gamma[0] * geom->dn[0];
     for (int64_t i = 1; i < G; ++i) {
@@ -392,6 +448,7 @@ static int64_t field_count(const ch_ib_state *st, int field) {
     case CH_IB_FIELD_V: return st->plan.N;
     case CH_IB_FIELD_W: return st->plan.d == 3 ? st->plan.N : -1;
     case CH_IB_FIELD_CI: return st->plan.G;
+    case CH_IB_FIELD_P: return st->plan.ns ? st->plan.N : -1;
     default: return -1;
   }
 }
@@ -418,6 +475,8 @@ extern "C" int ch_ib_state_set(ch_ib_state *st, int field, const void *src, int 
   if (field != CH_IB_FIELD_CI) {
     st->needs_init = 1;
     st->r_valid = 0;
+    st->ns_first = 1;
+    st->ut_valid = 0;
   }
   return CH_IB_OK;
 }
@@ -464,6 +523,7 @@ extern "C" int ch_ib_state_get(ch_ib_state *st, int field, void *dst, int dst_on
     case CH_IB_FIELD_V: src = p.F[1]; break;
     case CH_IB_FIELD_W: src = p.F[2]; break;
     case CH_IB_FIELD_CI: src = p.CI; break;
+    case CH_IB_FIELD_P: src = p.P[0]; break;
     case CH_IB_FIELD_ALPHA:
       if (!st->has_alpha) {
         if (st->es == 8) {
@@ -501,15 +561,38 @@ extern "C" int ch_ib_state_get(ch_ib_state *st, int field, void *dst, int dst_on
 // One step of the state's scheme; the explicit scheme's first step after (re)initialisation has no
 // previous rate.
 static hipError_t enqueue_one_step(ch_ib_state *st, chib::KernelTimer *tm) {
-  const chib::Plan &p = st->plan;
-  hipError_t e;
-  if (p.explicit_ab2) {
-    e = st->es == 8 ? chib::enqueue_explicit_step<double>(p, st->cur, !st->r_valid, tm)
-                    : chib::enqueue_explicit_step<float>(p, st->cur, !st->r_valid, tm);
-    if (e == hipSuccess) st->r_valid = 1;
-    return e;
+  chib::Plan &p = st->plan;
+  hipError_t e = hipSuccess;
+  chib::Plan q = p;   // the order-parameter part
+  if (p.ns) {
+    // the momentum step does the velocity fill; the semi-implicit rhs advects with 2u^n - u^(n-1)
+    q.vel_fill = 0;
+    if (!p.explicit_ab2) {
+      for (int a = 0; a < p.d && !st->ut_valid && e == hipSuccess; ++a)
+        e = hipMemcpyAsync(p.Ut[a], p.F[a], (size_t)p.N * st->es, hipMemcpyDeviceToDevice, p.stream);
+      if (e != hipSuccess) return e;
+      st->ut_valid = 1;
+      for (int a = 0; a < 3; ++a) q.Fadv[a] = p.Ut[a];
+    }
   }
-  return st->es == 8 ? chib::enqueue_step<double>(p, st->cur, tm) : chib::enqueue_step<float>(p, st->cur, tm);
+  if (p.explicit_ab2) {
+    e = st->es == 8 ? chib::enqueue_explicit_step<double>(q, st->cur, !st->r_valid, tm)
+                    : chib::enqueue_explicit_step<float>(q, st->cur, !st->r_valid, tm);
+    if (e == hipSuccess) st->r_valid = 1;
+  } else {
+    e = st->es == 8 ? chib::enqueue_step<double>(q, st->cur, tm) : chib::enqueue_step<float>(q, st->cur, tm);
+  }
+  if (e != hipSuccess || !p.ns) return e;
+  e = st->es == 8 ? chib::enqueue_momentum<double>(p, 1 - st->cur, st->ns_first, tm)
+                  : chib::enqueue_momentum<float>(p, 1 - st->cur, st->ns_first, tm);
+  if (e != hipSuccess) return e;
+  st->ns_first = 0;
+  // p^(n+1) is in W: it becomes p^n, p^n becomes p^(n-1), and p^(n-1)'s buffer the workspace
+  void *w = p.W;
+  p.W = p.P[1];
+  p.P[1] = p.P[0];
+  p.P[0] = w;
+  return e;
 }
 
 extern "C" int ch_ib_step(ch_ib_state *st, int n_steps) {
@@ -684,19 +767,38 @@ struct BlobHeader {
 };
 }  // namespace
 
+static unsigned blob_version(const chib::Plan &p) { return (p.explicit_ab2 ? 2u : 1u) + (p.ns ? 2u : 0u); }
+
+// Device fields of the momentum step kept in a blob, in order.
+static std::vector<const void *> ns_fields(const chib::Plan &p) {
+  std::vector<const void *> f;
+  if (!p.ns) return f;
+  f.push_back(p.P[0]);
+  f.push_back(p.P[1]);
+  for (int a = 0; a < p.d; ++a) f.push_back(p.Nh[a]);
+  for (int a = 0; a < p.d && p.Ut[0]; ++a) f.push_back(p.Ut[a]);
+  return f;
+}
+
+static size_t ns_extra(const chib::Plan &p, int es) {
+  return p.ns ? 2 * sizeof(int64_t) + ns_fields(p).size() * (size_t)p.N * es : 0;
+}
+
 extern "C" int ch_ib_state_save(ch_ib_state *st, void *buf, size_t *len) {
   if (!st || !len) return fail(CH_IB_EINVAL, "NULL argument");
   const chib::Plan &p = st->plan;
   const size_t fb = (size_t)p.N * st->es, gb = (size_t)p.G * st->es;
-  // version 2 (explicit scheme) appends the history flag and the previous step's rate
-  const size_t extra = p.explicit_ab2 ? sizeof(int64_t) + fb : 0;
+  // version 2 (explicit scheme) appends the history flag and the previous step's rate; versions 3
+  // and 4 (momentum step, semi-implicit / explicit) then append two flags, p^n, p^(n-1), the
+  // previous convective term and, semi-implicit, the advecting velocity
+  const size_t extra = (p.explicit_ab2 ? sizeof(int64_t) + fb : 0) + ns_extra(p, st->es);
   const size_t need = sizeof(BlobHeader) + (2 + p.d) * fb + 3 * gb + extra;
   if (!buf) {
     *len = need;
     return CH_IB_OK;
   }
   if (*len < need) return fail(CH_IB_ENOMEM, "buffer too small");
-  BlobHeader hd{kMagic, p.explicit_ab2 ? 2u : 1u, st->es, p.d, {p.n[0], p.n[1], p.n[2]}, st->needs_init,
+  BlobHeader hd{kMagic, blob_version(p), st->es, p.d, {p.n[0], p.n[1], p.n[2]}, st->needs_init,
                 p.G, p.NF, st->step};
   char *b = (char *)buf;
   std::memcpy(b, &hd, sizeof(hd));
@@ -720,6 +822,16 @@ extern "C" int ch_ib_state_save(ch_ib_state *st, void *buf, size_t *len) {
     std::memcpy(b, &rv, sizeof(rv));
     b += sizeof(rv);
     e = hipMemcpyAsync(b, p.R, fb, hipMemcpyDeviceToHost, p.stream);
+    b += fb;
+  }
+  if (p.ns && e == hipSuccess) {
+    const int64_t fl[2] = {st->ns_first, st->ut_valid};
+    std::memcpy(b, fl, sizeof(fl));
+    b += sizeof(fl);
+    for (const void *src : ns_fields(p)) {
+      if (e == hipSuccess) e = hipMemcpyAsync(b, src, fb, hipMemcpyDeviceToHost, p.stream);
+      b += fb;
+    }
   }
   if (e == hipSuccess) e = hipStreamSynchronize(p.stream);
   if (e != hipSuccess) return hip_fail(st, e, "save");
@@ -733,13 +845,13 @@ extern "C" int ch_ib_state_load(ch_ib_state *st, const void *buf, size_t len) {
   BlobHeader hd;
   if (len < sizeof(hd)) return fail(CH_IB_EINVAL, "blob too short");
   std::memcpy(&hd, buf, sizeof(hd));
-  if (hd.magic != kMagic || (hd.version != 1 && hd.version != 2)) return fail(CH_IB_EINVAL, "not a state blob");
-  if (hd.version != (p.explicit_ab2 ? 2u : 1u)) return fail(CH_IB_EINVAL, "blob saved with the other time scheme");
+  if (hd.magic != kMagic || hd.version < 1 || hd.version > 4) return fail(CH_IB_EINVAL, "not a state blob");
+  if (hd.version != blob_version(p)) return fail(CH_IB_EINVAL, "blob saved with another time scheme");
   if (hd.es != st->es || hd.d != p.d || hd.n[0] != p.n[0] || hd.n[1] != p.n[1] || hd.n[2] != p.n[2] ||
       hd.G != p.G || hd.NF != p.NF)
     return fail(CH_IB_EINVAL, "blob saved from a different grid, geometry or precision");
   const size_t fb = (size_t)p.N * st->es, gb = (size_t)p.G * st->es;
-  const size_t extra = p.explicit_ab2 ? sizeof(int64_t) + fb : 0;
+  const size_t extra = (p.explicit_ab2 ? sizeof(int64_t) + fb : 0) + ns_extra(p, st->es);
   const size_t need = sizeof(BlobHeader) + (2 + p.d) * fb + 3 * gb + extra;
   if (len < need) return fail(CH_IB_EINVAL, "blob too short");
   const char *b = (const char *)buf + sizeof(hd);
@@ -763,10 +875,22 @@ extern "C" int ch_ib_state_load(ch_ib_state *st, const void *buf, size_t len) {
     std::memcpy(&rv, b, sizeof(rv));
     b += sizeof(rv);
     e = hipMemcpyAsync(p.R, b, fb, hipMemcpyHostToDevice, p.stream);
+    b += fb;
+  }
+  int64_t fl[2] = {1, 0};
+  if (p.ns && e == hipSuccess) {
+    std::memcpy(fl, b, sizeof(fl));
+    b += sizeof(fl);
+    for (const void *dst : ns_fields(p)) {
+      if (e == hipSuccess) e = hipMemcpyAsync((void *)dst, b, fb, hipMemcpyHostToDevice, p.stream);
+      b += fb;
+    }
   }
   if (e == hipSuccess) e = hipStreamSynchronize(p.stream);
   if (e != hipSuccess) return hip_fail(st, e, "load");
   st->r_valid = rv ? 1 : 0;
+  st->ns_first = fl[0] ? 1 : 0;
+  st->ut_valid = fl[1] ? 1 : 0;
   st->step = hd.step;
   st->needs_init = hd.needs_init;
   st->sticky = CH_IB_OK;
@@ -870,6 +994,7 @@ extern "C" int ch_ib_batch_create(ch_ib_state *const *states, int n, void *ws, s
     if (s->plan.d != 2) return fail(CH_IB_EUNSUPPORTED, "batches hold 2D states only");
     if (s->plan.dynamic) return fail(CH_IB_EUNSUPPORTED, "batches hold static contact-angle states only");
     if (s->plan.explicit_ab2) return fail(CH_IB_EUNSUPPORTED, "batches hold semi-implicit states only");
+    if (s->plan.ns) return fail(CH_IB_EUNSUPPORTED, "batches hold states without the momentum step");
     if (s->sticky) return fail(s->sticky, "a member state is in an error state");
   }
   for (int c = 0; c < n; ++c) {

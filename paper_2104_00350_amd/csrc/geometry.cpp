@@ -232,41 +232,57 @@ extern "C" int ch_ib_geometry_build(const ch_ib_grid *grid, const ch_ib_shape *s
     for (int a = 0; a < d; ++a) x[a] = g->lo[a] + ((double)ijk[a] + 0.5) * h;
   };
 
-  // P1-P2: centre solid mask and volume fraction
+  // P1-P2: centre solid mask and volume fraction; with fa >= 0 the control volumes are the
+  // staggered cells of the faces normal to axis fa (shifted by h/2 along fa), the three further
+  // fractions of the staggered grid
   std::vector<uint8_t> csolid(N);
-  g->alpha.assign(N, 0.0);
   const double hs = h / sub;
   const int64_t per_cell = (int64_t)sub * sub * (d == 3 ? sub : 1);
-  parallel_for(N, [&](int64_t c) {
-    int ijk[3];
-    coords(c, ijk);
-    double xc[3] = {0, 0, 0};
-    centre(ijk, xc);
-    bool cs = S.solid(xc);
-    csolid[c] = cs;
-    bool cut = false;
-    for (const auto &sh : S.s) cut = cut || S.may_cut(sh, xc, h);
-    if (!cut) {
-      g->alpha[c] = cs ? 0.0 : 1.0;
-      return;
-    }
-    double base[3];
-    for (int a = 0; a < d; ++a) base[a] = g->lo[a] + (double)ijk[a] * h;
-    int64_t fluid = 0;
-    double x[3];
-    const int s2 = d == 3 ? sub : 1;
-    for (int k = 0; k < s2; ++k) {
-      if (d == 3) x[2] = base[2] + ((double)k + 0.5) * hs;
-      for (int j = 0; j < sub; ++j) {
-        x[1] = base[1] + ((double)j + 0.5) * hs;
-        for (int i = 0; i < sub; ++i) {
-          x[0] = base[0] + ((double)i + 0.5) * hs;
-          if (!S.solid(x)) ++fluid;
+  auto fractions = [&](int fa, std::vector<double> &out, uint8_t *mask) {
+    out.assign(N, 0.0);
+    double off[3] = {0.0, 0.0, 0.0};
+    if (fa >= 0) off[fa] = 0.5 * h;
+    parallel_for(N, [&](int64_t c) {
+      int ijk[3];
+      coords(c, ijk);
+      double xc[3] = {0, 0, 0};
+      centre(ijk, xc);
+      for (int a = 0; a < d; ++a) xc[a] = xc[a] + off[a];
+      bool cs = S.solid(xc);
+      if (mask) mask[c] = cs;
+      bool cut = false;
+      for (const auto &sh : S.s) cut = cut || S.may_cut(sh, xc, h);
+      if (!cut) {
+        out[c] = cs ? 0.0 : 1.0;
+        return;
+      }
+      double base[3];
+      for (int a = 0; a < d; ++a) base[a] = g->lo[a] + (double)ijk[a] * h + off[a];
+      int64_t fluid = 0;
+      double x[3];
+      const int s2 = d == 3 ? sub : 1;
+      for (int k = 0; k < s2; ++k) {
+        if (d == 3) x[2] = base[2] + ((double)k + 0.5) * hs;
+        for (int j = 0; j < sub; ++j) {
+          x[1] = base[1] + ((double)j + 0.5) * hs;
+          for (int i = 0; i < sub; ++i) {
+            x[0] = base[0] + ((double)i + 0.5) * hs;
+            if (!S.solid(x)) ++fluid;
+          }
         }
       }
+      out[c] = (double)fluid / (double)per_cell;
+    });
+  };
+  fractions(-1, g->alpha, csolid.data());
+  if (params->flags & CH_IB_FLAG_NAVIER_STOKES) {
+    std::vector<double> fr;
+    g->face_alpha.resize((size_t)d * N);
+    for (int a = 0; a < d; ++a) {
+      fractions(a, fr, nullptr);
+      std::copy(fr.begin(), fr.end(), g->face_alpha.begin() + (size_t)a * N);
     }
-    g->alpha[c] = (double)fluid / (double)per_cell;
-  });
+  }
 
   // ghosts
   auto lin_of = [&](const int *ijk) -> int64_t {
@@ -654,5 +670,24 @@ extern "C" int ch_ib_wall_field(const ch_ib_grid *grid, const ch_ib_shape *shape
     normal[c] = bn0;
     normal[(int64_t)nx * ny + c] = bn1;
   });
+  return CH_IB_OK;
+}
+
+extern "C" int ch_ib_geometry_face_fractions(const ch_ib_geometry *g, double *dst) {
+  using chib::fail;
+  if (!g || !dst) return fail(CH_IB_EINVAL, "NULL argument");
+  if (g->face_alpha.empty())
+    return fail(CH_IB_EUNSUPPORTED, "the geometry holds no staggered-cell fractions");
+  std::copy(g->face_alpha.begin(), g->face_alpha.end(), dst);
+  return CH_IB_OK;
+}
+
+extern "C" int ch_ib_geometry_set_face_fractions(ch_ib_geometry *g, const double *src) {
+  using chib::fail;
+  if (!g || !src) return fail(CH_IB_EINVAL, "NULL argument");
+  const size_t n = (size_t)g->ndim * (size_t)g->cells;
+  for (size_t i = 0; i < n; ++i)
+    if (!(src[i] >= 0.0 && src[i] <= 1.0)) return fail(CH_IB_EINVAL, "fractions must lie in [0, 1]");
+  g->face_alpha.assign(src, src + n);
   return CH_IB_OK;
 }

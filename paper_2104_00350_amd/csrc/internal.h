@@ -23,6 +23,7 @@ struct ch_ib_geometry {
   std::vector<int64_t> ap;       // [2][K][G]
   std::vector<double> w;         // [2][K][G]
   std::vector<double> alpha;     // [cells] or empty
+  std::vector<double> face_alpha;   // [ndim][cells] staggered-cell fractions, or empty
 };
 
 namespace chib {

@@ -28,6 +28,17 @@ struct Plan {
   void *W = nullptr;        // spectral workspace, N elements (explicit step: the chemical potential)
   void *R = nullptr;        // explicit step: rate of the previous step, N elements
   void *alpha = nullptr;    // N elements or nullptr (then alpha = 1)
+  void *Fadv[3] = {nullptr, nullptr, nullptr};   // advecting faces of the rhs pass (nullptr: F)
+
+  // momentum step (Navier-Stokes coupling): face fields of d components, N elements each
+  int ns = 0;
+  double Re = 1, rho1 = 1, rho2 = 1, mu1 = 1, mu2 = 1, g[3] = {0, 0, 0};
+  void *Us[3] = {nullptr, nullptr, nullptr};   // u** (prediction after penalisation, then filled)
+  void *Ut[3] = {nullptr, nullptr, nullptr};   // 2u^n - u^(n-1), the advecting velocity of the rhs pass
+  void *Nh[3] = {nullptr, nullptr, nullptr};   // convective term of the previous momentum step
+  void *Af[3] = {nullptr, nullptr, nullptr};   // staggered-cell fluid volume fractions
+  void *P[2] = {nullptr, nullptr};             // pressure p^n, p^(n-1)
+  int poisson = 0;          // bounded-axis pass divides by the Laplacian's eigenvalue (pressure)
 
   // ghost tables (SoA, sorted by cell)
   int64_t G = 0;
@@ -102,6 +113,13 @@ template <typename T> hipError_t enqueue_phi(const Plan &p, int cur, void *out);
 template <typename T>
 hipError_t enqueue_scalar_fill(const Plan &p, void *f, double a, double b, double g, const void *g_ghost);
 template <typename T> hipError_t enqueue_diag(const Plan &p, int cur);
+// Pressure solve in place on W: W <- the zero-mean p with lap_h p = W (zero flux through the box walls).
+template <typename T> hipError_t enqueue_poisson(const Plan &p);
+// Velocity ghost fill (slip and no-penetration) on the faces p.F with the order parameter Cfin.
+template <typename T> hipError_t enqueue_velocity_fill(const Plan &p, const void *Cfin);
+// Momentum step on the new order parameter C[cur] (prediction, penalisation, velocity fill,
+// pressure, correction); first: no previous convective term.  Leaves p^(n+1) in W.
+template <typename T> hipError_t enqueue_momentum(const Plan &p, int cur, int first, KernelTimer *tm = nullptr);
 
 // One grouped step over a batch of 2D cases (see the batched kernels).
 struct BatchLaunch {

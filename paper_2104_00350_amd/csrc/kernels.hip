@@ -807,7 +807,7 @@ __device__ __forceinline__ void neumann_body(unsigned char *smem_raw, T *__restr
                                                             const T *__restrict__ lamy, const T *__restrict__ lamz,
                                                             T a, T alpha_s, T inv_norm, const T *__restrict__ twr,
                                                             const T *__restrict__ twi, const T *__restrict__ dctc,
-                                                            const T *__restrict__ dcts, int tile) {
+                                                            const T *__restrict__ dcts, int tile, int poisson) {
   T *s = reinterpret_cast<T *>(smem_raw);
   const int N = 1 << logN, B = 1 << logB;
   const int t = tile;
@@ -845,11 +845,17 @@ __device__ __forceinline__ void neumann_body(unsigned char *smem_raw, T *__restr
     // cosine-transform coefficients X[k], X[N-k] of both columns
     T xa1 = T(2) * (c * var + sn * vai), xa2 = T(2) * (sn * var - c * vai);
     T xb1 = T(2) * (c * vbr + sn * vbi), xb2 = T(2) * (sn * vbr - c * vbi);
-    xa1 *= inv_norm / ((la + lk - a) * (la + lk + alpha_s));
-    xb1 *= inv_norm / ((lb + lk - a) * (lb + lk + alpha_s));
+    // (lam - a)(lam + alpha_s) for the order parameter; lam itself for the pressure, whose mean
+    // mode (lam = 0) is dropped
+    auto fac = [&](T l) {
+      if (poisson) return l != T(0) ? inv_norm / l : T(0);
+      return inv_norm / ((l - a) * (l + alpha_s));
+    };
+    xa1 *= fac(la + lk);
+    xb1 *= fac(lb + lk);
     if (k) {
-      xa2 *= inv_norm / ((la + lnk - a) * (la + lnk + alpha_s));
-      xb2 *= inv_norm / ((lb + lnk - a) * (lb + lnk + alpha_s));
+      xa2 *= fac(la + lnk);
+      xb2 *= fac(lb + lnk);
     } else {
       xa2 = T(0);
       xb2 = T(0);
@@ -883,9 +889,9 @@ __global__ __launch_bounds__(kThreads) void k_neumann_solve(T *__restrict__ W, i
                                                             const T *__restrict__ lamy, const T *__restrict__ lamz,
                                                             T a, T alpha_s, T inv_norm, const T *__restrict__ twr,
                                                             const T *__restrict__ twi, const T *__restrict__ dctc,
-                                                            const T *__restrict__ dcts) {
+                                                            const T *__restrict__ dcts, int poisson) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  neumann_body<T, E, MAXR>(smem_raw, W, logN, stride, logB, lognxb, outer, lamx, lamy, lamz, a, alpha_s, inv_norm, twr, twi, dctc, dcts, xcd_tile(blockIdx.x, gridDim.x));
+  neumann_body<T, E, MAXR>(smem_raw, W, logN, stride, logB, lognxb, outer, lamx, lamy, lamz, a, alpha_s, inv_norm, twr, twi, dctc, dcts, xcd_tile(blockIdx.x, gridDim.x), poisson);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -1640,6 +1646,10 @@ inline RhsCoef<T> make_coef(const Plan &p) {
 
 inline unsigned blocks_for(int64_t n) { return (unsigned)((n + kThreads - 1) / kThreads); }
 
+// Faces that advect C in the rhs pass: the extrapolated velocity when the momentum equation is
+// solved too, else the faces themselves.
+inline const void *adv_face(const Plan &p, int a) { return p.Fadv[a] ? p.Fadv[a] : p.F[a]; }
+
 // Launch shapes.  Each pass has a runtime-selected variant (see Plan::Shape): the log2 of
 // its lines (x passes) or columns (strided passes) per tile, the largest FFT radix (8 or
 // 16: fewer LDS passes against fewer registers) and, for the fused rhs pass, how many cells
@@ -1712,12 +1722,12 @@ hipError_t launch_neumann(const Plan &p, const Plan::Shape &sh) {
     hipLaunchKernelGGL((k_neumann_solve<T, E, 8>), dim3(nb), dim3(kThreads), lds, p.stream, (T *)p.W, p.logn[ax],
                        stride, lb, lxb, outer, (const T *)p.lam[0], lamy, (const T *)p.lam[ax], (T)p.a, (T)p.alpha_s,
                        (T)(1.0 / norm), (const T *)p.twr[ax], (const T *)p.twi[ax], (const T *)p.dctc,
-                       (const T *)p.dcts);
+                       (const T *)p.dcts, p.poisson);
   else
     hipLaunchKernelGGL((k_neumann_solve<T, E, 16>), dim3(nb), dim3(kThreads), lds, p.stream, (T *)p.W, p.logn[ax],
                        stride, lb, lxb, outer, (const T *)p.lam[0], lamy, (const T *)p.lam[ax], (T)p.a, (T)p.alpha_s,
                        (T)(1.0 / norm), (const T *)p.twr[ax], (const T *)p.twi[ax], (const T *)p.dctc,
-                       (const T *)p.dcts);
+                       (const T *)p.dcts, p.poisson);
   return hipGetLastError();
 }
 
@@ -1726,7 +1736,7 @@ void launch_rhs_variant(const Plan &p, const T *Cn, const T *Cp, int logL, unsig
   const Dims dm = make_dims(p);
   const RhsCoef<T> cf = make_coef<T>(p);
   hipLaunchKernelGGL((k_rhs_xdht<T, D, tile_elems<T>(), U, R>), dim3(nb), dim3(kThreads), lds, p.stream, Cn, Cp,
-                     (const T *)p.F[0], (const T *)p.F[1], (const T *)(D == 3 ? p.F[2] : p.F[1]), (T *)p.W, dm, cf,
+                     (const T *)adv_face(p, 0), (const T *)adv_face(p, 1), (const T *)(D == 3 ? adv_face(p, 2) : adv_face(p, 1)), (T *)p.W, dm, cf,
                      logL, (const T *)p.twr[0], (const T *)p.twi[0]);
 }
 
@@ -1740,7 +1750,7 @@ void launch_ym_variant(const Plan &p, const T *Cn, const T *Cp, int logL) {
   const unsigned nb = (unsigned)(p.n[1] >> logL);
   const size_t lds = ((size_t)(1 << logL) * line_pitch(p.n[0]) + ym_extra(p.n[0])) * sizeof(T);
   hipLaunchKernelGGL((k_rhs_xdht_ym<T, XM, R>), dim3(nb), dim3(kThreads), lds, p.stream, Cn, Cp,
-                     (const T *)p.F[0], (const T *)p.F[1], (T *)p.W, dm, cf, logL, (const T *)p.twr[0],
+                     (const T *)adv_face(p, 0), (const T *)adv_face(p, 1), (T *)p.W, dm, cf, logL, (const T *)p.twr[0],
                      (const T *)p.twi[0]);
 }
 
@@ -1761,7 +1771,7 @@ void launch_zm_variant(const Plan &p, const T *Cn, const T *Cp, int zc_log) {
   const unsigned nb = (unsigned)((p.n[1] / L) * (p.n[2] >> zc_log));
   const size_t lds = ((size_t)L * p.n[0] + (SPLIT ? 0 : (size_t)L * line_pitch(p.n[0]))) * sizeof(T);
   hipLaunchKernelGGL((k_rhs_xdht_zm<T, L, XM, R, SPLIT>), dim3(nb), dim3(kThreads), lds, p.stream, Cn, Cp,
-                     (const T *)p.F[0], (const T *)p.F[1], (const T *)p.F[2], (T *)p.W, dm, cf, zc_log,
+                     (const T *)adv_face(p, 0), (const T *)adv_face(p, 1), (const T *)adv_face(p, 2), (T *)p.W, dm, cf, zc_log,
                      (const T *)p.twr[0], (const T *)p.twi[0]);
 }
 
@@ -2092,13 +2102,13 @@ template <typename T>
 hipError_t enqueue_rhs(const Plan &p, int cur, void *out) {
   const Dims dm = make_dims(p);
   const RhsCoef<T> cf = make_coef<T>(p);
-  const T *F2 = (const T *)(p.d == 3 ? p.F[2] : p.F[1]);
+  const T *F2 = (const T *)(p.d == 3 ? adv_face(p, 2) : adv_face(p, 1));
   if (p.d == 2)
     hipLaunchKernelGGL((k_rhs_only<T, 2>), dim3(blocks_for(p.N)), dim3(kThreads), 0, p.stream, (const T *)p.C[cur],
-                       (const T *)p.C[1 - cur], (const T *)p.F[0], (const T *)p.F[1], F2, (T *)out, dm, cf, p.N);
+                       (const T *)p.C[1 - cur], (const T *)adv_face(p, 0), (const T *)adv_face(p, 1), F2, (T *)out, dm, cf, p.N);
   else
     hipLaunchKernelGGL((k_rhs_only<T, 3>), dim3(blocks_for(p.N)), dim3(kThreads), 0, p.stream, (const T *)p.C[cur],
-                       (const T *)p.C[1 - cur], (const T *)p.F[0], (const T *)p.F[1], F2, (T *)out, dm, cf, p.N);
+                       (const T *)p.C[1 - cur], (const T *)adv_face(p, 0), (const T *)adv_face(p, 1), F2, (T *)out, dm, cf, p.N);
   return hipGetLastError();
 }
 
@@ -2108,6 +2118,21 @@ hipError_t enqueue_solve(const Plan &p, const void *in, void *out) {
   if (e != hipSuccess) return e;
   if ((e = launch_spectral_tail<T>(p)) != hipSuccess) return e;
   return launch_xdht<T>(p, (const T *)p.W, (T *)out, p.shape[3]);
+}
+
+template <typename T>
+hipError_t enqueue_poisson(const Plan &p) {
+  Plan q = p;
+  q.poisson = 1;
+  hipError_t e = launch_xdht<T>(q, (const T *)q.W, (T *)q.W, q.shape[3]);
+  if (e != hipSuccess) return e;
+  if ((e = launch_spectral_tail<T>(q)) != hipSuccess) return e;
+  return launch_xdht<T>(q, (const T *)q.W, (T *)q.W, q.shape[3]);
+}
+
+template <typename T>
+hipError_t enqueue_velocity_fill(const Plan &p, const void *Cfin) {
+  return launch_velocity_fill<T>(p, (const T *)Cfin);
 }
 
 template <typename T>
@@ -2164,6 +2189,10 @@ template hipError_t enqueue_rhs<double>(const Plan &, int, void *);
 template hipError_t enqueue_rhs<float>(const Plan &, int, void *);
 template hipError_t enqueue_solve<double>(const Plan &, const void *, void *);
 template hipError_t enqueue_solve<float>(const Plan &, const void *, void *);
+template hipError_t enqueue_poisson<double>(const Plan &);
+template hipError_t enqueue_poisson<float>(const Plan &);
+template hipError_t enqueue_velocity_fill<double>(const Plan &, const void *);
+template hipError_t enqueue_velocity_fill<float>(const Plan &, const void *);
 template <typename T>
 hipError_t enqueue_explicit_step(const Plan &p, int cur, int first, KernelTimer *tm) {
   if (!p.R) return hipErrorInvalidValue;
@@ -2293,7 +2322,7 @@ __global__ __launch_bounds__(kThreads) void kb_neumann(const CaseDesc<T> *__rest
   const CaseDesc<T> &d = cs[c];
   neumann_body<T, E, R>(smem_raw, d.W, d.dm.lny, (int64_t)d.dm.nx, d.logB, d.lognxb, (int64_t)0, d.lamx,
                         (const T *)nullptr, d.lamy, d.a, d.alpha_s, d.inv_norm, d.twr1, d.twi1, d.dctc, d.dcts,
-                        (int)(blockIdx.x - off[c]));
+                        (int)(blockIdx.x - off[c]), 0);
 }
 
 template <typename T, int E, int R>

@@ -565,6 +565,7 @@ extern "C" int ch_ib_net_bind(ch_ib_net *n, ch_ib_state *st, const double *wall_
   if (p.d != 2 || r.es != 8) return chib::fail(CH_IB_EUNSUPPORTED, "the learned correction needs a 2D FP64 state");
   if (p.dynamic) return chib::fail(CH_IB_EUNSUPPORTED, "the learned correction needs the static condition");
   if (p.explicit_ab2) return chib::fail(CH_IB_EUNSUPPORTED, "the learned correction needs the semi-implicit scheme");
+  if (p.ns) return chib::fail(CH_IB_EUNSUPPORTED, "the learned correction runs without the momentum step");
   if ((p.n[0] % TS) || (p.n[1] % TS)) return chib::fail(CH_IB_EUNSUPPORTED, "grid sizes must be multiples of 16");
   if (p.N > n->max_cells) return chib::fail(CH_IB_EINVAL, "grid larger than max_cells");
   if (!(band_cells > 0)) return chib::fail(CH_IB_EINVAL, "band_cells must be > 0");
@@ -613,7 +614,7 @@ extern "C" int ch_ib_net_rebind(ch_ib_net *n, ch_ib_state *st) {
   int rc = chib::state_ref(st, &r);
   if (rc) return rc;
   const chib::Plan &p = *r.plan;
-  if (p.d != 2 || r.es != 8 || p.dynamic || p.explicit_ab2 || p.n[0] != n->nx || p.n[1] != n->ny || p.h != n->h)
+  if (p.d != 2 || r.es != 8 || p.dynamic || p.explicit_ab2 || p.ns || p.n[0] != n->nx || p.n[1] != n->ny || p.h != n->h)
     return chib::fail(CH_IB_EINVAL, "rebind needs a 2D FP64 static state on the bound grid");
   n->st = st;
   return CH_IB_OK;
