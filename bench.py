@@ -51,6 +51,19 @@ def algorithmic_bytes(name: str, cells: int, d: int, es: int, G: int, NF: int, d
     if name == "ghost_fills":                        # static: both fills, one launch plus the faces
         return (algorithmic_bytes("ghost_fill_C", cells, d, es, G, NF, dynamic)
                 + algorithmic_bytes("ghost_fill_u", cells, d, es, G, NF, dynamic))
+    # momentum step (Navier-Stokes coupling)
+    if name == "ns_phi":
+        return algorithmic_bytes("phi", cells, d, es, G, NF, dynamic)
+    if name == "ns_predict":                         # u^n, N^(n-1), alpha_face (d each), C, phi in; u**, N^n out
+        return cells * es * (5 * d + 2)
+    if name == "ns_vel_fill":
+        return algorithmic_bytes("ghost_fill_u", cells, d, es, G, NF, dynamic)
+    if name == "ns_pressure_rhs":                    # u** (d), C, p^n, p^(n-1) in; rhs out
+        return cells * es * (d + 4)
+    if name == "ns_poisson":                         # d + (d - 1) passes, one read and one write each
+        return cells * es * 2 * (2 * d - 1)
+    if name == "ns_correct":                         # u^n, u** (d each), C, p^(n+1), p^n, p^(n-1) in; u^(n+1), 2u^(n+1) - u^n out
+        return cells * es * (4 * d + 4)
     return 0.0
 
 
@@ -74,6 +87,8 @@ def kernel_template(name: str, shapes, es: int, nx: int) -> list:
         return [f"k_neumann_solve<{t}, {E}, {shapes[2][1]}>"]
     if name == "xdht_out":
         return [f"k_xdht<{t}, {E}, {shapes[3][1]}>"]
+    if name in ("ns_predict", "ns_pressure_rhs", "ns_correct"):
+        return [f"k_{name}<{t}>"]
     if name == "ghost_fill_C":
         return [f"k_fill_static<{t}>"]
     if name == "ghost_fill_u":
@@ -191,6 +206,41 @@ def explicit_benchmark(chib, geo, case, steps: int, precision: int, NF: int, sem
             "time_per_unit_sim_time_vs_semi_implicit": round(10 * ms_step / semi_ms, 3)}
 
 
+def ns_benchmark(chib, case, steps: int, precision: int, semi_ms: float, NF: int) -> dict:
+    """The coupled order-parameter + momentum step (Navier-Stokes coupling, sections 3.3-3.5) on
+    the same 256^3 workload, matched fluids (rho1 = rho2, mu1 = mu2: the explicit viscous term
+    then allows the workload's dt), started from rest: kernel times, bytes and the cost over the
+    order-parameter step alone."""
+    import dataclasses
+    prm = dataclasses.replace(case.params, navier_stokes=True)
+    g = case.grid
+    geo = chib.Geometry.build(g.n, g.lo, g.hi, case.shapes, prm)
+    st = chib.State(geo, prm, precision)
+    C0, faces = case.initial_fields()
+    st.set_initial(C0, faces)
+    st.step(5)
+    st.sync()
+    t0 = time.perf_counter()
+    ms = st.step_timed(steps)
+    wall = time.perf_counter() - t0
+    dg = st.diagnostics()
+    es = 8 if precision == 64 else 4
+    cells = g.cells
+    kern = {}
+    for name, t in ms.items():
+        b = algorithmic_bytes(name, cells, 3, es, st.G, NF, False)
+        kern[name] = {"ms": round(t, 5), "alg_bytes": int(b), "GB_s": round(b / (t * 1e-3) / 1e9, 1),
+                      "frac_of_8TBs": round(b / (t * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+    import numpy as np
+    umax = max(float(np.max(np.abs(st.get(chib.FIELD_U + a)))) for a in range(3))
+    ms_step = 1e3 * wall / steps
+    st.close()
+    return {"workload": "same 3D sphere workload with the momentum step (Re 5, Ca 0.05, matched fluids)",
+            "steps": steps, "status": dg["status"], "max_abs_C": dg["max_abs_C"], "max_abs_u": umax,
+            "cell_updates_per_s": cells * steps / wall, "ms_per_step": round(ms_step, 5),
+            "vs_order_parameter_step": round(ms_step / semi_ms, 3), "kernels": kern}
+
+
 def scalar_fill_benchmark(chib, st, case, reps: int = 50) -> dict:
     """Mixed-condition ghost fill of an arbitrary scalar (Robin, per-ghost g) on the 256^3 ghost set,
     timed with HIP events on the stream it is enqueued on."""
@@ -293,6 +343,8 @@ def main() -> int:
                     help="steps of the learned-correction comparison (0: skip)")
     ap.add_argument("--explicit-steps", type=int, default=100,
                     help="timed steps of the explicit scheme on the same workload (0: skip)")
+    ap.add_argument("--ns-steps", type=int, default=50,
+                    help="timed steps with the momentum step (Navier-Stokes coupling) on the same workload (0: skip)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="also run one plain device copy of this size (for counter calibration)")
     args = ap.parse_args()
@@ -408,6 +460,9 @@ def main() -> int:
         print("[bench] explicit scheme", file=sys.stderr, flush=True)
         out["explicit"] = explicit_benchmark(chib, geo, case, args.explicit_steps, args.precision, NF,
                                              out["ms_per_step"])
+    if args.ns_steps > 0:
+        print("[bench] Navier-Stokes coupling", file=sys.stderr, flush=True)
+        out["navier_stokes"] = ns_benchmark(chib, case, args.ns_steps, args.precision, out["ms_per_step"], NF)
     if args.sweep_steps > 0:
         print("[bench] batched sweep (64 cases)", file=sys.stderr, flush=True)
         out["batched_sweep"] = sweep_benchmark(chib, torch, args.sweep_steps)

@@ -237,6 +237,8 @@ extern "C" int ch_ib_state_create(const ch_ib_grid *grid, const ch_ib_geometry *
   if ((params->flags & CH_IB_FLAG_NAVIER_STOKES) &&
       geom->face_alpha.size() != (size_t)geom->ndim * (size_t)geom->cells)
     return fail(CH_IB_EINVAL, "the momentum step needs a geometry with staggered-cell fractions");
+  if ((params->flags & CH_IB_FLAG_NAVIER_STOKES) && geom->cells >= ((int64_t)1 << 31))
+    return fail(CH_IB_EUNSUPPORTED, "the momentum step indexes cells with 32-bit integers (fewer than 2^31 cells)");
   auto *st = new ch_ib_state();
   st->geom = *geom;
   st->prm = *params;

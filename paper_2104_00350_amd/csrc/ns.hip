@@ -28,10 +28,11 @@ namespace chib {
 
 namespace {
 
-constexpr int kNsThreads = 256;
+constexpr int kNsThreads = 256;   // the tiled walk below assumes 2^8 threads
 
 struct NsGrid {
-  int n[3];       // cells per axis (1 beyond d)
+  int n[3];       // cells per axis (1 beyond d); powers of two
+  int ln[3];      // log2 of n
   int d;
   int64_t N;
 };
@@ -49,38 +50,6 @@ struct FaceSet {
   T *f[3];
 };
 
-__device__ __forceinline__ int64_t lin3(const NsGrid &g, const int *q) {
-  return (int64_t)q[0] + (int64_t)g.n[0] * ((int64_t)q[1] + (int64_t)g.n[1] * q[2]);
-}
-
-// q + s e_b with periodic wrap on the periodic axes (the bounded axis is left as is).
-__device__ __forceinline__ void step_to(const NsGrid &g, const int *q, int b, int s, int *r) {
-  r[0] = q[0];
-  r[1] = q[1];
-  r[2] = q[2];
-  r[b] += s;
-  if (b < g.d - 1) r[b] = (r[b] + g.n[b]) % g.n[b];
-}
-
-// Face value u_a at cell q: zero outside the box along the bounded axis and on the top wall face.
-template <typename T>
-__device__ __forceinline__ T face_at(const NsGrid &g, const T *__restrict__ F, int a, const int *q) {
-  const int w = q[g.d - 1], nw = g.n[g.d - 1];
-  if (w < 0 || w >= nw) return T(0);
-  if (a == g.d - 1 && w == nw - 1) return T(0);
-  return F[lin3(g, q)];
-}
-
-// Cell scalar at q, reflected across the bounded axis' walls.
-template <typename T>
-__device__ __forceinline__ T cell_at(const NsGrid &g, const T *__restrict__ f, const int *q) {
-  int r[3] = {q[0], q[1], q[2]};
-  const int bw = g.d - 1;
-  if (r[bw] < 0) r[bw] = 0;
-  if (r[bw] >= g.n[bw]) r[bw] = g.n[bw] - 1;
-  return f[lin3(g, r)];
-}
-
 template <typename T>
 __device__ __forceinline__ T rho_of(const NsCoef<T> &k, T C) {
   return T(0.5) * ((C + T(1)) * k.rho2 - (C - T(1)) * k.rho1);
@@ -92,27 +61,93 @@ __device__ __forceinline__ T mu_of(const NsCoef<T> &k, T C) {
 }
 
 __device__ __forceinline__ void coords(const NsGrid &g, int64_t c, int *q) {
-  q[0] = (int)(c % g.n[0]);
-  const int64_t r = c / g.n[0];
-  q[1] = (int)(r % g.n[1]);
-  q[2] = (int)(r / g.n[1]);
+  q[0] = (int)(c & (g.n[0] - 1));
+  q[1] = (int)((c >> g.ln[0]) & (g.n[1] - 1));
+  q[2] = (int)(c >> (g.ln[0] + g.ln[1]));
+}
+
+// Cells a launch visits: one per thread (flat), or, on 3D grids, a tile of 2^ltx x 2^lty columns
+// per workgroup marched through zc consecutive planes, so that the planes above and below a cell
+// are still in the caches when its stencil reads them.
+struct NsWalk {
+  int flat;
+  int ltx, lty;         // tile: 2^ltx cells along x by 2^lty along y (ltx + lty = log2 of the workgroup)
+  int lbx, lby;         // log2 of the tile counts along x and y
+  int zc;               // planes per workgroup
+};
+
+template <typename F>
+__device__ __forceinline__ void for_each_cell(const NsWalk &wk, const NsGrid &g, F f) {
+  if (wk.flat) {
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c < g.N) f(c);
+    return;
+  }
+  const int b = (int)blockIdx.x;
+  const int bx = b & ((1 << wk.lbx) - 1);
+  const int by = (b >> wk.lbx) & ((1 << wk.lby) - 1);
+  const int bz = b >> (wk.lbx + wk.lby);
+  const int i = (bx << wk.ltx) + (int)(threadIdx.x & ((1u << wk.ltx) - 1));
+  const int j = (by << wk.lty) + (int)(threadIdx.x >> wk.ltx);
+  const int64_t row = (int64_t)i + ((int64_t)j << g.ln[0]);
+  for (int k = bz * wk.zc; k < (bz + 1) * wk.zc; ++k) f(row + ((int64_t)k << (g.ln[0] + g.ln[1])));
 }
 
 // Prediction (Eq. PredictionExp) and penalisation (Eq. Penalization2) on the d faces of each cell:
 //   u** = alpha_f (u^n + dt (-(3/2 N^n - 1/2 N^(n-1)) + ((1/Re) V + kappa phi_f dC/dx_a) / rho_f + g_a))
 // N: conservative central convective term; V: viscous term with mu from C^(n+1); phi = W.
 // Writes N^n over N^(n-1).  first: forward Euler for the convective term.
-template <typename T>
-__global__ __launch_bounds__(kNsThreads) void k_ns_predict(FaceSet<T> U, const T *__restrict__ C,
-                                                           const T *__restrict__ phi, FaceSet<T> Nh,
-                                                           FaceSet<T> Af, FaceSet<T> Us, NsGrid g, NsCoef<T> k,
-                                                           int first) {
-  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= g.N) return;
-  const int d = g.d, bw = d - 1, nw = g.n[bw];
+// Neighbour offsets of a cell: op[b] / om[b] move one cell up / down along axis b (periodic axes
+// wrap, the bounded axis steps a plane; validity along it is checked by the caller).
+template <int D>
+__device__ __forceinline__ void nbr_offsets(const NsGrid &g, const int *q, int *op, int *om) {
+#pragma unroll
+  for (int b = 0; b < D; ++b) {
+    const int sh = b == 0 ? 0 : (b == 1 ? g.ln[0] : g.ln[0] + g.ln[1]);
+    if (b < D - 1) {
+      op[b] = (((q[b] + 1) & (g.n[b] - 1)) - q[b]) << sh;
+      om[b] = (((q[b] - 1) & (g.n[b] - 1)) - q[b]) << sh;
+    } else {
+      op[b] = 1 << sh;
+      om[b] = -(1 << sh);
+    }
+  }
+}
+
+template <typename T, int D>
+__device__ __forceinline__ void ns_predict_cell(FaceSet<T> U, const T *__restrict__ C,
+                                                const T *__restrict__ phi, FaceSet<T> Nh,
+                                                FaceSet<T> Af, FaceSet<T> Us, NsGrid g, NsCoef<T> k,
+                                                int first, int64_t c64) {
+  constexpr int d = D, bw = D - 1;
+  const int c = (int)c64;
+  const int nw = g.n[bw];
   int q[3];
-  coords(g, c, q);
+  coords(g, c64, q);
   const int w = q[bw];
+  int op[3], om[3];
+  nbr_offsets<D>(g, q, op, om);
+  auto step = [&](int ax, int sgn) { return sgn > 0 ? op[ax] : om[ax]; };
+  // face value of component a at index i whose bounded coordinate is wq (zero outside the box and
+  // on the top wall face); the load always happens, from the cell itself when i is not valid, so
+  // that every load of the stencil can be in flight at once
+  auto fv = [&](const T *f, int a, int i, int wq) -> T {
+    const bool ok = wq >= 0 && wq < nw && !(a == bw && wq == nw - 1);
+    const T v = f[ok ? i : c];
+    return ok ? v : T(0);
+  };
+  auto F1 = [&](const T *f, int a, int ax, int sgn) -> T {
+    return fv(f, a, c + step(ax, sgn), w + (ax == bw ? sgn : 0));
+  };
+  auto F2 = [&](const T *f, int a, int ax1, int s1, int ax2, int s2) -> T {
+    return fv(f, a, c + step(ax1, s1) + step(ax2, s2), w + (ax1 == bw ? s1 : 0) + (ax2 == bw ? s2 : 0));
+  };
+  // cell scalar one cell away (reflected on the bounded axis)
+  auto roff = [&](int ax, int sgn) {
+    if (ax == bw && (w + sgn < 0 || w + sgn >= nw)) return 0;
+    return step(ax, sgn);
+  };
+#pragma unroll
   for (int a = 0; a < d; ++a) {
     if (a == bw && w == nw - 1) {   // top wall face: no penetration
       Us.f[a][c] = T(0);
@@ -120,67 +155,52 @@ __global__ __launch_bounds__(kNsThreads) void k_ns_predict(FaceSet<T> U, const T
       continue;
     }
     const T *ua = U.f[a];
-    int qa[3], qm[3];
-    step_to(g, q, a, 1, qa);
-    step_to(g, q, a, -1, qm);
-    const T u0 = face_at(g, ua, a, q);
+    const T u0 = ua[c];
     // convective term
     T N = T(0);
+#pragma unroll
     for (int b = 0; b < d; ++b) {
       if (b == a) {
-        const T uc0 = T(0.5) * (face_at(g, ua, a, qm) + u0);
-        const T uc1 = T(0.5) * (u0 + face_at(g, ua, a, qa));
+        const T uc0 = T(0.5) * (F1(ua, a, a, -1) + u0);
+        const T uc1 = T(0.5) * (u0 + F1(ua, a, a, 1));
         N += (uc1 * uc1 - uc0 * uc0) * k.inv_h;
       } else {
         const T *ub = U.f[b];
-        int qb[3], qbm[3], qab[3], qbma[3];
-        step_to(g, q, b, 1, qb);
-        step_to(g, q, b, -1, qbm);
-        step_to(g, qbm, a, 1, qbma);
-        (void)qab;
-        T E1 = T(0.5) * (u0 + face_at(g, ua, a, qb)) * T(0.5) * (face_at(g, ub, b, q) + face_at(g, ub, b, qa));
-        if (b == bw && w == nw - 1) E1 = T(0);
-        T E0 = T(0);
-        if (!(b == bw && w == 0))
-          E0 = T(0.5) * (face_at(g, ua, a, qbm) + u0) * T(0.5) * (face_at(g, ub, b, qbm) + face_at(g, ub, b, qbma));
+        const T e1 = T(0.5) * (u0 + F1(ua, a, b, 1)) * T(0.5) * (fv(ub, b, c, w) + F1(ub, b, a, 1));
+        const T e0 = T(0.5) * (F1(ua, a, b, -1) + u0) * T(0.5) * (F1(ub, b, b, -1) + F2(ub, b, b, -1, a, 1));
+        const T E1 = (b == bw && w == nw - 1) ? T(0) : e1;
+        const T E0 = (b == bw && w == 0) ? T(0) : e0;
         N += (E1 - E0) * k.inv_h;
       }
     }
     // viscous term
     const T mu_c = mu_of(k, C[c]);
-    const T mu_a = mu_of(k, cell_at(g, C, qa));
-    const T tn0 = T(2) * mu_c * (u0 - face_at(g, ua, a, qm)) * k.inv_h;
-    const T tn1 = T(2) * mu_a * (face_at(g, ua, a, qa) - u0) * k.inv_h;
+    const T mu_a = mu_of(k, C[c + roff(a, 1)]);
+    const T tn0 = T(2) * mu_c * (u0 - F1(ua, a, a, -1)) * k.inv_h;
+    const T tn1 = T(2) * mu_a * (F1(ua, a, a, 1) - u0) * k.inv_h;
     T V = (tn1 - tn0) * k.inv_h;
+#pragma unroll
     for (int b = 0; b < d; ++b) {
       if (b == a) continue;
       const T *ub = U.f[b];
-      int qb[3], qab[3], qbm[3], qabm[3], qbma[3];
-      step_to(g, q, b, 1, qb);
-      step_to(g, qa, b, 1, qab);
-      step_to(g, q, b, -1, qbm);
-      step_to(g, qa, b, -1, qabm);
-      step_to(g, qbm, a, 1, qbma);
-      (void)qabm;
       // edge c + e_a/2 + e_b/2
-      const T me1 = T(0.25) * (mu_c + mu_a + mu_of(k, cell_at(g, C, qb)) + mu_of(k, cell_at(g, C, qab)));
-      const T ub_up = (b == bw && w == nw - 1) ? -u0 : face_at(g, ua, a, qb);
-      const T tau1 = me1 * ((ub_up - u0) * k.inv_h + (face_at(g, ub, b, qa) - face_at(g, ub, b, q)) * k.inv_h);
-      T tau0;
-      if (b == bw && w == 0) {   // edge on the bottom wall: no-slip image, u_b = 0 along the wall
-        tau0 = T(0.5) * (mu_c + mu_a) * (u0 - (-u0)) * k.inv_h;
-      } else {
-        const T mu_b = mu_of(k, cell_at(g, C, qbm));
-        const T mu_ab = mu_of(k, cell_at(g, C, qbma));
-        const T me0 = T(0.25) * (mu_b + mu_ab + mu_c + mu_a);
-        const T ua_m = face_at(g, ua, a, qbm);
-        tau0 = me0 * ((u0 - ua_m) * k.inv_h + (face_at(g, ub, b, qbma) - face_at(g, ub, b, qbm)) * k.inv_h);
-      }
+      const T me1 = T(0.25) * (mu_c + mu_a + mu_of(k, C[c + roff(b, 1)]) + mu_of(k, C[c + roff(a, 1) + roff(b, 1)]));
+      const T ub_up = (b == bw && w == nw - 1) ? -u0 : F1(ua, a, b, 1);
+      const T tau1 = me1 * ((ub_up - u0) * k.inv_h + (F1(ub, b, a, 1) - fv(ub, b, c, w)) * k.inv_h);
+      // edge c + e_a/2 - e_b/2; on the bottom wall the no-slip image and u_b = 0 along the wall
+      const T mu_b = mu_of(k, C[c + roff(b, -1)]);
+      const T mu_ab = mu_of(k, C[c + roff(b, -1) + roff(a, 1)]);
+      const T me0 = T(0.25) * (mu_b + mu_ab + mu_c + mu_a);
+      const T ua_m = F1(ua, a, b, -1);
+      const T tin = me0 * ((u0 - ua_m) * k.inv_h + (F2(ub, b, b, -1, a, 1) - F1(ub, b, b, -1)) * k.inv_h);
+      const T twall = T(0.5) * (mu_c + mu_a) * (u0 - (-u0)) * k.inv_h;
+      const T tau0 = (b == bw && w == 0) ? twall : tin;
       V += (tau1 - tau0) * k.inv_h;
     }
     // capillary force and density on the face
-    const T C0 = C[c], C1 = cell_at(g, C, qa);
-    const T F = k.kappa * (T(0.5) * (phi[c] + cell_at(g, phi, qa))) * (C1 - C0) * k.inv_h;
+    const int ia = c + roff(a, 1);
+    const T C0 = C[c], C1 = C[ia];
+    const T F = k.kappa * (T(0.5) * (phi[c] + phi[ia])) * (C1 - C0) * k.inv_h;
     const T rf = T(0.5) * (rho_of(k, C0) + rho_of(k, C1));
     const T Np = first ? N : Nh.f[a][c];
     const T us = u0 + k.dt * (-(T(1.5) * N - T(0.5) * Np) + (V * k.inv_re + F) / rf + k.g[a]);
@@ -189,71 +209,99 @@ __global__ __launch_bounds__(kNsThreads) void k_ns_predict(FaceSet<T> U, const T
   }
 }
 
+template <typename T, int D>
+__global__ __launch_bounds__(kNsThreads) void k_ns_predict(FaceSet<T> U, const T *__restrict__ C,
+                                                           const T *__restrict__ phi, FaceSet<T> Nh,
+                                                           FaceSet<T> Af, FaceSet<T> Us, NsGrid g, NsCoef<T> k,
+                                                           int first, NsWalk wk) {
+  for_each_cell(wk, g, [&](int64_t c) { ns_predict_cell<T, D>(U, C, phi, Nh, Af, Us, g, k, first, c); });
+}
+
 // Right-hand side of Eq. PressurePoisson at the cell centres:
 //   div((1 - rho0/rho_f) grad p^) + (rho0/dt) div u**,  p^ = 2 P0 - P1; no flux through the walls.
-template <typename T>
-__global__ __launch_bounds__(kNsThreads) void k_ns_pressure_rhs(FaceSet<T> Us, const T *__restrict__ C,
-                                                                const T *__restrict__ P0, const T *__restrict__ P1,
-                                                                T *__restrict__ R, NsGrid g, NsCoef<T> k) {
-  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= g.N) return;
-  const int d = g.d, bw = d - 1, nw = g.n[bw];
+template <typename T, int D>
+__device__ __forceinline__ void ns_prhs_cell(FaceSet<T> Us, const T *__restrict__ C,
+                                             const T *__restrict__ P0, const T *__restrict__ P1,
+                                             T *__restrict__ R, NsGrid g, NsCoef<T> k, int64_t c64) {
+  constexpr int d = D, bw = D - 1;
+  const int c = (int)c64;
+  const int nw = g.n[bw];
   int q[3];
-  coords(g, c, q);
+  coords(g, c64, q);
   const int w = q[bw];
-  auto ph = [&](const int *r) { return T(2) * cell_at(g, P0, r) - cell_at(g, P1, r); };
-  // flux (1 - rho0/rho_f) dp^/dx_a on the face of cell r along a (zero on the top wall face)
-  auto flux = [&](const int *r, int a) {
-    if (a == bw && r[bw] == nw - 1) return T(0);
-    int ra[3];
-    step_to(g, r, a, 1, ra);
-    const T rf = T(0.5) * (rho_of(k, cell_at(g, C, r)) + rho_of(k, cell_at(g, C, ra)));
-    return (T(1) - k.rho0 / rf) * ((ph(ra) - ph(r)) * k.inv_h);
-  };
+  int op[3], om[3];
+  nbr_offsets<D>(g, q, op, om);
+  auto ph = [&](int i) { return T(2) * P0[i] - P1[i]; };
+  const T phc = ph(c);
+  const T rc = rho_of(k, C[c]);
   T acc1 = T(0), acc2 = T(0);
+#pragma unroll
   for (int a = 0; a < d; ++a) {
-    int qm[3];
-    step_to(g, q, a, -1, qm);
-    const bool below_wall = (a == bw && w == 0);
-    const T fu = flux(q, a);
-    const T fl = below_wall ? T(0) : flux(qm, a);
+    // flux (1 - rho0/rho_f) dp^/dx_a through the upper and the lower face of the cell along a
+    // (every load happens, from the cell itself where a face lies on a box wall)
+    const bool top = a == bw && w == nw - 1, bottom = a == bw && w == 0;
+    const int i1 = c + (top ? 0 : op[a]);
+    const int i0 = c + (bottom ? 0 : om[a]);
+    const T rf1 = T(0.5) * (rc + rho_of(k, C[i1]));
+    const T rf0 = T(0.5) * (rho_of(k, C[i0]) + rc);
+    const T fu1 = (T(1) - k.rho0 / rf1) * ((ph(i1) - phc) * k.inv_h);
+    const T fl0 = (T(1) - k.rho0 / rf0) * ((phc - ph(i0)) * k.inv_h);
+    const T uu1 = Us.f[a][c], ul0 = Us.f[a][i0];
+    const T fu = top ? T(0) : fu1, uu = top ? T(0) : uu1;
+    const T fl = bottom ? T(0) : fl0, ul = bottom ? T(0) : ul0;
     acc1 += fu - fl;
-    acc2 += face_at(g, Us.f[a], a, q) - face_at(g, Us.f[a], a, qm);
+    acc2 += uu - ul;
   }
   R[c] = acc1 * k.inv_h + k.rho0_dt * (acc2 * k.inv_h);
+}
+
+template <typename T, int D>
+__global__ __launch_bounds__(kNsThreads) void k_ns_pressure_rhs(FaceSet<T> Us, const T *__restrict__ C,
+                                                                const T *__restrict__ P0, const T *__restrict__ P1,
+                                                                T *__restrict__ R, NsGrid g, NsCoef<T> k, NsWalk wk) {
+  for_each_cell(wk, g, [&](int64_t c) { ns_prhs_cell<T, D>(Us, C, P0, P1, R, g, k, c); });
 }
 
 // Correction (Eq. correction): u^(n+1) = u** - dt (grad p^(n+1) / rho0 + (1/rho_f - 1/rho0) grad p^)
 // on every face but the top wall face; also writes the advecting velocity 2u^(n+1) - u^n of the
 // next order-parameter step (Ut, may be absent).
-template <typename T>
-__global__ __launch_bounds__(kNsThreads) void k_ns_correct(FaceSet<T> U, FaceSet<T> Ut, FaceSet<T> Us,
-                                                           const T *__restrict__ C, const T *__restrict__ Pn,
-                                                           const T *__restrict__ P0, const T *__restrict__ P1,
-                                                           NsGrid g, NsCoef<T> k, int with_ut) {
-  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= g.N) return;
-  const int d = g.d, bw = d - 1, nw = g.n[bw];
+template <typename T, int D>
+__device__ __forceinline__ void ns_correct_cell(FaceSet<T> U, FaceSet<T> Ut, FaceSet<T> Us,
+                                                const T *__restrict__ C, const T *__restrict__ Pn,
+                                                const T *__restrict__ P0, const T *__restrict__ P1,
+                                                NsGrid g, NsCoef<T> k, int with_ut, int64_t c64) {
+  constexpr int d = D, bw = D - 1;
+  const int c = (int)c64;
+  const int nw = g.n[bw];
   int q[3];
-  coords(g, c, q);
+  coords(g, c64, q);
   const int w = q[bw];
+  int op[3], om[3];
+  nbr_offsets<D>(g, q, op, om);
   const T phc = T(2) * P0[c] - P1[c];
   const T rc = rho_of(k, C[c]);
+  const T pc = Pn[c];
+#pragma unroll
   for (int a = 0; a < d; ++a) {
-    T un = T(0);
-    if (!(a == bw && w == nw - 1)) {
-      int qa[3];
-      step_to(g, q, a, 1, qa);
-      const int64_t ca = lin3(g, qa);
-      const T Gn = (Pn[ca] - Pn[c]) * k.inv_h;
-      const T Gh = ((T(2) * P0[ca] - P1[ca]) - phc) * k.inv_h;
-      const T rf = T(0.5) * (rc + rho_of(k, C[ca]));
-      un = Us.f[a][c] - k.dt * (Gn * k.inv_rho0 + (T(1) / rf - k.inv_rho0) * Gh);
-    }
+    const bool top = a == bw && w == nw - 1;
+    const int ca = c + (top ? 0 : op[a]);
+    const T Gn = (Pn[ca] - pc) * k.inv_h;
+    const T Gh = ((T(2) * P0[ca] - P1[ca]) - phc) * k.inv_h;
+    const T rf = T(0.5) * (rc + rho_of(k, C[ca]));
+    const T u1 = Us.f[a][c] - k.dt * (Gn * k.inv_rho0 + (T(1) / rf - k.inv_rho0) * Gh);
+    const T un = top ? T(0) : u1;
     const T uo = U.f[a][c];
     U.f[a][c] = un;
     if (with_ut) Ut.f[a][c] = T(2) * un - uo;
   }
+}
+
+template <typename T, int D>
+__global__ __launch_bounds__(kNsThreads) void k_ns_correct(FaceSet<T> U, FaceSet<T> Ut, FaceSet<T> Us,
+                                                           const T *__restrict__ C, const T *__restrict__ Pn,
+                                                           const T *__restrict__ P0, const T *__restrict__ P1,
+                                                           NsGrid g, NsCoef<T> k, int with_ut, NsWalk wk) {
+  for_each_cell(wk, g, [&](int64_t c) { ns_correct_cell<T, D>(U, Ut, Us, C, Pn, P0, P1, g, k, with_ut, c); });
 }
 
 template <typename T>
@@ -280,9 +328,31 @@ NsGrid ns_grid(const Plan &p) {
   g.n[0] = p.n[0];
   g.n[1] = p.n[1];
   g.n[2] = p.d == 3 ? p.n[2] : 1;
+  g.ln[0] = p.logn[0];
+  g.ln[1] = p.logn[1];
+  g.ln[2] = p.d == 3 ? p.logn[2] : 0;
   g.d = p.d;
   g.N = p.N;
   return g;
+}
+
+// 3D: tiles of 64 x 4 columns (fewer along x on narrower grids) marched through 16 planes; 2D: flat.
+NsWalk ns_walk(const Plan &p, unsigned *nb) {
+  NsWalk w{};
+  w.flat = 1;
+  *nb = (unsigned)((p.N + kNsThreads - 1) / kNsThreads);
+  if (p.d != 3) return w;
+  const int ltx = p.logn[0] < 6 ? p.logn[0] : 6;
+  const int lty = 8 - ltx;   // 256 threads
+  if (lty > p.logn[1]) return w;
+  w.flat = 0;
+  w.ltx = ltx;
+  w.lty = lty;
+  w.lbx = p.logn[0] - ltx;
+  w.lby = p.logn[1] - lty;
+  w.zc = p.n[2] < 16 ? p.n[2] : 16;
+  *nb = (unsigned)((1u << (w.lbx + w.lby)) * (unsigned)(p.n[2] / w.zc));
+  return w;
 }
 
 template <typename T>
@@ -303,7 +373,8 @@ hipError_t enqueue_momentum(const Plan &p, int cur, int first, KernelTimer *tm) 
   if (!p.ns || !p.P[0] || !p.P[1]) return hipErrorInvalidValue;
   const NsGrid g = ns_grid(p);
   const NsCoef<T> k = ns_coef<T>(p);
-  const unsigned nb = (unsigned)((p.N + kNsThreads - 1) / kNsThreads);
+  unsigned nb = 0;
+  const NsWalk wk = ns_walk(p, &nb);
   const T *C = (const T *)p.C[cur];
   const FaceSet<T> U = faces<T>(p.F, p.d), Us = faces<T>(p.Us, p.d), Nh = faces<T>(p.Nh, p.d);
   const FaceSet<T> Af = faces<T>(p.Af, p.d);
@@ -313,8 +384,12 @@ hipError_t enqueue_momentum(const Plan &p, int cur, int first, KernelTimer *tm) 
   if (e == hipSuccess) e = enqueue_phi<T>(p, cur, p.W);
   mark("ns_predict");
   if (e == hipSuccess) {
-    hipLaunchKernelGGL((k_ns_predict<T>), dim3(nb), dim3(kNsThreads), 0, p.stream, U, C, (const T *)p.W, Nh, Af, Us,
-                       g, k, first);
+    if (p.d == 2)
+      hipLaunchKernelGGL((k_ns_predict<T, 2>), dim3(nb), dim3(kNsThreads), 0, p.stream, U, C, (const T *)p.W, Nh, Af,
+                         Us, g, k, first, wk);
+    else
+      hipLaunchKernelGGL((k_ns_predict<T, 3>), dim3(nb), dim3(kNsThreads), 0, p.stream, U, C, (const T *)p.W, Nh, Af,
+                         Us, g, k, first, wk);
     e = hipGetLastError();
   }
   mark("ns_vel_fill");
@@ -326,16 +401,24 @@ hipError_t enqueue_momentum(const Plan &p, int cur, int first, KernelTimer *tm) 
   }
   mark("ns_pressure_rhs");
   if (e == hipSuccess) {
-    hipLaunchKernelGGL((k_ns_pressure_rhs<T>), dim3(nb), dim3(kNsThreads), 0, p.stream, Us, C, (const T *)p.P[0],
-                       (const T *)p.P[1], (T *)p.W, g, k);
+    if (p.d == 2)
+      hipLaunchKernelGGL((k_ns_pressure_rhs<T, 2>), dim3(nb), dim3(kNsThreads), 0, p.stream, Us, C,
+                         (const T *)p.P[0], (const T *)p.P[1], (T *)p.W, g, k, wk);
+    else
+      hipLaunchKernelGGL((k_ns_pressure_rhs<T, 3>), dim3(nb), dim3(kNsThreads), 0, p.stream, Us, C,
+                         (const T *)p.P[0], (const T *)p.P[1], (T *)p.W, g, k, wk);
     e = hipGetLastError();
   }
   mark("ns_poisson");
   if (e == hipSuccess) e = enqueue_poisson<T>(p);
   mark("ns_correct");
   if (e == hipSuccess) {
-    hipLaunchKernelGGL((k_ns_correct<T>), dim3(nb), dim3(kNsThreads), 0, p.stream, U, Ut, Us, C, (const T *)p.W,
-                       (const T *)p.P[0], (const T *)p.P[1], g, k, with_ut ? 1 : 0);
+    if (p.d == 2)
+      hipLaunchKernelGGL((k_ns_correct<T, 2>), dim3(nb), dim3(kNsThreads), 0, p.stream, U, Ut, Us, C,
+                         (const T *)p.W, (const T *)p.P[0], (const T *)p.P[1], g, k, with_ut ? 1 : 0, wk);
+    else
+      hipLaunchKernelGGL((k_ns_correct<T, 3>), dim3(nb), dim3(kNsThreads), 0, p.stream, U, Ut, Us, C,
+                         (const T *)p.W, (const T *)p.P[0], (const T *)p.P[1], g, k, with_ut ? 1 : 0, wk);
     e = hipGetLastError();
   }
   if (tm && e == hipSuccess) e = tm->end(p.stream);
