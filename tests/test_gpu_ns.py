@@ -120,6 +120,23 @@ def test_coupled_steps_3d(chib):
         _check(chib, st, orc, 3, f"3D step {orc.step_count}")
 
 
+def test_coupled_steps_3d_wide(chib):
+    """A grid 64 cells wide with a wall and a bump: the prediction walks whole 64 x 4 column tiles."""
+    grid = W.Grid((64, 8, 32), (0.0, 0.0, 0.0), (2.0, 0.25, 1.0))
+    prm = W.Params(Cn=0.04, Pe=50.0, Re=10.0, Ca=0.2, theta_deg=60.0, slip_length=0.02, dt=1e-4,
+                   navier_stokes=True, rho1=0.2, rho2=1.0, mu1=0.5, mu2=1.0, body_force=(0.0, 0.0, -0.3))
+    shapes = [W.Shape(W.HALFPLANE, (0.0, 0.0, 0.3, 0.0, 0.0, 1.0)), W.Shape(W.SPHERE, (1.0, 0.125, 0.25, 0.2))]
+    C0, _ = W.droplet_field(grid, (1.0, 0.125, 0.55), 0.25, prm.Cn, 1e-3, 5)
+    rng = np.random.default_rng(17)
+    faces = [0.05 * rng.standard_normal(grid.shape) for _ in range(3)]
+    st, orc = _pair(chib, grid, prm, shapes, C0, faces)
+    st.step(0)
+    for k in (1, 19):
+        st.step(k)
+        orc.step(k)
+        _check(chib, st, orc, 3, f"3D tiled step {orc.step_count}")
+
+
 def test_fp32_tracks_the_fp64_oracle(chib):
     grid, prm, shapes, C0, faces = _drop_2d()
     st, orc = _pair(chib, grid, prm, shapes, C0, faces, precision=32)
