@@ -206,7 +206,7 @@ def explicit_benchmark(chib, geo, case, steps: int, precision: int, NF: int, sem
             "time_per_unit_sim_time_vs_semi_implicit": round(10 * ms_step / semi_ms, 3)}
 
 
-def ns_benchmark(chib, case, steps: int, precision: int, semi_ms: float, NF: int) -> dict:
+def ns_benchmark(chib, case, steps: int, precision: int, semi_ms: float, NF: int, shapes) -> dict:
     """The coupled order-parameter + momentum step (Navier-Stokes coupling, sections 3.3-3.5) on
     the same 256^3 workload, matched fluids (rho1 = rho2, mu1 = mu2: the explicit viscous term
     then allows the workload's dt), started from rest: kernel times, bytes and the cost over the
@@ -216,6 +216,7 @@ def ns_benchmark(chib, case, steps: int, precision: int, semi_ms: float, NF: int
     g = case.grid
     geo = chib.Geometry.build(g.n, g.lo, g.hi, case.shapes, prm)
     st = chib.State(geo, prm, precision)
+    st.set_shapes(shapes)          # the order-parameter passes run with the main state's launch shapes
     C0, faces = case.initial_fields()
     st.set_initial(C0, faces)
     st.step(5)
@@ -462,7 +463,8 @@ def main() -> int:
                                              out["ms_per_step"])
     if args.ns_steps > 0:
         print("[bench] Navier-Stokes coupling", file=sys.stderr, flush=True)
-        out["navier_stokes"] = ns_benchmark(chib, case, args.ns_steps, args.precision, out["ms_per_step"], NF)
+        out["navier_stokes"] = ns_benchmark(chib, case, args.ns_steps, args.precision, out["ms_per_step"], NF,
+                                            st.shapes())
     if args.sweep_steps > 0:
         print("[bench] batched sweep (64 cases)", file=sys.stderr, flush=True)
         out["batched_sweep"] = sweep_benchmark(chib, torch, args.sweep_steps)
