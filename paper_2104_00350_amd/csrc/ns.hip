@@ -217,6 +217,163 @@ __global__ __launch_bounds__(kNsThreads) void k_ns_predict(FaceSet<T> U, const T
   for_each_cell(wk, g, [&](int64_t c) { ns_predict_cell<T, D>(U, C, phi, Nh, Af, Us, g, k, first, c); });
 }
 
+// 3D prediction with each edge formed once.  The convective flux E_ab = (u_a mean along b)(u_b mean
+// along a) and the shear stress tau_ab = mu_e (du_a/dx_b + du_b/dx_a) of an edge are symmetric in a and
+// b and are used by four faces; the per-cell kernel forms them four times.  Here a workgroup owns a
+// 64 x 4 tile of columns and marches it through zc planes: per plane it forms the xy, xz and yz edges
+// of the tile and of the halo column and row below it into LDS, every face takes its two edge
+// differences from there, and the xz and yz edges of the plane below come from registers.  Same
+// formulas and wall rules as ns_predict_cell (the four-cell mean viscosity of an edge is summed in the
+// order of its lower-axis face, so the other face's value may differ in the last bit).
+constexpr int kEx = 64, kEy = 4, kEhx = kEx + 1, kEhy = kEy + 1;
+
+// E and tau of the xy (0), xz (1) and yz (2) edges at cell (qx, qy, qz): edge o lies at the cell
+// centre plus half a cell along each of its two axes.
+template <typename T>
+__device__ __forceinline__ void ns_edges(const FaceSet<T> &U, const T *__restrict__ C, const NsGrid &g,
+                                         const NsCoef<T> &k, int qx, int qy, int qz, T *E, T *Tau) {
+  const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
+  const int cq = qx + (qy << g.ln[0]) + (qz << (g.ln[0] + g.ln[1]));
+  const int ox = ((qx + 1) & (nx - 1)) - qx;
+  const int oy = (((qy + 1) & (ny - 1)) - qy) << g.ln[0];
+  const bool top = qz == nz - 1;
+  const int oz = top ? 0 : (1 << (g.ln[0] + g.ln[1]));   // (unused at the top, kept in the box)
+  const T ux0 = U.f[0][cq], uy0 = U.f[1][cq];
+  const T uzr = U.f[2][cq];
+  const T uz0 = top ? T(0) : uzr;
+  const T ux_y = U.f[0][cq + oy], uy_x = U.f[1][cq + ox];
+  const T ux_z = U.f[0][cq + oz], uy_z = U.f[1][cq + oz];
+  const T uzx = U.f[2][cq + ox], uzy = U.f[2][cq + oy];
+  const T uz_x = top ? T(0) : uzx, uz_y = top ? T(0) : uzy;
+  const T mu_c = mu_of(k, C[cq]), mu_x = mu_of(k, C[cq + ox]), mu_y = mu_of(k, C[cq + oy]);
+  const T mu_xy = mu_of(k, C[cq + ox + oy]);
+  const T mu_z = mu_of(k, C[cq + oz]), mu_xz = mu_of(k, C[cq + ox + oz]), mu_yz = mu_of(k, C[cq + oy + oz]);
+  // xy
+  E[0] = T(0.5) * (ux0 + ux_y) * T(0.5) * (uy0 + uy_x);
+  Tau[0] = T(0.25) * (mu_c + mu_x + mu_y + mu_xy) * ((ux_y - ux0) * k.inv_h + (uy_x - uy0) * k.inv_h);
+  // xz and yz: on the top wall E = 0, the tangential velocity has the image -u, u_z = 0 along the wall
+  const T e1 = T(0.5) * (ux0 + ux_z) * T(0.5) * (uz0 + uz_x);
+  const T e2 = T(0.5) * (uy0 + uy_z) * T(0.5) * (uz0 + uz_y);
+  E[1] = top ? T(0) : e1;
+  E[2] = top ? T(0) : e2;
+  const T ux_up = top ? -ux0 : ux_z, uy_up = top ? -uy0 : uy_z;
+  Tau[1] = T(0.25) * (mu_c + mu_x + mu_z + mu_xz) * ((ux_up - ux0) * k.inv_h + (uz_x - uz0) * k.inv_h);
+  Tau[2] = T(0.25) * (mu_c + mu_y + mu_z + mu_yz) * ((uy_up - uy0) * k.inv_h + (uz_y - uz0) * k.inv_h);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kNsThreads) void k_ns_predict_edges(FaceSet<T> U, const T *__restrict__ C,
+                                                                const T *__restrict__ phi, FaceSet<T> Nh,
+                                                                FaceSet<T> Af, FaceSet<T> Us, NsGrid g,
+                                                                NsCoef<T> k, int first, int zc) {
+  __shared__ T sE[3][kEhy][kEhx];
+  __shared__ T sT[3][kEhy][kEhx];
+  const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
+  const int tiles_x = nx / kEx, tiles_y = ny / kEy;
+  int bidx = (int)blockIdx.x;
+  const int bx = bidx % tiles_x;
+  bidx /= tiles_x;
+  const int by = bidx % tiles_y;
+  const int bz = bidx / tiles_y;
+  const int x0 = bx * kEx, y0 = by * kEy, z0 = bz * zc;
+  const int tid = (int)threadIdx.x;
+  const int tx = tid & (kEx - 1), ty = tid >> 6;
+  const int x = x0 + tx, y = y0 + ty;
+  const int X = tx + 1, Y = ty + 1;
+  const int plane_sh = g.ln[0] + g.ln[1];
+  const int oxp = ((x + 1) & (nx - 1)) - x, oxm = ((x - 1) & (nx - 1)) - x;
+  const int oyp = (((y + 1) & (ny - 1)) - y) << g.ln[0], oym = (((y - 1) & (ny - 1)) - y) << g.ln[0];
+  // xz and yz edges of the plane below this thread's cell
+  T Ezx, Tzx, Ezy, Tzy;
+  if (z0 == 0) {   // the bottom wall: no flux, shear from the no-slip image
+    const int c = x + (y << g.ln[0]);
+    const T mu_c = mu_of(k, C[c]);
+    const T ux = U.f[0][c], uy = U.f[1][c];
+    Ezx = T(0);
+    Ezy = T(0);
+    Tzx = T(0.5) * (mu_c + mu_of(k, C[c + oxp])) * (ux - (-ux)) * k.inv_h;
+    Tzy = T(0.5) * (mu_c + mu_of(k, C[c + oyp])) * (uy - (-uy)) * k.inv_h;
+  } else {
+    T E[3], Tau[3];
+    ns_edges(U, C, g, k, x, y, z0 - 1, E, Tau);
+    Ezx = E[1];
+    Tzx = Tau[1];
+    Ezy = E[2];
+    Tzy = Tau[2];
+  }
+  for (int kz = z0; kz < z0 + zc; ++kz) {
+    for (int e = tid; e < kEhx * kEhy; e += kNsThreads) {
+      const int yy = e / kEhx, xx = e - yy * kEhx;
+      T E[3], Tau[3];
+      ns_edges(U, C, g, k, (x0 - 1 + xx) & (nx - 1), (y0 - 1 + yy) & (ny - 1), kz, E, Tau);
+#pragma unroll
+      for (int o = 0; o < 3; ++o) {
+        sE[o][yy][xx] = E[o];
+        sT[o][yy][xx] = Tau[o];
+      }
+    }
+    __syncthreads();
+    const int c = x + (y << g.ln[0]) + (kz << plane_sh);
+    const int ozp = kz < nz - 1 ? (1 << plane_sh) : 0, ozm = kz > 0 ? -(1 << plane_sh) : 0;
+    const int op[3] = {oxp, oyp, ozp}, om[3] = {oxm, oym, ozm};
+    const T C0 = C[c];
+    const T mu_c = mu_of(k, C0);
+    const T phc = phi[c];
+    const T rc = rho_of(k, C0);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      if (a == 2 && kz == nz - 1) {   // top wall face
+        Us.f[a][c] = T(0);
+        Nh.f[a][c] = T(0);
+        continue;
+      }
+      const T *ua = U.f[a];
+      const T u0 = ua[c];
+      const T umr = ua[c + om[a]], upr = ua[c + op[a]];
+      // the face below the bottom wall and the top wall face are zero
+      const T um = (a == 2 && kz == 0) ? T(0) : umr;
+      const T up = (a == 2 && kz + 1 == nz - 1) ? T(0) : upr;
+      T N = T(0), V;
+      const T uc0 = T(0.5) * (um + u0), uc1 = T(0.5) * (u0 + up);
+      const T Ca = C[c + op[a]];
+      const T mu_a = mu_of(k, Ca);
+      const T tn0 = T(2) * mu_c * (u0 - um) * k.inv_h;
+      const T tn1 = T(2) * mu_a * (up - u0) * k.inv_h;
+      V = (tn1 - tn0) * k.inv_h;
+      if (a == 0) {
+        N += (uc1 * uc1 - uc0 * uc0) * k.inv_h;
+        N += (sE[0][Y][X] - sE[0][Y - 1][X]) * k.inv_h;
+        N += (sE[1][Y][X] - Ezx) * k.inv_h;
+        V += (sT[0][Y][X] - sT[0][Y - 1][X]) * k.inv_h;
+        V += (sT[1][Y][X] - Tzx) * k.inv_h;
+      } else if (a == 1) {
+        N += (sE[0][Y][X] - sE[0][Y][X - 1]) * k.inv_h;
+        N += (uc1 * uc1 - uc0 * uc0) * k.inv_h;
+        N += (sE[2][Y][X] - Ezy) * k.inv_h;
+        V += (sT[0][Y][X] - sT[0][Y][X - 1]) * k.inv_h;
+        V += (sT[2][Y][X] - Tzy) * k.inv_h;
+      } else {
+        N += (sE[1][Y][X] - sE[1][Y][X - 1]) * k.inv_h;
+        N += (sE[2][Y][X] - sE[2][Y - 1][X]) * k.inv_h;
+        N += (uc1 * uc1 - uc0 * uc0) * k.inv_h;
+        V += (sT[1][Y][X] - sT[1][Y][X - 1]) * k.inv_h;
+        V += (sT[2][Y][X] - sT[2][Y - 1][X]) * k.inv_h;
+      }
+      const T F = k.kappa * (T(0.5) * (phc + phi[c + op[a]])) * (Ca - C0) * k.inv_h;
+      const T rf = T(0.5) * (rc + rho_of(k, Ca));
+      const T Np = first ? N : Nh.f[a][c];
+      const T us = u0 + k.dt * (-(T(1.5) * N - T(0.5) * Np) + (V * k.inv_re + F) / rf + k.g[a]);
+      Us.f[a][c] = Af.f[a][c] * us;
+      Nh.f[a][c] = N;
+    }
+    Ezx = sE[1][Y][X];
+    Tzx = sT[1][Y][X];
+    Ezy = sE[2][Y][X];
+    Tzy = sT[2][Y][X];
+    __syncthreads();   // the next plane's edges overwrite the buffers
+  }
+}
+
 // Right-hand side of Eq. PressurePoisson at the cell centres:
 //   div((1 - rho0/rho_f) grad p^) + (rho0/dt) div u**,  p^ = 2 P0 - P1; no flux through the walls.
 template <typename T, int D>
@@ -387,7 +544,12 @@ hipError_t enqueue_momentum(const Plan &p, int cur, int first, KernelTimer *tm) 
     if (p.d == 2)
       hipLaunchKernelGGL((k_ns_predict<T, 2>), dim3(nb), dim3(kNsThreads), 0, p.stream, U, C, (const T *)p.W, Nh, Af,
                          Us, g, k, first, wk);
-    else
+    else if (p.n[0] % kEx == 0 && p.n[1] % kEy == 0) {
+      const int zc = p.n[2] < 16 ? p.n[2] : 16;
+      const unsigned nbe = (unsigned)((p.n[0] / kEx) * (p.n[1] / kEy) * (p.n[2] / zc));
+      hipLaunchKernelGGL((k_ns_predict_edges<T>), dim3(nbe), dim3(kNsThreads), 0, p.stream, U, C, (const T *)p.W, Nh,
+                         Af, Us, g, k, first, zc);
+    } else
       hipLaunchKernelGGL((k_ns_predict<T, 3>), dim3(nb), dim3(kNsThreads), 0, p.stream, U, C, (const T *)p.W, Nh, Af,
                          Us, g, k, first, wk);
     e = hipGetLastError();
