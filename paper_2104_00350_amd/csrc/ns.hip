@@ -461,6 +461,116 @@ __global__ __launch_bounds__(kNsThreads) void k_ns_correct(FaceSet<T> U, FaceSet
   for_each_cell(wk, g, [&](int64_t c) { ns_correct_cell<T, D>(U, Ut, Us, C, Pn, P0, P1, g, k, with_ut, c); });
 }
 
+// 3D z-marching forms of the pressure rhs and the correction (tiled walk only): a thread carries its
+// column's values of the planes below and above from one plane to the next instead of fetching them
+// again; x and y neighbours come through the caches.  Same expressions as the per-cell forms.
+struct ZCol {
+  int c0;          // linear index of the column's first plane
+  int oxp, oxm, oyp, oym;
+  int k0, k1;      // planes [k0, k1)
+  int psh;         // log2 of the plane size
+};
+
+__device__ __forceinline__ ZCol zcol(const NsWalk &wk, const NsGrid &g) {
+  ZCol z;
+  const int b = (int)blockIdx.x;
+  const int bx = b & ((1 << wk.lbx) - 1);
+  const int by = (b >> wk.lbx) & ((1 << wk.lby) - 1);
+  const int bz = b >> (wk.lbx + wk.lby);
+  const int i = (bx << wk.ltx) + (int)(threadIdx.x & ((1u << wk.ltx) - 1));
+  const int j = (by << wk.lty) + (int)(threadIdx.x >> wk.ltx);
+  z.psh = g.ln[0] + g.ln[1];
+  z.k0 = bz * wk.zc;
+  z.k1 = z.k0 + wk.zc;
+  z.c0 = i + (j << g.ln[0]) + (z.k0 << z.psh);
+  z.oxp = ((i + 1) & (g.n[0] - 1)) - i;
+  z.oxm = ((i - 1) & (g.n[0] - 1)) - i;
+  z.oyp = (((j + 1) & (g.n[1] - 1)) - j) << g.ln[0];
+  z.oym = (((j - 1) & (g.n[1] - 1)) - j) << g.ln[0];
+  return z;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kNsThreads) void k_ns_pressure_rhs_zm(FaceSet<T> Us, const T *__restrict__ C,
+                                                                   const T *__restrict__ P0,
+                                                                   const T *__restrict__ P1, T *__restrict__ R,
+                                                                   NsGrid g, NsCoef<T> k, NsWalk wk) {
+  const ZCol z = zcol(wk, g);
+  const int nz = g.n[2], pl = 1 << z.psh;
+  auto ph = [&](int i) { return T(2) * P0[i] - P1[i]; };
+  int c = z.c0;
+  const int cb = z.k0 > 0 ? c - pl : c;     // the plane below (the first plane itself at the bottom)
+  T ph_m = ph(cb), r_m = rho_of(k, C[cb]), uz_m = Us.f[2][cb];
+  T phc = ph(c), rc = rho_of(k, C[c]);
+  for (int kz = z.k0; kz < z.k1; ++kz, c += pl) {
+    const bool top = kz == nz - 1, bottom = kz == 0;
+    const int cp = top ? c : c + pl;
+    const T ph_p = ph(cp), r_p = rho_of(k, C[cp]);
+    T acc1 = T(0), acc2 = T(0);
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+      const int i1 = c + (a == 0 ? z.oxp : z.oyp), i0 = c + (a == 0 ? z.oxm : z.oym);
+      const T rf1 = T(0.5) * (rc + rho_of(k, C[i1]));
+      const T rf0 = T(0.5) * (rho_of(k, C[i0]) + rc);
+      const T fu = (T(1) - k.rho0 / rf1) * ((ph(i1) - phc) * k.inv_h);
+      const T fl = (T(1) - k.rho0 / rf0) * ((phc - ph(i0)) * k.inv_h);
+      acc1 += fu - fl;
+      acc2 += Us.f[a][c] - Us.f[a][i0];
+    }
+    const T uzc = Us.f[2][c];
+    const T fu1 = (T(1) - k.rho0 / (T(0.5) * (rc + r_p))) * ((ph_p - phc) * k.inv_h);
+    const T fl0 = (T(1) - k.rho0 / (T(0.5) * (r_m + rc))) * ((phc - ph_m) * k.inv_h);
+    const T fu = top ? T(0) : fu1, uu = top ? T(0) : uzc;
+    const T fl = bottom ? T(0) : fl0, ul = bottom ? T(0) : uz_m;
+    acc1 += fu - fl;
+    acc2 += uu - ul;
+    R[c] = acc1 * k.inv_h + k.rho0_dt * (acc2 * k.inv_h);
+    ph_m = phc;
+    r_m = rc;
+    uz_m = uzc;
+    phc = ph_p;
+    rc = r_p;
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kNsThreads) void k_ns_correct_zm(FaceSet<T> U, FaceSet<T> Ut, FaceSet<T> Us,
+                                                              const T *__restrict__ C, const T *__restrict__ Pn,
+                                                              const T *__restrict__ P0, const T *__restrict__ P1,
+                                                              NsGrid g, NsCoef<T> k, int with_ut, NsWalk wk) {
+  const ZCol z = zcol(wk, g);
+  const int nz = g.n[2], pl = 1 << z.psh;
+  int c = z.c0;
+  T pc = Pn[c], phc = T(2) * P0[c] - P1[c], rc = rho_of(k, C[c]);
+  for (int kz = z.k0; kz < z.k1; ++kz, c += pl) {
+    const bool top = kz == nz - 1;
+    const int cp = top ? c : c + pl;
+    const T p_p = Pn[cp], ph_p = T(2) * P0[cp] - P1[cp], r_p = rho_of(k, C[cp]);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      T Gn, Gh, rf;
+      if (a < 2) {
+        const int ca = c + (a == 0 ? z.oxp : z.oyp);
+        Gn = (Pn[ca] - pc) * k.inv_h;
+        Gh = ((T(2) * P0[ca] - P1[ca]) - phc) * k.inv_h;
+        rf = T(0.5) * (rc + rho_of(k, C[ca]));
+      } else {
+        Gn = (p_p - pc) * k.inv_h;
+        Gh = (ph_p - phc) * k.inv_h;
+        rf = T(0.5) * (rc + r_p);
+      }
+      const T u1 = Us.f[a][c] - k.dt * (Gn * k.inv_rho0 + (T(1) / rf - k.inv_rho0) * Gh);
+      const T un = (a == 2 && top) ? T(0) : u1;
+      const T uo = U.f[a][c];
+      U.f[a][c] = un;
+      if (with_ut) Ut.f[a][c] = T(2) * un - uo;
+    }
+    pc = p_p;
+    phc = ph_p;
+    rc = r_p;
+  }
+}
+
 template <typename T>
 NsCoef<T> ns_coef(const Plan &p) {
   NsCoef<T> k;
@@ -566,6 +676,9 @@ hipError_t enqueue_momentum(const Plan &p, int cur, int first, KernelTimer *tm) 
     if (p.d == 2)
       hipLaunchKernelGGL((k_ns_pressure_rhs<T, 2>), dim3(nb), dim3(kNsThreads), 0, p.stream, Us, C,
                          (const T *)p.P[0], (const T *)p.P[1], (T *)p.W, g, k, wk);
+    else if (!wk.flat)
+      hipLaunchKernelGGL((k_ns_pressure_rhs_zm<T>), dim3(nb), dim3(kNsThreads), 0, p.stream, Us, C,
+                         (const T *)p.P[0], (const T *)p.P[1], (T *)p.W, g, k, wk);
     else
       hipLaunchKernelGGL((k_ns_pressure_rhs<T, 3>), dim3(nb), dim3(kNsThreads), 0, p.stream, Us, C,
                          (const T *)p.P[0], (const T *)p.P[1], (T *)p.W, g, k, wk);
@@ -577,6 +690,9 @@ hipError_t enqueue_momentum(const Plan &p, int cur, int first, KernelTimer *tm) 
   if (e == hipSuccess) {
     if (p.d == 2)
       hipLaunchKernelGGL((k_ns_correct<T, 2>), dim3(nb), dim3(kNsThreads), 0, p.stream, U, Ut, Us, C,
+                         (const T *)p.W, (const T *)p.P[0], (const T *)p.P[1], g, k, with_ut ? 1 : 0, wk);
+    else if (!wk.flat)
+      hipLaunchKernelGGL((k_ns_correct_zm<T>), dim3(nb), dim3(kNsThreads), 0, p.stream, U, Ut, Us, C,
                          (const T *)p.W, (const T *)p.P[0], (const T *)p.P[1], g, k, with_ut ? 1 : 0, wk);
     else
       hipLaunchKernelGGL((k_ns_correct<T, 3>), dim3(nb), dim3(kNsThreads), 0, p.stream, U, Ut, Us, C,
