@@ -137,6 +137,32 @@ def test_coupled_steps_3d_wide(chib):
         _check(chib, st, orc, 3, f"3D tiled step {orc.step_count}")
 
 
+def test_coupled_steps_dynamic_contact_angle(chib):
+    """Contact-line friction (Vs > 0): the dynamic ghost fill reads u^n and the velocity fill on u**
+    carries the capillary bracket."""
+    import dataclasses
+    grid, prm, shapes, C0, faces = _drop_2d()
+    prm = dataclasses.replace(prm, Vs=20.0)
+    st, orc = _pair(chib, grid, prm, shapes, C0, faces)
+    st.step(0)
+    for k in (1, 49):
+        st.step(k)
+        orc.step(k)
+        _check(chib, st, orc, 2, f"2D dynamic step {orc.step_count}")
+
+
+def test_coupled_steps_3d_explicit(chib):
+    import dataclasses
+    grid, prm, shapes, C0, faces = _drop_3d()
+    prm = dataclasses.replace(prm, explicit=True, dt=2e-5)
+    st, orc = _pair(chib, grid, prm, shapes, C0, faces)
+    st.step(0)
+    for k in (1, 19):
+        st.step(k)
+        orc.step(k)
+        _check(chib, st, orc, 3, f"3D explicit step {orc.step_count}")
+
+
 def test_fp32_tracks_the_fp64_oracle(chib):
     grid, prm, shapes, C0, faces = _drop_2d()
     st, orc = _pair(chib, grid, prm, shapes, C0, faces, precision=32)
