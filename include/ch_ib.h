@@ -166,7 +166,8 @@ int ch_ib_geometry_import(const ch_ib_grid *grid, const ch_ib_ghost_tables *tabl
 /* Fluid fractions of the staggered (face-centred) cells, section 4.1.1's other three volume
  * fractions: ndim fields of cells doubles, field a for the faces between cell c and c + e_a, each
  * control volume the cell shifted by h/2 along a, counted with the same subgrid points.
- * ch_ib_geometry_build computes them when params->flags has CH_IB_FLAG_NAVIER_STOKES.
+ * ch_ib_geometry_build and ch_ib_geometry_build_device compute them when params->flags has
+ * CH_IB_FLAG_NAVIER_STOKES (the device builder bit for bit with the host builder).
  * ch_ib_geometry_face_fractions: copies them to dst (ndim * cells doubles, caller-allocated);
  *   EUNSUPPORTED if the geometry holds none (imported or built without the flag).
  * ch_ib_geometry_set_face_fractions: replaces them with a copy of src (same layout; every value
@@ -229,7 +230,8 @@ int ch_ib_state_get(ch_ib_state *st, int field, void *dst, int dst_on_device);
  *   momentum step of sections 3.3-3.5 on the staggered grid, with rho and mu linear in C^(n+1),
  *   phi the chemical potential above and the capillary force 3/(2 sqrt2 Re Ca Cn) phi grad C:
  *   Adams-Bashforth prediction (Eq. PredictionExp; the first step after the fields are set uses a
- *   forward Euler convective term), penalisation u** = alpha_face u* (Eq. Penalization2), the
+ *   forward Euler convective term and no pressure history, p^n = p^(n-1) = 0), penalisation
+ *   u** = alpha_face u* (Eq. Penalization2), the
  *   velocity ghost fill on u**, the pressure of Eq. PressurePoisson (rho0 = min(rho1, rho2),
  *   p^ = 2p^n - p^(n-1), zero-mean, no flux through the box walls) by the same transforms, and
  *   the correction of Eq. correction.  The box walls of the bounded axis are no-slip.  Needs a

@@ -479,6 +479,11 @@ extern "C" int ch_ib_state_set(ch_ib_state *st, int field, const void *src, int 
     st->r_valid = 0;
     st->ns_first = 1;
     st->ut_valid = 0;
+    // new fields restart the momentum history: no pressure yet (p^ = 0 in the first step)
+    for (int k = 0; k < 2 && p.ns && e == hipSuccess; ++k)
+      e = hipMemsetAsync(p.P[k], 0, (size_t)p.N * st->es, p.stream);
+    if (p.ns && e == hipSuccess) e = hipStreamSynchronize(p.stream);
+    if (e != hipSuccess) return hip_fail(st, e, "state_set");
   }
   return CH_IB_OK;
 }

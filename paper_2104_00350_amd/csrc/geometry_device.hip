@@ -41,6 +41,7 @@ struct GeomArgs {
   double h, hs, d1, d2;
   int sub;
   int64_t N;
+  double off[3];   // control-volume shift: 0 for the cells, h/2 along one axis for staggered cells
 };
 
 __device__ bool solid_one(const DevShapes &S, int i, const double *x) {
@@ -158,8 +159,9 @@ __global__ __launch_bounds__(kGeomThreads) void k_gd_classify(GeomArgs A, double
   coords(S, c, ijk);
   double xc[3] = {0, 0, 0};
   for (int a = 0; a < d; ++a) xc[a] = S.lo[a] + ((double)ijk[a] + 0.5) * A.h;
+  for (int a = 0; a < d; ++a) xc[a] = xc[a] + A.off[a];
   const bool cs = solid(S, xc);
-  csolid[c] = cs ? 1 : 0;
+  if (csolid) csolid[c] = cs ? 1 : 0;
   bool cut = false;
   for (int i = 0; i < S.n_shapes; ++i) cut = cut || may_cut(S, i, xc, A.h);
   cutf[c] = cut ? 1 : 0;
@@ -179,7 +181,7 @@ __global__ __launch_bounds__(kGeomThreads) void k_gd_subgrid(GeomArgs A, const i
   int ijk[3];
   coords(S, c, ijk);
   double base[3] = {0, 0, 0};
-  for (int a = 0; a < d; ++a) base[a] = S.lo[a] + (double)ijk[a] * A.h;
+  for (int a = 0; a < d; ++a) base[a] = S.lo[a] + (double)ijk[a] * A.h + A.off[a];
   const int sub = A.sub;
   const int per_cell = sub * sub * (d == 3 ? sub : 1);   // sub <= 1000 (checked on the host)
   // point q = i + sub (j + sub k); lane starts at q = lane and strides by 64, carried digit-wise
@@ -635,6 +637,36 @@ extern "C" int ch_ib_geometry_build_device(const ch_ib_grid *grid, const ch_ib_s
   }
   g->gidx.assign(gidx32.begin(), gidx32.end());
   g->ap.assign(ap32.begin(), ap32.end());
+  // staggered-cell fractions for the momentum step: the same counting in cells shifted by h/2 along
+  // each axis (the cell fractions are on the host already, so their device buffer is reused)
+  if (params->flags & CH_IB_FLAG_NAVIER_STOKES) {
+    g->face_alpha.resize((size_t)d * N);
+    for (int a = 0; a < d && e == hipSuccess; ++a) {
+      GeomArgs B = A;
+      B.off[a] = 0.5 * tmp.h;
+      int64_t nc = 0;
+      hipLaunchKernelGGL(k_gd_classify, dim3(nb), dim3(kGeomThreads), 0, s, B, alpha, (unsigned char *)nullptr, cutf);
+      hipLaunchKernelGGL(k_gd_list<1>, dim3(nb), dim3(kGeomThreads), 0, s, B, (const unsigned char *)cutf, bcount,
+                         (const int *)nullptr, (int *)nullptr, bad);
+      e = hipGetLastError();
+      if (e == hipSuccess) e = offsets(&nc);
+      if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_gd_list<1>, dim3(nb), dim3(kGeomThreads), 0, s, B, (const unsigned char *)cutf, bcount,
+                           (const int *)boff, cutlist, bad);
+        if (nc)
+          hipLaunchKernelGGL(k_gd_subgrid, dim3((unsigned)((nc + 3) / 4)), dim3(kGeomThreads), 0, s, B,
+                             (const int *)cutlist, nc, alpha);
+        e = hipGetLastError();
+      }
+      if (e == hipSuccess)
+        e = hipMemcpyAsync(g->face_alpha.data() + (size_t)a * N, alpha, (size_t)N * 8, hipMemcpyDeviceToHost, s);
+      if (e == hipSuccess) e = hipStreamSynchronize(s);
+    }
+    if (e != hipSuccess) {
+      delete g;
+      return hip_error(e, "device geometry (staggered fractions)");
+    }
+  }
   *out = g;
   return CH_IB_OK;
 }

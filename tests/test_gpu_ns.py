@@ -93,8 +93,10 @@ def test_staggered_fractions_equal_the_oracle(chib):
         geo = chib.Geometry.build(grid.n, grid.lo, grid.hi, shapes, prm)
         got = geo.face_fractions()
         want = face_fractions(grid, shapes, prm)
+        dev = chib.Geometry.build_device(grid.n, grid.lo, grid.hi, shapes, prm).face_fractions()
         for a in range(grid.ndim):
             assert np.array_equal(got[a], want[a]), a
+            assert np.array_equal(dev[a], got[a]), ("device builder", a)
 
 
 @pytest.mark.parametrize("explicit,steps", [(False, 200), (True, 60)])
@@ -175,6 +177,20 @@ def test_fp32_tracks_the_fp64_oracle(chib):
     assert max(float(np.max(np.abs(a - b))) for a, b in zip(uf, orc.faces)) <= 1e-3 * us
 
 
+def test_setting_fields_restarts_the_momentum_history(chib):
+    """Fields set again mid-run: the next steps equal those of a fresh state from the same fields."""
+    grid, prm, shapes, C0, faces = _drop_2d()
+    st, _ = _pair(chib, grid, prm, shapes, C0, faces)
+    st.step(9)
+    C1, U1 = st.get(chib.FIELD_C), [st.get(chib.FIELD_U + a) for a in range(2)]
+    st.set_initial(C1, U1)
+    st.step(6)
+    fresh, _ = _pair(chib, grid, prm, shapes, C1, U1)
+    fresh.step(6)
+    for f in (chib.FIELD_C, chib.FIELD_P, chib.FIELD_U, chib.FIELD_V):
+        assert np.array_equal(st.get(f), fresh.get(f)), f
+
+
 def test_checkpoint_continues_bit_for_bit(chib):
     grid, prm, shapes, C0, faces = _drop_2d()
     st, _ = _pair(chib, grid, prm, shapes, C0, faces)
@@ -198,6 +214,10 @@ def test_errors(chib):
     assert e.value.code == chib.EINVAL
     with pytest.raises(chib.ChibError) as e:
         geo.face_fractions()
+    assert e.value.code == chib.EUNSUPPORTED
+    with pytest.raises(chib.ChibError) as e:          # device geometry built without the flag
+        dataclass_prm = __import__("dataclasses").replace(prm, navier_stokes=False)
+        chib.Geometry.build_device(grid.n, grid.lo, grid.hi, shapes, dataclass_prm).face_fractions()
     assert e.value.code == chib.EUNSUPPORTED
     bad = np.full((2,) + grid.shape, 1.5)
     with pytest.raises(chib.ChibError) as e:
