@@ -106,9 +106,11 @@ def measured_traffic(name: str, shapes, es: int, nx: int):
     if es != 8 or not os.path.exists(path):
         return None
     rec = json.load(open(path))
-    src = open(os.path.join(ROOT, "paper_2104_00350_amd", "csrc", "kernels.hip"), "rb").read()
-    if hashlib.sha256(src).hexdigest() != rec.get("kernels_hip_sha256"):
-        return None
+    hashes = rec.get("sources_sha256") or {}
+    for f in ("kernels.hip", "ns.hip"):
+        src = open(os.path.join(ROOT, "paper_2104_00350_amd", "csrc", f), "rb").read()
+        if hashlib.sha256(src).hexdigest() != hashes.get(f):
+            return None
     total = 0
     for k in kernel_template(name, shapes, es, nx):
         if k not in rec["per_dispatch"]:

@@ -220,12 +220,13 @@ __global__ __launch_bounds__(kNsThreads) void k_ns_predict(FaceSet<T> U, const T
 // 3D prediction with each edge formed once.  The convective flux E_ab = (u_a mean along b)(u_b mean
 // along a) and the shear stress tau_ab = mu_e (du_a/dx_b + du_b/dx_a) of an edge are symmetric in a and
 // b and are used by four faces; the per-cell kernel forms them four times.  Here a workgroup owns a
-// 64 x 4 tile of columns and marches it through zc planes: per plane it forms the xy, xz and yz edges
+// 64 x 8 tile of columns and marches it through zc planes: per plane it forms the xy, xz and yz edges
 // of the tile and of the halo column and row below it into LDS, every face takes its two edge
 // differences from there, and the xz and yz edges of the plane below come from registers.  Same
 // formulas and wall rules as ns_predict_cell (the four-cell mean viscosity of an edge is summed in the
 // order of its lower-axis face, so the other face's value may differ in the last bit).
-constexpr int kEx = 64, kEy = 4, kEhx = kEx + 1, kEhy = kEy + 1;
+constexpr int kEx = 64, kEy = 8, kEhx = kEx + 1, kEhy = kEy + 1;
+constexpr int kEThreads = kEx * kEy;   // one thread per column of the tile
 
 // E and tau of the xy (0), xz (1) and yz (2) edges at cell (qx, qy, qz): edge o lies at the cell
 // centre plus half a cell along each of its two axes.
@@ -262,7 +263,7 @@ __device__ __forceinline__ void ns_edges(const FaceSet<T> &U, const T *__restric
 }
 
 template <typename T>
-__global__ __launch_bounds__(kNsThreads) void k_ns_predict_edges(FaceSet<T> U, const T *__restrict__ C,
+__global__ __launch_bounds__(kEThreads) void k_ns_predict_edges(FaceSet<T> U, const T *__restrict__ C,
                                                                 const T *__restrict__ phi, FaceSet<T> Nh,
                                                                 FaceSet<T> Af, FaceSet<T> Us, NsGrid g,
                                                                 NsCoef<T> k, int first, int zc) {
@@ -302,7 +303,7 @@ __global__ __launch_bounds__(kNsThreads) void k_ns_predict_edges(FaceSet<T> U, c
     Tzy = Tau[2];
   }
   for (int kz = z0; kz < z0 + zc; ++kz) {
-    for (int e = tid; e < kEhx * kEhy; e += kNsThreads) {
+    for (int e = tid; e < kEhx * kEhy; e += kEThreads) {
       const int yy = e / kEhx, xx = e - yy * kEhx;
       T E[3], Tau[3];
       ns_edges(U, C, g, k, (x0 - 1 + xx) & (nx - 1), (y0 - 1 + yy) & (ny - 1), kz, E, Tau);
@@ -657,7 +658,7 @@ hipError_t enqueue_momentum(const Plan &p, int cur, int first, KernelTimer *tm) 
     else if (p.n[0] % kEx == 0 && p.n[1] % kEy == 0) {
       const int zc = p.n[2] < 16 ? p.n[2] : 16;
       const unsigned nbe = (unsigned)((p.n[0] / kEx) * (p.n[1] / kEy) * (p.n[2] / zc));
-      hipLaunchKernelGGL((k_ns_predict_edges<T>), dim3(nbe), dim3(kNsThreads), 0, p.stream, U, C, (const T *)p.W, Nh,
+      hipLaunchKernelGGL((k_ns_predict_edges<T>), dim3(nbe), dim3(kEThreads), 0, p.stream, U, C, (const T *)p.W, Nh,
                          Af, Us, g, k, first, zc);
     } else
       hipLaunchKernelGGL((k_ns_predict<T, 3>), dim3(nb), dim3(kNsThreads), 0, p.stream, U, C, (const T *)p.W, Nh, Af,

@@ -123,12 +123,13 @@ def test_coupled_steps_3d(chib):
 
 
 def test_coupled_steps_3d_wide(chib):
-    """A grid 64 cells wide with a wall and a bump: the prediction walks whole 64 x 4 column tiles."""
-    grid = W.Grid((64, 8, 32), (0.0, 0.0, 0.0), (2.0, 0.25, 1.0))
+    """A grid 64 cells wide and 16 deep with a wall and a bump: the prediction walks whole 64 x 8
+    column tiles, two of them along y, so the halo row between tiles is exercised."""
+    grid = W.Grid((64, 16, 32), (0.0, 0.0, 0.0), (2.0, 0.5, 1.0))
     prm = W.Params(Cn=0.04, Pe=50.0, Re=10.0, Ca=0.2, theta_deg=60.0, slip_length=0.02, dt=1e-4,
                    navier_stokes=True, rho1=0.2, rho2=1.0, mu1=0.5, mu2=1.0, body_force=(0.0, 0.0, -0.3))
-    shapes = [W.Shape(W.HALFPLANE, (0.0, 0.0, 0.3, 0.0, 0.0, 1.0)), W.Shape(W.SPHERE, (1.0, 0.125, 0.25, 0.2))]
-    C0, _ = W.droplet_field(grid, (1.0, 0.125, 0.55), 0.25, prm.Cn, 1e-3, 5)
+    shapes = [W.Shape(W.HALFPLANE, (0.0, 0.0, 0.3, 0.0, 0.0, 1.0)), W.Shape(W.SPHERE, (1.0, 0.25, 0.25, 0.2))]
+    C0, _ = W.droplet_field(grid, (1.0, 0.25, 0.55), 0.25, prm.Cn, 1e-3, 5)
     rng = np.random.default_rng(17)
     faces = [0.05 * rng.standard_normal(grid.shape) for _ in range(3)]
     st, orc = _pair(chib, grid, prm, shapes, C0, faces)
