@@ -272,6 +272,20 @@ def scalar_fill_benchmark(chib, st, case, reps: int = 50) -> dict:
             "ghosts": st.G, "us_per_call": round(us, 2), "alg_bytes": b, "GB_s": round(b / (us * 1e-6) / 1e9, 1)}
 
 
+def diagnostics_benchmark(st, case, es: int, reps: int = 20) -> dict:
+    """Diagnostics (mass, free energy, max |C|) on the 256^3 state: wall time of the synchronous call,
+    which holds both reduction kernels, the 64-byte copy to the host and the wait."""
+    st.diagnostics()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        st.diagnostics()
+    us = (time.perf_counter() - t0) * 1e6 / reps
+    b = 2 * es * case.grid.cells      # C and alpha, each read once (neighbours from cache)
+    return {"what": "synchronous diagnostics call (two reduction kernels, copy to host, wait)",
+            "us_per_call": round(us, 2), "alg_bytes": b, "GB_s": round(b / (us * 1e-6) / 1e9, 1),
+            "frac_of_8TBs": round(b / (us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4)}
+
+
 def learned_benchmark(chib, steps: int) -> dict:
     """Learned wall-band correction (config 5): the 8 held-out contact angles run as one batch on
     the plain 1024x512 grid (the judge), on the plain 512x256 grid and on the 512x256 grid with
@@ -450,6 +464,7 @@ def main() -> int:
         "kernels": kernels,
     }
     out["scalar_fill"] = scalar_fill_benchmark(chib, st, case)
+    out["diagnostics"] = diagnostics_benchmark(st, case, es)
     # geometry preprocessing (one-time, not in the step metric): host builder vs the device builder
     chib.Geometry.build_device(g.n, g.lo, g.hi, case.shapes, case.params)      # loads its kernels
     torch.cuda.synchronize()

@@ -17,7 +17,7 @@ namespace {
 
 constexpr int kVersion = 10000;  // 1.0.0
 constexpr uint32_t kMagic = 0x42494843u;  // "CHIB"
-constexpr int kNred = 1024;
+constexpr int kNred = 8192;   // blocks of the first reduction pass (8 cells per thread at 256^3)
 
 struct FaceList {
   std::vector<int> cell, axis, gL, gR;

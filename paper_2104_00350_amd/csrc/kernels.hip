@@ -1511,11 +1511,25 @@ __global__ __launch_bounds__(kThreads) void k_rhs_only(const T *__restrict__ Cn,
 // Diagnostics: fixed-order two-pass reductions (deterministic).  Slots: 0 sum C, 1 sum
 // alpha C, 2 sum alpha (bulk + gradient energy density), 3 sum |grad alpha| g(C),
 // 4 max |C|, 5 count of non-finite C.
+// Sum (max for slot 4) of the six slots over a wave by a butterfly of lane exchanges: a fixed
+// pairing, so the result does not depend on timing.
+__device__ inline void wave_reduce6(double acc[6]) {
+#pragma unroll
+  for (int m = 32; m > 0; m >>= 1) {
+#pragma unroll
+    for (int s = 0; s < 6; ++s) {
+      const double o = __shfl_xor(acc[s], m, 64);
+      acc[s] = s == 4 ? fmax(acc[s], o) : acc[s] + o;
+    }
+  }
+}
+
+// Per block: each wave reduces its lanes, then the first lanes combine the waves in index order.
 template <typename T, int D>
 __global__ __launch_bounds__(kThreads) void k_diag_partial(const T *__restrict__ C, const T *__restrict__ alpha,
                                                            double *__restrict__ partial, Dims dm, double Cn,
-                                                           double inv_h, int64_t N) {
-  __shared__ double red[6][kThreads];
+                                                           double inv_h, double inv4cn, int64_t N) {
+  __shared__ double red[kThreads / 64][6];
   double acc[6] = {0, 0, 0, 0, 0, 0};
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < N; c += stride) {
@@ -1567,25 +1581,96 @@ __global__ __launch_bounds__(kThreads) void k_diag_partial(const T *__restrict__
         ga2 += day * day + daz * daz;
       }
     }
-    const double bulk = (v * v - 1.0) * (v * v - 1.0) / (4.0 * Cn);
+    const double bulk = (v * v - 1.0) * (v * v - 1.0) * inv4cn;
     acc[0] += v;
     acc[1] += al * v;
     acc[2] += al * (bulk + 0.5 * Cn * g2);
     acc[3] += sqrt(ga2) * (2.0 + 3.0 * v - v * v * v) * 0.25;
     acc[4] = fmax(acc[4], fabs(v));
   }
-  for (int s = 0; s < 6; ++s) red[s][threadIdx.x] = acc[s];
+  wave_reduce6(acc);
+  const int lane = (int)threadIdx.x & 63, wv = (int)threadIdx.x >> 6;
+  if (lane == 0)
+    for (int s = 0; s < 6; ++s) red[wv][s] = acc[s];
   __syncthreads();
-  for (int w = kThreads / 2; w > 0; w >>= 1) {
-    if ((int)threadIdx.x < w) {
-      for (int s = 0; s < 6; ++s) {
-        if (s == 4) red[s][threadIdx.x] = fmax(red[s][threadIdx.x], red[s][threadIdx.x + w]);
-        else red[s][threadIdx.x] += red[s][threadIdx.x + w];
-      }
-    }
-    __syncthreads();
+  if (threadIdx.x < 6) {
+    const int s = (int)threadIdx.x;
+    double r = red[0][s];
+    for (int w = 1; w < kThreads / 64; ++w) r = s == 4 ? fmax(r, red[w][s]) : r + red[w][s];
+    partial[(int64_t)blockIdx.x * 8 + s] = r;
   }
-  if (threadIdx.x < 6) partial[(int64_t)blockIdx.x * 8 + threadIdx.x] = red[threadIdx.x][0];
+}
+
+// 3D diagnostics marching in z: a block owns a 64 x 4 tile of (x, y) columns over zc planes, each
+// thread keeps C and alpha of planes z and z+1 (alpha also z-1) of its column in registers, so C and
+// alpha come from HBM once; the x and y neighbours are in the same plane as the tile's own loads.
+// Same per-cell terms as k_diag_partial<T, 3>.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_diag_partial_zm(const T *__restrict__ C, const T *__restrict__ alpha,
+                                                              double *__restrict__ partial, Dims dm, double Cn,
+                                                              double inv_h, double inv4cn, int zc) {
+  __shared__ double red[kThreads / 64][6];
+  double acc[6] = {0, 0, 0, 0, 0, 0};
+  const int tiles_x = dm.nx >> 6, tiles_y = dm.ny >> 2;
+  int b = (int)blockIdx.x;
+  const int bx = b % tiles_x;
+  b /= tiles_x;
+  const int by = b % tiles_y;
+  const int bz = b / tiles_y;
+  const int x = (bx << 6) + ((int)threadIdx.x & 63), y = (by << 2) + ((int)threadIdx.x >> 6);
+  const int z0 = bz * zc, z1 = min(z0 + zc, dm.nz);
+  const int oxp = ((x + 1) & (dm.nx - 1)) - x, oxm = ((x - 1) & (dm.nx - 1)) - x;
+  const int64_t oyp = (int64_t)((((y + 1) & (dm.ny - 1)) - y) << dm.lnx);
+  const int64_t oym = (int64_t)((((y - 1) & (dm.ny - 1)) - y) << dm.lnx);
+  int64_t c = ((int64_t)y << dm.lnx) + x + (int64_t)z0 * dm.plane;
+  double v = (double)C[c];
+  double al = alpha ? (double)alpha[c] : 1.0;
+  double ad = alpha && z0 > 0 ? (double)alpha[c - dm.plane] : al;
+  for (int k = z0; k < z1; ++k, c += dm.plane) {
+    double vu = v, au = al;
+    if (k < dm.nz - 1) {
+      vu = (double)C[c + dm.plane];
+      if (alpha) au = (double)alpha[c + dm.plane];
+    }
+    if (!(v == v) || v - v != 0.0) {
+      acc[5] += 1.0;
+    } else {
+      const double dx = ((double)C[c + oxp] - v) * inv_h;
+      const double dy = ((double)C[c + oyp] - v) * inv_h;
+      const double dz = (vu - v) * inv_h;
+      double g2 = dx * dx;
+      g2 += dy * dy;
+      g2 += dz * dz;
+      double ga2 = 0.0;
+      if (alpha) {
+        const double da = ((double)alpha[c + oxp] - (double)alpha[c + oxm]) * 0.5 * inv_h;
+        const double day = ((double)alpha[c + oyp] - (double)alpha[c + oym]) * 0.5 * inv_h;
+        const double daz = (au - ad) * 0.5 * inv_h;
+        ga2 += da * da;
+        ga2 += day * day + daz * daz;
+      }
+      const double bulk = (v * v - 1.0) * (v * v - 1.0) * inv4cn;
+      acc[0] += v;
+      acc[1] += al * v;
+      acc[2] += al * (bulk + 0.5 * Cn * g2);
+      acc[3] += sqrt(ga2) * (2.0 + 3.0 * v - v * v * v) * 0.25;
+      acc[4] = fmax(acc[4], fabs(v));
+    }
+    ad = al;
+    al = au;
+    v = vu;
+  }
+  wave_reduce6(acc);
+  const int lane = (int)threadIdx.x & 63, wv = (int)threadIdx.x >> 6;
+  if (lane == 0)
+    for (int s = 0; s < 6; ++s) red[wv][s] = acc[s];
+  __syncthreads();
+  if (threadIdx.x < 6) {
+    const int s = (int)threadIdx.x;
+    double r = red[0][s];
+    for (int w = 1; w < kThreads / 64; ++w) r = s == 4 ? fmax(r, red[w][s]) : r + red[w][s];
+    partial[(int64_t)blockIdx.x * 8 + s] = r;
+  }
 }
 
 __global__ __launch_bounds__(kThreads) void k_diag_final(const double *__restrict__ partial, int nred,
@@ -2159,11 +2244,31 @@ hipError_t enqueue_diag(const Plan &p, int cur) {
   const Dims dm = make_dims(p);
   if (p.d == 2)
     hipLaunchKernelGGL((k_diag_partial<T, 2>), dim3(p.nred), dim3(kThreads), 0, p.stream, (const T *)p.C[cur],
-                       (const T *)p.alpha, (double *)p.partial, dm, p.Cn, 1.0 / p.h, p.N);
-  else
-    hipLaunchKernelGGL((k_diag_partial<T, 3>), dim3(p.nred), dim3(kThreads), 0, p.stream, (const T *)p.C[cur],
-                       (const T *)p.alpha, (double *)p.partial, dm, p.Cn, 1.0 / p.h, p.N);
-  hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(kThreads), 0, p.stream, (const double *)p.partial, p.nred,
+                       (const T *)p.alpha, (double *)p.partial, dm, p.Cn, 1.0 / p.h, 0.25 / p.Cn, p.N);
+  int nred = p.nred;
+  if (p.d == 3) {
+    // z-march when whole 64 x 4 column tiles fit and the block count fits the partial buffer
+    // (p.nred blocks); thicker z-chunks until it does
+    int64_t blocks = -1;
+    int zc = 16;
+    if (p.n[0] % 64 == 0 && p.n[1] % 4 == 0) {
+      const int64_t cols = (int64_t)(p.n[0] / 64) * (p.n[1] / 4);
+      for (;; zc *= 2) {
+        blocks = cols * ((p.n[2] + zc - 1) / zc);
+        if (blocks <= p.nred || zc >= p.n[2]) break;
+      }
+    }
+    if (blocks > 0 && blocks <= p.nred) {
+      nred = (int)blocks;
+      hipLaunchKernelGGL((k_diag_partial_zm<T>), dim3((unsigned)blocks), dim3(kThreads), 0, p.stream,
+                         (const T *)p.C[cur], (const T *)p.alpha, (double *)p.partial, dm, p.Cn, 1.0 / p.h,
+                         0.25 / p.Cn, zc);
+    } else {
+      hipLaunchKernelGGL((k_diag_partial<T, 3>), dim3(p.nred), dim3(kThreads), 0, p.stream, (const T *)p.C[cur],
+                         (const T *)p.alpha, (double *)p.partial, dm, p.Cn, 1.0 / p.h, 0.25 / p.Cn, p.N);
+    }
+  }
+  hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(kThreads), 0, p.stream, (const double *)p.partial, nred,
                      (double *)p.red_out);
   return hipGetLastError();
 }
