@@ -139,6 +139,25 @@ def test_diagnostics_3d_grid_stride(chib):
     assert dg == st.diagnostics()
 
 
+@pytest.mark.parametrize("n", [(64, 32), (16, 8, 8)])
+def test_wall_free_box_full_steps(chib, n):
+    """No immersed wall: zero ghosts and no face touching one, so the fills have empty lists; the
+    steps (advection by a random flow included) still match the oracle."""
+    d = len(n)
+    grid = W.Grid(n, (0.0,) * d, tuple(v / 16.0 for v in n))
+    prm = W.Params(Cn=0.1, Pe=50.0, dt=1e-3)
+    centre = tuple(0.5 * v / 16.0 for v in n)
+    case = W.Case("wall_free", grid, [], prm, 100, centre, 0.25 * min(n) / 16.0, 1e-2, 5)
+    st, orc, T = _pair(chib, case, _random_faces(grid, 6, 0.2))
+    assert len(T.gidx) == 0
+    _say("wall-free box", n)
+    st.step(100)
+    orc.step(100)
+    assert _linf(st.get(chib.FIELD_C), orc.C) <= 1e-9
+    for a in range(d):
+        assert _linf(st.get(chib.FIELD_U + a), orc.faces[a]) == 0.0
+
+
 def test_config1_own_geometry(chib):
     case = W.config1()
     st, orc, _ = _pair(chib, case, own_geometry=True)
