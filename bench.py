@@ -286,6 +286,26 @@ def diagnostics_benchmark(st, case, es: int, reps: int = 20) -> dict:
             "frac_of_8TBs": round(b / (us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4)}
 
 
+def host_round_trip_benchmark(chib, st, case, ks=(1, 100)) -> dict:
+    """Rate when the caller hands C over in host memory: set C from a pageable host array, K steps,
+    C back to the host, wall time of the whole.  (Setting C restarts the history, so each K starts
+    with the initial fill, as a host-side caller's first step would.)"""
+    cells = case.grid.cells
+    C_host = st.get(chib.FIELD_C)
+    out = {"what": "set C from pageable host memory + K steps + get C to host (wall)"}
+    for k in ks:
+        st.set(chib.FIELD_C, C_host)
+        st.step(1)
+        st.sync()
+        t0 = time.perf_counter()
+        st.set(chib.FIELD_C, C_host)
+        st.step(k)
+        C_host = st.get(chib.FIELD_C)
+        dt = time.perf_counter() - t0
+        out[f"K{k}"] = {"ms": round(dt * 1e3, 3), "cell_updates_per_s": cells * k / dt}
+    return out
+
+
 def learned_benchmark(chib, steps: int) -> dict:
     """Learned wall-band correction (config 5): the 8 held-out contact angles run as one batch on
     the plain 1024x512 grid (the judge), on the plain 512x256 grid and on the 512x256 grid with
@@ -465,6 +485,7 @@ def main() -> int:
     }
     out["scalar_fill"] = scalar_fill_benchmark(chib, st, case)
     out["diagnostics"] = diagnostics_benchmark(st, case, es)
+    out["host_round_trip"] = host_round_trip_benchmark(chib, st, case)
     # geometry preprocessing (one-time, not in the step metric): host builder vs the device builder
     chib.Geometry.build_device(g.n, g.lo, g.hi, case.shapes, case.params)      # loads its kernels
     torch.cuda.synchronize()
