@@ -139,6 +139,26 @@ def test_diagnostics_3d_grid_stride(chib):
     assert dg == st.diagnostics()
 
 
+def test_diagnostics_thick_z_chunks(chib):
+    """512 x 512 x 256 (64M cells): 16-plane chunks would need 16384 reduction blocks, more than the
+    partial buffer holds, so the z-march takes 32-plane chunks.  Random field, no wall; the oracle's
+    diagnostics of the same field."""
+    g = W.Grid((512, 512, 256), (0.0, 0.0, 0.0), (2.0, 2.0, 1.0))
+    prm = W.Params(Cn=0.02, Pe=100.0, dt=1e-4)
+    T = build_tables(g, [], prm)
+    geo = _geom_from_oracle(chib, W.Case("thick", g, [], prm, 0, (1.0, 1.0, 0.5), 0.25, 0.0, None), T)
+    rng = np.random.default_rng(21)
+    C0 = 0.2 + 0.6 * rng.standard_normal(g.shape)
+    st = chib.State(geo, prm)
+    st.set_initial(C0)
+    _say("diagnostics 512x512x256")
+    dg = st.diagnostics()
+    dref = diagnostics(g, prm, T.alpha, C0)
+    for k in ("mass_box", "mass_fluid", "free_energy", "max_abs_C"):
+        assert abs(dg[k] - dref[k]) <= 1e-9 * max(1.0, abs(dref[k])), k
+    assert dg == st.diagnostics()
+
+
 @pytest.mark.parametrize("n", [(64, 32), (16, 8, 8)])
 def test_wall_free_box_full_steps(chib, n):
     """No immersed wall: zero ghosts and no face touching one, so the fills have empty lists; the
