@@ -159,6 +159,23 @@ def test_diagnostics_thick_z_chunks(chib):
     assert dg == st.diagnostics()
 
 
+def test_diagnostics_fp32_state(chib):
+    """FP32 state, 3D z-march: the reductions run in double on the stored floats.  No wall, so the
+    initial fill leaves the field as set and the oracle sees the same float-rounded values."""
+    g = W.Grid((256, 64, 64), (0.0, 0.0, 0.0), (4.0, 1.0, 1.0))
+    prm = W.Params(Cn=0.05, Pe=100.0, dt=1e-4)
+    T = build_tables(g, [], prm)
+    geo = _geom_from_oracle(chib, W.Case("fp32", g, [], prm, 0, (2.0, 0.5, 0.5), 0.25, 0.0, None), T)
+    rng = np.random.default_rng(33)
+    C0 = (0.1 + 0.7 * rng.standard_normal(g.shape)).astype(np.float32).astype(np.float64)
+    st = chib.State(geo, prm, 32)
+    st.set_initial(C0)
+    dg = st.diagnostics()
+    dref = diagnostics(g, prm, T.alpha, C0)
+    for k in ("mass_box", "mass_fluid", "free_energy", "max_abs_C"):
+        assert abs(dg[k] - dref[k]) <= 1e-9 * max(1.0, abs(dref[k])), k
+
+
 @pytest.mark.parametrize("n", [(64, 32), (16, 8, 8)])
 def test_wall_free_box_full_steps(chib, n):
     """No immersed wall: zero ghosts and no face touching one, so the fills have empty lists; the
