@@ -98,18 +98,27 @@ def kernel_template(name: str, shapes, es: int, nx: int) -> list:
     return []
 
 
+def code_digest(path: str) -> str:
+    """sha256 of a source file with its comments and whitespace removed, so that the recorded counters
+    stay valid across edits that change no code."""
+    import hashlib
+    import re
+    src = open(path, encoding="utf-8").read()
+    src = re.sub(r"/\*.*?\*/", " ", src, flags=re.S)
+    src = re.sub(r"//[^\n]*", " ", src)
+    return hashlib.sha256("".join(src.split()).encode()).hexdigest()
+
+
 def measured_traffic(name: str, shapes, es: int, nx: int):
     """HBM bytes per launch from the committed counter summary, or None when the kernel source has
     changed since the counters were taken (or the kernel was not profiled)."""
-    import hashlib
     path = os.path.join(ROOT, "profiles", "hbm_traffic_sphere256_fp64.json")
     if es != 8 or not os.path.exists(path):
         return None
     rec = json.load(open(path))
-    hashes = rec.get("sources_sha256") or {}
+    digests = rec.get("sources_code_sha256") or {}
     for f in ("kernels.hip", "ns.hip"):
-        src = open(os.path.join(ROOT, "paper_2104_00350_amd", "csrc", f), "rb").read()
-        if hashlib.sha256(src).hexdigest() != hashes.get(f):
+        if code_digest(os.path.join(ROOT, "paper_2104_00350_amd", "csrc", f)) != digests.get(f):
             return None
     total = 0
     for k in kernel_template(name, shapes, es, nx):
@@ -209,7 +218,7 @@ def explicit_benchmark(chib, geo, case, steps: int, precision: int, NF: int, sem
 
 
 def ns_benchmark(chib, case, steps: int, precision: int, semi_ms: float, NF: int, shapes) -> dict:
-    """The coupled order-parameter + momentum step (Navier-Stokes coupling, sections 3.3-3.5) on
+    """The coupled order-parameter + momentum step (Navier-Stokes coupling, sections 4.2.3, 4.3 and 4.4) on
     the same 256^3 workload, matched fluids (rho1 = rho2, mu1 = mu2: the explicit viscous term
     then allows the workload's dt), started from rest: kernel times, bytes and the cost over the
     order-parameter step alone."""

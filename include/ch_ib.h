@@ -69,11 +69,11 @@ enum {
 
 /* ---- params.flags ---------------------------------------------------------------------- */
 enum {
-  CH_IB_FLAG_VELOCITY_FILL = 1, /* refill faces touching ghosts every step (section 4.4) */
+  CH_IB_FLAG_VELOCITY_FILL = 1, /* refill faces touching ghosts every step (section 4.3) */
   CH_IB_FLAG_EXPLICIT = 2,       /* explicit Adams-Bashforth step (Eq. ExpCH) instead of the
                                     semi-implicit one; needs a time step about ten times smaller */
   CH_IB_FLAG_NAVIER_STOKES = 4   /* advance the face velocities with the momentum equation too
-                                    (sections 2 and 3.3-3.5); implies the velocity fill */
+                                    (sections 2, 3.2, 4.2.3, 4.3 and 4.4); implies the velocity fill */
 };
 
 typedef struct {
@@ -219,7 +219,7 @@ int ch_ib_state_get(ch_ib_state *st, int field, void *dst, int dst_on_device);
  *   the explicit chemical-potential part), the two Helmholtz solves of Appendix A.1 as one
  *   spectral division (Hartley transforms on periodic axes, DCT-II on the bounded axis), the
  *   contact-angle ghost fill of C (section 4.2.2) and, with CH_IB_FLAG_VELOCITY_FILL, the
- *   no-penetration / Navier-slip fill of the faces touching ghosts (section 4.4).
+ *   no-penetration / Navier-slip fill of the faces touching ghosts (section 4.3).
  *   With CH_IB_FLAG_EXPLICIT the step is Eq. ExpCH instead: the chemical potential on every
  *   cell (ghosts take the mirror value, dphi/dn = 0), the rate R = -div(u C) + lap(phi)/Pe, and
  *   C^(n+1) = C^n + dt (3/2 R^n - 1/2 R^(n-1)) (second-order Adams-Bashforth; the first step
@@ -227,7 +227,7 @@ int ch_ib_state_get(ch_ib_state *st, int field, void *dst, int dst_on_device);
  *   fills.  The workspace then holds one more field for R.
  *   With CH_IB_FLAG_NAVIER_STOKES the faces follow the momentum equation: after the order-parameter
  *   step (semi-implicit: advected by 2u^n - u^(n-1), Appendix A.1; explicit: by u^n) comes the
- *   momentum step of sections 3.3-3.5 on the staggered grid, with rho and mu linear in C^(n+1),
+ *   momentum step of sections 4.2.3, 4.3 and 4.4 on the staggered grid, with rho and mu linear in C^(n+1),
  *   phi the chemical potential above and the capillary force 3/(2 sqrt2 Re Ca Cn) phi grad C:
  *   Adams-Bashforth prediction (Eq. PredictionExp; the first step after the fields are set uses a
  *   forward Euler convective term and no pressure history, p^n = p^(n-1) = 0), penalisation

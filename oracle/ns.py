@@ -1,5 +1,5 @@
 """Oracle Navier-Stokes coupling: explicit momentum step, volume penalisation, variable-density
-pressure projection (sections 2 and 3.2-3.5, Eqs. NS equation, PredictionExp, Penalization2,
+pressure projection (sections 2, 3.2, 4.2.3, 4.3 and 4.4, Eqs. NS equation, PredictionExp, Penalization2,
 PressurePoisson, correction).
 
 TEST INFRASTRUCTURE ONLY (see the package docstring).
@@ -25,7 +25,7 @@ both walls is zero (the top wall face is stored and kept at zero, the bottom one
 tangential velocity is reflected with a sign change across the wall, the pressure gradient
 through the wall is zero, and cell-centred scalars (C, mu) are reflected.
 
-One coupled step (block diagram of section 5 / Fig. Chart):
+One coupled step (the block diagram of Fig. Chart, end of section 4):
  1. order-parameter step with the current velocity (semi-implicit: the advecting velocity is the
     extrapolation 2u^n - u^(n-1) of Appendix A.1; explicit: u^n), ghost fill of C;
  2. phi, rho~, mu~ from C^(n+1);
@@ -34,7 +34,7 @@ One coupled step (block diagram of section 5 / Fig. Chart):
     quantity reduce to that quantity), the body force constant in time;
     the first step uses forward Euler for the convective term;
  4. penalisation u** = alpha_face u* (Eq. Penalization2, stationary walls);
- 5. velocity ghost fill on u** (section 3.4, the existing slip / no-penetration fill);
+ 5. velocity ghost fill on u** (section 4.3, the existing slip / no-penetration fill);
  6. pressure (Eq. PressurePoisson) with rho0 = min(rho1, rho2), p^ = 2p^n - p^(n-1), solved with
     the cosine / Fourier eigen-decomposition of the discrete Laplacian (zero-mean solution);
  7. correction (Eq. correction) on every face except the box-wall faces.

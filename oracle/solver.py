@@ -19,7 +19,7 @@ The second-order discrete Laplacian is the one diagonalised by those
 transforms.  Then the ghost values of C are overwritten from the contact-angle
 condition (section 4.2.2, Eqs. interpolationAtWall ... UpdateC) and the
 velocity at faces touching ghosts from the no-penetration and Navier-slip
-conditions (section 4.4, Eqs. NoPenetration ... UpdateVandW).
+conditions (section 4.3, Eqs. NoPenetration ... UpdateVandW).
 """
 from __future__ import annotations
 
@@ -323,7 +323,7 @@ class OracleState:
 
     # -- velocity fill -------------------------------------------------------------
     def fill_velocity(self, Cfin: np.ndarray) -> None:
-        """No-penetration and Navier-slip ghost velocities, then faces touching ghosts (section 4.4).
+        """No-penetration and Navier-slip ghost velocities, then faces touching ghosts (section 4.3).
 
         V_nG = -V_nM/gamma (Eq. NoPenetration);
         V_tG = V_tM (ls - dn)/(ls + gamma dn) - Kc grad_t C_I ls (gamma+1) dn / (mu (ls + gamma dn))
@@ -444,7 +444,7 @@ class OracleState:
     # -- momentum ---------------------------------------------------------------------
     def momentum_step(self) -> None:
         """Prediction, penalisation, velocity ghost fill, pressure and correction with the new C
-        (sections 3.3-3.5; the operators are in ``oracle.ns``)."""
+        (sections 4.2.3, 4.3 and 4.4; the operators are in ``oracle.ns``)."""
         from . import ns
         grid = self.grid
         prm = self.params

@@ -23,7 +23,7 @@ struct FaceList {
   std::vector<int> cell, axis, gL, gR;
 };
 
-// Faces with a ghost on either side (section 4.4: their velocity is re-interpolated).
+// Faces with a ghost on either side (section 4.3: their velocity is re-interpolated).
 FaceList build_faces(const ch_ib_geometry &g) {
   FaceList fl;
   const int d = g.ndim;

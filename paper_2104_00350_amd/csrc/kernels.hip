@@ -1,5 +1,5 @@
 // Device kernels of one time step of the hybrid ghost-cell IB / Cahn-Hilliard method
-// (Appendix A.1 and sections 4.2.2, 4.4 of the paper), written for gfx950 (CDNA4):
+// (Appendix A.1 and sections 4.2.2 and 4.3 of the paper), written for gfx950 (CDNA4):
 // 64-wide wavefronts, 256-thread workgroups, 32 KB LDS tiles, XCD-aware tile order.
 //
 // Step pipeline (C^n in C[cur], C^(n-1) in C[1-cur]; the step overwrites C[1-cur]):

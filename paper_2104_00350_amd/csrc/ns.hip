@@ -1,4 +1,4 @@
-// Momentum step of the Navier-Stokes coupling on the staggered grid (sections 2 and 3.3-3.5):
+// Momentum step of the Navier-Stokes coupling on the staggered grid (sections 2, 3.2, 4.2.3, 4.3 and 4.4):
 // explicit Adams-Bashforth prediction (Eq. PredictionExp), volume penalisation with the
 // staggered-cell fluid fractions (Eq. Penalization2), the slip / no-penetration velocity ghost
 // fill, the variable-density pressure equation (Eq. PressurePoisson, rho0 = min(rho1, rho2),

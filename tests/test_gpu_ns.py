@@ -1,4 +1,4 @@
-"""GPU parity of the Navier-Stokes coupling (momentum step of sections 3.3-3.5) against the FP64
+"""GPU parity of the Navier-Stokes coupling (momentum step of sections 4.2.3, 4.3 and 4.4) against the FP64
 oracle on identical inputs (oracle ghost tables and staggered-cell fractions imported), plus the
 properties that hold at any size.
 

@@ -1,4 +1,4 @@
-"""Pins of the oracle's ghost-cell fills (sections 4.2.2 and 4.4) and of the mass identity.
+"""Pins of the oracle's ghost-cell fills (sections 4.2.2 and 4.3) and of the mass identity.
 
 CPU only.  The pins are special cases with known answers (constant and linear
 fields, pure phases, the exact tanh wedge that satisfies the continuous

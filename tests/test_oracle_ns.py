@@ -1,4 +1,4 @@
-"""Pins of the oracle's momentum step (sections 2 and 3.3-3.5), CPU only.
+"""Pins of the oracle's momentum step (sections 2, 3.2, 4.2.3, 4.3 and 4.4), CPU only.
 
 - Pressure solve: equals the zero-mean solution of the 5/7-point Laplacian with zero flux through
   the box walls, assembled cell by cell here and solved with a sparse direct solver.
