@@ -317,7 +317,7 @@ def host_round_trip_benchmark(chib, st, case, ks=(1, 100)) -> dict:
 
 def learned_benchmark(chib, steps: int) -> dict:
     """Learned wall-band correction (config 5): the 8 held-out contact angles run as one batch on
-    the plain 1024x512 grid (the judge), on the plain 512x256 grid and on the 512x256 grid with
+    the plain 1024x512 grid (the reference), on the plain 512x256 grid and on the 512x256 grid with
     the committed trained correction; contact angles measured with the same routine."""
     import numpy as np
     import torch
@@ -396,7 +396,7 @@ def main() -> int:
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print(json.dumps({"error": "this build runs on exactly one GPU; multi-GPU runs are not part of it"}))
+        print(json.dumps({"error": "chib runs on one GPU; runs across several GPUs are not implemented"}))
         return 2
 
     import numpy as np

@@ -41,7 +41,7 @@ enum {
   CH_IB_EHIP = -3,         /* a HIP runtime call failed */
   CH_IB_ENOMEM = -4,       /* workspace or caller buffer too small */
   CH_IB_ENAN = -5,         /* a non-finite value was found in the state */
-  CH_IB_EUNSUPPORTED = -6  /* valid request this build does not implement (e.g. non power-of-two grid) */
+  CH_IB_EUNSUPPORTED = -6  /* valid request the library does not implement (e.g. non power-of-two grid) */
 };
 
 /* ---- wall shapes (solid region; several shapes form a union) --------------------------

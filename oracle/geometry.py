@@ -9,7 +9,7 @@ Follows section 4.1 of the paper ("Preliminary computations"):
 * averaging points and inverse-squared-distance weights of the two
   interpolation points (4.1.4, Eq. "weright averaged").
 
-Readings of silent or garbled passages (each is also listed in the design doc):
+Readings of silent or garbled passages:
 
 * the normal is m / sqrt(m.m + eps0) with eps0 = 1e-30 (the printed formula
   repeats one component and puts a grid spacing in the numerator);

@@ -9,7 +9,7 @@ orders the calls.
   with the target correction restrict(fine) - coarse.
 * Training: Adam on random batches of stored tiles that hold band cells; the loss is the mean
   squared error of the correction over the band cells of the batch.
-* Scoring: for held-out angles, the plain fine run (the judge), the plain coarse run and the
+* Scoring: for held-out angles, the plain fine run (the reference), the plain coarse run and the
   corrected coarse run (correction every `interval` steps) advance the same number of steps;
   the contact angles of all three are measured with the same routine (angle.measure) and the
   wall-clock times of the runs are compared.  A corrected run whose max |C| exceeds
