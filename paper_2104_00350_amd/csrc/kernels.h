@@ -136,6 +136,17 @@ template <typename T> size_t case_desc_bytes();
 template <typename T> void case_tiles(const Plan &p, int *tiles, size_t *lds);
 template <typename T> hipError_t enqueue_batch_step(const BatchLaunch &bl, int parity);
 
+// Logical tile of hardware block b of nb: blocks are dealt round-robin to the 8 XCDs, so this
+// gives each XCD a run of consecutive tiles and neighbouring tiles (which read each other's halo
+// lines) share its L2.  A permutation of [0, nb) when nb is a multiple of 8, else the identity.
+__device__ __forceinline__ int xcd_tile(int b, int nb) {
+  if ((nb & 7) == 0) {
+    const int per = nb >> 3;
+    return (b & 7) * per + (b >> 3);
+  }
+  return b;
+}
+
 // Launch-shape helpers shared with the host (elements per LDS tile).
 template <typename T> constexpr int tile_elems() { return 32768 / (int)sizeof(T); }  // 32 KB of LDS
 

@@ -472,9 +472,8 @@ struct ZCol {
   int psh;         // log2 of the plane size
 };
 
-__device__ __forceinline__ ZCol zcol(const NsWalk &wk, const NsGrid &g) {
+__device__ __forceinline__ ZCol zcol(const NsWalk &wk, const NsGrid &g, int b) {
   ZCol z;
-  const int b = (int)blockIdx.x;
   const int bx = b & ((1 << wk.lbx) - 1);
   const int by = (b >> wk.lbx) & ((1 << wk.lby) - 1);
   const int bz = b >> (wk.lbx + wk.lby);
@@ -496,7 +495,9 @@ __global__ __launch_bounds__(kNsThreads) void k_ns_pressure_rhs_zm(FaceSet<T> Us
                                                                    const T *__restrict__ P0,
                                                                    const T *__restrict__ P1, T *__restrict__ R,
                                                                    NsGrid g, NsCoef<T> k, NsWalk wk) {
-  const ZCol z = zcol(wk, g);
+  // XCD-aware tile order: the y-neighbour tiles whose rows this pass re-reads run on the same L2
+  // (0.298 -> 0.280 ms at 256^3; the correction and the prediction ran slower with it)
+  const ZCol z = zcol(wk, g, xcd_tile(blockIdx.x, gridDim.x));
   const int nz = g.n[2], pl = 1 << z.psh;
   auto ph = [&](int i) { return T(2) * P0[i] - P1[i]; };
   int c = z.c0;
@@ -539,7 +540,7 @@ __global__ __launch_bounds__(kNsThreads) void k_ns_correct_zm(FaceSet<T> U, Face
                                                               const T *__restrict__ C, const T *__restrict__ Pn,
                                                               const T *__restrict__ P0, const T *__restrict__ P1,
                                                               NsGrid g, NsCoef<T> k, int with_ut, NsWalk wk) {
-  const ZCol z = zcol(wk, g);
+  const ZCol z = zcol(wk, g, (int)blockIdx.x);
   const int nz = g.n[2], pl = 1 << z.psh;
   int c = z.c0;
   T pc = Pn[c], phc = T(2) * P0[c] - P1[c], rc = rho_of(k, C[c]);
