@@ -140,6 +140,24 @@ def test_coupled_steps_3d_wide(chib):
         _check(chib, st, orc, 3, f"3D tiled step {orc.step_count}")
 
 
+def test_coupled_steps_wall_free_3d(chib):
+    """No immersed wall: no ghosts (the velocity fill on u** has nothing to do), every staggered
+    fraction is 1, and a 64 x 8 grid goes through the edge-sharing prediction."""
+    grid = W.Grid((64, 8, 16), (0.0, 0.0, 0.0), (2.0, 0.25, 0.5))
+    prm = W.Params(Cn=0.04, Pe=50.0, Re=10.0, Ca=0.2, dt=1e-4, navier_stokes=True,
+                   rho1=0.2, rho2=1.0, mu1=0.5, mu2=1.0, body_force=(0.0, 0.0, -0.3))
+    C0, _ = W.droplet_field(grid, (1.0, 0.125, 0.25), 0.15, prm.Cn, 1e-3, 9)
+    rng = np.random.default_rng(19)
+    faces = [0.05 * rng.standard_normal(grid.shape) for _ in range(3)]
+    st, orc = _pair(chib, grid, prm, [], C0, faces)
+    assert len(orc.T.gidx) == 0
+    st.step(0)
+    for k in (1, 19):
+        st.step(k)
+        orc.step(k)
+        _check(chib, st, orc, 3, f"3D wall-free step {orc.step_count}")
+
+
 def test_coupled_steps_dynamic_contact_angle(chib):
     """Contact-line friction (Vs > 0): the dynamic ghost fill reads u^n and the velocity fill on u**
     carries the capillary bracket."""
