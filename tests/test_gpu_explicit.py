@@ -100,6 +100,23 @@ def test_explicit_3d_z_marching_kernels(chib):
     assert _linf(st.get(chib.FIELD_C), orc.C) <= 1e-9
 
 
+@pytest.mark.parametrize("n", [(64, 32), (64, 8, 16)])
+def test_explicit_wall_free_box(chib, n):
+    """No immersed wall: zero ghosts, so the phi ghost pass and the fills have empty lists; (64, 8, 16)
+    takes the z-marching phi and update kernels."""
+    d = len(n)
+    grid = W.Grid(n, (0.0,) * d, tuple(v / 16.0 for v in n))
+    prm = W.Params(Cn=0.1, Pe=50.0, dt=1e-5, explicit=True)
+    centre = tuple(0.5 * v / 16.0 for v in n)
+    case = W.Case("explicit_wall_free", grid, [], prm, 60, centre, 0.25 * min(n) / 16.0, 1e-2, 4)
+    st, orc = _pair(chib, case, _faces(grid, 12, 0.3))
+    assert len(orc.T.gidx) == 0
+    _say("explicit wall-free", n)
+    st.step(60)
+    orc.step(60)
+    assert _linf(st.get(chib.FIELD_C), orc.C) <= 1e-9
+
+
 def test_explicit_fp32_tracks_the_fp64_oracle(chib):
     case = _explicit(W.config1(), 2e-5)
     st, orc = _pair(chib, case, precision=32)
