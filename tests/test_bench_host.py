@@ -1,0 +1,25 @@
+"""Host-side logic of bench.py that needs no GPU."""
+import os
+import sys
+
+sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+
+import bench  # noqa: E402
+
+
+def test_code_digest_ignores_comments_and_whitespace(tmp_path):
+    a = tmp_path / "a.hip"
+    b = tmp_path / "b.hip"
+    c = tmp_path / "c.hip"
+    a.write_text("// header\nint f(int x) {\n  return x + 1;  /* one */\n}\n")
+    b.write_text("/* other\n   header */\nint f(int x) { return x + 1; }  // same code\n")
+    c.write_text("int f(int x) { return x + 2; }\n")
+    assert bench.code_digest(str(a)) == bench.code_digest(str(b))
+    assert bench.code_digest(str(a)) != bench.code_digest(str(c))
+
+
+def test_committed_counters_match_the_kernel_code():
+    """The committed HBM counter summary was taken on the kernel code in the tree, so bench.py reports
+    its traffic for the dominant kernel (in the launch shape the counters were taken with)."""
+    t = bench.measured_traffic("rhs_xdht", [[3, 8, 4], [4, 16, 1], [4, 16, 1], [3, 8, 1]], 8, 256)
+    assert t is not None and t > 0
