@@ -380,7 +380,7 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--precision", type=int, default=64, choices=(64, 32))
     ap.add_argument("--n", type=int, default=256, help="cells per axis of the sphere workload")
-    ap.add_argument("--cpu-steps", type=int, default=3)
+    ap.add_argument("--cpu-steps", type=int, default=15)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="keep the default launch shapes")
     ap.add_argument("--shapes", default="", help="fixed launch shapes 'a,b,c;d,e,f;g,h,i;j,k,l' instead of tuning")
