@@ -10,8 +10,10 @@ in the right-hand side, which is the only reading that reproduces the printed
 alpha_s and the bound on S):
 
     C~ = 2C^n - C^(n-1),  C^ = 2C^n - C^(n-1)/2
-    Q  = (Pe/Cn^2) (C^/dt - div_h(u C~)) + lap_h((C~^3 - C~ - S C~)/Cn^2)
+    Q  = (Pe/Cn^2) (C^/dt - div_h(u C~)) + lap_h(g),  g = (C~^3 - C~ - S C~)/Cn^2
     (lap_h - a)(lap_h + alpha_s) C* = Q,   a = alpha_s + S/Cn^2
+
+with the wall condition dphi/dn = 0 carried by g at the ghost cells (see rhs)
 
 solved with a cosine transform along the bounded (last) axis (Neumann box
 walls) and Fourier transforms along the periodic axes (end of Appendix A.1).
@@ -386,7 +388,20 @@ class OracleState:
             self.fill_velocity(self.C)
 
     def rhs(self) -> np.ndarray:
-        """Right-hand side Q of the first Helmholtz equation (Eq. Helmholtz1, psi -> psi')."""
+        """Right-hand side Q of the first Helmholtz equation (Eq. Helmholtz1, psi -> psi'),
+        with the wall condition dphi/dn = 0 imposed at the ghosts.
+
+        The stabilised step's chemical potential is the explicit part
+        phi~ = psi'(C~) - Cn^2 lap_h C~ plus the implicit correction
+        (S - Cn^2 lap_h)(C^(n+1) - C~), which vanishes as dt -> 0.  Dividing by Cn^2,
+        g = (psi'(C~) - S C~)/Cn^2 is phi~/Cn^2 + (lap_h - S/Cn^2) C~, and the second term
+        cancels against the implicit operator.  The end of section 4.2.2 imposes
+        dphi/dn = 0 at the ghosts by the mirror value, "in a similar way" as for C; in the
+        semi-implicit step that is done on phi~, the part the right-hand side carries:
+        g_G <- g_G + (phi~_M - phi~_G)/Cn^2.  phi~ at the averaging points of M uses the
+        filled ghost values of C^n and C^(n-1) (Eq. interpolationAtWall's C^_G).  The
+        correction term is left to the whole-box solve.
+        """
         prm = self.params
         grid = self.grid
         Cn2 = prm.Cn * prm.Cn
@@ -397,6 +412,10 @@ class OracleState:
         uadv = [2.0 * u - up for u, up in zip(self.faces, self.u_prev)] if prm.navier_stokes else self.faces
         A = advection(Ct, uadv, grid)
         g = (Ct * Ct * Ct - Ct - self.S * Ct) / Cn2
+        if self.T.n_ghost:
+            phit = (Ct * Ct * Ct - Ct - Cn2 * laplacian(Ct, grid)).reshape(-1)
+            gf = g.reshape(-1)
+            gf[self.T.gidx] += (mirror_value(phit, self.T) - phit[self.T.gidx]) / Cn2
         return (prm.Pe / Cn2) * (Cc / prm.dt - A) + laplacian(g, grid)
 
     def provisional(self) -> np.ndarray:

@@ -6,8 +6,7 @@
   conserved to round-off, with advection on.
 - Without immersed walls the explicit and the semi-implicit schemes discretise the same equation:
   their difference shrinks at the semi-implicit stabilisation's first order as dt falls.  (Near an
-  immersed wall they differ at O(1) by design: the explicit rate imposes dphi/dn = 0 at the ghosts,
-  the spectral semi-implicit solve spans the whole box.)
+  immersed wall they converge too, more slowly: tests/test_oracle_wall.py.)
 - The chemical potential is C^3 - C in the interior of a linear field; ghosts carry the mirror value.
 """
 import dataclasses
