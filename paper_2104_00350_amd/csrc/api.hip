@@ -60,6 +60,69 @@ FaceList build_faces(const ch_ib_geometry &g) {
   return fl;
 }
 
+// Cells whose rhs the wall condition dphi/dn = 0 changes (section 4.2.2): every ghost and its face
+// neighbours, sorted by cell, each with its own ghost index and those of its 2d face neighbours
+// (-1 where the cell or the neighbour is no ghost), and the first entry of every x-row.
+struct PatchList {
+  std::vector<int> cell;   // [NP]
+  std::vector<int> ref;    // [2d+1][NP]
+  std::vector<int> row;    // [rows+1]
+};
+
+PatchList build_patch(const ch_ib_geometry &g) {
+  PatchList pl;
+  const int d = g.ndim;
+  const int64_t G = g.n_ghost;
+  if (G == 0) return pl;
+  const int nx = g.n[0], ny = g.n[1];
+  auto shift = [&](int64_t c, int a, int s) -> int64_t {
+    int q[3] = {(int)(c % nx), (int)((c / nx) % ny), (int)(c / ((int64_t)nx * ny))};
+    q[a] += s;
+    if (a < d - 1) q[a] = (q[a] + g.n[a]) % g.n[a];
+    if (q[a] < 0 || q[a] >= g.n[a]) return -1;   // beyond a box wall (never for a ghost's neighbour)
+    return q[0] + (int64_t)nx * (q[1] + (int64_t)ny * q[2]);
+  };
+  std::vector<int64_t> cells;
+  cells.reserve((size_t)G * (2 * d + 1));
+  for (int64_t gi = 0; gi < G; ++gi) {
+    const int64_t c = g.gidx[gi];
+    cells.push_back(c);
+    for (int a = 0; a < d; ++a)
+      for (int sgn : {1, -1}) {
+        const int64_t q = shift(c, a, sgn);
+        if (q >= 0) cells.push_back(q);
+      }
+  }
+  std::sort(cells.begin(), cells.end());
+  cells.erase(std::unique(cells.begin(), cells.end()), cells.end());
+  const int64_t NP = (int64_t)cells.size();
+  auto ghost_of = [&](int64_t c) -> int {
+    if (c < 0) return -1;
+    auto it = std::lower_bound(g.gidx.begin(), g.gidx.end(), c);
+    return (it != g.gidx.end() && *it == c) ? (int)(it - g.gidx.begin()) : -1;
+  };
+  const int nref = 2 * d + 1;
+  pl.cell.resize(NP);
+  pl.ref.assign((size_t)nref * NP, -1);
+  for (int64_t e = 0; e < NP; ++e) {
+    const int64_t c = cells[e];
+    pl.cell[e] = (int)c;
+    pl.ref[e] = ghost_of(c);
+    for (int a = 0; a < d; ++a) {
+      pl.ref[(size_t)(1 + 2 * a) * NP + e] = ghost_of(shift(c, a, 1));
+      pl.ref[(size_t)(2 + 2 * a) * NP + e] = ghost_of(shift(c, a, -1));
+    }
+  }
+  const int64_t rows = g.cells / nx;
+  pl.row.assign((size_t)rows + 1, 0);
+  int64_t e = 0;
+  for (int64_t r = 0; r <= rows; ++r) {
+    while (e < NP && cells[e] / nx < r) ++e;
+    pl.row[r] = (int)e;
+  }
+  return pl;
+}
+
 struct Layout {
   size_t total = 0;
   size_t off(size_t bytes) {
@@ -71,13 +134,14 @@ struct Layout {
 
 struct Offsets {
   size_t C[2], F[3], W, R, alpha, gidx, normal, dn, gamma, ap, w, CGn, CGnm1, CMs, CI, CGnew, UG;
+  size_t dg, pl_cell, pl_ref, pl_row;
   size_t Us[3], Ut[3], Nh[3], Af[3], P[2];
   size_t f_cell, f_axis, f_gL, f_gR, stashL, stashR;
   size_t twr[3], twi[3], dctc, dcts, lam[3], partial, red_out;
   size_t total;
 };
 
-Offsets plan_layout(const ch_ib_geometry &g, int es, int64_t NF, bool explicit_ab2, bool ns) {
+Offsets plan_layout(const ch_ib_geometry &g, int es, int64_t NF, int64_t NP, bool explicit_ab2, bool ns) {
   Layout L;
   Offsets o{};
   const int64_t N = g.cells, G = g.n_ghost;
@@ -109,6 +173,10 @@ Offsets plan_layout(const ch_ib_geometry &g, int es, int64_t NF, bool explicit_a
   o.CI = L.off(G * es);
   o.CGnew = L.off(G * es);
   o.UG = L.off(d * G * es);
+  o.dg = L.off(G * es);
+  o.pl_cell = L.off(NP * 4);
+  o.pl_ref = L.off((2 * d + 1) * NP * 4);
+  o.pl_row = L.off((N / g.n[0] + 1) * 4);
   o.f_cell = L.off(NF * 4);
   o.f_axis = L.off(NF * 4);
   o.f_gL = L.off(NF * 4);
@@ -213,8 +281,9 @@ extern "C" size_t ch_ib_workspace_bytes(const ch_ib_grid *grid, const ch_ib_geom
   if (params->precision != 64 && params->precision != 32) return 0;
   const int es = params->precision == 64 ? 8 : 4;
   FaceList fl = build_faces(*geom);
-  return plan_layout(*geom, es, (int64_t)fl.cell.size(), (params->flags & CH_IB_FLAG_EXPLICIT) != 0,
-                     (params->flags & CH_IB_FLAG_NAVIER_STOKES) != 0)
+  PatchList pl = build_patch(*geom);
+  return plan_layout(*geom, es, (int64_t)fl.cell.size(), (int64_t)pl.cell.size(),
+                     (params->flags & CH_IB_FLAG_EXPLICIT) != 0, (params->flags & CH_IB_FLAG_NAVIER_STOKES) != 0)
              .total +
          256;
 }
@@ -247,8 +316,10 @@ extern "C" int ch_ib_state_create(const ch_ib_grid *grid, const ch_ib_geometry *
   st->has_alpha = !geom->alpha.empty();
   FaceList fl = build_faces(*geom);
   const int64_t NF = (int64_t)fl.cell.size();
+  PatchList pl = build_patch(*geom);
+  const int64_t NP = (int64_t)pl.cell.size();
   const bool ns = (params->flags & CH_IB_FLAG_NAVIER_STOKES) != 0;
-  st->off = plan_layout(*geom, st->es, NF, (params->flags & CH_IB_FLAG_EXPLICIT) != 0, ns);
+  st->off = plan_layout(*geom, st->es, NF, NP, (params->flags & CH_IB_FLAG_EXPLICIT) != 0, ns);
   const Offsets &o = st->off;
   chib::Plan &p = st->plan;
   const int d = geom->ndim;
@@ -313,6 +384,11 @@ extern "C" int ch_ib_state_create(const ch_ib_grid *grid, const ch_ib_geometry *
   p.CI = W0 + o.CI;
   p.CGnew = W0 + o.CGnew;
   p.UG = W0 + o.UG;
+  p.dg = W0 + o.dg;
+  p.NP = NP;
+  p.pl_cell = (const int *)(W0 + o.pl_cell);
+  p.pl_ref = (const int *)(W0 + o.pl_ref);
+  p.pl_row = (const int *)(W0 + o.pl_row);
   p.NF = NF;
   p.f_cell = (const int *)(W0 + o.f_cell);
   p.f_axis = (const int *)(W0 + o.f_axis);
@@ -384,6 +460,13 @@ extern "C" int ch_ib_state_create(const ch_ib_grid *grid, const ch_ib_geometry *
     up(geom->dn, (void *)p.dn);
     up(geom->gamma, (void *)p.gamma);
     up(geom->w, (void *)p.w);
+  }
+  if (NP && e == hipSuccess) {
+    e = hipMemcpyAsync((void *)p.pl_cell, pl.cell.data(), NP * 4, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync((void *)p.pl_ref, pl.ref.data(), pl.ref.size() * 4, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync((void *)p.pl_row, pl.row.data(), pl.row.size() * 4, hipMemcpyHostToDevice, s);
   }
   if (NF && e == hipSuccess) {
     e = hipMemcpyAsync((void *)p.f_cell, fl.cell.data(), NF * 4, hipMemcpyHostToDevice, s);

@@ -52,6 +52,15 @@ struct Plan {
   void *CGn = nullptr, *CGnm1 = nullptr, *CMs = nullptr, *CI = nullptr, *CGnew = nullptr;
   void *UG = nullptr;              // [d][G]
 
+  // wall condition dphi/dn = 0 of the semi-implicit step: per ghost the change of g,
+  // dg = (phi~_M - phi~_G)/Cn^2, and the cells whose rhs it changes (ghosts and their face
+  // neighbours, sorted by cell) with the first of them on each x-row
+  void *dg = nullptr;              // [G]
+  int64_t NP = 0;
+  const int *pl_cell = nullptr;    // [NP]
+  const int *pl_ref = nullptr;     // [2d+1][NP]: own ghost index, then the ghost at +e_a and -e_a per axis, or -1
+  const int *pl_row = nullptr;     // [rows+1]
+
   // faces touching ghosts (velocity fill)
   int64_t NF = 0;
   const int *f_cell = nullptr;     // left cell of the face

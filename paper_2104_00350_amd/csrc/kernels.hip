@@ -47,6 +47,51 @@ struct RhsCoef {
   T inv_h2;
 };
 
+// The wall condition dphi/dn = 0 in the rhs (end of section 4.2.2, Eq. WallBCS): g at every ghost
+// G becomes g_G + dg_G, dg_G = (phi~_M - phi~_G)/Cn^2 with phi~ = C~^3 - C~ - Cn^2 lap_h C~ the
+// explicit chemical potential of the step (k_ghost_dphi).  Through lap_h(g) that changes Q at the
+// ghost by -2d dg_G/h^2 and at each face neighbour by +dg_G/h^2: a sparse patch of Q on the
+// ghosts and their neighbours, listed sorted by cell with the first entry of each x-row.
+// dg == nullptr: no patch (no ghosts).
+template <typename T>
+struct GhostPatch {
+  const int *cell;   // [np]
+  const int *ref;    // [nref][np]: own ghost index, then the ghost neighbours (+e_a, -e_a per axis), or -1
+  const int *row;    // [rows + 1]
+  const T *dg;       // [G]
+  int64_t np;
+  int nref;          // 2d + 1
+  T twod;            // 2d
+  T inv_h2;
+};
+
+// Change of Q at patched cell e: (sum of the neighbouring ghosts' dg - 2d dg_own) / h^2.
+template <typename T>
+__device__ __forceinline__ T patch_value(const GhostPatch<T> &gp, int64_t e) {
+  T acc = T(0);
+  for (int j = 1; j < gp.nref; ++j) {
+    const int id = gp.ref[(int64_t)j * gp.np + e];
+    if (id >= 0) acc += gp.dg[id];
+  }
+  const int own = gp.ref[e];
+  if (own >= 0) acc -= gp.twod * gp.dg[own];
+  return acc * gp.inv_h2;
+}
+
+// Patches of x-row R added to the values q[m] a thread holds for columns x = tid + 256 m of that
+// row.  R is uniform across the workgroup, so every lane walks the same (short) entry list.
+template <typename T, int XM>
+__device__ __forceinline__ void patch_row(const GhostPatch<T> &gp, int64_t R, int lnx, int tid, T (&q)[XM]) {
+  const int e1 = gp.row[R + 1];
+  for (int e = gp.row[R]; e < e1; ++e) {
+    const int x = gp.cell[e] & ((1 << lnx) - 1);
+    const T dq = patch_value(gp, e);
+#pragma unroll
+    for (int m = 0; m < XM; ++m)
+      if (x == tid + 256 * m) q[m] += dq;
+  }
+}
+
 
 // ---------------------------------------------------------------------------------------
 // Register DFTs of length R in {2, 4, 8, 16}, natural order in and out.  Forward uses
@@ -394,7 +439,7 @@ __device__ __forceinline__ void rhs_xdht_body(unsigned char *smem_raw, const T *
                                                        const T *__restrict__ F0, const T *__restrict__ F1,
                                                        const T *__restrict__ F2, T *__restrict__ W, Dims dm,
                                                        RhsCoef<T> cf, int logL, const T *__restrict__ twr,
-                                                       const T *__restrict__ twi, int tile) {
+                                                       const T *__restrict__ twi, int tile, const GhostPatch<T> &gp) {
   T *s = reinterpret_cast<T *>(smem_raw);
   const int L = 1 << logL;
   const int nx = dm.nx;
@@ -432,6 +477,16 @@ __device__ __forceinline__ void rhs_xdht_body(unsigned char *smem_raw, const T *
       }
     }
   }
+  if (gp.dg) {   // the ghost patches of the tile's lines, one entry per thread
+    __syncthreads();
+    const int e1 = gp.row[line0 + L];
+    for (int e = gp.row[line0] + threadIdx.x; e < e1; e += blockDim.x) {
+      const int c = gp.cell[e];
+      const int l = (c >> dm.lnx) - line0;
+      const int i = c & (nx - 1);
+      s[l * pitch + i + (i >> 4)] += patch_value(gp, e);
+    }
+  }
   __syncthreads();
   lds_fft<T, E, false, MAXR>(s, dm.lnx, logL - 1, 2 * pitch, 1, pitch, 1, false, twr, twi);
   const int half = tot >> 1;
@@ -453,9 +508,10 @@ __global__ __launch_bounds__(kThreads) void k_rhs_xdht(const T *__restrict__ Cn,
                                                        const T *__restrict__ F0, const T *__restrict__ F1,
                                                        const T *__restrict__ F2, T *__restrict__ W, Dims dm,
                                                        RhsCoef<T> cf, int logL, const T *__restrict__ twr,
-                                                       const T *__restrict__ twi) {
+                                                       const T *__restrict__ twi, GhostPatch<T> gp) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  rhs_xdht_body<T, D, E, U, MAXR>(smem_raw, Cn, Cp, F0, F1, F2, W, dm, cf, logL, twr, twi, xcd_tile(blockIdx.x, gridDim.x));
+  rhs_xdht_body<T, D, E, U, MAXR>(smem_raw, Cn, Cp, F0, F1, F2, W, dm, cf, logL, twr, twi, xcd_tile(blockIdx.x, gridDim.x),
+                                  gp);
 }
 
 // Extra LDS of the y-marching K1 (two rows of C~ for the x neighbours) over the line tile.
@@ -474,7 +530,7 @@ __device__ __forceinline__ void rhs_ym_body(unsigned char *smem_raw, const T *__
                                             const T *__restrict__ Cp, const T *__restrict__ F0,
                                             const T *__restrict__ F1, T *__restrict__ W, Dims dm, RhsCoef<T> cf,
                                             int logL, const T *__restrict__ twr, const T *__restrict__ twi,
-                                            int tile) {
+                                            int tile, const GhostPatch<T> &gp) {
   const int nx = dm.nx, ny = dm.ny;
   const int L = 1 << logL;
   const int pitch = line_pitch(nx);
@@ -520,9 +576,11 @@ __device__ __forceinline__ void rhs_ym_body(unsigned char *smem_raw, const T *__
       }
     }
     __syncthreads();   // the row is in LDS; the ring slot written next row was last read two rows ago
+    T qv[XM];
 #pragma unroll
     for (int m = 0; m < XM; ++m) {
       const int i = tid + 256 * m;
+      qv[m] = T(0);
       if (i < nx) {
         const T v0 = T(2) * a0[m] - b0[m];
         const T cxp = xb[(i + 1) & (nx - 1)], cxm = xb[(i - 1) & (nx - 1)];
@@ -534,7 +592,7 @@ __device__ __forceinline__ void rhs_ym_body(unsigned char *smem_raw, const T *__
         const T A = flux * T(0.5) * cf.inv_h;
         const T lap = (gsum - T(4) * g0) * klap;
         const T h0 = T(2) * a0[m] - T(0.5) * b0[m];
-        fb[r * pitch + i + (i >> 4)] = cf.pe_cn2 * (h0 * cf.inv_dt - A) + lap;
+        qv[m] = cf.pe_cn2 * (h0 * cf.inv_dt - A) + lap;
         // slide the window down one row and request the row after next
         cm[m] = v0;
         a0[m] = a1[m];
@@ -547,6 +605,12 @@ __device__ __forceinline__ void rhs_ym_body(unsigned char *smem_raw, const T *__
           bn[m] = rowp(Cp, y + 3)[i];
         }
       }
+    }
+    if (gp.dg) patch_row<T, XM>(gp, y, dm.lnx, tid, qv);
+#pragma unroll
+    for (int m = 0; m < XM; ++m) {
+      const int i = tid + 256 * m;
+      if (i < nx) fb[r * pitch + i + (i >> 4)] = qv[m];
     }
   }
   __syncthreads();
@@ -569,9 +633,10 @@ template <typename T, int XM, int R>
 __global__ __launch_bounds__(kThreads, R == 8 ? 4 : 3) void k_rhs_xdht_ym(const T *__restrict__ Cn, const T *__restrict__ Cp,
                                                           const T *__restrict__ F0, const T *__restrict__ F1,
                                                           T *__restrict__ W, Dims dm, RhsCoef<T> cf, int logL,
-                                                          const T *__restrict__ twr, const T *__restrict__ twi) {
+                                                          const T *__restrict__ twr, const T *__restrict__ twi,
+                                                          GhostPatch<T> gp) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  rhs_ym_body<T, XM, R>(smem_raw, Cn, Cp, F0, F1, W, dm, cf, logL, twr, twi, xcd_tile(blockIdx.x, gridDim.x));
+  rhs_ym_body<T, XM, R>(smem_raw, Cn, Cp, F0, F1, W, dm, cf, logL, twr, twi, xcd_tile(blockIdx.x, gridDim.x), gp);
 }
 
 // K1 for 3D grids, marching in z (2.5D blocking): a workgroup owns L consecutive y rows and
@@ -585,7 +650,7 @@ __global__ __launch_bounds__(kThreads) void k_rhs_xdht_zm(const T *__restrict__ 
                                                           const T *__restrict__ F0, const T *__restrict__ F1,
                                                           const T *__restrict__ F2, T *__restrict__ W, Dims dm,
                                                           RhsCoef<T> cf, int zc_log, const T *__restrict__ twr,
-                                                          const T *__restrict__ twi) {
+                                                          const T *__restrict__ twi, GhostPatch<T> gp) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T *plane = reinterpret_cast<T *>(smem_raw);        // L rows x nx: C~ of plane z
   const int nx = dm.nx;
@@ -666,10 +731,24 @@ __global__ __launch_bounds__(kThreads) void k_rhs_xdht_zm(const T *__restrict__ 
         const T A = flux * T(0.5) * cf.inv_h;
         const T lap = (gsum - T(6) * gf(v0)) * cf.inv_h2;
         q[m][r] = cf.pe_cn2 * (h0[m][r] * cf.inv_dt - A) + lap;
-        if constexpr (SPLIT) W[c] = q[m][r];
+      }
+    }
+    if (gp.dg) {
+#pragma unroll
+      for (int r = 0; r < L; ++r) {
+        T qr[XM];
+#pragma unroll
+        for (int m = 0; m < XM; ++m) qr[m] = q[m][r];
+        patch_row<T, XM>(gp, (int64_t)z * dm.ny + y0 + r, dm.lnx, tid, qr);
+#pragma unroll
+        for (int m = 0; m < XM; ++m) q[m][r] = qr[m];
       }
     }
     if constexpr (SPLIT) {
+#pragma unroll
+      for (int m = 0; m < XM; ++m)
+#pragma unroll
+        for (int r = 0; r < L; ++r) W[zb + (int64_t)(y0 + r) * nx + tid + 256 * m] = q[m][r];
       __syncthreads();   // every x-neighbour read of this plane is done before the next write
     } else {
 #pragma unroll
@@ -1083,6 +1162,78 @@ __global__ __launch_bounds__(kThreads) void k_commit_ghosts(T *__restrict__ C, c
   C[gidx[g]] = v;
   CGnm1[g] = init ? v : CGn[g];
   CGn[g] = v;
+}
+
+// Explicit chemical potential phi~ = C~^3 - C~ - Cn^2 lap_h C~ of the semi-implicit step at one cell,
+// C~ = 2C^n - C^(n-1); periodic axes wrap, the bounded axis reflects (the Laplacian of the solve).
+template <typename T>
+__device__ __forceinline__ T phit_at(const T *__restrict__ Cn, const T *__restrict__ Cp, int64_t c, const Dims &dm,
+                                     int d, T cn2, T inv_h2) {
+  auto ct = [&](int64_t q) { return T(2) * Cn[q] - Cp[q]; };
+  const int i = (int)(c & (dm.nx - 1));
+  const int64_t r = c >> dm.lnx;
+  const int j = (int)(r & (dm.ny - 1));
+  const int k = (int)(r >> dm.lny);
+  const int64_t rowb = c - i;
+  const T v = ct(c);
+  T acc = ct(rowb + ((i + 1) & (dm.nx - 1))) + ct(rowb + ((i - 1) & (dm.nx - 1)));
+  if (d == 2) {
+    acc = acc + (j < dm.ny - 1 ? ct(c + dm.nx) : v);
+    acc = acc + (j > 0 ? ct(c - dm.nx) : v);
+  } else {
+    const int jp = (j + 1) & (dm.ny - 1), jm = (j - 1) & (dm.ny - 1);
+    acc = acc + ct(c + (int64_t)(jp - j) * dm.nx);
+    acc = acc + ct(c + (int64_t)(jm - j) * dm.nx);
+    acc = acc + (k < dm.nz - 1 ? ct(c + dm.plane) : v);
+    acc = acc + (k > 0 ? ct(c - dm.plane) : v);
+  }
+  const T lap = (acc - T(2 * d) * v) * inv_h2;
+  return v * v * v - v - cn2 * lap;
+}
+
+// The wall condition dphi/dn = 0 of the semi-implicit step (end of section 4.2.2, Eq. WallBCS):
+// per ghost, dg = (phi~_M - phi~_G)/Cn^2 with phi~_M = 2 IDW(IP1) - IDW(IP2) of phi~ (Eq.
+// extrapolation).  Sixteen lanes per ghost: lane s < 2K one weighted averaging point, lane 2K
+// the ghost itself; fixed-order lane-group sum.
+template <typename T>
+__device__ __forceinline__ void ghost_dphi_body(const T *__restrict__ Cn, const T *__restrict__ Cp,
+                                                const int *__restrict__ gidx, const int *__restrict__ ap,
+                                                const T *__restrict__ w, T *__restrict__ dg, int64_t G, int K,
+                                                const Dims &dm, int d, T cn2, T inv_h2, T inv_cn2, int64_t tile) {
+  const int64_t g = ((int64_t)tile * blockDim.x + threadIdx.x) >> 4;
+  const int sl = threadIdx.x & 15;
+  T v = T(0);
+  if (g < G && sl <= 2 * K) {
+    int64_t c;
+    T coef;
+    if (sl < 2 * K) {
+      const int64_t i = (int64_t)sl * G + g;
+      c = ap[i];
+      coef = (sl < K ? T(2) : T(-1)) * w[i];
+    } else {
+      c = gidx[g];
+      coef = T(-1);
+    }
+    v = coef * phit_at(Cn, Cp, c, dm, d, cn2, inv_h2);
+  }
+  const T sum = group16_sum(v);
+  if (g < G && sl == 0) dg[g] = sum * inv_cn2;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_ghost_dphi(const T *__restrict__ Cn, const T *__restrict__ Cp,
+                                                         const int *__restrict__ gidx, const int *__restrict__ ap,
+                                                         const T *__restrict__ w, T *__restrict__ dg, int64_t G,
+                                                         int K, Dims dm, int d, T cn2, T inv_h2, T inv_cn2) {
+  ghost_dphi_body<T>(Cn, Cp, gidx, ap, w, dg, G, K, dm, d, cn2, inv_h2, inv_cn2, blockIdx.x);
+}
+
+// The ghost patch added to a rhs field stored cell by cell (stage entry point).
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_rhs_patch(T *__restrict__ Q, GhostPatch<T> gp) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= gp.np) return;
+  Q[gp.cell[e]] += patch_value(gp, e);
 }
 
 // K7a: ghost velocities (Eqs. NoPenetration, UpdateVtan, UpdateVandW in vector form) and,
@@ -1723,6 +1874,34 @@ inline RhsCoef<T> make_coef(const Plan &p) {
 
 inline unsigned blocks_for(int64_t n) { return (unsigned)((n + kThreads - 1) / kThreads); }
 
+// Ghost patch of the rhs (no patch without ghosts, and none for the explicit step).
+template <typename T>
+inline GhostPatch<T> make_patch(const Plan &p) {
+  GhostPatch<T> gp{};
+  if (p.G > 0 && p.dg && p.NP > 0) {
+    gp.cell = p.pl_cell;
+    gp.ref = p.pl_ref;
+    gp.row = p.pl_row;
+    gp.dg = (const T *)p.dg;
+    gp.np = p.NP;
+  }
+  gp.nref = 2 * p.d + 1;
+  gp.twod = (T)(2 * p.d);
+  gp.inv_h2 = (T)(1.0 / (p.h * p.h));
+  return gp;
+}
+
+// dg of every ghost from C^n, C^(n-1) (before the rhs pass of a semi-implicit step).
+template <typename T>
+hipError_t launch_ghost_dphi(const Plan &p, const T *Cn, const T *Cp) {
+  if (p.G == 0 || !p.dg) return hipSuccess;
+  const Dims dm = make_dims(p);
+  hipLaunchKernelGGL((k_ghost_dphi<T>), dim3(blocks_for(p.G * 16)), dim3(kThreads), 0, p.stream, Cn, Cp, p.gidx,
+                     p.ap, (const T *)p.w, (T *)p.dg, p.G, p.K, dm, p.d, (T)(p.Cn * p.Cn), (T)(1.0 / (p.h * p.h)),
+                     (T)(1.0 / (p.Cn * p.Cn)));
+  return hipGetLastError();
+}
+
 // Faces that advect C in the rhs pass: the extrapolated velocity when the momentum equation is
 // solved too, else the faces themselves.
 inline const void *adv_face(const Plan &p, int a) { return p.Fadv[a] ? p.Fadv[a] : p.F[a]; }
@@ -1814,7 +1993,7 @@ void launch_rhs_variant(const Plan &p, const T *Cn, const T *Cp, int logL, unsig
   const RhsCoef<T> cf = make_coef<T>(p);
   hipLaunchKernelGGL((k_rhs_xdht<T, D, tile_elems<T>(), U, R>), dim3(nb), dim3(kThreads), lds, p.stream, Cn, Cp,
                      (const T *)adv_face(p, 0), (const T *)adv_face(p, 1), (const T *)(D == 3 ? adv_face(p, 2) : adv_face(p, 1)), (T *)p.W, dm, cf,
-                     logL, (const T *)p.twr[0], (const T *)p.twi[0]);
+                     logL, (const T *)p.twr[0], (const T *)p.twi[0], make_patch<T>(p));
 }
 
 // y-marching variant (2D, nx up to 1024): unroll = 3.
@@ -1828,7 +2007,7 @@ void launch_ym_variant(const Plan &p, const T *Cn, const T *Cp, int logL) {
   const size_t lds = ((size_t)(1 << logL) * line_pitch(p.n[0]) + ym_extra(p.n[0])) * sizeof(T);
   hipLaunchKernelGGL((k_rhs_xdht_ym<T, XM, R>), dim3(nb), dim3(kThreads), lds, p.stream, Cn, Cp,
                      (const T *)adv_face(p, 0), (const T *)adv_face(p, 1), (T *)p.W, dm, cf, logL, (const T *)p.twr[0],
-                     (const T *)p.twi[0]);
+                     (const T *)p.twi[0], make_patch<T>(p));
 }
 
 template <typename T, int R>
@@ -1849,7 +2028,7 @@ void launch_zm_variant(const Plan &p, const T *Cn, const T *Cp, int zc_log) {
   const size_t lds = ((size_t)L * p.n[0] + (SPLIT ? 0 : (size_t)L * line_pitch(p.n[0]))) * sizeof(T);
   hipLaunchKernelGGL((k_rhs_xdht_zm<T, L, XM, R, SPLIT>), dim3(nb), dim3(kThreads), lds, p.stream, Cn, Cp,
                      (const T *)adv_face(p, 0), (const T *)adv_face(p, 1), (const T *)adv_face(p, 2), (T *)p.W, dm, cf, zc_log,
-                     (const T *)p.twr[0], (const T *)p.twi[0]);
+                     (const T *)p.twr[0], (const T *)p.twi[0], make_patch<T>(p));
 }
 
 // Stencil-only z-march (the rhs Q into W, no transform) with L rows per tile.
@@ -2034,6 +2213,10 @@ hipError_t enqueue_step(const Plan &p, int cur, KernelTimer *tm) {
     if (tm && e == hipSuccess) e = tm->mark(name, p.stream);
   };
   const bool split = p.d == 3 && p.shape[0].unroll >= 6 && zm_ok(p);
+  if (p.G) {
+    mark("ghost_dphi");
+    if (e == hipSuccess) e = launch_ghost_dphi<T>(p, Cn, Cp);
+  }
   mark(split ? "rhs_stencil" : "rhs_xdht");
   if (e == hipSuccess)
     e = p.d == 2 ? launch_rhs<T, 2>(p, Cn, Cp, p.shape[0], true) : launch_rhs<T, 3>(p, Cn, Cp, p.shape[0], true);
@@ -2080,8 +2263,9 @@ hipError_t tune_shapes(Plan &p, int cur, int reps) {
   };
   const T *Cn = (const T *)p.C[cur];
   const T *Cp = (const T *)p.C[1 - cur];
+  e = launch_ghost_dphi<T>(p, Cn, Cp);   // the rhs candidates read the ghost patch
   // pass 0: fused rhs
-  {
+  if (e == hipSuccess) {
     const int hi = max_log_lines(p, E);
     float best = 1e30f;
     Plan::Shape bs = p.shape[0];
@@ -2180,12 +2364,17 @@ hipError_t enqueue_rhs(const Plan &p, int cur, void *out) {
   const Dims dm = make_dims(p);
   const RhsCoef<T> cf = make_coef<T>(p);
   const T *F2 = (const T *)(p.d == 3 ? adv_face(p, 2) : adv_face(p, 1));
+  hipError_t e = launch_ghost_dphi<T>(p, (const T *)p.C[cur], (const T *)p.C[1 - cur]);
+  if (e != hipSuccess) return e;
   if (p.d == 2)
     hipLaunchKernelGGL((k_rhs_only<T, 2>), dim3(blocks_for(p.N)), dim3(kThreads), 0, p.stream, (const T *)p.C[cur],
                        (const T *)p.C[1 - cur], (const T *)adv_face(p, 0), (const T *)adv_face(p, 1), F2, (T *)out, dm, cf, p.N);
   else
     hipLaunchKernelGGL((k_rhs_only<T, 3>), dim3(blocks_for(p.N)), dim3(kThreads), 0, p.stream, (const T *)p.C[cur],
                        (const T *)p.C[1 - cur], (const T *)adv_face(p, 0), (const T *)adv_face(p, 1), F2, (T *)out, dm, cf, p.N);
+  const GhostPatch<T> gp = make_patch<T>(p);
+  if (gp.dg)
+    hipLaunchKernelGGL((k_rhs_patch<T>), dim3(blocks_for(gp.np)), dim3(kThreads), 0, p.stream, (T *)out, gp);
   return hipGetLastError();
 }
 
@@ -2371,6 +2560,8 @@ struct CaseDesc {
   const int *f_cell, *f_axis, *f_gL, *f_gR;
   T *stashL, *stashR;
   unsigned nbg;
+  GhostPatch<T> gp;        // dphi/dn = 0 at the ghosts: dg (written by kb_dphi) and the rhs patch
+  T cn2, inv_h2, inv_cn2;
 };
 
 namespace {
@@ -2392,7 +2583,17 @@ __global__ __launch_bounds__(kThreads) void kb_rhs(const CaseDesc<T> *__restrict
   const int c = find_case(off, n, blockIdx.x);
   const CaseDesc<T> &d = cs[c];
   rhs_xdht_body<T, 2, E, U, R>(smem_raw, d.C[parity], d.C[1 - parity], d.F0, d.F1, d.F1, d.W, d.dm, d.cf,
-                               d.logL_rhs, d.twr0, d.twi0, (int)(blockIdx.x - off[c]));
+                               d.logL_rhs, d.twr0, d.twi0, (int)(blockIdx.x - off[c]), d.gp);
+}
+
+// dg of every ghost of every case, before the rhs pass.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void kb_dphi(const CaseDesc<T> *__restrict__ cs, const int *__restrict__ off,
+                                                    int n, int parity) {
+  const int c = find_case(off, n, blockIdx.x);
+  const CaseDesc<T> &d = cs[c];
+  ghost_dphi_body<T>(d.C[parity], d.C[1 - parity], d.gidx, d.ap, d.w, const_cast<T *>(d.gp.dg), d.G, d.K, d.dm, 2,
+                     d.cn2, d.inv_h2, d.inv_cn2, (int64_t)(blockIdx.x - off[c]));
 }
 
 template <typename T, int R>
@@ -2404,11 +2605,11 @@ __global__ __launch_bounds__(kThreads, R == 8 ? 4 : 3) void kb_rhs_ym(const Case
   const int t = (int)(blockIdx.x - off[c]);
   // the same instantiation as the single-state launch for this width, so results match bit for bit
   if (d.dm.nx <= 256)
-    rhs_ym_body<T, 1, R>(smem_raw, d.C[parity], d.C[1 - parity], d.F0, d.F1, d.W, d.dm, d.cf, d.logL_rhs, d.twr0, d.twi0, t);
+    rhs_ym_body<T, 1, R>(smem_raw, d.C[parity], d.C[1 - parity], d.F0, d.F1, d.W, d.dm, d.cf, d.logL_rhs, d.twr0, d.twi0, t, d.gp);
   else if (d.dm.nx <= 512)
-    rhs_ym_body<T, 2, R>(smem_raw, d.C[parity], d.C[1 - parity], d.F0, d.F1, d.W, d.dm, d.cf, d.logL_rhs, d.twr0, d.twi0, t);
+    rhs_ym_body<T, 2, R>(smem_raw, d.C[parity], d.C[1 - parity], d.F0, d.F1, d.W, d.dm, d.cf, d.logL_rhs, d.twr0, d.twi0, t, d.gp);
   else
-    rhs_ym_body<T, 4, R>(smem_raw, d.C[parity], d.C[1 - parity], d.F0, d.F1, d.W, d.dm, d.cf, d.logL_rhs, d.twr0, d.twi0, t);
+    rhs_ym_body<T, 4, R>(smem_raw, d.C[parity], d.C[1 - parity], d.F0, d.F1, d.W, d.dm, d.cf, d.logL_rhs, d.twr0, d.twi0, t, d.gp);
 }
 
 template <typename T, int E, int R>
@@ -2516,6 +2717,10 @@ void fill_case_desc(const Plan &p, int cur, void *desc_host) {
   d.stashL = (T *)p.stashL;
   d.stashR = (T *)p.stashR;
   d.nbg = blocks_for(p.G * 16);
+  d.gp = make_patch<T>(p);
+  d.cn2 = (T)(p.Cn * p.Cn);
+  d.inv_h2 = (T)(1.0 / (p.h * p.h));
+  d.inv_cn2 = (T)(1.0 / (p.Cn * p.Cn));
   std::memcpy(desc_host, &d, sizeof(d));
 }
 
@@ -2524,7 +2729,7 @@ size_t case_desc_bytes() {
   return sizeof(CaseDesc<T>);
 }
 
-// Per-phase tile counts of one case (0 rhs, 1 neumann, 2 out, 3 fill, 4 velg, 5 velf) and the
+// Per-phase tile counts of one case (0 rhs, 1 neumann, 2 out, 3 fill, 4 dphi, 5 velf) and the
 // LDS bytes of its tiles (0 rhs, 1 neumann, 2 out).
 template <typename T>
 void case_tiles(const Plan &p, int *tiles, size_t *lds) {
@@ -2537,7 +2742,7 @@ void case_tiles(const Plan &p, int *tiles, size_t *lds) {
   tiles[2] = p.n[1] >> lo;
   const bool vf = p.vel_fill && p.G > 0;
   tiles[3] = (int)blocks_for(p.G * 16) + (vf ? (int)(blocks_for(p.G * 16) + blocks_for(p.NF)) : 0);
-  tiles[4] = 0;   // the ghost velocities run inside phase 3 (kb_fill)
+  tiles[4] = make_patch<T>(p).dg ? (int)blocks_for(p.G * 16) : 0;   // (the ghost velocities run inside phase 3)
   tiles[5] = vf ? (int)blocks_for(p.NF) : 0;
   lds[0] = (size_t)(1 << lr) * line_pitch(p.n[0]) * sizeof(T);
   lds[1] = (size_t)col_tile(p.n[1], 1 << lb) * sizeof(T);
@@ -2555,6 +2760,7 @@ hipError_t enqueue_batch_step(const BatchLaunch &bl, int parity) {
   const unsigned nb0 = bl.total[0], nb1 = bl.total[1], nb2 = bl.total[2];
   const unsigned nb3 = bl.total[3], nb4 = bl.total[4], nb5 = bl.total[5];
   const bool r8 = bl.radix_rhs == 8, u2 = bl.unroll >= 2;
+  if (nb4) hipLaunchKernelGGL((kb_dphi<T>), dim3(nb4), dim3(kThreads), 0, bl.stream, cs, O(4), n, parity);
   if (bl.unroll == 3 && bl.lds[3]) {
     if (r8) hipLaunchKernelGGL((kb_rhs_ym<T, 8>), dim3(nb0), dim3(kThreads), bl.lds[3], bl.stream, cs, O(0), n, parity);
     else hipLaunchKernelGGL((kb_rhs_ym<T, 16>), dim3(nb0), dim3(kThreads), bl.lds[3], bl.stream, cs, O(0), n, parity);
@@ -2567,7 +2773,6 @@ hipError_t enqueue_batch_step(const BatchLaunch &bl, int parity) {
   if (bl.radix_out == 8) hipLaunchKernelGGL((kb_out<T, E, 8>), dim3(nb2), dim3(kThreads), bl.lds[2], bl.stream, cs, O(2), n, parity);
   else hipLaunchKernelGGL((kb_out<T, E, 16>), dim3(nb2), dim3(kThreads), bl.lds[2], bl.stream, cs, O(2), n, parity);
   if (nb3) hipLaunchKernelGGL((kb_fill<T>), dim3(nb3), dim3(kThreads), 0, bl.stream, cs, O(3), n, parity);
-  (void)nb4;
   if (nb5) hipLaunchKernelGGL((kb_velf<T>), dim3(nb5), dim3(kThreads), 0, bl.stream, cs, O(5), n);
   return hipGetLastError();
 }
