@@ -251,17 +251,33 @@ def test_3d_sphere_50_steps(chib):
         assert _linf(st.get(chib.FIELD_U + a), orc.faces[a]) <= 1e-9
 
 
-def test_3d_config3_full_size_few_steps(chib):
-    """Config 3 at its full 256^3 size: three steps compared on every cell."""
+def test_config3_full_size_200_steps_fp64_and_fp32(chib):
+    """Config 3 at its full 256^3 size over 200 steps, on every cell: the FP64 path within the
+    project's 1e-9 of the oracle; the FP32 path reported (L-inf, L2) against the sanity gate
+    L-inf <= 1e-4 proposed for it before it was run."""
     case = W.config3(256)
-    _say("config3 256^3: oracle geometry")
-    st, orc, _ = _pair(chib, case)
-    _say("config3 256^3: steps")
-    st.step(3)
-    orc.step(3)
-    err = _linf(st.get(chib.FIELD_C), orc.C)
-    _say("config3 Linf", err)
-    assert err <= 1e-9
+    _say("config3 256^3: oracle tables")
+    T = build_tables(case.grid, case.shapes, case.params)
+    geo = _geom_from_oracle(chib, case, T)
+    C0, f0 = case.initial_fields()
+    out = {}
+    for prec in (64, 32):
+        _say("config3 256^3: GPU", prec, "bit, 200 steps")
+        st = chib.State(geo, case.params, prec)
+        st.set_initial(C0, f0)
+        st.step(200)
+        out[prec] = st.get(chib.FIELD_C)
+        del st
+        torch.cuda.empty_cache()
+    _say("config3 256^3: oracle, 200 steps")
+    orc = OracleState(case.grid, case.params, T, C0, f0)
+    orc.step(200)
+    err64 = _linf(out[64], orc.C)
+    d32 = np.asarray(out[32], dtype=np.float64) - orc.C
+    err32, l2_32 = float(np.max(np.abs(d32))), float(np.sqrt(np.mean(d32 * d32)))
+    _say("config3 200 steps: FP64 Linf", err64, "FP32 Linf", err32, "FP32 L2", l2_32)
+    assert err64 <= 1e-9
+    assert err32 <= 1e-4
 
 
 def test_fp32_path_tracks_fp64_oracle(chib):
@@ -370,25 +386,19 @@ def test_y_marching_rhs_2d(chib, maker, steps):
 
 @pytest.mark.parametrize("i", range(6))
 def test_config2_full_length_5000_steps(chib, i):
-    """Config 2 at its full length.  Over 5000 steps rounding differences are amplified while
-    contact lines jump between crests, so the bound is derived from the arithmetic: a second GPU
-    run that differs only in its FFT radices (another correct FP64 summation order) measures how
-    far two correct orderings drift apart; the oracle must stay within 1e-9 or within five times
-    that spread of the GPU result.  The factor is empirical: the two GPU orderings share their
-    transform and stencil structure while the oracle sums its FFTs in a different order, and the
-    measured oracle/spread ratios over the six cases are 1.0 to 3.7."""
+    """Config 2 at its full length: gated at 200 steps by the project's L-inf <= 1e-9 and held at
+    1000, 2000 and 5000 steps to a bound fixed before these runs: rounding differences of a step
+    map that does not expand them accumulate at most linearly, 1e-9 per 200 steps.  The values are
+    printed at each checkpoint."""
     case = W.config2(i)
     st, orc, T = _pair(chib, case)
-    st2, _, _ = _pair(chib, case)
-    st.set_shapes([[4, 8, 1], [3, 8, 1], [3, 8, 1], [3, 8, 1]])
-    st2.set_shapes([[4, 16, 1], [3, 16, 1], [3, 16, 1], [3, 16, 1]])
-    _say("config2 full length", case.name)
-    st.step(5000)
-    st2.step(5000)
-    orc.step(5000)
-    C1 = st.get(chib.FIELD_C)
-    err = _linf(C1, orc.C)
-    spread = _linf(C1, st2.get(chib.FIELD_C))
-    _say("config2", case.name, "Linf vs oracle", err, "radix-8 vs radix-16 spread", spread)
-    assert np.all(np.isfinite(C1))
-    assert err <= max(1e-9, 5.0 * spread)
+    done = 0
+    for n in (200, 1000, 2000, 5000):
+        st.step(n - done)
+        orc.step(n - done)
+        done = n
+        C1 = st.get(chib.FIELD_C)
+        err = _linf(C1, orc.C)
+        _say("config2", case.name, "step", n, "Linf vs oracle", err)
+        assert np.all(np.isfinite(C1))
+        assert err <= 1e-9 * n / 200, (n, err)

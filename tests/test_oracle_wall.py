@@ -11,6 +11,8 @@
 - The dynamic fill's wall-advection term u_I . grad_t C_I and the capillary bracket Kc of
   Eq. UpdateVtan, on linear fields where both are known in closed form.
 - The central difference at the box walls reflects the field as the Laplacian does.
+- Young's relation: a flat-wall droplet with the momentum step on relaxes to the cap of theta
+  (2 degrees at Cn/h = 1.28, fixed before the runs); 90 degrees misses it on this grid (see there).
 """
 import dataclasses
 import math
@@ -220,3 +222,33 @@ def test_gradient_reflects_at_the_box_walls():
     assert gr[1][1] == (f[5, 2] - f[4, 2]) / (2 * h)
     assert gr[1][2] == (f[3, 7] - f[1, 7]) / (2 * h)
     assert gr[0][2] == (f[2, 0] - f[2, 6]) / (2 * h)              # periodic wrap along x
+
+
+def _relaxed_cap(theta, steps=3000, yw=0.1):
+    """Flat-wall droplet with the momentum step on (128 x 64, Cn/h = 1.28, matched fluids), released
+    as a half disc (apparent angle 90 degrees) and relaxed; returns the cap-fit angle."""
+    from oracle.geometry import face_fractions
+    from paper_2104_00350_amd import angle
+    grid = W.Grid((128, 64), (0.0, 0.0), (2.0, 1.0))
+    prm = W.Params(Cn=0.02, Pe=100.0, Re=10.0, Ca=0.05, theta_deg=theta, slip_length=0.05, dt=2e-4,
+                   navier_stokes=True)
+    shapes = [W.Shape(W.HALFPLANE, (0.0, yw, 0.0, 0.0, 1.0, 0.0))]
+    T = build_tables(grid, shapes, prm)
+    C0, faces = W.droplet_field(grid, (1.0, yw), 0.3, prm.Cn, 0.0, None)
+    o = OracleState(grid, prm, T, C0, faces, face_alpha=face_fractions(grid, shapes, prm))
+    o.step(steps)
+    m = angle.measure_cap(o.C, grid.lo, grid.hi, W.HALFPLANE, shapes[0].p, prm.Cn)
+    return m["mean"]
+
+
+@pytest.mark.parametrize("theta", [
+    60.0,
+    pytest.param(90.0, marks=pytest.mark.xfail(strict=True, reason=(
+        "measured 87.1 degrees: at h = 1/64 the relaxed angle depends on where the wall cuts the "
+        "cells (88.9, 87.1, 90.0, 92.4 degrees for the wall at 6.0, 6.4, 6.5, 6.75 cells; 88.6 and 91.6 "
+        "with the fluid at rest at Pe = 2), and the error shrinks with h (91.0 degrees at h = 1/128)"))),
+    120.0])
+def test_flat_wall_droplet_relaxes_to_the_cap_of_theta(theta):
+    """Young's relation (section 2) makes a droplet on a flat wall relax to a circular cap that meets
+    the wall at the prescribed angle.  Tolerance fixed before the runs: 2 degrees at Cn/h = 1.28."""
+    assert abs(_relaxed_cap(theta) - theta) <= 2.0
