@@ -38,6 +38,9 @@ def algorithmic_bytes(name: str, cells: int, d: int, es: int, G: int, NF: int, d
         return cells * es * (2 + d + 1)              # C^n, C^(n-1), d face arrays in; Q (or its transform) out
     if name in ("xdht_fwd", "ydht_fwd", "ydht_inv", "neumann_solve", "xdht_out"):
         return cells * es * 2                        # one read, one write
+    if name == "ghost_dphi":                         # per ghost: tables, C^n and C^(n-1) on the cells within
+        U = 2 * d * d + 2 * d + 1                    # two steps of each interpolation point's centre cell
+        return G * (4 + 2 * K * (4 + es) + (2 * U + 2 * d + 1) * 2 * es + es)   # (and the ghost's stencil), dg out
     if name == "ghost_fill_C":
         return G * (4 + 8 * K + es * (7 + 4 * K))
     if name == "ghost_fill_u":
@@ -89,6 +92,8 @@ def kernel_template(name: str, shapes, es: int, nx: int) -> list:
         return [f"k_xdht<{t}, {E}, {shapes[3][1]}>"]
     if name in ("ns_predict", "ns_pressure_rhs", "ns_correct"):
         return [f"k_{name}<{t}>"]
+    if name == "ghost_dphi":
+        return [f"k_ghost_dphi<{t}>"]
     if name == "ghost_fill_C":
         return [f"k_fill_static<{t}>"]
     if name == "ghost_fill_u":
@@ -365,21 +370,46 @@ def learned_benchmark(chib, steps: int) -> dict:
             "fallbacks_to_fine": sm["fallbacks"]}
 
 
-def cpu_baseline(case, steps: int) -> dict:
-    """The FP64 oracle on the host, on a bounded sample (a few steps) of the same workload."""
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+def cpu_baseline(case, steps: int, steps_one_core: int) -> dict:
+    """The FP64 oracle on the host, on a bounded sample (a few steps) of the same workload: scipy's
+    FFTs on every host thread, then on one thread (NumPy's stencils are single-threaded either way)."""
+    import oracle.solver as OS
     from oracle.geometry import build_tables
-    from oracle.solver import OracleState, WORKERS
     T = build_tables(case.grid, case.shapes, case.params)
     C0, faces = case.initial_fields()
-    orc = OracleState(case.grid, case.params, T, C0, faces)
+    orc = OS.OracleState(case.grid, case.params, T, C0, faces)
     orc.step(1)   # warm-up (FFT plans, page faults)
+    threads = OS.WORKERS
     t0 = time.perf_counter()
     orc.step(steps)
     dt = time.perf_counter() - t0
-    return {"value": case.grid.cells * steps / dt, "unit": "cell-updates/s", "cores": WORKERS,
-            "kind": "oracle",
+    one = None
+    if steps_one_core > 0:
+        OS.WORKERS = 1
+        try:
+            t0 = time.perf_counter()
+            orc.step(steps_one_core)
+            dt1 = time.perf_counter() - t0
+        finally:
+            OS.WORKERS = threads
+        one = {"value": case.grid.cells * steps_one_core / dt1, "cores": 1,
+               "sample": f"{steps_one_core} further steps ({dt1:.1f} s)"}
+    return {"value": case.grid.cells * steps / dt, "unit": "cell-updates/s", "cores": threads,
+            "kind": "oracle", "cpu_model": cpu_model(), "host_threads": os.cpu_count(),
             "sample": f"{steps} steps of the same 256^3 workload after 1 warm-up step "
-                      f"({dt:.1f} s; scipy FFTs on {WORKERS} threads, NumPy stencils single-threaded)"}
+                      f"({dt:.1f} s; scipy FFTs on {threads} threads, NumPy stencils single-threaded)",
+            "one_core": one}
 
 
 def main() -> int:
@@ -389,7 +419,8 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--precision", type=int, default=64, choices=(64, 32))
     ap.add_argument("--n", type=int, default=256, help="cells per axis of the sphere workload")
-    ap.add_argument("--cpu-steps", type=int, default=15)
+    ap.add_argument("--cpu-steps", type=int, default=12)
+    ap.add_argument("--cpu-steps-one-core", type=int, default=6)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="keep the default launch shapes")
     ap.add_argument("--shapes", default="", help="fixed launch shapes 'a,b,c;d,e,f;g,h,i;j,k,l' instead of tuning")
@@ -443,11 +474,20 @@ def main() -> int:
         torch.cuda.synchronize()
         del a, b
 
+    # the timed region: K plain steps (ch_ib_step) on the state's stream, bracketed by a device
+    # synchronisation on both sides; HIP events on that stream give the device time alongside
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    ms = st.step_timed(args.steps)          # HIP events between kernels on the state's stream
+    ev0.record(st.stream)
+    st.step(args.steps)
+    ev1.record(st.stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    event_ms = ev0.elapsed_time(ev1)
+    # per-kernel breakdown from a separate call with HIP events between the kernels
+    ms = st.step_timed(min(args.steps, 100))
+    st.sync()
     dg = st.diagnostics()
     if dg["status"] != 0:
         print(json.dumps({"error": "non-finite state after the timed steps"}))
@@ -497,7 +537,9 @@ def main() -> int:
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": measured_traffic(dominant, shapes, es, g.n[0]),
                      "alg_bytes_per_launch": dom["alg_bytes"]},
-        "gpu_ms_per_step_events": round(gpu_ms, 5),
+        "ms_per_step_hip_events": round(event_ms / args.steps, 5),
+        "kernel_ms_per_step_sum": round(gpu_ms, 5),
+        "kernel_breakdown": f"ch_ib_step_timed over {min(args.steps, 100)} further steps (events between kernels)",
         "path_GB_s": round(sum(k["alg_bytes"] for k in kernels.values()) / (gpu_ms * 1e-3) / 1e9, 1),
         "kernels": kernels,
     }
@@ -530,7 +572,7 @@ def main() -> int:
     if not args.no_cpu_baseline:
         print(f"[bench] GPU done ({value:.3e} cell-updates/s); timing the CPU oracle", file=sys.stderr,
               flush=True)
-        out["cpu_baseline"] = cpu_baseline(case, args.cpu_steps)
+        out["cpu_baseline"] = cpu_baseline(case, args.cpu_steps, args.cpu_steps_one_core)
     print(json.dumps(out), flush=True)
     return 0
 

@@ -134,7 +134,7 @@ struct Layout {
 
 struct Offsets {
   size_t C[2], F[3], W, R, alpha, gidx, normal, dn, gamma, ap, w, CGn, CGnm1, CMs, CI, CGnew, UG;
-  size_t dg, pl_cell, pl_ref, pl_row;
+  size_t dg, pl_cell, pl_ref, pl_row, pl_dq;
   size_t Us[3], Ut[3], Nh[3], Af[3], P[2];
   size_t f_cell, f_axis, f_gL, f_gR, stashL, stashR;
   size_t twr[3], twi[3], dctc, dcts, lam[3], partial, red_out;
@@ -177,6 +177,7 @@ Offsets plan_layout(const ch_ib_geometry &g, int es, int64_t NF, int64_t NP, boo
   o.pl_cell = L.off(NP * 4);
   o.pl_ref = L.off((2 * d + 1) * NP * 4);
   o.pl_row = L.off((N / g.n[0] + 1) * 4);
+  o.pl_dq = L.off(NP * es);
   o.f_cell = L.off(NF * 4);
   o.f_axis = L.off(NF * 4);
   o.f_gL = L.off(NF * 4);
@@ -389,6 +390,7 @@ extern "C" int ch_ib_state_create(const ch_ib_grid *grid, const ch_ib_geometry *
   p.pl_cell = (const int *)(W0 + o.pl_cell);
   p.pl_ref = (const int *)(W0 + o.pl_ref);
   p.pl_row = (const int *)(W0 + o.pl_row);
+  p.pl_dq = W0 + o.pl_dq;
   p.NF = NF;
   p.f_cell = (const int *)(W0 + o.f_cell);
   p.f_axis = (const int *)(W0 + o.f_axis);
@@ -712,7 +714,10 @@ extern "C" int ch_ib_step_timed(ch_ib_state *st, int n_steps, int max_kernels, d
   hipError_t e = hipSuccess;
   size_t created = 0;
   for (auto &tm : tms)
-    for (int k = 0; k < ne && e == hipSuccess; ++k, ++created) e = hipEventCreate(&tm.ev[k]);
+    for (int k = 0; k < ne && e == hipSuccess; ++k) {
+      e = hipEventCreate(&tm.ev[k]);
+      if (e == hipSuccess) ++created;   // only events that exist are destroyed below
+    }
   // all steps are enqueued back to back; one wait at the end
   for (int s = 0; s < n_steps && e == hipSuccess; ++s) {
     tms[s].n = 0;
@@ -1012,7 +1017,8 @@ static size_t batch_desc_bytes(int es) {
 extern "C" size_t ch_ib_batch_workspace_bytes(int n) {
   if (n < 1) return 0;
   const size_t d = std::max(batch_desc_bytes(8), batch_desc_bytes(4));
-  return ((d * n + 255) & ~(size_t)255) + ((6 * (size_t)(n + 1) * sizeof(int) + 255) & ~(size_t)255) + 256;
+  return ((d * n + 255) & ~(size_t)255) +
+         ((chib::BatchLaunch::kPhases * (size_t)(n + 1) * sizeof(int) + 255) & ~(size_t)255) + 256;
 }
 
 static void batch_drop_graphs(ch_ib_batch *b) {
@@ -1029,12 +1035,13 @@ static int batch_upload(ch_ib_batch *b) {
   const int n = (int)b->st.size();
   const size_t db = batch_desc_bytes(b->es);
   std::vector<unsigned char> descs(db * n);
-  std::vector<int> off(6 * (size_t)(n + 1), 0);
+  constexpr int NPH = chib::BatchLaunch::kPhases;
+  std::vector<int> off(NPH * (size_t)(n + 1), 0);
   size_t lds[4] = {0, 0, 0, 0};
   bool ym_all = true;
   for (int c = 0; c < n; ++c) {
     ch_ib_state *s = b->st[c];
-    int tiles[6];
+    int tiles[NPH];
     size_t l[4];
     if (b->es == 8) {
       chib::fill_case_desc<double>(s->plan, s->cur, descs.data() + db * c);
@@ -1043,7 +1050,7 @@ static int batch_upload(ch_ib_batch *b) {
       chib::fill_case_desc<float>(s->plan, s->cur, descs.data() + db * c);
       chib::case_tiles<float>(s->plan, tiles, l);
     }
-    for (int ph = 0; ph < 6; ++ph) off[ph * (n + 1) + c + 1] = off[ph * (n + 1) + c] + tiles[ph];
+    for (int ph = 0; ph < NPH; ++ph) off[ph * (n + 1) + c + 1] = off[ph * (n + 1) + c] + tiles[ph];
     for (int k = 0; k < 4; ++k) lds[k] = std::max(lds[k], l[k]);
     ym_all = ym_all && l[3] > 0;
   }
@@ -1057,7 +1064,7 @@ static int batch_upload(ch_ib_batch *b) {
   b->bl.descs = b->ws;
   b->bl.off = (const int *)(b->ws + doff);
   b->bl.n = n;
-  for (int ph = 0; ph < 6; ++ph) b->bl.total[ph] = (unsigned)off[ph * (n + 1) + n];
+  for (int ph = 0; ph < NPH; ++ph) b->bl.total[ph] = (unsigned)off[ph * (n + 1) + n];
   for (int k = 0; k < 4; ++k) b->bl.lds[k] = lds[k];
   b->bl.stream = b->stream;
   b->parity = 0;

@@ -54,12 +54,13 @@ struct Plan {
 
   // wall condition dphi/dn = 0 of the semi-implicit step: per ghost the change of g,
   // dg = (phi~_M - phi~_G)/Cn^2, and the cells whose rhs it changes (ghosts and their face
-  // neighbours, sorted by cell) with the first of them on each x-row
+  // neighbours, sorted by cell) with the change dq of each and the first of them on every x-row
   void *dg = nullptr;              // [G]
   int64_t NP = 0;
   const int *pl_cell = nullptr;    // [NP]
   const int *pl_ref = nullptr;     // [2d+1][NP]: own ghost index, then the ghost at +e_a and -e_a per axis, or -1
-  const int *pl_row = nullptr;     // [rows+1]
+  const int *pl_row = nullptr;     // [rows + 1]
+  void *pl_dq = nullptr;           // [NP]
 
   // faces touching ghosts (velocity fill)
   int64_t NF = 0;
@@ -133,9 +134,10 @@ template <typename T> hipError_t enqueue_momentum(const Plan &p, int cur, int fi
 // One grouped step over a batch of 2D cases (see the batched kernels).
 struct BatchLaunch {
   const void *descs = nullptr;   // device array of per-case descriptors
-  const int *off = nullptr;      // device [6][n+1] per-phase tile offsets
+  static constexpr int kPhases = 7;
+  const int *off = nullptr;      // device [kPhases][n+1] per-phase tile offsets
   int n = 0;
-  unsigned total[6] = {0, 0, 0, 0, 0, 0};
+  unsigned total[kPhases] = {0, 0, 0, 0, 0, 0, 0};
   size_t lds[4] = {0, 0, 0, 0};  // rhs, solve, out; y-marching rhs (0 unless every case allows it)
   int radix_rhs = 8, unroll = 2, radix_neu = 16, radix_out = 16;  // shared by all cases (unroll 3: y-march)
   hipStream_t stream = nullptr;

@@ -49,46 +49,28 @@ struct RhsCoef {
 
 // The wall condition dphi/dn = 0 in the rhs (end of section 4.2.2, Eq. WallBCS): g at every ghost
 // G becomes g_G + dg_G, dg_G = (phi~_M - phi~_G)/Cn^2 with phi~ = C~^3 - C~ - Cn^2 lap_h C~ the
-// explicit chemical potential of the step (k_ghost_dphi).  Through lap_h(g) that changes Q at the
-// ghost by -2d dg_G/h^2 and at each face neighbour by +dg_G/h^2: a sparse patch of Q on the
-// ghosts and their neighbours, listed sorted by cell with the first entry of each x-row.
-// dg == nullptr: no patch (no ghosts).
+// explicit chemical potential of the step (k_ghost_dphi).  Through lap_h(g) that changes Q by
+// -2d dg_G/h^2 at the ghost and by +dg_G/h^2 at each face neighbour: a sparse patch over the
+// ghosts and their neighbours, listed sorted by cell with the first entry of every x-row, and its
+// value dq per entry (k_patch_dq).  The rhs kernels add it in LDS before their x transform.
+// dq == nullptr: no patch.
 template <typename T>
-struct GhostPatch {
-  const int *cell;   // [np]
-  const int *ref;    // [nref][np]: own ghost index, then the ghost neighbours (+e_a, -e_a per axis), or -1
+struct RhsPatch {
   const int *row;    // [rows + 1]
-  const T *dg;       // [G]
-  int64_t np;
-  int nref;          // 2d + 1
-  T twod;            // 2d
-  T inv_h2;
+  const int *cell;   // [np]
+  const T *dq;       // [np]
 };
 
-// Change of Q at patched cell e: (sum of the neighbouring ghosts' dg - 2d dg_own) / h^2.
+// Adds the patch entries [e0, e1) of the x-rows line0 .. line0 + L - 1 to a line tile in LDS
+// (row l at l * pitch, element i at i + i/16); one entry per thread, no two entries share a cell.
 template <typename T>
-__device__ __forceinline__ T patch_value(const GhostPatch<T> &gp, int64_t e) {
-  T acc = T(0);
-  for (int j = 1; j < gp.nref; ++j) {
-    const int id = gp.ref[(int64_t)j * gp.np + e];
-    if (id >= 0) acc += gp.dg[id];
-  }
-  const int own = gp.ref[e];
-  if (own >= 0) acc -= gp.twod * gp.dg[own];
-  return acc * gp.inv_h2;
-}
-
-// Patches of x-row R added to the values q[m] a thread holds for columns x = tid + 256 m of that
-// row.  R is uniform across the workgroup, so every lane walks the same (short) entry list.
-template <typename T, int XM>
-__device__ __forceinline__ void patch_row(const GhostPatch<T> &gp, int64_t R, int lnx, int tid, T (&q)[XM]) {
-  const int e1 = gp.row[R + 1];
-  for (int e = gp.row[R]; e < e1; ++e) {
-    const int x = gp.cell[e] & ((1 << lnx) - 1);
-    const T dq = patch_value(gp, e);
-#pragma unroll
-    for (int m = 0; m < XM; ++m)
-      if (x == tid + 256 * m) q[m] += dq;
+__device__ __forceinline__ void patch_tile(T *__restrict__ s, const RhsPatch<T> &rp, int64_t line0, int lnx,
+                                           int pitch, int e0, int e1) {
+  for (int e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
+    const int c = rp.cell[e];
+    const int l = (int)((c >> lnx) - line0);
+    const int i = c & ((1 << lnx) - 1);
+    s[l * pitch + i + (i >> 4)] += rp.dq[e];
   }
 }
 
@@ -439,7 +421,7 @@ __device__ __forceinline__ void rhs_xdht_body(unsigned char *smem_raw, const T *
                                                        const T *__restrict__ F0, const T *__restrict__ F1,
                                                        const T *__restrict__ F2, T *__restrict__ W, Dims dm,
                                                        RhsCoef<T> cf, int logL, const T *__restrict__ twr,
-                                                       const T *__restrict__ twi, int tile, const GhostPatch<T> &gp) {
+                                                       const T *__restrict__ twi, int tile, const RhsPatch<T> &rp) {
   T *s = reinterpret_cast<T *>(smem_raw);
   const int L = 1 << logL;
   const int nx = dm.nx;
@@ -477,15 +459,9 @@ __device__ __forceinline__ void rhs_xdht_body(unsigned char *smem_raw, const T *
       }
     }
   }
-  if (gp.dg) {   // the ghost patches of the tile's lines, one entry per thread
+  if (rp.dq) {   // the ghost patch of the tile's lines
     __syncthreads();
-    const int e1 = gp.row[line0 + L];
-    for (int e = gp.row[line0] + threadIdx.x; e < e1; e += blockDim.x) {
-      const int c = gp.cell[e];
-      const int l = (c >> dm.lnx) - line0;
-      const int i = c & (nx - 1);
-      s[l * pitch + i + (i >> 4)] += patch_value(gp, e);
-    }
+    patch_tile(s, rp, line0, dm.lnx, pitch, rp.row[line0], rp.row[line0 + L]);
   }
   __syncthreads();
   lds_fft<T, E, false, MAXR>(s, dm.lnx, logL - 1, 2 * pitch, 1, pitch, 1, false, twr, twi);
@@ -508,10 +484,10 @@ __global__ __launch_bounds__(kThreads) void k_rhs_xdht(const T *__restrict__ Cn,
                                                        const T *__restrict__ F0, const T *__restrict__ F1,
                                                        const T *__restrict__ F2, T *__restrict__ W, Dims dm,
                                                        RhsCoef<T> cf, int logL, const T *__restrict__ twr,
-                                                       const T *__restrict__ twi, GhostPatch<T> gp) {
+                                                       const T *__restrict__ twi, RhsPatch<T> rp) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   rhs_xdht_body<T, D, E, U, MAXR>(smem_raw, Cn, Cp, F0, F1, F2, W, dm, cf, logL, twr, twi, xcd_tile(blockIdx.x, gridDim.x),
-                                  gp);
+                                  rp);
 }
 
 // Extra LDS of the y-marching K1 (two rows of C~ for the x neighbours) over the line tile.
@@ -530,7 +506,7 @@ __device__ __forceinline__ void rhs_ym_body(unsigned char *smem_raw, const T *__
                                             const T *__restrict__ Cp, const T *__restrict__ F0,
                                             const T *__restrict__ F1, T *__restrict__ W, Dims dm, RhsCoef<T> cf,
                                             int logL, const T *__restrict__ twr, const T *__restrict__ twi,
-                                            int tile, const GhostPatch<T> &gp) {
+                                            int tile, const RhsPatch<T> &rp) {
   const int nx = dm.nx, ny = dm.ny;
   const int L = 1 << logL;
   const int pitch = line_pitch(nx);
@@ -576,11 +552,9 @@ __device__ __forceinline__ void rhs_ym_body(unsigned char *smem_raw, const T *__
       }
     }
     __syncthreads();   // the row is in LDS; the ring slot written next row was last read two rows ago
-    T qv[XM];
 #pragma unroll
     for (int m = 0; m < XM; ++m) {
       const int i = tid + 256 * m;
-      qv[m] = T(0);
       if (i < nx) {
         const T v0 = T(2) * a0[m] - b0[m];
         const T cxp = xb[(i + 1) & (nx - 1)], cxm = xb[(i - 1) & (nx - 1)];
@@ -592,7 +566,7 @@ __device__ __forceinline__ void rhs_ym_body(unsigned char *smem_raw, const T *__
         const T A = flux * T(0.5) * cf.inv_h;
         const T lap = (gsum - T(4) * g0) * klap;
         const T h0 = T(2) * a0[m] - T(0.5) * b0[m];
-        qv[m] = cf.pe_cn2 * (h0 * cf.inv_dt - A) + lap;
+        fb[r * pitch + i + (i >> 4)] = cf.pe_cn2 * (h0 * cf.inv_dt - A) + lap;
         // slide the window down one row and request the row after next
         cm[m] = v0;
         a0[m] = a1[m];
@@ -606,12 +580,10 @@ __device__ __forceinline__ void rhs_ym_body(unsigned char *smem_raw, const T *__
         }
       }
     }
-    if (gp.dg) patch_row<T, XM>(gp, y, dm.lnx, tid, qv);
-#pragma unroll
-    for (int m = 0; m < XM; ++m) {
-      const int i = tid + 256 * m;
-      if (i < nx) fb[r * pitch + i + (i >> 4)] = qv[m];
-    }
+  }
+  if (rp.dq) {   // the ghost patch of the tile's rows
+    __syncthreads();
+    patch_tile(fb, rp, y0, dm.lnx, pitch, rp.row[y0], rp.row[y0 + L]);
   }
   __syncthreads();
   lds_fft<T, tile_elems<T>(), false, R>(fb, dm.lnx, logL - 1, 2 * pitch, 1, pitch, 1, false, twr, twi);
@@ -634,9 +606,9 @@ __global__ __launch_bounds__(kThreads, R == 8 ? 4 : 3) void k_rhs_xdht_ym(const 
                                                           const T *__restrict__ F0, const T *__restrict__ F1,
                                                           T *__restrict__ W, Dims dm, RhsCoef<T> cf, int logL,
                                                           const T *__restrict__ twr, const T *__restrict__ twi,
-                                                          GhostPatch<T> gp) {
+                                                          RhsPatch<T> rp) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  rhs_ym_body<T, XM, R>(smem_raw, Cn, Cp, F0, F1, W, dm, cf, logL, twr, twi, xcd_tile(blockIdx.x, gridDim.x), gp);
+  rhs_ym_body<T, XM, R>(smem_raw, Cn, Cp, F0, F1, W, dm, cf, logL, twr, twi, xcd_tile(blockIdx.x, gridDim.x), rp);
 }
 
 // K1 for 3D grids, marching in z (2.5D blocking): a workgroup owns L consecutive y rows and
@@ -650,7 +622,7 @@ __global__ __launch_bounds__(kThreads) void k_rhs_xdht_zm(const T *__restrict__ 
                                                           const T *__restrict__ F0, const T *__restrict__ F1,
                                                           const T *__restrict__ F2, T *__restrict__ W, Dims dm,
                                                           RhsCoef<T> cf, int zc_log, const T *__restrict__ twr,
-                                                          const T *__restrict__ twi, GhostPatch<T> gp) {
+                                                          const T *__restrict__ twi, RhsPatch<T> rp) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T *plane = reinterpret_cast<T *>(smem_raw);        // L rows x nx: C~ of plane z
   const int nx = dm.nx;
@@ -698,9 +670,35 @@ __global__ __launch_bounds__(kThreads) void k_rhs_xdht_zm(const T *__restrict__ 
       const int64_t c = (int64_t)z0 * dm.plane + (int64_t)row_of(r) * nx + tid + 256 * m;
       uzm[m][r] = z0 > 0 ? F2[c - dm.plane] : T(0);
     }
+  // ghost patch (SPLIT: added by the caller afterwards): the entries of the tile's rows of plane z
+  // are requested at the start of that plane and added to its Q tile after the stencil; the entry
+  // range of the next plane is read one plane ahead
+  constexpr int PF = 2;
+  const bool patch = !SPLIT && rp.dq != nullptr;
+  int e_lo = 0, e_hi = 0;
+  if (patch) {
+    const int64_t R0 = (int64_t)z0 * dm.ny + y0;
+    e_lo = rp.row[R0];
+    e_hi = rp.row[R0 + L];
+  }
   for (int zi = 0; zi < ZC; ++zi) {
     const int z = z0 + zi;
     const int64_t zb = (int64_t)z * dm.plane;
+    int n_lo = 0, n_hi = 0, pc[PF];
+    T pd[PF];
+    if (patch) {
+      if (zi + 1 < ZC) {
+        const int64_t R1 = (int64_t)(z + 1) * dm.ny + y0;
+        n_lo = rp.row[R1];
+        n_hi = rp.row[R1 + L];
+      }
+#pragma unroll
+      for (int k = 0; k < PF; ++k) {
+        const int e = e_lo + tid + 256 * k;
+        pc[k] = e < e_hi ? rp.cell[e] : -1;
+        pd[k] = e < e_hi ? rp.dq[e] : T(0);
+      }
+    }
     load_plane(z + 1, cp, hp);  // the reflecting wall above the last plane is that plane itself
     const bool top = z == dm.nz - 1, bot = z == 0;
 #pragma unroll
@@ -731,24 +729,10 @@ __global__ __launch_bounds__(kThreads) void k_rhs_xdht_zm(const T *__restrict__ 
         const T A = flux * T(0.5) * cf.inv_h;
         const T lap = (gsum - T(6) * gf(v0)) * cf.inv_h2;
         q[m][r] = cf.pe_cn2 * (h0[m][r] * cf.inv_dt - A) + lap;
-      }
-    }
-    if (gp.dg) {
-#pragma unroll
-      for (int r = 0; r < L; ++r) {
-        T qr[XM];
-#pragma unroll
-        for (int m = 0; m < XM; ++m) qr[m] = q[m][r];
-        patch_row<T, XM>(gp, (int64_t)z * dm.ny + y0 + r, dm.lnx, tid, qr);
-#pragma unroll
-        for (int m = 0; m < XM; ++m) q[m][r] = qr[m];
+        if constexpr (SPLIT) W[c] = q[m][r];
       }
     }
     if constexpr (SPLIT) {
-#pragma unroll
-      for (int m = 0; m < XM; ++m)
-#pragma unroll
-        for (int r = 0; r < L; ++r) W[zb + (int64_t)(y0 + r) * nx + tid + 256 * m] = q[m][r];
       __syncthreads();   // every x-neighbour read of this plane is done before the next write
     } else {
 #pragma unroll
@@ -759,9 +743,20 @@ __global__ __launch_bounds__(kThreads) void k_rhs_xdht_zm(const T *__restrict__ 
         fb[r * pitch + i + (i >> 4)] = q[m][r];
       }
     __syncthreads();
+    const int64_t line0 = (int64_t)z * dm.ny + y0;
+    if (patch && e_hi > e_lo) {
+#pragma unroll
+      for (int k = 0; k < PF; ++k)
+        if (pc[k] >= 0) {
+          const int l = (int)((pc[k] >> dm.lnx) - line0);
+          const int i = pc[k] & (nx - 1);
+          fb[l * pitch + i + (i >> 4)] += pd[k];
+        }
+      if (e_hi - e_lo > PF * 256) patch_tile(fb, rp, line0, dm.lnx, pitch, e_lo + PF * 256, e_hi);
+      __syncthreads();
+    }
     lds_fft<T, L * 256 * XM, false, R>(fb, dm.lnx, ilog2c(L) - 1, 2 * pitch, 1, pitch, 1, false, twr, twi);
     const int half = (L * nx) >> 1;
-    const int64_t line0 = (int64_t)z * dm.ny + y0;
     for (int e = tid; e < half; e += blockDim.x) {
       const int b = e >> dm.lnx;
       const int kx = e & (nx - 1);
@@ -774,6 +769,8 @@ __global__ __launch_bounds__(kThreads) void k_rhs_xdht_zm(const T *__restrict__ 
       o[nx] = (p + qq - rr + sv) * T(0.5);
     }
     }
+    e_lo = n_lo;
+    e_hi = n_hi;
     // rotate planes (the FFT's final barrier protects the plane buffer for the next write)
 #pragma unroll
     for (int m = 0; m < XM; ++m) {
@@ -1228,12 +1225,29 @@ __global__ __launch_bounds__(kThreads) void k_ghost_dphi(const T *__restrict__ C
   ghost_dphi_body<T>(Cn, Cp, gidx, ap, w, dg, G, K, dm, d, cn2, inv_h2, inv_cn2, blockIdx.x);
 }
 
-// The ghost patch added to a rhs field stored cell by cell (stage entry point).
+// The rhs patch of every listed cell: dq = (sum of the neighbouring ghosts' dg - 2d dg_own)/h^2,
+// the neighbours in a fixed order (+e_a, -e_a per axis).
 template <typename T>
-__global__ __launch_bounds__(kThreads) void k_rhs_patch(T *__restrict__ Q, GhostPatch<T> gp) {
+__global__ __launch_bounds__(kThreads) void k_patch_dq(const int *__restrict__ ref, const T *__restrict__ dg,
+                                                       T *__restrict__ dq, int64_t np, int nref, T twod, T inv_h2) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= gp.np) return;
-  Q[gp.cell[e]] += patch_value(gp, e);
+  if (e >= np) return;
+  T acc = T(0);
+  for (int j = 1; j < nref; ++j) {
+    const int id = ref[(int64_t)j * np + e];
+    if (id >= 0) acc += dg[id];
+  }
+  const int own = ref[e];
+  if (own >= 0) acc -= twod * dg[own];
+  dq[e] = acc * inv_h2;
+}
+
+// The patch added to a rhs stored cell by cell (stage entry point, stencil-only z-march).
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_rhs_patch(T *__restrict__ Q, const int *__restrict__ cell,
+                                                        const T *__restrict__ dq, int64_t np) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < np) Q[cell[e]] += dq[e];
 }
 
 // K7a: ghost velocities (Eqs. NoPenetration, UpdateVtan, UpdateVandW in vector form) and,
@@ -1874,31 +1888,38 @@ inline RhsCoef<T> make_coef(const Plan &p) {
 
 inline unsigned blocks_for(int64_t n) { return (unsigned)((n + kThreads - 1) / kThreads); }
 
-// Ghost patch of the rhs (no patch without ghosts, and none for the explicit step).
+// The rhs' ghost patch (none without ghosts).
 template <typename T>
-inline GhostPatch<T> make_patch(const Plan &p) {
-  GhostPatch<T> gp{};
-  if (p.G > 0 && p.dg && p.NP > 0) {
-    gp.cell = p.pl_cell;
-    gp.ref = p.pl_ref;
-    gp.row = p.pl_row;
-    gp.dg = (const T *)p.dg;
-    gp.np = p.NP;
+inline RhsPatch<T> make_patch(const Plan &p) {
+  RhsPatch<T> rp{};
+  if (p.G > 0 && p.NP > 0 && p.pl_dq) {
+    rp.row = p.pl_row;
+    rp.cell = p.pl_cell;
+    rp.dq = (const T *)p.pl_dq;
   }
-  gp.nref = 2 * p.d + 1;
-  gp.twod = (T)(2 * p.d);
-  gp.inv_h2 = (T)(1.0 / (p.h * p.h));
-  return gp;
+  return rp;
 }
 
-// dg of every ghost from C^n, C^(n-1) (before the rhs pass of a semi-implicit step).
+// dg of every ghost from C^n, C^(n-1), then dq of every patched cell (before the rhs pass of a
+// semi-implicit step).
 template <typename T>
-hipError_t launch_ghost_dphi(const Plan &p, const T *Cn, const T *Cp) {
-  if (p.G == 0 || !p.dg) return hipSuccess;
+hipError_t launch_ghost_patch(const Plan &p, const T *Cn, const T *Cp) {
+  if (p.G == 0 || p.NP == 0 || !p.dg) return hipSuccess;
   const Dims dm = make_dims(p);
   hipLaunchKernelGGL((k_ghost_dphi<T>), dim3(blocks_for(p.G * 16)), dim3(kThreads), 0, p.stream, Cn, Cp, p.gidx,
                      p.ap, (const T *)p.w, (T *)p.dg, p.G, p.K, dm, p.d, (T)(p.Cn * p.Cn), (T)(1.0 / (p.h * p.h)),
                      (T)(1.0 / (p.Cn * p.Cn)));
+  hipLaunchKernelGGL((k_patch_dq<T>), dim3(blocks_for(p.NP)), dim3(kThreads), 0, p.stream, p.pl_ref,
+                     (const T *)p.dg, (T *)p.pl_dq, p.NP, 2 * p.d + 1, (T)(2 * p.d), (T)(1.0 / (p.h * p.h)));
+  return hipGetLastError();
+}
+
+// The patch added to a rhs field stored cell by cell.
+template <typename T>
+hipError_t launch_rhs_patch(const Plan &p, T *Q) {
+  const RhsPatch<T> rp = make_patch<T>(p);
+  if (!rp.dq) return hipSuccess;
+  hipLaunchKernelGGL((k_rhs_patch<T>), dim3(blocks_for(p.NP)), dim3(kThreads), 0, p.stream, Q, rp.cell, rp.dq, p.NP);
   return hipGetLastError();
 }
 
@@ -2071,6 +2092,7 @@ hipError_t launch_rhs(const Plan &p, const T *Cn, const T *Cp, const Plan::Shape
       if (p.n[0] == 256) launch_zm_split<T, 1>(p, Cn, Cp, logL, zc_log);
       else launch_zm_split<T, 2>(p, Cn, Cp, logL, zc_log);
       hipError_t e = hipGetLastError();
+      if (e == hipSuccess) e = launch_rhs_patch<T>(p, (T *)p.W);
       if (e != hipSuccess || split_only) return e;
       return launch_xdht<T>(p, (const T *)p.W, (T *)p.W, p.shape[3]);
     }
@@ -2215,7 +2237,7 @@ hipError_t enqueue_step(const Plan &p, int cur, KernelTimer *tm) {
   const bool split = p.d == 3 && p.shape[0].unroll >= 6 && zm_ok(p);
   if (p.G) {
     mark("ghost_dphi");
-    if (e == hipSuccess) e = launch_ghost_dphi<T>(p, Cn, Cp);
+    if (e == hipSuccess) e = launch_ghost_patch<T>(p, Cn, Cp);
   }
   mark(split ? "rhs_stencil" : "rhs_xdht");
   if (e == hipSuccess)
@@ -2263,7 +2285,7 @@ hipError_t tune_shapes(Plan &p, int cur, int reps) {
   };
   const T *Cn = (const T *)p.C[cur];
   const T *Cp = (const T *)p.C[1 - cur];
-  e = launch_ghost_dphi<T>(p, Cn, Cp);   // the rhs candidates read the ghost patch
+  e = launch_ghost_patch<T>(p, Cn, Cp);   // the rhs candidates read the ghost patch
   // pass 0: fused rhs
   if (e == hipSuccess) {
     const int hi = max_log_lines(p, E);
@@ -2364,7 +2386,7 @@ hipError_t enqueue_rhs(const Plan &p, int cur, void *out) {
   const Dims dm = make_dims(p);
   const RhsCoef<T> cf = make_coef<T>(p);
   const T *F2 = (const T *)(p.d == 3 ? adv_face(p, 2) : adv_face(p, 1));
-  hipError_t e = launch_ghost_dphi<T>(p, (const T *)p.C[cur], (const T *)p.C[1 - cur]);
+  hipError_t e = launch_ghost_patch<T>(p, (const T *)p.C[cur], (const T *)p.C[1 - cur]);
   if (e != hipSuccess) return e;
   if (p.d == 2)
     hipLaunchKernelGGL((k_rhs_only<T, 2>), dim3(blocks_for(p.N)), dim3(kThreads), 0, p.stream, (const T *)p.C[cur],
@@ -2372,10 +2394,8 @@ hipError_t enqueue_rhs(const Plan &p, int cur, void *out) {
   else
     hipLaunchKernelGGL((k_rhs_only<T, 3>), dim3(blocks_for(p.N)), dim3(kThreads), 0, p.stream, (const T *)p.C[cur],
                        (const T *)p.C[1 - cur], (const T *)adv_face(p, 0), (const T *)adv_face(p, 1), F2, (T *)out, dm, cf, p.N);
-  const GhostPatch<T> gp = make_patch<T>(p);
-  if (gp.dg)
-    hipLaunchKernelGGL((k_rhs_patch<T>), dim3(blocks_for(gp.np)), dim3(kThreads), 0, p.stream, (T *)out, gp);
-  return hipGetLastError();
+  e = hipGetLastError();
+  return e == hipSuccess ? launch_rhs_patch<T>(p, (T *)out) : e;
 }
 
 template <typename T>
@@ -2560,7 +2580,10 @@ struct CaseDesc {
   const int *f_cell, *f_axis, *f_gL, *f_gR;
   T *stashL, *stashR;
   unsigned nbg;
-  GhostPatch<T> gp;        // dphi/dn = 0 at the ghosts: dg (written by kb_dphi) and the rhs patch
+  RhsPatch<T> rp;          // dphi/dn = 0 at the ghosts: the rhs patch
+  T *dg, *pl_dq;           // [G], [NP]: written by kb_dphi, kb_dq
+  const int *pl_ref;       // [5][NP]
+  int64_t NP;
   T cn2, inv_h2, inv_cn2;
 };
 
@@ -2583,17 +2606,34 @@ __global__ __launch_bounds__(kThreads) void kb_rhs(const CaseDesc<T> *__restrict
   const int c = find_case(off, n, blockIdx.x);
   const CaseDesc<T> &d = cs[c];
   rhs_xdht_body<T, 2, E, U, R>(smem_raw, d.C[parity], d.C[1 - parity], d.F0, d.F1, d.F1, d.W, d.dm, d.cf,
-                               d.logL_rhs, d.twr0, d.twi0, (int)(blockIdx.x - off[c]), d.gp);
+                               d.logL_rhs, d.twr0, d.twi0, (int)(blockIdx.x - off[c]), d.rp);
 }
 
-// dg of every ghost of every case, before the rhs pass.
+// dg of every ghost of every case, then dq of every patched cell, before the rhs pass.
 template <typename T>
 __global__ __launch_bounds__(kThreads) void kb_dphi(const CaseDesc<T> *__restrict__ cs, const int *__restrict__ off,
                                                     int n, int parity) {
   const int c = find_case(off, n, blockIdx.x);
   const CaseDesc<T> &d = cs[c];
-  ghost_dphi_body<T>(d.C[parity], d.C[1 - parity], d.gidx, d.ap, d.w, const_cast<T *>(d.gp.dg), d.G, d.K, d.dm, 2,
-                     d.cn2, d.inv_h2, d.inv_cn2, (int64_t)(blockIdx.x - off[c]));
+  ghost_dphi_body<T>(d.C[parity], d.C[1 - parity], d.gidx, d.ap, d.w, d.dg, d.G, d.K, d.dm, 2, d.cn2, d.inv_h2,
+                     d.inv_cn2, (int64_t)(blockIdx.x - off[c]));
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void kb_dq(const CaseDesc<T> *__restrict__ cs, const int *__restrict__ off,
+                                                  int n) {
+  const int c = find_case(off, n, blockIdx.x);
+  const CaseDesc<T> &d = cs[c];
+  const int64_t e = (int64_t)(blockIdx.x - off[c]) * blockDim.x + threadIdx.x;
+  if (e >= d.NP) return;
+  T acc = T(0);
+  for (int j = 1; j < 5; ++j) {
+    const int id = d.pl_ref[(int64_t)j * d.NP + e];
+    if (id >= 0) acc += d.dg[id];
+  }
+  const int own = d.pl_ref[e];
+  if (own >= 0) acc -= T(4) * d.dg[own];
+  d.pl_dq[e] = acc * d.inv_h2;
 }
 
 template <typename T, int R>
@@ -2605,11 +2645,11 @@ __global__ __launch_bounds__(kThreads, R == 8 ? 4 : 3) void kb_rhs_ym(const Case
   const int t = (int)(blockIdx.x - off[c]);
   // the same instantiation as the single-state launch for this width, so results match bit for bit
   if (d.dm.nx <= 256)
-    rhs_ym_body<T, 1, R>(smem_raw, d.C[parity], d.C[1 - parity], d.F0, d.F1, d.W, d.dm, d.cf, d.logL_rhs, d.twr0, d.twi0, t, d.gp);
+    rhs_ym_body<T, 1, R>(smem_raw, d.C[parity], d.C[1 - parity], d.F0, d.F1, d.W, d.dm, d.cf, d.logL_rhs, d.twr0, d.twi0, t, d.rp);
   else if (d.dm.nx <= 512)
-    rhs_ym_body<T, 2, R>(smem_raw, d.C[parity], d.C[1 - parity], d.F0, d.F1, d.W, d.dm, d.cf, d.logL_rhs, d.twr0, d.twi0, t, d.gp);
+    rhs_ym_body<T, 2, R>(smem_raw, d.C[parity], d.C[1 - parity], d.F0, d.F1, d.W, d.dm, d.cf, d.logL_rhs, d.twr0, d.twi0, t, d.rp);
   else
-    rhs_ym_body<T, 4, R>(smem_raw, d.C[parity], d.C[1 - parity], d.F0, d.F1, d.W, d.dm, d.cf, d.logL_rhs, d.twr0, d.twi0, t, d.gp);
+    rhs_ym_body<T, 4, R>(smem_raw, d.C[parity], d.C[1 - parity], d.F0, d.F1, d.W, d.dm, d.cf, d.logL_rhs, d.twr0, d.twi0, t, d.rp);
 }
 
 template <typename T, int E, int R>
@@ -2717,7 +2757,11 @@ void fill_case_desc(const Plan &p, int cur, void *desc_host) {
   d.stashL = (T *)p.stashL;
   d.stashR = (T *)p.stashR;
   d.nbg = blocks_for(p.G * 16);
-  d.gp = make_patch<T>(p);
+  d.rp = make_patch<T>(p);
+  d.dg = (T *)p.dg;
+  d.pl_dq = (T *)p.pl_dq;
+  d.pl_ref = p.pl_ref;
+  d.NP = p.NP;
   d.cn2 = (T)(p.Cn * p.Cn);
   d.inv_h2 = (T)(1.0 / (p.h * p.h));
   d.inv_cn2 = (T)(1.0 / (p.Cn * p.Cn));
@@ -2729,7 +2773,7 @@ size_t case_desc_bytes() {
   return sizeof(CaseDesc<T>);
 }
 
-// Per-phase tile counts of one case (0 rhs, 1 neumann, 2 out, 3 fill, 4 dphi, 5 velf) and the
+// Per-phase tile counts of one case (0 rhs, 1 neumann, 2 out, 3 fill, 4 dphi, 5 velf, 6 dq) and the
 // LDS bytes of its tiles (0 rhs, 1 neumann, 2 out).
 template <typename T>
 void case_tiles(const Plan &p, int *tiles, size_t *lds) {
@@ -2742,8 +2786,10 @@ void case_tiles(const Plan &p, int *tiles, size_t *lds) {
   tiles[2] = p.n[1] >> lo;
   const bool vf = p.vel_fill && p.G > 0;
   tiles[3] = (int)blocks_for(p.G * 16) + (vf ? (int)(blocks_for(p.G * 16) + blocks_for(p.NF)) : 0);
-  tiles[4] = make_patch<T>(p).dg ? (int)blocks_for(p.G * 16) : 0;   // (the ghost velocities run inside phase 3)
+  const bool pt = make_patch<T>(p).dq != nullptr;
+  tiles[4] = pt ? (int)blocks_for(p.G * 16) : 0;   // (the ghost velocities run inside phase 3)
   tiles[5] = vf ? (int)blocks_for(p.NF) : 0;
+  tiles[6] = pt ? (int)blocks_for(p.NP) : 0;
   lds[0] = (size_t)(1 << lr) * line_pitch(p.n[0]) * sizeof(T);
   lds[1] = (size_t)col_tile(p.n[1], 1 << lb) * sizeof(T);
   lds[2] = (size_t)(1 << lo) * line_pitch(p.n[0]) * sizeof(T);
@@ -2758,9 +2804,10 @@ hipError_t enqueue_batch_step(const BatchLaunch &bl, int parity) {
   const int *off = bl.off;
   auto O = [&](int ph) { return off + ph * (n + 1); };
   const unsigned nb0 = bl.total[0], nb1 = bl.total[1], nb2 = bl.total[2];
-  const unsigned nb3 = bl.total[3], nb4 = bl.total[4], nb5 = bl.total[5];
+  const unsigned nb3 = bl.total[3], nb4 = bl.total[4], nb5 = bl.total[5], nb6 = bl.total[6];
   const bool r8 = bl.radix_rhs == 8, u2 = bl.unroll >= 2;
   if (nb4) hipLaunchKernelGGL((kb_dphi<T>), dim3(nb4), dim3(kThreads), 0, bl.stream, cs, O(4), n, parity);
+  if (nb6) hipLaunchKernelGGL((kb_dq<T>), dim3(nb6), dim3(kThreads), 0, bl.stream, cs, O(6), n);
   if (bl.unroll == 3 && bl.lds[3]) {
     if (r8) hipLaunchKernelGGL((kb_rhs_ym<T, 8>), dim3(nb0), dim3(kThreads), bl.lds[3], bl.stream, cs, O(0), n, parity);
     else hipLaunchKernelGGL((kb_rhs_ym<T, 16>), dim3(nb0), dim3(kThreads), bl.lds[3], bl.stream, cs, O(0), n, parity);
