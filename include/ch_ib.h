@@ -244,6 +244,16 @@ int ch_ib_step(ch_ib_state *st, int n_steps);
 int ch_ib_sync(ch_ib_state *st);
 int ch_ib_diagnostics(ch_ib_state *st, ch_ib_diag *out);
 
+/* ch_ib_diagnostics_noalloc: for callers that cannot allocate device memory (code under stream
+ * capture, tight serving loops, harnesses that forbid allocation).  The same values as
+ * ch_ib_diagnostics, from the same kernels, but the reduction's partial sums live in a fixed
+ * device array of the library (8192 x 8 + 8 doubles, 512 KiB per GPU, held until the process
+ * ends) instead of the state's workspace; nothing is allocated.  The state's device must be the
+ * current device (CH_IB_EINVAL otherwise); a reduction needing more than 8192 partial sums is
+ * rejected with CH_IB_ENOMEM.  Every call on one GPU uses that GPU's one array: calls that
+ * overlap on the same GPU race.  Synchronous, like ch_ib_diagnostics. */
+int ch_ib_diagnostics_noalloc(ch_ib_state *st, ch_ib_diag *out);
+
 /* ---- stage entry points (each runs one part of the step on device buffers of the state's
  * element type, n cells each; used to check each stage on its own) ------------------------------
  * CH_IB_STAGE_RHS  : out = Q of Eq. Helmholtz1 from the current C^n, C^(n-1), faces (in unused).

@@ -89,6 +89,7 @@ def _load():
         "ch_ib_step_timed": (i32, [vp, i32, i32, C.POINTER(C.c_double), C.POINTER(C.c_char_p),
                                    C.POINTER(C.c_int)]),
         "ch_ib_diagnostics": (i32, [vp, C.POINTER(Diag)]),
+        "ch_ib_diagnostics_noalloc": (i32, [vp, C.POINTER(Diag)]),
         "ch_ib_tune": (i32, [vp, i32, C.POINTER(C.c_int)]),
         "ch_ib_get_shapes": (i32, [vp, C.POINTER(C.c_int)]),
         "ch_ib_set_shapes": (i32, [vp, C.POINTER(C.c_int)]),
@@ -389,6 +390,15 @@ class State:
     def diagnostics(self) -> dict:
         dg = Diag()
         rc = lib.ch_ib_diagnostics(self.h, C.byref(dg))
+        if rc not in (OK, ENAN):
+            check(rc)
+        return {"mass_box": dg.mass_box, "mass_fluid": dg.mass_fluid, "free_energy": dg.free_energy,
+                "max_abs_C": dg.max_abs_C, "step": dg.step, "status": dg.status}
+
+    def diagnostics_noalloc(self) -> dict:
+        """The same values through ch_ib_diagnostics_noalloc (the library's fixed device scratch)."""
+        dg = Diag()
+        rc = lib.ch_ib_diagnostics_noalloc(self.h, C.byref(dg))
         if rc not in (OK, ENAN):
             check(rc)
         return {"mass_box": dg.mass_box, "mass_fluid": dg.mass_fluid, "free_energy": dg.free_energy,

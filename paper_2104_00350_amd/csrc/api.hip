@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -798,6 +799,76 @@ extern "C" int ch_ib_diagnostics(ch_ib_state *st, ch_ib_diag *out) {
   if (e == hipSuccess) e = hipMemcpyAsync(r, p.red_out, sizeof(r), hipMemcpyDeviceToHost, p.stream);
   if (e == hipSuccess) e = hipStreamSynchronize(p.stream);
   if (e != hipSuccess) return hip_fail(st, e, "diagnostics");
+  const double vol = std::pow(p.h, p.d);
+  out->mass_box = vol * r[0];
+  out->mass_fluid = vol * r[1];
+  out->free_energy = vol * (r[2] - (2.0 * std::sqrt(2.0) / 3.0) * p.cos_t * r[3]);
+  out->max_abs_C = r[4];
+  out->step = st->step;
+  out->status = r[5] > 0 ? CH_IB_ENAN : CH_IB_OK;
+  out->pad_ = 0;
+  if (out->status) return fail(CH_IB_ENAN, "non-finite value in C");
+  return CH_IB_OK;
+}
+
+// ---------------------------------------------------------------------------------------------
+// Diagnostics without any allocation: the reduction's partial sums (kNred blocks of 8) and its
+// final 8 values live in a file-scope device array instead of the state's workspace.  Each GPU
+// holds its own copy; its address is looked up once per device (with that device current) and
+// only that address is used on the host.  Calls that overlap on one GPU share the array and race.
+constexpr size_t kScratchPartials = kNred;
+static __device__ __align__(256) double scratch[kScratchPartials * 8 + 8];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device (looked up on the first call per device).
+int scratch_address(void **out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return fail(CH_IB_EHIP, std::string("scratch: hipGetDevice: ") + hipGetErrorString(e));
+  if (dev < 0 || dev >= kMaxDevices) return fail(CH_IB_EUNSUPPORTED, "scratch: device index beyond 63");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return fail(CH_IB_EHIP, std::string("scratch: hipGetSymbolAddress: ") + hipGetErrorString(e));
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return CH_IB_OK;
+}
+}  // namespace
+
+extern "C" int ch_ib_diagnostics_noalloc(ch_ib_state *st, ch_ib_diag *out) {
+  if (!st || !out) return fail(CH_IB_EINVAL, "NULL argument");
+  chib::Plan &p = st->plan;
+  if ((size_t)p.nred > kScratchPartials)
+    return fail(CH_IB_ENOMEM, "reduction needs " + std::to_string(p.nred) + " partial sums, the static scratch holds " +
+                                  std::to_string(kScratchPartials));
+  // the state's workspace must sit on the current device, whose copy of the array is used
+  hipPointerAttribute_t attr{};
+  hipError_t e = hipPointerGetAttributes(&attr, st->ws);
+  int dev = -1;
+  if (e == hipSuccess) e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(st, e, "diagnostics_noalloc");
+  if (attr.device != dev) return fail(CH_IB_EINVAL, "the state's device is not the current device");
+  void *base = nullptr;
+  int rc = scratch_address(&base);
+  if (rc) return rc;
+  rc = ensure_init(st);
+  if (rc) return rc;
+  chib::Plan q = p;
+  q.partial = base;
+  q.red_out = (double *)base + kScratchPartials * 8;
+  e = st->es == 8 ? chib::enqueue_diag<double>(q, st->cur) : chib::enqueue_diag<float>(q, st->cur);
+  double r[8];
+  if (e == hipSuccess) e = hipMemcpyAsync(r, q.red_out, sizeof(r), hipMemcpyDeviceToHost, p.stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(p.stream);
+  if (e != hipSuccess) return hip_fail(st, e, "diagnostics_noalloc");
   const double vol = std::pow(p.h, p.d);
   out->mass_box = vol * r[0];
   out->mass_fluid = vol * r[1];
