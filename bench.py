@@ -329,41 +329,38 @@ def host_round_trip_benchmark(chib, st, case, ks=(1, 100)) -> dict:
     return out
 
 
-def learned_benchmark(chib, steps: int) -> dict:
-    """Learned wall-band correction (config 5): the 8 held-out contact angles run as one batch on
-    the plain 1024x512 grid (the reference), on the plain 512x256 grid and on the 512x256 grid with
-    the committed trained correction; contact angles measured with the same routine."""
+def learned_benchmark(chib, n_angles: int) -> dict:
+    """Learned wall-band correction (config 5 with the momentum step on): the first `n_angles` held-out
+    contact angles, each on the plain 1024x512 grid (the reference), the plain 512x256 grid and the
+    512x256 grid with the committed correction trained on momentum-step runs, 80000 steps of 2.5e-5
+    (t = 2); states advance one after another; contact angles from the same cap fit."""
     import numpy as np
     import torch
     import workloads as W
     from paper_2104_00350_amd import learned as LR
     _, eval_a = LR.study_angles()
-    coarse = W.config5(False)
+    coarse = W.config5_flow(False)
     net = chib.Net(coarse.grid.cells, coarse.grid.cells // 256, 1, 1, 0.1, torch.cuda.current_stream())
-    net.set_params(np.load(LR.WEIGHTS))
-    cps = sorted({min(steps, c) for c in (2000, 5000, 10000, 20000)})
-    ev = LR.evaluate(net, W.config5, eval_a, 100, cps, 0.5, log=lambda m: None)
+    net.set_params(np.load(LR.WEIGHTS_FLOW))
+    cps = [8000, 20000, 40000, 80000]
+    ev = LR.evaluate(net, W.config5_flow, eval_a[:n_angles], 400, cps, 0.5, log=lambda m: None)
     net.close()
     sm = LR.summarize(ev, cps)
-    return {"workload": "config 5: 2D sinusoidal wall y = 0.3 + 0.1 sin(2 pi x / 0.5) in [0,4]x[0,2], droplet "
-                        "R = 0.4, Cn = 0.01, Pe = 300, 8 held-out angles in [30, 150] deg, "
-                        f"{max(cps)} steps, correction every 100 steps at weight 0.5",
+    return {"workload": "config 5 with the momentum step: 2D sinusoidal wall y = 0.3 + 0.1 sin(2 pi x / 0.5) in "
+                        "[0,4]x[0,2], droplet R = 0.4, Cn = 0.01, Pe = 300, Re = 10, Ca = 0.05, l_s = 0.01, "
+                        f"held-out angles {[round(a, 1) for a in eval_a[:n_angles]]}, 80000 steps of dt = 2.5e-5, "
+                        "correction every 400 steps at weight 0.5",
+            "study_file": "profiles/learned_study_cfg5flow.json (all 8 held-out angles)",
             "speedup_learned_vs_plain_fine": round(sm["speedup_learned_vs_fine"], 3),
             "speedup_plain_coarse_vs_plain_fine": round(sm["speedup_coarse_vs_fine"], 3),
             "seconds": {"fine": round(sm["fine_s"], 3), "coarse": round(sm["coarse_s"], 3),
                         "learned": round(sm["learned_s"], 3)},
-            "angle_measure": "circular-cap fit beyond 3 Cn from the wall (equilibrium angle); near-wall local "
-                             "fit alongside",
             "angle_err_vs_fine_deg": [{"step": p["step"], "cases": p["cases"],
                                        "plain_coarse": p["mean_abs_err_coarse_deg"],
                                        "learned": p["mean_abs_err_learned_deg"],
-                                       "fine_vs_prescribed": p["mean_abs_fine_minus_theta_deg"],
-                                       "local_fit": {"cases": p["cases_local"],
-                                                     "plain_coarse": p["mean_abs_err_coarse_deg_local"],
-                                                     "learned": p["mean_abs_err_learned_deg_local"]}}
+                                       "fine_vs_prescribed": p["mean_abs_fine_minus_theta_deg"]}
                                       for p in sm["per_checkpoint"]],
             "within_1deg": {"cap_fit_vs_fine": sm["learned_within_1deg_cap_fit"],
-                            "local_fit_vs_fine": sm["learned_within_1deg_local_fit"],
                             "fine_at_equilibrium": sm["fine_at_equilibrium"],
                             "equilibrium_target_met": bool(sm["learned_within_1deg_cap_fit"]
                                                            and sm["fine_at_equilibrium"])},
@@ -425,8 +422,8 @@ def main() -> int:
     ap.add_argument("--no-tune", action="store_true", help="keep the default launch shapes")
     ap.add_argument("--shapes", default="", help="fixed launch shapes 'a,b,c;d,e,f;g,h,i;j,k,l' instead of tuning")
     ap.add_argument("--sweep-steps", type=int, default=2000, help="steps per case of the batched sweep (0: skip)")
-    ap.add_argument("--learned-steps", type=int, default=20000,
-                    help="steps of the learned-correction comparison (0: skip)")
+    ap.add_argument("--learned-angles", type=int, default=2,
+                    help="held-out angles of the learned-correction comparison, 1..8 (0: skip)")
     ap.add_argument("--explicit-steps", type=int, default=100,
                     help="timed steps of the explicit scheme on the same workload (0: skip)")
     ap.add_argument("--ns-steps", type=int, default=50,
@@ -566,9 +563,10 @@ def main() -> int:
     if args.sweep_steps > 0:
         print("[bench] batched sweep (64 cases)", file=sys.stderr, flush=True)
         out["batched_sweep"] = sweep_benchmark(chib, torch, args.sweep_steps)
-    if args.learned_steps > 0:
-        print("[bench] learned correction study (config 5, held-out angles)", file=sys.stderr, flush=True)
-        out["learned"] = learned_benchmark(chib, args.learned_steps)
+    if args.learned_angles > 0:
+        print("[bench] learned correction study (config 5 with the momentum step, held-out angles)", file=sys.stderr,
+              flush=True)
+        out["learned"] = learned_benchmark(chib, min(args.learned_angles, 8))
     if not args.no_cpu_baseline:
         print(f"[bench] GPU done ({value:.3e} cell-updates/s); timing the CPU oracle", file=sys.stderr,
               flush=True)

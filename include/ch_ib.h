@@ -379,7 +379,8 @@ int ch_ib_coefficients(const ch_ib_params *params, double *S, double *alpha_s, d
  * ch_ib_net_set_params / get_params: CH_IB_NET_NPARAMS floats (layout: W1[9][32][16] (tap, out,
  *   in; inputs 5..15 must be zero), b1[32], W2[9][32][32], b2[32], W3[9][32], b3; tap = 3 ky + kx
  *   multiplies the input at (x + kx - 1, y + ky - 1)); set_params also resets the optimiser.
- * ch_ib_net_bind: attaches a 2D FP64 static-condition state whose grid sizes are multiples of 16;
+ * ch_ib_net_bind: attaches a 2D FP64 static-condition state (semi-implicit, with or without the
+ *   momentum step) whose grid sizes are multiples of 16;
  *   wall_dist[N] and wall_normal[2][N] are host arrays (as ch_ib_wall_field returns), copied;
  *   the band tiles are the 16x16 tiles holding a cell with 0 < dist <= band_cells h.
  * ch_ib_net_rebind: attaches another state with the same grid and wall (same tiles and wall
@@ -401,7 +402,11 @@ int ch_ib_coefficients(const ch_ib_params *params, double *S, double *alpha_s, d
  *   twice as many cells per axis, same box).  both_levels = 0: the coarse state restarts from it
  *   (C_prev := C, ghosts refilled) at its next step; both_levels = 1: C_prev is restricted from
  *   the fine C_prev as well and the ghosts of C are refilled at once (the two-level history is
- *   kept; static condition only).  Synchronous. */
+ *   kept; static condition only).  With both_levels = 1 and the momentum step on both states
+ *   (EINVAL if only one runs it) the momentum state is restricted too: every coarse face is the
+ *   mean of the two fine faces that tile it (u^n, the advecting velocity and the previous
+ *   convective term; a divergence-free fine field stays divergence-free), both pressure levels
+ *   by 2x2 means, and the history flags follow the fine state.  Synchronous. */
 #define CH_IB_NET_NPARAMS 14177
 typedef struct ch_ib_net ch_ib_net;
 int ch_ib_wall_field(const ch_ib_grid *grid, const ch_ib_shape *shapes, int n_shapes, double *dist, double *normal);

@@ -602,6 +602,12 @@ void chib::state_mark_reinit(ch_ib_state *st) {
   if (st) st->needs_init = 1;
 }
 
+void chib::state_copy_momentum_flags(const ch_ib_state *from, ch_ib_state *to) {
+  if (!from || !to) return;
+  to->ns_first = from->ns_first;
+  to->ut_valid = from->ut_valid;
+}
+
 extern "C" int ch_ib_state_get(ch_ib_state *st, int field, void *dst, int dst_on_device) {
   if (!st || !dst) return fail(CH_IB_EINVAL, "NULL argument");
   const int64_t cnt = field_count(st, field);

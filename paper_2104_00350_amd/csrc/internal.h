@@ -46,5 +46,8 @@ struct StateRef {
 };
 int state_ref(ch_ib_state *st, StateRef *out);
 void state_mark_reinit(ch_ib_state *st);
+// The momentum step's history flags (first step pending, advecting velocity valid) of `from`
+// given to `to` (whose momentum fields were restricted from `from`'s).
+void state_copy_momentum_flags(const ch_ib_state *from, ch_ib_state *to);
 
 }  // namespace chib

@@ -436,6 +436,20 @@ __global__ __launch_bounds__(kT) void k_restrict2(const double *Cf, int lnxf, do
   Cc[c] = 0.25 * ((Cf[f0] + Cf[f0 + 1]) + (Cf[f1] + Cf[f1 + 1]));
 }
 
+// Staggered faces of a 2x finer grid onto the coarse faces: each coarse face is the mean of the two
+// fine faces that tile it (x faces: the right faces of fine column 2i+1, rows 2j and 2j+1; y faces:
+// the top faces of fine row 2j+1, columns 2i and 2i+1), so the flux through every coarse cell's
+// boundary is the fine flux through it and a discretely divergence-free fine field restricts to
+// a divergence-free coarse one.
+__global__ __launch_bounds__(kT) void k_restrict2_faces(const double *Uf, const double *Vf, int lnxf, double *Uc,
+                                                        double *Vc, int lnxc, int64_t Nc) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= Nc) return;
+  const int64_t i = c & ((1 << lnxc) - 1), j = c >> lnxc;
+  Uc[c] = 0.5 * (Uf[((2 * j) << lnxf) + 2 * i + 1] + Uf[((2 * j + 1) << lnxf) + 2 * i + 1]);
+  Vc[c] = 0.5 * (Vf[((2 * j + 1) << lnxf) + 2 * i] + Vf[((2 * j + 1) << lnxf) + 2 * i + 1]);
+}
+
 }  // namespace net
 }  // namespace chib
 
@@ -565,7 +579,6 @@ extern "C" int ch_ib_net_bind(ch_ib_net *n, ch_ib_state *st, const double *wall_
   if (p.d != 2 || r.es != 8) return chib::fail(CH_IB_EUNSUPPORTED, "the learned correction needs a 2D FP64 state");
   if (p.dynamic) return chib::fail(CH_IB_EUNSUPPORTED, "the learned correction needs the static condition");
   if (p.explicit_ab2) return chib::fail(CH_IB_EUNSUPPORTED, "the learned correction needs the semi-implicit scheme");
-  if (p.ns) return chib::fail(CH_IB_EUNSUPPORTED, "the learned correction runs without the momentum step");
   if ((p.n[0] % TS) || (p.n[1] % TS)) return chib::fail(CH_IB_EUNSUPPORTED, "grid sizes must be multiples of 16");
   if (p.N > n->max_cells) return chib::fail(CH_IB_EINVAL, "grid larger than max_cells");
   if (!(band_cells > 0)) return chib::fail(CH_IB_EINVAL, "band_cells must be > 0");
@@ -614,7 +627,7 @@ extern "C" int ch_ib_net_rebind(ch_ib_net *n, ch_ib_state *st) {
   int rc = chib::state_ref(st, &r);
   if (rc) return rc;
   const chib::Plan &p = *r.plan;
-  if (p.d != 2 || r.es != 8 || p.dynamic || p.explicit_ab2 || p.ns || p.n[0] != n->nx || p.n[1] != n->ny || p.h != n->h)
+  if (p.d != 2 || r.es != 8 || p.dynamic || p.explicit_ab2 || p.n[0] != n->nx || p.n[1] != n->ny || p.h != n->h)
     return chib::fail(CH_IB_EINVAL, "rebind needs a 2D FP64 static state on the bound grid");
   n->st = st;
   return CH_IB_OK;
@@ -774,6 +787,8 @@ extern "C" int ch_ib_restrict2(ch_ib_state *fine, ch_ib_state *coarse, int both_
     return chib::fail(CH_IB_EUNSUPPORTED, "restriction: 2D FP64 states only");
   if (pf.n[0] != 2 * pc.n[0] || pf.n[1] != 2 * pc.n[1])
     return chib::fail(CH_IB_EINVAL, "restriction: the fine grid must have twice the cells per axis");
+  if (both_levels && pf.ns != pc.ns)
+    return chib::fail(CH_IB_EINVAL, "restriction: both states run the momentum step or neither does");
   // both states on one stream order: the fine state's work is finished before the copy
   hipError_t e = hipStreamSynchronize(pf.stream);
   if (e == hipSuccess) {
@@ -783,10 +798,29 @@ extern "C" int ch_ib_restrict2(ch_ib_state *fine, ch_ib_state *coarse, int both_
                          (const double *)pf.C[cf], pf.logn[0], (double *)pc.C[cc], pc.logn[0], pc.N);
       e = hipGetLastError();
     }
+    if (e == hipSuccess && both_levels && pc.ns) {
+      // the momentum state: faces u^n, the advecting 2u^n - u^(n-1) and the previous convective
+      // term by face means, both pressure levels by cell means; the history flags follow
+      const unsigned nb = (unsigned)((pc.N + kT - 1) / kT);
+      hipLaunchKernelGGL(k_restrict2_faces, dim3(nb), dim3(kT), 0, pc.stream, (const double *)pf.F[0],
+                         (const double *)pf.F[1], pf.logn[0], (double *)pc.F[0], (double *)pc.F[1], pc.logn[0], pc.N);
+      if (pf.Ut[0] && pc.Ut[0])
+        hipLaunchKernelGGL(k_restrict2_faces, dim3(nb), dim3(kT), 0, pc.stream, (const double *)pf.Ut[0],
+                           (const double *)pf.Ut[1], pf.logn[0], (double *)pc.Ut[0], (double *)pc.Ut[1], pc.logn[0],
+                           pc.N);
+      hipLaunchKernelGGL(k_restrict2_faces, dim3(nb), dim3(kT), 0, pc.stream, (const double *)pf.Nh[0],
+                         (const double *)pf.Nh[1], pf.logn[0], (double *)pc.Nh[0], (double *)pc.Nh[1], pc.logn[0],
+                         pc.N);
+      for (int k = 0; k < 2; ++k)
+        hipLaunchKernelGGL(k_restrict2, dim3(nb), dim3(kT), 0, pc.stream, (const double *)pf.P[k], pf.logn[0],
+                           (double *)pc.P[k], pc.logn[0], pc.N);
+      e = hipGetLastError();
+    }
     if (e == hipSuccess && both_levels) e = chib::enqueue_ghost_refresh<double>(pc, rc_.cur);
   }
   if (e == hipSuccess) e = hipStreamSynchronize(pc.stream);
   if (e != hipSuccess) return net_hip(e, "restrict2");
   if (!both_levels) chib::state_mark_reinit(coarse);
+  else if (pc.ns) chib::state_copy_momentum_flags(fine, coarse);
   return CH_IB_OK;
 }

@@ -33,6 +33,8 @@ BAND_CELLS = 5.0
 FALLBACK_MAX_C = 1.15
 # parameters trained by `python -m paper_2104_00350_amd.learned --weights-out ...` (defaults)
 WEIGHTS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "weights", "wallband_sin512.npy")
+# the same network trained on runs with the momentum step (`--flow`)
+WEIGHTS_FLOW = os.path.join(os.path.dirname(os.path.abspath(__file__)), "weights", "wallband_sin512_flow.npy")
 
 
 def init_params(seed: int) -> np.ndarray:
@@ -141,7 +143,22 @@ def evaluate(net: "chib.Net", make_case, angles: Sequence[float], interval: int,
             g = cases[0].grid
             dist, nrm = chib.wall_field(g.n, g.lo, g.hi, cases[0].shapes)
             net.bind(states[0], dist, nrm, BAND_CELLS)
-        batch = chib.Batch(states)
+        # batches hold states without the momentum step: those advance one after another
+        batch = chib.Batch(states) if not cases[0].params.navier_stokes else None
+
+        def advance(k):
+            if batch is not None:
+                batch.step(k)
+            else:
+                for st in states:
+                    st.step(k)
+
+        def wait():
+            if batch is not None:
+                batch.sync()
+            else:
+                for st in states:
+                    st.sync()
         done, wall = 0, 0.0
         meas = [[] for _ in angles]
         meas_loc = [[] for _ in angles]
@@ -152,17 +169,18 @@ def evaluate(net: "chib.Net", make_case, angles: Sequence[float], interval: int,
             t0 = time.perf_counter()
             while done < cp:
                 k = min(interval, cp - done) if learned else cp - done
-                batch.step(k)
+                advance(k)
                 done += k
                 if learned and k == interval:
-                    batch.sync()
+                    wait()
                     for st in states:
                         net.rebind(st)
                         net.apply(weight)
                     torch.cuda.synchronize()
-            batch.sync()
+            wait()
             torch.cuda.synchronize()
             wall += time.perf_counter() - t0
+            log(f"[learned] {kind}: step {done} ({wall:.1f} s)")
             for a, (st, case) in enumerate(zip(states, cases)):
                 dg = st.diagnostics()
                 maxc[a] = max(maxc[a], dg["max_abs_C"] if dg["status"] == 0 else float("inf"))
@@ -176,7 +194,8 @@ def evaluate(net: "chib.Net", make_case, angles: Sequence[float], interval: int,
             if learned:
                 recs[a][kind]["fallback_to_fine"] = fallback[a]
         log(f"[learned] {kind}: {len(angles)} cases x {done} steps in {wall:.2f} s")
-        batch.close()
+        if batch is not None:
+            batch.close()
         for st in states:
             st.close()
         for r in recs:
@@ -249,13 +268,16 @@ def main(argv=None) -> int:
     ap.add_argument("--out-scale", type=float, default=0.1)
     ap.add_argument("--checkpoints", default="2000,5000,10000,20000")
     ap.add_argument("--weight", type=float, default=0.5, help="fraction of the correction applied")
+    ap.add_argument("--flow", action="store_true",
+                    help="the momentum step on (config 5 with Re and Ca active; dt 2.5e-5, four times the steps)")
     ap.add_argument("--weights-out", default="")
     ap.add_argument("--weights-in", default="")
     ap.add_argument("--json", default="")
     args = ap.parse_args(argv)
+    make = W.config5_flow if args.flow else W.config5
     train_a, eval_a = study_angles(n_train=args.train_angles, n_eval=args.eval_angles)
-    coarse = W.config5(False)
-    cells = W.config5(True).grid.cells
+    coarse = make(False)
+    cells = make(True).grid.cells
     per_angle = ((args.steps - args.start) // args.stride + 1) * (coarse.grid.cells // 256)
     stream = torch.cuda.current_stream()
     net = chib.Net(cells, coarse.grid.cells // 256, per_angle * len(train_a) if not args.weights_in else 1,
@@ -266,7 +288,7 @@ def main(argv=None) -> int:
         losses, data = [], {"slots": np.zeros(0), "stored": 0}
     else:
         net.set_params(init_params(7))
-        data = generate(net, W.config5, train_a, args.steps, args.interval, args.start, args.stride,
+        data = generate(net, make, train_a, args.steps, args.interval, args.start, args.stride,
                         log=lambda m: print(m, file=sys.stderr, flush=True))
         t1 = time.perf_counter()
         print(f"[learned] data {t1 - t0:.1f}s", file=sys.stderr, flush=True)
@@ -275,9 +297,11 @@ def main(argv=None) -> int:
         if args.weights_out:
             np.save(args.weights_out, net.get_params())
     cps = [int(c) for c in args.checkpoints.split(",")]
-    ev = evaluate(net, W.config5, eval_a, args.interval, cps, args.weight,
+    ev = evaluate(net, make, eval_a, args.interval, cps, args.weight,
                   log=lambda m: print(m, file=sys.stderr, flush=True))
-    res = {"train_angles": train_a, "eval_angles": eval_a, "interval": args.interval, "weight": args.weight,
+    res = {"workload": coarse.name.rsplit("_th", 1)[0], "dt": coarse.params.dt,
+           "momentum_step": bool(coarse.params.navier_stokes),
+           "train_angles": train_a, "eval_angles": eval_a, "interval": args.interval, "weight": args.weight,
            "band_cells": BAND_CELLS,
            "out_scale": args.out_scale, "samples_with_band_cells": int(len(data["slots"])),
            "tiles_stored": int(data["stored"]), "loss_trace": losses, "checkpoints": cps,

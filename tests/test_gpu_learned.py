@@ -210,6 +210,7 @@ def test_restriction_matches_the_two_by_two_mean(chib):
 
 
 def test_bind_rejects_unsupported_states(chib):
+    """The dynamic condition and grid sizes that are not multiples of 16 are rejected."""
     dyn = W.small_case(64, 32, kind="sin", Vs=100.0)
     st = chib.state_for_case(dyn)
     g = dyn.grid
@@ -234,6 +235,57 @@ def test_study_driver_with_the_committed_weights(chib):
     net = chib.Net(coarse.grid.cells, coarse.grid.cells // 256, 1, 1, 0.1, torch.cuda.current_stream())
     net.set_params(np.load(LR.WEIGHTS))
     ev = LR.evaluate(net, W.config5, [90.0], 100, [300], 0.5, log=lambda m: None)
+    rec = ev["cases"][0]
+    for kind in ("fine", "coarse", "learned"):
+        assert np.isfinite(rec[kind]["angles"][0]) and rec[kind]["max_abs_C"] < 1.1
+    assert not rec["learned"]["fallback_to_fine"]
+    net.close()
+
+
+def test_restriction_of_a_momentum_state(chib):
+    """With the momentum step the restriction also carries the velocity: every coarse face is the
+    mean of the two fine faces that tile it, the pressure the 2x2 mean; a discretely divergence-free
+    fine field stays divergence-free on the coarse grid, and the coarse state steps on from it."""
+    import dataclasses
+
+    def mk(n):
+        c = W.small_case(n, n // 2, kind="sin", theta_deg=70.0)
+        c.params = dataclasses.replace(c.params, navier_stokes=True, dt=5e-5)
+        return c
+    fine_c, coarse_c = mk(128), mk(64)
+    fine, coarse = chib.state_for_case(fine_c), chib.state_for_case(coarse_c)
+    fine.step(40)
+    coarse.step(3)                     # its own history, replaced by the restriction
+    chib.restrict2(fine, coarse, both_levels=True)
+    uf, vf = fine.get(chib.FIELD_U), fine.get(chib.FIELD_V)
+    uc, vc = coarse.get(chib.FIELD_U), coarse.get(chib.FIELD_V)
+    assert np.max(np.abs(uf)) > 1e-3                        # the fine flow is not at rest
+    assert np.array_equal(uc, 0.5 * (uf[0::2, 1::2] + uf[1::2, 1::2]))
+    assert np.array_equal(vc, 0.5 * (vf[1::2, 0::2] + vf[1::2, 1::2]))
+    R = lambda a: 0.25 * ((a[0::2, 0::2] + a[0::2, 1::2]) + (a[1::2, 0::2] + a[1::2, 1::2]))
+    assert np.max(np.abs(coarse.get(chib.FIELD_P) - R(fine.get(chib.FIELD_P)))) <= 1e-13
+
+    def div(u, v, h):
+        vb = np.vstack([np.zeros((1, v.shape[1])), v[:-1]])   # no flux through the bottom box wall
+        vt = v.copy()
+        vt[-1] = 0.0                                          # nor through the top one
+        return (u - np.roll(u, 1, axis=1)) / h + (vt - vb) / h
+    df = np.max(np.abs(div(uf, vf, fine_c.grid.h)))
+    dc = np.max(np.abs(div(uc, vc, coarse_c.grid.h)))
+    _say("divergence fine", df, "coarse", dc)
+    assert dc <= max(df, 1e-11)
+    coarse.step(5)
+    assert coarse.diagnostics()["status"] == 0
+
+
+def test_study_driver_with_the_momentum_step(chib):
+    """The learned correction binds to states that run the momentum step, and the scoring driver
+    advances such states one by one (batches hold frozen-flow states only)."""
+    from paper_2104_00350_amd import learned as LR
+    coarse = W.config5_flow(False)
+    net = chib.Net(coarse.grid.cells, coarse.grid.cells // 256, 1, 1, 0.1, torch.cuda.current_stream())
+    net.set_params(np.load(LR.WEIGHTS))
+    ev = LR.evaluate(net, W.config5_flow, [90.0], 400, [800], 0.5, log=lambda m: None)
     rec = ev["cases"][0]
     for kind in ("fine", "coarse", "learned"):
         assert np.isfinite(rec[kind]["angles"][0]) and rec[kind]["max_abs_C"] < 1.1

@@ -227,6 +227,19 @@ def config5(fine: bool, theta_deg: float = 60.0, seed: int = 2104) -> Case:
                 (2.125, 0.4), 0.4, 1e-3, seed)
 
 
+def config5_flow(fine: bool, theta_deg: float = 60.0, seed: int = 2104) -> Case:
+    """The learned-correction study's case with the momentum step on (Re 10, Ca 0.05, matched fluids).
+
+    The explicit viscous term limits the step on the fine grid to about Re h^2/4 = 3.8e-5, so the
+    simulated time t = 2 of the frozen-flow runs (20000 steps of 1e-4) is covered by 80000 steps of
+    2.5e-5 on both grids."""
+    c = config5(fine, theta_deg, seed)
+    c.params = dataclasses.replace(c.params, dt=2.5e-5, navier_stokes=True)
+    c.name = c.name.replace("cfg5_", "cfg5flow_")
+    c.steps = 80000
+    return c
+
+
 def small_case(nx: int = 64, ny: int = 32, theta_deg: float = 60.0, kind: str = "flat",
                Vs: float = 0.0, seed: int = 7, velocity_fill: bool = True,
                slip_length: float = 0.01) -> Case:
