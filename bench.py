@@ -239,7 +239,7 @@ def ns_benchmark(chib, case, steps: int, precision: int, semi_ms: float, NF: int
     import dataclasses
     prm = dataclasses.replace(case.params, navier_stokes=True)
     g = case.grid
-    geo = chib.Geometry.build(g.n, g.lo, g.hi, case.shapes, prm)
+    geo = chib.Geometry.build_device(g.n, g.lo, g.hi, case.shapes, prm)
     st = chib.State(geo, prm, precision)
     st.set_shapes(shapes)          # the order-parameter passes run with the main state's launch shapes
     C0, faces = case.initial_fields()
@@ -367,6 +367,40 @@ def learned_benchmark(chib, n_angles: int) -> dict:
             "fallbacks_to_fine": sm["fallbacks"]}
 
 
+def geometry_benchmark(chib, torch, case, tabs100, t_dev100: float) -> dict:
+    """Geometry preprocessing (one-time, not in the step metric).  The workload's tables use the
+    paper's 100 subgrid points per direction (device builder).  The host builder is timed and
+    compared bit for bit at 20 points per direction (at 100 it takes about a minute on the host),
+    and the tables at 20 are compared with those at 100: how much the coarser count moves the
+    volume fractions, normals and wall distances."""
+    import dataclasses
+    import numpy as np
+    g = case.grid
+    prm20 = dataclasses.replace(case.params, subgrid=20)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    dev20 = chib.Geometry.build_device(g.n, g.lo, g.hi, case.shapes, prm20).export()
+    t_dev20 = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    host20 = chib.Geometry.build(g.n, g.lo, g.hi, case.shapes, prm20).export()
+    t_host20 = time.perf_counter() - t0
+    same = all(np.array_equal(dev20[k], host20[k]) for k in dev20)
+    out = {"subgrid": 100, "device_builder_s": round(t_dev100, 4), "ghosts": int(tabs100["gidx"].size),
+           "at_20_subgrid_points": {"device_builder_s": round(t_dev20, 4), "host_builder_s": round(t_host20, 4),
+                                    "device_tables_equal_host": same, "ghosts": int(dev20["gidx"].size)}}
+    a100, a20 = tabs100["alpha"], dev20["alpha"]
+    cmp = {"max_abs_alpha_diff": float(np.max(np.abs(a100 - a20))),
+           "cells_with_alpha_diff": int(np.count_nonzero(a100 != a20)),
+           "same_ghost_list": bool(np.array_equal(tabs100["gidx"], dev20["gidx"]))}
+    if cmp["same_ghost_list"]:
+        n1, n2 = tabs100["normal"], dev20["normal"]
+        cosang = np.clip(np.sum(n1 * n2, axis=0) / (np.linalg.norm(n1, axis=0) * np.linalg.norm(n2, axis=0)), -1, 1)
+        cmp["max_normal_angle_diff_deg"] = float(np.degrees(np.max(np.arccos(cosang))))
+        cmp["max_dn_diff_over_h"] = float(np.max(np.abs(tabs100["dn"] - dev20["dn"])) / g.h)
+    out["tables_20_vs_100"] = cmp
+    return out
+
+
 def cpu_model() -> str:
     try:
         for line in open("/proc/cpuinfo"):
@@ -381,11 +415,15 @@ def cpu_model() -> str:
 def cpu_baseline(case, steps: int, steps_one_core: int) -> dict:
     """The FP64 oracle on the host, on a bounded sample (a few steps) of the same workload: scipy's
     FFTs on every host thread, then on one thread (NumPy's stencils are single-threaded either way)."""
+    import dataclasses
     import oracle.solver as OS
     from oracle.geometry import build_tables
-    T = build_tables(case.grid, case.shapes, case.params)
+    # the oracle's tables with 20 subgrid points per direction (at 100 the oracle's counting alone
+    # takes a quarter of an hour; the timed steps do the same work either way)
+    T = build_tables(case.grid, case.shapes, dataclasses.replace(case.params, subgrid=20))
     C0, faces = case.initial_fields()
     orc = OS.OracleState(case.grid, case.params, T, C0, faces)
+    print("[bench] oracle tables built; timing its steps", file=sys.stderr, flush=True)
     orc.step(1)   # warm-up (FFT plans, page faults)
     threads = OS.WORKERS
     t0 = time.perf_counter()
@@ -404,7 +442,8 @@ def cpu_baseline(case, steps: int, steps_one_core: int) -> dict:
                "sample": f"{steps_one_core} further steps ({dt1:.1f} s)"}
     return {"value": case.grid.cells * steps / dt, "unit": "cell-updates/s", "cores": threads,
             "kind": "oracle", "cpu_model": cpu_model(), "host_threads": os.cpu_count(),
-            "sample": f"{steps} steps of the same 256^3 workload after 1 warm-up step "
+            "sample": f"{steps} steps of the same 256^3 workload after 1 warm-up step, tables counted with 20 "
+                      "subgrid points per direction "
                       f"({dt:.1f} s; scipy FFTs on {threads} threads, NumPy stencils single-threaded)",
             "one_core": one}
 
@@ -446,8 +485,10 @@ def main() -> int:
         return 2
     case = W.config3(args.n)
     g = case.grid
+    chib.Geometry.build_device(g.n, g.lo, g.hi, case.shapes, case.params)      # loads its kernels
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
-    geo = chib.Geometry.build(g.n, g.lo, g.hi, case.shapes, case.params)
+    geo = chib.Geometry.build_device(g.n, g.lo, g.hi, case.shapes, case.params)   # 100 subgrid points per direction
     t_geom = time.perf_counter() - t0
     st = chib.State(geo, case.params, args.precision)
     C0, faces = case.initial_fields()
@@ -543,15 +584,7 @@ def main() -> int:
     out["scalar_fill"] = scalar_fill_benchmark(chib, st, case)
     out["diagnostics"] = diagnostics_benchmark(st, case, es)
     out["host_round_trip"] = host_round_trip_benchmark(chib, st, case)
-    # geometry preprocessing (one-time, not in the step metric): host builder vs the device builder
-    chib.Geometry.build_device(g.n, g.lo, g.hi, case.shapes, case.params)      # loads its kernels
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    geo_dev = chib.Geometry.build_device(g.n, g.lo, g.hi, case.shapes, case.params)
-    t_dev = time.perf_counter() - t0
-    same = all(np.array_equal(a, b) for a, b in zip(geo_dev.export().values(), tabs.values()))
-    out["geometry"] = {"host_builder_s": round(t_geom, 4), "device_builder_s": round(t_dev, 4),
-                       "ghosts": st.G, "device_tables_equal_host": same}
+    out["geometry"] = geometry_benchmark(chib, torch, case, tabs, t_geom)
     if args.explicit_steps > 0:
         print("[bench] explicit scheme", file=sys.stderr, flush=True)
         out["explicit"] = explicit_benchmark(chib, geo, case, args.explicit_steps, args.precision, NF,

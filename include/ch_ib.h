@@ -101,7 +101,7 @@ typedef struct {
   double S;                   /* stabilisation of Appendix A.1; <= 0 selects Cn sqrt(6 Pe/dt) */
   double d1_cells;            /* intersect-to-mirror distance in cells; <= 0 selects 2 */
   double d2_cells;            /* mirror-to-interpolation-point spacing in cells; <= 0 selects 1.5 */
-  int subgrid;                /* subgrid points per direction for the volume fraction; 0: 100 (2D) / 20 (3D) */
+  int subgrid;                /* subgrid points per direction for the volume fraction; 0: 100 */
   int precision;              /* 64 (FP64) or 32 (FP32) arithmetic on the device */
   int flags;                  /* CH_IB_FLAG_* */
   /* momentum step (CH_IB_FLAG_NAVIER_STOKES only; all four must then be positive): densities and

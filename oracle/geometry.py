@@ -15,8 +15,8 @@ Readings of silent or garbled passages:
   repeats one component and puts a grid spacing in the numerator);
 * the corner gradient divides by the sum of the two adjacent spacings along the
   same axis, averaged over the 2^(d-1) cell pairs;
-* subgrid points sit at sub-cell centres; 100 per direction in 2D as the paper
-  states, 20 per direction in 3D by default (cost grows as n^3), configurable;
+* subgrid points sit at sub-cell centres, 100 per direction as the paper states
+  (in 3D too; configurable);
 * a ghost is a solid cell centre with at least one face neighbour whose centre
   is fluid; a ghost touching the bounded (last) axis' box wall is rejected;
 * the intersect point is found by marching from the ghost along n in steps of
@@ -146,7 +146,7 @@ def _may_be_cut(shape: Shape, Xc: Sequence[np.ndarray], grid: Grid) -> np.ndarra
 def default_subgrid(grid: Grid, params: Params) -> int:
     if params.subgrid > 0:
         return int(params.subgrid)
-    return 100 if grid.ndim == 2 else 20
+    return 100
 
 
 def cell_index_coords(grid: Grid):

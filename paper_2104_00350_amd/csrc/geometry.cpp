@@ -8,7 +8,7 @@
 // the method in this project):
 //  - unit normal n = m / sqrt(m.m + 1e-30), m the mean of the 2^d corner gradients, each
 //    corner gradient the mean one-cell difference of alpha across the corner divided by h;
-//  - subgrid points at sub-cell centres, 100 per direction in 2D and 20 in 3D by default;
+//  - subgrid points at sub-cell centres, 100 per direction by default (the paper's count);
 //  - ghost: solid cell centre with a face neighbour whose centre is fluid; a ghost in the
 //    first or last cell layer of the bounded axis is rejected;
 //  - intersect point: march from the ghost along n in steps of h/100 to the first fluid
@@ -219,7 +219,7 @@ extern "C" int ch_ib_geometry_build(const ch_ib_grid *grid, const ch_ib_shape *s
     }
     S.s.push_back(shapes[i]);
   }
-  const int sub = params->subgrid > 0 ? params->subgrid : (d == 2 ? 100 : 20);
+  const int sub = params->subgrid > 0 ? params->subgrid : 100;
   const int64_t N = g->cells;
   const int nx = g->n[0], ny = g->n[1], nz = g->n[2];
 

@@ -531,7 +531,7 @@ extern "C" int ch_ib_geometry_build_device(const ch_ib_grid *grid, const ch_ib_s
     A.S.bs[i] = std::sin(shapes[i].p[4]);
   }
   A.h = tmp.h;
-  A.sub = params->subgrid > 0 ? params->subgrid : (d == 2 ? 100 : 20);
+  A.sub = params->subgrid > 0 ? params->subgrid : 100;
   if (A.sub > 1000) return fail(CH_IB_EUNSUPPORTED, "at most 1000 subgrid points per direction on the device builder");
   A.hs = tmp.h / A.sub;
   A.d1 = (params->d1_cells > 0 ? params->d1_cells : 2.0) * tmp.h;

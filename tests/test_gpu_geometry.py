@@ -54,7 +54,11 @@ def test_device_geometry_matches_the_oracle_and_the_host_builder(chib, maker):
 
 
 def test_device_geometry_of_the_256_sphere_equals_the_host_builder(chib):
+    """Bit for bit at full size, with 20 subgrid points per direction (at the default 100 the
+    host builder alone takes about a minute here; the next test checks 100 on a smaller sphere)."""
+    import dataclasses
     c = W.config3(256)
+    c.params = dataclasses.replace(c.params, subgrid=20)
     g = c.grid
     t0 = time.perf_counter()
     dev = chib.Geometry.build_device(g.n, g.lo, g.hi, c.shapes, c.params)
@@ -66,6 +70,25 @@ def test_device_geometry_of_the_256_sphere_equals_the_host_builder(chib):
     a, b = dev.export(), host.export()
     for key in ("gidx", "ap", "alpha", "normal", "dn", "gamma", "w"):
         assert np.array_equal(a[key], b[key]), key
+
+
+def test_volume_fractions_of_a_sphere_at_100_subgrid_points(chib):
+    """The paper's 100 subgrid points per direction (the default) in 3D: the device builder's volume
+    fractions and tables equal the oracle's and the host builder's on a small sphere."""
+    g = W.Grid((16, 16, 16), (-1.0, -1.0, -1.0), (1.0, 1.0, 1.0))
+    prm = W.Params(Cn=0.2, Pe=10.0)
+    shapes = [W.Shape(W.SPHERE, (0.05, -0.02, 0.03, 0.31))]
+    dev = chib.Geometry.build_device(g.n, g.lo, g.hi, shapes, prm).export()
+    host = chib.Geometry.build(g.n, g.lo, g.hi, shapes, prm).export()
+    T = build_tables(g, shapes, prm)
+    cut = (T.alpha > 0) & (T.alpha < 1)
+    assert cut.sum() >= 50
+    for key in ("gidx", "ap", "alpha", "normal", "dn", "gamma", "w"):
+        assert np.array_equal(dev[key], host[key]), key
+    assert np.array_equal(dev["alpha"], T.alpha.reshape(-1))
+    assert np.array_equal(dev["gidx"], T.gidx) and np.array_equal(dev["ap"], T.ap)
+    for key, ref in (("normal", T.normal), ("dn", T.dn), ("gamma", T.gamma), ("w", T.w)):
+        assert np.max(np.abs(dev[key] - ref)) <= 1e-12 * max(1.0, np.max(np.abs(ref))), key
 
 
 def test_device_geometry_errors(chib):

@@ -49,7 +49,8 @@ def _drop_2d(explicit=False, theta=70.0, nx=64, ny=32):
 def _drop_3d():
     grid = W.Grid((32, 16, 32), (0.0, 0.0, 0.0), (1.0, 0.5, 1.0))
     prm = W.Params(Cn=0.04, Pe=50.0, Re=10.0, Ca=0.2, theta_deg=60.0, slip_length=0.02, dt=1e-4,
-                   navier_stokes=True, rho1=0.2, rho2=1.0, mu1=0.5, mu2=1.0, body_force=(0.0, 0.0, -0.3))
+                   navier_stokes=True, rho1=0.2, rho2=1.0, mu1=0.5, mu2=1.0, body_force=(0.0, 0.0, -0.3),
+                   subgrid=20)   # 20 subgrid points per direction: the oracle counts in seconds
     shapes = [W.Shape(W.SPHERE, (0.5, 0.25, -0.75, 1.0))]
     C0, _ = W.droplet_field(grid, (0.5, 0.25, 0.4), 0.2, prm.Cn, 1e-3, 5)
     rng = np.random.default_rng(13)
@@ -89,7 +90,7 @@ def test_staggered_fractions_equal_the_oracle(chib):
              (W.Grid((64, 32), (0.0, 0.0), (2.0, 1.0)), [W.Shape(W.SPHERE, (1.0, 0.45, 0.0, 0.3))]),
              (W.Grid((16, 8, 16), (0.0, 0.0, 0.0), (1.0, 0.5, 1.0)), [W.Shape(W.SPHERE, (0.5, 0.25, -0.75, 1.0))])]
     for grid, shapes in cases:
-        prm = W.Params(Cn=0.04, Pe=50.0, navier_stokes=True)
+        prm = W.Params(Cn=0.04, Pe=50.0, navier_stokes=True, subgrid=20 if grid.ndim == 3 else 0)
         geo = chib.Geometry.build(grid.n, grid.lo, grid.hi, shapes, prm)
         got = geo.face_fractions()
         want = face_fractions(grid, shapes, prm)
@@ -127,7 +128,8 @@ def test_coupled_steps_3d_wide(chib):
     column tiles, two of them along y, so the halo row between tiles is exercised."""
     grid = W.Grid((64, 16, 32), (0.0, 0.0, 0.0), (2.0, 0.5, 1.0))
     prm = W.Params(Cn=0.04, Pe=50.0, Re=10.0, Ca=0.2, theta_deg=60.0, slip_length=0.02, dt=1e-4,
-                   navier_stokes=True, rho1=0.2, rho2=1.0, mu1=0.5, mu2=1.0, body_force=(0.0, 0.0, -0.3))
+                   navier_stokes=True, rho1=0.2, rho2=1.0, mu1=0.5, mu2=1.0, body_force=(0.0, 0.0, -0.3),
+                   subgrid=20)
     shapes = [W.Shape(W.HALFPLANE, (0.0, 0.0, 0.3, 0.0, 0.0, 1.0)), W.Shape(W.SPHERE, (1.0, 0.25, 0.25, 0.2))]
     C0, _ = W.droplet_field(grid, (1.0, 0.25, 0.55), 0.25, prm.Cn, 1e-3, 5)
     rng = np.random.default_rng(17)
@@ -256,7 +258,7 @@ def test_full_size_sphere_divergence_free(chib):
     case = W.config3()
     prm = dataclasses.replace(case.params, navier_stokes=True, rho1=0.1, rho2=1.0, mu1=0.5, mu2=1.0)
     grid = case.grid
-    geo = chib.Geometry.build(grid.n, grid.lo, grid.hi, case.shapes, prm)
+    geo = chib.Geometry.build_device(grid.n, grid.lo, grid.hi, case.shapes, prm)
     st = chib.State(geo, prm)
     C0, _ = case.initial_fields()
     st.set_initial(C0)
