@@ -77,11 +77,12 @@ def kernel_template(name: str, shapes, es: int, nx: int) -> list:
     if name == "rhs_xdht":
         lt, r, u = shapes[0]
         if u >= 3 and nx in (256, 512):
-            return [f"k_rhs_xdht_zm<{t}, {2 ** min(max(lt, 1), 3)}, {nx // 256}, {r}, false>"]
-        return [f"k_rhs_xdht<{t}, 3, {E}, {u}, {r}>"]
+            L = 2 ** min(max(lt, 1), 3 if nx == 256 else 2)
+            return [f"k_rhs_xdht_zm<{t}, {L}, {nx // 256}, {8 if (r == 4 and L == 8) else r}, false>"]
+        return [f"k_rhs_xdht<{t}, 3, {E}, {u}, {max(r, 8)}>"]
     if name == "rhs_stencil":
         lt = shapes[0][0]
-        return [f"k_rhs_xdht_zm<{t}, {2 ** min(max(lt, 1), 3)}, {nx // 256}, 8, true>"]
+        return [f"k_rhs_xdht_zm<{t}, {2 ** min(max(lt, 1), 3 if nx == 256 else 2)}, {nx // 256}, 8, true>"]
     if name == "xdht_fwd":
         return [f"k_xdht<{t}, {E}, {shapes[3][1]}>"]
     if name in ("ydht_fwd", "ydht_inv"):

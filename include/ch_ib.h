@@ -293,7 +293,8 @@ int ch_ib_step_timed(ch_ib_state *st, int n_steps, int max_kernels, double *ms_o
 /* ---- launch-shape autotuning ------------------------------------------------------------------
  * The four field passes of a step (0 fused rhs + x transform, 1 strided y transform (3D only),
  * 2 bounded-axis solve, 3 x transform out) each have a launch shape of three ints:
- * {log2 lines or columns per tile, largest FFT radix (8 or 16), third field}.  The third field is
+ * {log2 lines or columns per tile, largest FFT radix (8 or 16; pass 0 also 4, which only the
+ * z-marching kernel with up to 4 rows per tile uses, the others taking 8), third field}.  The third field is
  * 1 for passes 1-3; for pass 0 it is the cells in flight per thread (1 or 2) of the line-tiled
  * kernel; for 2D grids with nx <= 1024, 3 selects the y-marching kernel (rows y-1..y+1 held per
  * thread, each value loaded and combined once); for 3D grids, 3..5 select the z-marching kernel
@@ -307,7 +308,8 @@ int ch_ib_step_timed(ch_ib_state *st, int n_steps, int max_kernels, double *ms_o
  *   buffers (the fields are left unchanged), keeps the fastest and writes the 12 chosen ints to
  *   shapes_out (may be NULL).  Synchronous.
  * ch_ib_get_shapes / ch_ib_set_shapes: read or impose the 12 ints (e.g. from a cache); values
- *   are clamped to what the grid and the LDS tile allow; EINVAL on a radix other than 8 or 16. */
+ *   are clamped to what the grid and the LDS tile allow; EINVAL on a radix other than 8 or 16
+ *   (or 4 for pass 0). */
 int ch_ib_tune(ch_ib_state *st, int reps, int *shapes_out);
 int ch_ib_get_shapes(const ch_ib_state *st, int *shapes_out);
 int ch_ib_set_shapes(ch_ib_state *st, const int *shapes);

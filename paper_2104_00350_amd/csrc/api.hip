@@ -768,7 +768,7 @@ extern "C" int ch_ib_get_shapes(const ch_ib_state *st, int *out) {
 extern "C" int ch_ib_set_shapes(ch_ib_state *st, const int *in) {
   if (!st || !in) return fail(CH_IB_EINVAL, "NULL argument");
   for (int k = 0; k < 4; ++k)
-    if ((in[3 * k + 1] != 8 && in[3 * k + 1] != 16) || in[3 * k] < 1 || in[3 * k] > 11 || in[3 * k + 2] < 1 ||
+    if ((in[3 * k + 1] != 8 && in[3 * k + 1] != 16 && (k != 0 || in[3 * k + 1] != 4)) || in[3 * k] < 1 || in[3 * k] > 11 || in[3 * k + 2] < 1 ||
         in[3 * k + 2] > (k == 0 ? 8 : 2))
       return fail(CH_IB_EINVAL, "shape out of range");
   for (int k = 0; k < 4; ++k) st->plan.shape[k] = {in[3 * k], in[3 * k + 1], in[3 * k + 2]};

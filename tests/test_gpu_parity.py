@@ -361,7 +361,7 @@ def test_tuned_shapes_keep_parity(chib):
     st, orc, _ = _pair(chib, case)
     shapes = st.tune(2)
     _say("tuned shapes", shapes)
-    assert all(s[1] in (8, 16) for s in shapes)
+    assert shapes[0][1] in (4, 8, 16) and all(s[1] in (8, 16) for s in shapes[1:])
     st.step(20)
     orc.step(20)
     assert _linf(st.get(chib.FIELD_C), orc.C) <= 1e-9
@@ -375,10 +375,13 @@ def test_tuned_shapes_keep_parity(chib):
         st.set_shapes([[2, 4, 1]] * 4)
 
 
-def test_z_marching_rhs_variants(chib):
-    """Every shape of the z-marching rhs kernel (3D, nx = 256), fused with the x transform or split
-    from it, matches the oracle step."""
-    grid = W.Grid((256, 16, 32), (-2.0, -0.125, -0.25), (2.0, 0.125, 0.25))
+@pytest.mark.parametrize("n", [(256, 16, 32), (512, 8, 32)])
+def test_z_marching_rhs_variants(chib, n):
+    """Every shape of the z-marching rhs kernel (3D, nx = 256 and 512: one and two columns per
+    thread), fused with the x transform or split from it, matches the oracle step.  Chunks of 8 to
+    256 planes cover chunks shorter than, equal to and (clamped) longer than the grid."""
+    h = 4.0 / n[0]
+    grid = W.Grid(n, (-2.0, -0.5 * h * n[1], -0.5 * h * n[2]), (2.0, 0.5 * h * n[1], 0.5 * h * n[2]))
     prm = W.Params(Cn=0.02, Pe=100.0, Ca=0.1, theta_deg=70.0, slip_length=0.01, dt=1e-4, subgrid=20)
     case = W.Case("slab3d", grid, [W.Shape(W.HALFPLANE, (0.0, 0.0, -0.1, 0.0, 0.0, 1.0))], prm, 10,
                   (0.0, 0.0, -0.1), 0.2, 1e-3, 5)
@@ -388,13 +391,13 @@ def test_z_marching_rhs_variants(chib):
     blob = st.save()
     orc.step(6)
     for lt in (1, 2, 3):
-        for radix in (8, 16):
+        for radix in (4, 8, 16):
             for zc in (3, 4, 5, 6, 7, 8):      # 6..8: stencil-only z-march + separate x transform
                 st.load(blob)
                 st.set_shapes([[lt, radix, zc], [3, 8, 1], [4, 16, 1], [3, 8, 1]])
                 st.step(6)
                 err = _linf(st.get(chib.FIELD_C), orc.C)
-                assert err <= 1e-11, (lt, radix, zc, err)
+                assert err <= 1e-11, (n, lt, radix, zc, err)
 
 
 @pytest.mark.parametrize("maker,steps", [(lambda: W.small_case(128, 64, kind="sin", theta_deg=50.0), 60),
