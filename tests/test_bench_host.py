@@ -21,7 +21,8 @@ def test_code_digest_ignores_comments_and_whitespace(tmp_path):
 def test_committed_counters_match_the_kernel_code():
     """The committed HBM counter summary was taken on the kernel code in the tree, so bench.py reports
     its traffic for the dominant kernel (in the launch shape the counters were taken with)."""
-    t16 = bench.measured_traffic("rhs_xdht", [[3, 8, 4], [4, 16, 1], [4, 16, 1], [3, 8, 1]], 8, 256)
-    t8 = bench.measured_traffic("rhs_xdht", [[3, 8, 3], [4, 16, 1], [4, 16, 1], [3, 8, 1]], 8, 256)
-    assert t16 is not None and t8 is not None and t8 > t16 > 0   # thinner z-chunks re-read more halo
-    assert bench.measured_traffic("rhs_xdht", [[2, 8, 4], [4, 16, 1], [4, 16, 1], [3, 8, 1]], 8, 256) is None
+    rest = [[3, 8, 1], [4, 16, 1], [3, 8, 1]]
+    t32 = bench.measured_traffic("rhs_xdht", [[2, 4, 5]] + rest, 8, 256)
+    t16 = bench.measured_traffic("rhs_xdht", [[2, 4, 4]] + rest, 8, 256)
+    assert t16 is not None and t32 is not None and t16 > t32 > 0   # thinner z-chunks re-read more halo
+    assert bench.measured_traffic("rhs_xdht", [[2, 8, 4]] + rest, 8, 256) is None
