@@ -325,13 +325,17 @@ int ch_ib_set_shapes(ch_ib_state *st, const int *shapes);
  *   condition (Vs = 0); their pending initial fills are done here.  The batch keeps pointers to
  *   the states: while it exists, the member states must not be stepped on their own or freed.
  *   device_workspace (caller-owned, 256-byte aligned) must outlive the batch.  EUNSUPPORTED for
- *   3D, dynamic or explicit-scheme states, EINVAL for mixed precisions.
+ *   3D, dynamic or explicit-scheme states, EINVAL for mixed precisions.  Members with the
+ *   momentum step (Navier-Stokes coupling, section 4.4) are accepted: the grouped launches cover
+ *   the others, and each of these is advanced by its own launches (those of ch_ib_step, on the
+ *   batch's stream, one member after another), with the same results as ch_ib_step.
  * ch_ib_batch_step: enqueues n_steps steps for every member on the batch's stream (graph replays
  *   plus at most one direct step; on the NULL stream, which cannot be captured, direct grouped
- *   launches only); the members' step counters and buffer roles are updated.
+ *   launches only; then the momentum members' steps); the members' step counters and buffer
+ *   roles are updated.
  * ch_ib_batch_tune: tunes the launch shapes of one member per distinct grid size
- *   (ch_ib_tune), applies them to all members of that size, then times full batched steps for
- *   the choices shared by the grouped kernels and the tile heights (greedy: rhs radix and rhs
+ *   (ch_ib_tune), applies them to all members of that size, then times full batched steps of the
+ *   grouped members for the choices shared by the grouped kernels and the tile heights (greedy: rhs radix and rhs
  *   kernel, then per grid size the rhs, solve and output tile heights, written to the members'
  *   shapes, then the solve radix, then the output radix); radix_out[0..2] (rhs, solve, out) and
  *   *unroll_out (either may be NULL) receive the shared choices.  Leaves the fields unchanged.

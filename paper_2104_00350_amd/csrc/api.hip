@@ -1077,6 +1077,8 @@ extern "C" void ch_ib_state_free(ch_ib_state *st) { delete st; }
 
 struct ch_ib_batch {
   std::vector<ch_ib_state *> st;
+  std::vector<ch_ib_state *> grp;   // members advanced by the grouped launches
+  std::vector<ch_ib_state *> seq;   // members with the momentum step: their own launches, in turn
   int es = 8;
   char *ws = nullptr;
   size_t ws_bytes = 0;
@@ -1109,7 +1111,7 @@ static void batch_drop_graphs(ch_ib_batch *b) {
 
 // Uploads descriptors (from each member's current buffer roles) and tile offsets.
 static int batch_upload(ch_ib_batch *b) {
-  const int n = (int)b->st.size();
+  const int n = (int)b->grp.size();
   const size_t db = batch_desc_bytes(b->es);
   std::vector<unsigned char> descs(db * n);
   constexpr int NPH = chib::BatchLaunch::kPhases;
@@ -1117,7 +1119,7 @@ static int batch_upload(ch_ib_batch *b) {
   size_t lds[4] = {0, 0, 0, 0};
   bool ym_all = true;
   for (int c = 0; c < n; ++c) {
-    ch_ib_state *s = b->st[c];
+    ch_ib_state *s = b->grp[c];
     int tiles[NPH];
     size_t l[4];
     if (b->es == 8) {
@@ -1133,10 +1135,13 @@ static int batch_upload(ch_ib_batch *b) {
   }
   if (!ym_all) lds[3] = 0;
   const size_t doff = (db * n + 255) & ~(size_t)255;
-  hipError_t e = hipMemcpyAsync(b->ws, descs.data(), descs.size(), hipMemcpyHostToDevice, b->stream);
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(b->ws + doff, off.data(), off.size() * sizeof(int), hipMemcpyHostToDevice, b->stream);
-  if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+  hipError_t e = hipSuccess;
+  if (n > 0) {
+    e = hipMemcpyAsync(b->ws, descs.data(), descs.size(), hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(b->ws + doff, off.data(), off.size() * sizeof(int), hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+  }
   if (e != hipSuccess) return hip_fail(nullptr, e, "batch upload");
   b->bl.descs = b->ws;
   b->bl.off = (const int *)(b->ws + doff);
@@ -1150,6 +1155,7 @@ static int batch_upload(ch_ib_batch *b) {
 }
 
 static hipError_t batch_direct_step(ch_ib_batch *b, int parity) {
+  if (b->bl.n == 0) return hipSuccess;   // no member for the grouped launches
   return b->es == 8 ? chib::enqueue_batch_step<double>(b->bl, parity) : chib::enqueue_batch_step<float>(b->bl, parity);
 }
 
@@ -1168,7 +1174,6 @@ extern "C" int ch_ib_batch_create(ch_ib_state *const *states, int n, void *ws, s
     if (s->plan.d != 2) return fail(CH_IB_EUNSUPPORTED, "batches hold 2D states only");
     if (s->plan.dynamic) return fail(CH_IB_EUNSUPPORTED, "batches hold static contact-angle states only");
     if (s->plan.explicit_ab2) return fail(CH_IB_EUNSUPPORTED, "batches hold semi-implicit states only");
-    if (s->plan.ns) return fail(CH_IB_EUNSUPPORTED, "batches hold states without the momentum step");
     if (s->sticky) return fail(s->sticky, "a member state is in an error state");
   }
   for (int c = 0; c < n; ++c) {
@@ -1179,19 +1184,21 @@ extern "C" int ch_ib_batch_create(ch_ib_state *const *states, int n, void *ws, s
   }
   auto *b = new ch_ib_batch();
   b->st.assign(states, states + n);
+  for (ch_ib_state *s : b->st) (s->plan.ns ? b->seq : b->grp).push_back(s);
   b->es = es;
   b->ws = (char *)ws;
   b->ws_bytes = bytes;
   b->stream = (hipStream_t)stream;
-  // shared kernel choices follow the first member's shapes (so that a batched step is the same
-  // computation as stepping each member with those shapes)
-  b->bl.radix_rhs = states[0]->plan.shape[0].radix;
+  // shared kernel choices follow the first grouped member's shapes (so that a batched step is the
+  // same computation as stepping each member with those shapes)
+  const ch_ib_state *s0 = b->grp.empty() ? states[0] : b->grp[0];
+  b->bl.radix_rhs = s0->plan.shape[0].radix;
   {
-    const int u = states[0]->plan.shape[0].unroll;   // 3: y-march where every case allows it
+    const int u = s0->plan.shape[0].unroll;   // 3: y-march where every case allows it
     b->bl.unroll = u == 3 ? 3 : std::min(u, 2);
   }
-  b->bl.radix_neu = states[0]->plan.shape[2].radix;
-  b->bl.radix_out = states[0]->plan.shape[3].radix;
+  b->bl.radix_neu = s0->plan.shape[2].radix;
+  b->bl.radix_out = s0->plan.shape[3].radix;
   int rc = batch_upload(b);
   if (rc) {
     delete b;
@@ -1205,7 +1212,7 @@ extern "C" int ch_ib_batch_step(ch_ib_batch *b, int n_steps) {
   if (!b) return fail(CH_IB_EINVAL, "NULL batch");
   if (n_steps < 0) return fail(CH_IB_EINVAL, "n_steps must be >= 0");
   hipError_t e = hipSuccess;
-  int left = n_steps;
+  int left = b->grp.empty() ? 0 : n_steps;
   if (!b->stream) {  // the legacy NULL stream cannot be captured: direct grouped launches
     for (; left > 0 && e == hipSuccess; --left) {
       e = batch_direct_step(b, b->parity);
@@ -1237,9 +1244,23 @@ extern "C" int ch_ib_batch_step(ch_ib_batch *b, int n_steps) {
     if (e == hipSuccess) b->parity ^= 1;
   }
   if (e != hipSuccess) return hip_fail(nullptr, e, "batch step");
-  for (ch_ib_state *s : b->st) {
+  for (ch_ib_state *s : b->grp) {
     s->step += n_steps;
     if (n_steps & 1) s->cur = 1 - s->cur;
+  }
+  // members with the momentum step: the same launches as ch_ib_step, on the batch's stream
+  for (ch_ib_state *s : b->seq) {
+    const hipStream_t own = s->plan.stream;
+    s->plan.stream = b->stream;
+    for (int i = 0; i < n_steps && e == hipSuccess; ++i) {
+      e = enqueue_one_step(s, nullptr);
+      if (e == hipSuccess) {
+        s->cur = 1 - s->cur;
+        s->step++;
+      }
+    }
+    s->plan.stream = own;
+    if (e != hipSuccess) return hip_fail(s, e, "batch step");
   }
   return CH_IB_OK;
 }
@@ -1268,15 +1289,30 @@ extern "C" int ch_ib_batch_tune(ch_ib_batch *b, int reps, int *radix_out, int *u
       if (o->plan.n[0] == key.first && o->plan.n[1] == key.second)
         for (int k = 0; k < 4; ++k) o->plan.shape[k] = s->plan.shape[k];
   }
-  // 2. the shared radix / cells in flight: time full batched steps (an even number, so that every
-  // member's buffer roles end where they started; the fields advance, so restore them after)
-  std::vector<std::vector<unsigned char>> saved(b->st.size());
-  for (size_t c = 0; c < b->st.size(); ++c) {
+  // 2. the shared radix / cells in flight: time full batched steps of the grouped members (an even
+  // number, so that every member's buffer roles end where they started; the fields advance, so
+  // restore them after).  Members with the momentum step keep the shapes of step 1.
+  if (b->grp.empty()) {
+    if (radix_out) {
+      radix_out[0] = b->bl.radix_rhs;
+      radix_out[1] = b->bl.radix_neu;
+      radix_out[2] = b->bl.radix_out;
+    }
+    if (unroll_out) *unroll_out = b->bl.unroll;
+    return CH_IB_OK;
+  }
+  sizes.clear();
+  for (ch_ib_state *s : b->grp) {
+    std::pair<int, int> key{s->plan.n[0], s->plan.n[1]};
+    if (std::find(sizes.begin(), sizes.end(), key) == sizes.end()) sizes.push_back(key);
+  }
+  std::vector<std::vector<unsigned char>> saved(b->grp.size());
+  for (size_t c = 0; c < b->grp.size(); ++c) {
     size_t len = 0;
-    int rc = ch_ib_state_save(b->st[c], nullptr, &len);
+    int rc = ch_ib_state_save(b->grp[c], nullptr, &len);
     if (rc) return rc;
     saved[c].resize(len);
-    rc = ch_ib_state_save(b->st[c], saved[c].data(), &len);
+    rc = ch_ib_state_save(b->grp[c], saved[c].data(), &len);
     if (rc) return rc;
   }
   int rc = batch_upload(b);
@@ -1326,7 +1362,7 @@ extern "C" int ch_ib_batch_tune(ch_ib_batch *b, int reps, int *radix_out, int *u
     for (const auto &key : sizes) {
       if (e != hipSuccess) break;
       std::vector<ch_ib_state *> grp;
-      for (ch_ib_state *s : b->st)
+      for (ch_ib_state *s : b->grp)
         if (s->plan.n[0] == key.first && s->plan.n[1] == key.second) grp.push_back(s);
       const int hi = b->es == 8 ? chib::max_log_tile<double>(grp[0]->plan, pass)
                                 : chib::max_log_tile<float>(grp[0]->plan, pass);
@@ -1366,8 +1402,8 @@ extern "C" int ch_ib_batch_tune(ch_ib_batch *b, int reps, int *radix_out, int *u
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (e != hipSuccess) return hip_fail(nullptr, e, "batch tune");
-  for (size_t c = 0; c < b->st.size(); ++c) {
-    rc = ch_ib_state_load(b->st[c], saved[c].data(), saved[c].size());
+  for (size_t c = 0; c < b->grp.size(); ++c) {
+    rc = ch_ib_state_load(b->grp[c], saved[c].data(), saved[c].size());
     if (rc) return rc;
   }
   rc = batch_upload(b);

@@ -6,7 +6,7 @@ import numpy as np
 import pytest
 
 import workloads as W
-from oracle.geometry import build_tables
+from oracle.geometry import build_tables, face_fractions
 from oracle.solver import OracleState
 
 pytestmark = pytest.mark.gpu
@@ -33,6 +33,8 @@ def _make(chib, case, faces_seed):
     T = build_tables(case.grid, case.shapes, case.params)
     g = case.grid
     geo = chib.Geometry.from_tables(g.n, g.lo, g.hi, T.gidx, T.normal, T.dn, T.gamma, T.ap, T.w, T.alpha)
+    if case.params.navier_stokes:   # the momentum step needs the staggered-cell fractions too
+        geo.set_face_fractions(face_fractions(g, case.shapes, case.params))
     st = chib.State(geo, case.params)
     C0, _ = case.initial_fields()
     rng = np.random.default_rng(faces_seed)
@@ -102,3 +104,54 @@ def test_batch_rejects_3d_and_dynamic(chib):
     with pytest.raises(chib.ChibError) as e:
         chib.Batch([sd])
     assert e.value.code == chib.EUNSUPPORTED
+
+
+def test_momentum_members_step_like_single_states(chib):
+    """Members with the momentum step ride along in a batch (their own launches on the batch's
+    stream) and end bit for bit where stepping them alone ends; the grouped member beside them
+    too, through graph replays, a direct step and a tuning pass."""
+    import dataclasses
+    cases = [W.small_case(64, 32, kind="sin", theta_deg=70.0, seed=8),
+             W.small_case(64, 32, kind="flat", theta_deg=50.0),
+             W.small_case(128, 64, kind="circle", theta_deg=110.0, seed=9)]
+    for i in (0, 2):
+        cases[i] = dataclasses.replace(cases[i], params=dataclasses.replace(cases[i].params, navier_stokes=True))
+    singles = [_make(chib, c, 30 + i)[0] for i, c in enumerate(cases)]
+    members = [_make(chib, c, 30 + i)[0] for i, c in enumerate(cases)]
+    b = chib.Batch(members)
+    b.step(9)
+    b.sync()
+    for s in singles:
+        s.step(9)
+    fields = (chib.FIELD_C, chib.FIELD_C_PREV, chib.FIELD_U, chib.FIELD_V)
+    for i, (s, m) in enumerate(zip(singles, members)):
+        for f in fields + ((chib.FIELD_P,) if i != 1 else ()):
+            assert np.array_equal(s.get(f), m.get(f)), (i, f)
+        assert m.diagnostics()["step"] == 9
+    b.tune(1)   # (the grouped member's shared FFT radices may now differ from its own shapes)
+    for s, m in zip(singles, members):
+        s.set_shapes(m.shapes())
+    b.step(4)
+    b.sync()
+    for s in singles:
+        s.step(4)
+    for i, (s, m) in enumerate(zip(singles, members)):
+        for f in fields:
+            if i == 1:
+                assert float(np.max(np.abs(s.get(f) - m.get(f)))) <= 1e-11, (i, f)
+            else:
+                assert np.array_equal(s.get(f), m.get(f)), (i, f)
+
+
+def test_batch_of_momentum_members_only(chib):
+    """A batch whose every member has the momentum step (no grouped launches at all)."""
+    import dataclasses
+    c = W.small_case(64, 32, kind="tilted", theta_deg=100.0, seed=5)
+    c = dataclasses.replace(c, params=dataclasses.replace(c.params, navier_stokes=True))
+    single, member = _make(chib, c, 41)[0], _make(chib, c, 41)[0]
+    b = chib.Batch([member])
+    b.step(3)
+    b.sync()
+    single.step(3)
+    assert np.array_equal(single.get(chib.FIELD_C), member.get(chib.FIELD_C))
+    assert np.array_equal(single.get(chib.FIELD_U), member.get(chib.FIELD_U))
