@@ -134,7 +134,7 @@ struct Layout {
 };
 
 struct Offsets {
-  size_t C[2], F[3], W, R, alpha, gidx, normal, dn, gamma, ap, w, CGn, CGnm1, CMs, CI, CGnew, UG;
+  size_t C[2], F[3], W, R, alpha, gidx, normal, dn, gamma, ap, w, apg, wg, CGn, CGnm1, CMs, CI, CGnew, UG;
   size_t dg, pl_cell, pl_ref, pl_row, pl_dq;
   size_t Us[3], Ut[3], Nh[3], Af[3], P[2];
   size_t f_cell, f_axis, f_gL, f_gR, stashL, stashR;
@@ -168,6 +168,8 @@ Offsets plan_layout(const ch_ib_geometry &g, int es, int64_t NF, int64_t NP, boo
   o.gamma = L.off(G * es);
   o.ap = L.off(2 * K * G * 4);
   o.w = L.off(2 * K * G * es);
+  o.apg = L.off(chib::kGhostSlots * G * 4);
+  o.wg = L.off(chib::kGhostSlots * G * es);
   o.CGn = L.off(G * es);
   o.CGnm1 = L.off(G * es);
   o.CMs = L.off(G * es);
@@ -380,6 +382,8 @@ extern "C" int ch_ib_state_create(const ch_ib_grid *grid, const ch_ib_geometry *
   p.gamma = W0 + o.gamma;
   p.ap = (const int *)(W0 + o.ap);
   p.w = W0 + o.w;
+  p.apg = (const int *)(W0 + o.apg);
+  p.wg = W0 + o.wg;
   p.CGn = W0 + o.CGn;
   p.CGnm1 = W0 + o.CGnm1;
   p.CMs = W0 + o.CMs;
@@ -441,6 +445,15 @@ extern "C" int ch_ib_state_create(const ch_ib_grid *grid, const ch_ib_geometry *
   std::vector<int> gidx32(G), ap32(geom->ap.size());
   for (int64_t i = 0; i < G; ++i) gidx32[i] = (int)geom->gidx[i];
   for (size_t i = 0; i < geom->ap.size(); ++i) ap32[i] = (int)geom->ap[i];
+  // ghost-major copies: slot k of ghost g at g * kGhostSlots + k
+  const int KK = 2 * geom->n_ap;
+  std::vector<int> apg32((size_t)G * chib::kGhostSlots, 0);
+  std::vector<double> wgv((size_t)G * chib::kGhostSlots, 0.0);
+  for (int64_t g = 0; g < G; ++g)
+    for (int k = 0; k < KK; ++k) {
+      apg32[(size_t)g * chib::kGhostSlots + k] = ap32[(size_t)k * G + g];
+      wgv[(size_t)g * chib::kGhostSlots + k] = geom->w[(size_t)k * G + g];
+    }
   hipStream_t s = p.stream;
   std::vector<std::vector<double>> keep_d;
   std::vector<std::vector<float>> keep_f;
@@ -463,6 +476,8 @@ extern "C" int ch_ib_state_create(const ch_ib_grid *grid, const ch_ib_geometry *
     up(geom->dn, (void *)p.dn);
     up(geom->gamma, (void *)p.gamma);
     up(geom->w, (void *)p.w);
+    if (e == hipSuccess) e = hipMemcpyAsync((void *)p.apg, apg32.data(), apg32.size() * 4, hipMemcpyHostToDevice, s);
+    up(wgv, (void *)p.wg);
   }
   if (NP && e == hipSuccess) {
     e = hipMemcpyAsync((void *)p.pl_cell, pl.cell.data(), NP * 4, hipMemcpyHostToDevice, s);

@@ -9,6 +9,8 @@ namespace chib {
 
 // Everything one step needs, as plain values and device pointers (element type T chosen
 // by the launcher: double for precision 64, float for precision 32).
+constexpr int kGhostSlots = 16;   // lanes (and table slots) per ghost in the ghost kernels
+
 struct Plan {
   int d = 2;
   int n[3] = {1, 1, 1};
@@ -49,6 +51,10 @@ struct Plan {
   const void *gamma = nullptr;     // [G]
   const int *ap = nullptr;         // [2][K][G]
   const void *w = nullptr;         // [2][K][G]
+  // the same two tables ghost-major, kGhostSlots slots per ghost (slots >= 2K: cell 0, weight 0), for
+  // the kernels that give each ghost a lane group: one wave request then covers a few cache lines
+  const int *apg = nullptr;        // [G][kGhostSlots]
+  const void *wg = nullptr;        // [G][kGhostSlots]
   void *CGn = nullptr, *CGnm1 = nullptr, *CMs = nullptr, *CI = nullptr, *CGnew = nullptr;
   void *UG = nullptr;              // [d][G]
 

@@ -1185,7 +1185,7 @@ __device__ __forceinline__ void fill_static_body(T *__restrict__ C, const int *_
   const int cgi = gidx[gs];
   T v = T(0);
   if (g < G && sl < 2 * K) {
-    const int64_t i = (int64_t)sl * G + g;
+    const int64_t i = g * kGhostSlots + sl;
     v = (sl < K ? T(2) : T(-1)) * w[i] * C[ap[i]];
   }
   const T CM = group16_sum(v);
@@ -1336,7 +1336,7 @@ __device__ __forceinline__ void ghost_dphi_body(const T *__restrict__ Cn, const 
     int64_t c;
     T coef;
     if (sl < 2 * K) {
-      const int64_t i = (int64_t)sl * G + g;
+      const int64_t i = g * kGhostSlots + sl;
       c = ap[i];
       coef = (sl < K ? T(2) : T(-1)) * w[i];
     } else {
@@ -1426,7 +1426,7 @@ __device__ __forceinline__ void vel_ghosts_body(
   T gm[3] = {0, 0, 0}, um[3] = {0, 0, 0}, gg[3] = {0, 0, 0};
   if (g < G) {
     if (sl < 2 * K) {
-      const int64_t i = (int64_t)sl * G + g;
+      const int64_t i = g * kGhostSlots + sl;
       const T cw = (sl < K ? T(2) : T(-1)) * w[i];
       const int64_t c = ap[i];
       T gk[3] = {0, 0, 0};
@@ -2040,7 +2040,7 @@ hipError_t launch_ghost_patch(const Plan &p, const T *Cn, const T *Cp) {
   if (p.G == 0 || p.NP == 0 || !p.dg) return hipSuccess;
   const Dims dm = make_dims(p);
   hipLaunchKernelGGL((k_ghost_dphi<T>), dim3(blocks_for(p.G * 16)), dim3(kThreads), 0, p.stream, Cn, Cp, p.gidx,
-                     p.ap, (const T *)p.w, (T *)p.dg, p.G, p.K, dm, p.d, (T)(p.Cn * p.Cn), (T)(1.0 / (p.h * p.h)),
+                     p.apg, (const T *)p.wg, (T *)p.dg, p.G, p.K, dm, p.d, (T)(p.Cn * p.Cn), (T)(1.0 / (p.h * p.h)),
                      (T)(1.0 / (p.Cn * p.Cn)));
   hipLaunchKernelGGL((k_patch_dq<T>), dim3(blocks_for(p.NP)), dim3(kThreads), 0, p.stream, p.pl_ref,
                      (const T *)p.dg, (T *)p.pl_dq, p.NP, 2 * p.d + 1, (T)(2 * p.d), (T)(1.0 / (p.h * p.h)));
@@ -2281,7 +2281,7 @@ hipError_t launch_ghost_fill(const Plan &p, T *Cout, int init) {
     const T cb = (T)(p.cos_t / (1.4142135623730951 * p.Cn));
     hipLaunchKernelGGL((k_fill_static<T>), dim3(blocks_for(p.G * 16)), dim3(kThreads), 0, p.stream, Cout, p.gidx,
                        (const T *)p.dn,
-                       (const T *)p.gamma, p.ap, (const T *)p.w, (T *)p.CGn, (T *)p.CGnm1, (T *)p.CMs, p.G, p.K, cb,
+                       (const T *)p.gamma, p.apg, (const T *)p.wg, (T *)p.CGn, (T *)p.CGnm1, (T *)p.CMs, p.G, p.K, cb,
                        init);
   } else {
     if (!init)
@@ -2313,7 +2313,7 @@ hipError_t launch_static_fills(const Plan &p, T *Cout) {
   const unsigned nbc = blocks_for(p.G * 16), nbg = blocks_for(p.G * 16);
   const T cb = (T)(p.cos_t / (1.4142135623730951 * p.Cn));
   hipLaunchKernelGGL((k_fill_static_vel<T>), dim3(nbc + nbg + blocks_for(p.NF)), dim3(kThreads), 0, p.stream, Cout,
-                     p.gidx, (const T *)p.dn, (const T *)p.gamma, p.ap, (const T *)p.w, (T *)p.CGn, (T *)p.CGnm1,
+                     p.gidx, (const T *)p.dn, (const T *)p.gamma, p.apg, (const T *)p.wg, (T *)p.CGn, (T *)p.CGnm1,
                      (T *)p.CMs, p.G, p.K, cb, (const T *)p.F[0], (const T *)p.F[1], (const T *)p.F[2],
                      (const T *)p.normal, (T *)p.UG, p.f_cell, p.f_axis, p.f_gL, p.f_gR, (T *)p.stashL,
                      (T *)p.stashR, p.NF, dm, p.d, (T)(0.5 / p.h), (T)p.Cn, (T)p.cos_t, (T)(1.0 / p.Ca),
@@ -2329,7 +2329,7 @@ hipError_t launch_velocity_fill(const Plan &p, const T *Cfin) {
   const unsigned nbg = blocks_for(p.G * 16);
   hipLaunchKernelGGL((k_vel_ghosts<T>), dim3(nbg + blocks_for(p.NF)), dim3(kThreads), 0, p.stream, Cfin,
                      (const T *)p.F[0], (const T *)p.F[1], (const T *)p.F[2], p.gidx, (const T *)p.normal,
-                     (const T *)p.dn, (const T *)p.gamma, p.ap, (const T *)p.w, (const T *)p.CMs, (T *)p.UG, p.G,
+                     (const T *)p.dn, (const T *)p.gamma, p.apg, (const T *)p.wg, (const T *)p.CMs, (T *)p.UG, p.G,
                      p.K, p.f_cell, p.f_axis, p.f_gL, p.f_gR, (T *)p.stashL, (T *)p.stashR, p.NF, dm, p.d,
                      (T)(0.5 / p.h), (T)p.Cn, (T)p.cos_t, (T)(1.0 / p.Ca), (T)(1.0 / p.mu), (T)p.ls,
                      p.dynamic ? 1 : 0, nbg);
@@ -2867,11 +2867,11 @@ void fill_case_desc(const Plan &p, int cur, void *desc_host) {
   d.logB = clamp_log(p.shape[2].log_tile, max_log_cols(p, p.n[1], E));
   d.lognxb = p.logn[0] - d.logB;
   d.gidx = p.gidx;
-  d.ap = p.ap;
+  d.ap = p.apg;   // the batch's ghost kernels take the ghost-major tables
   d.dn = (const T *)p.dn;
   d.gam = (const T *)p.gamma;
   d.normal = (const T *)p.normal;
-  d.w = (const T *)p.w;
+  d.w = (const T *)p.wg;
   d.CGn = (T *)p.CGn;
   d.CGnm1 = (T *)p.CGnm1;
   d.CMs = (T *)p.CMs;
