@@ -677,6 +677,10 @@ __global__ __launch_bounds__(kThreads, (L == 2 && XM == 1 && R == 4) ? 3 : 1) vo
   T cm[XM][L], c0[XM][L + 2], cp[XM][L + 2], h0[XM][L], hp[XM][L], na[XM][L + 2], nb[XM][L + 2];
   // faces of plane z (F1 at rows -1..L-1, z faces of plane z-1 below) and of plane z+1 in flight
   T f0[XM][L], f1[XM][L + 1], f2[XM][L], uzm[XM][L], nf0[XM][L], nf1[XM][L + 1], nf2[XM][L];
+  // Cache policy: C^n, C^(n-1) and the x and z faces are read here for the last time in the step and
+  // W is read next by another pass over the whole grid, so all of them go as non-temporal (streaming)
+  // accesses that leave the L2 and the Infinity Cache to the y faces (rows shared by neighbouring
+  // tiles) and to the next passes; measured 181 -> 168 us together with the x pass out's streaming reads
   auto load_c = [&](int z) {   // planes beyond the box reflect onto the boundary plane
     const int64_t zb = zbase(z);
 #pragma unroll
@@ -684,8 +688,8 @@ __global__ __launch_bounds__(kThreads, (L == 2 && XM == 1 && R == 4) ? 3 : 1) vo
 #pragma unroll
       for (int r = 0; r < L + 2; ++r) {
         const int64_t q = zb + (int64_t)row_of(r - 1) * nx + tid + 256 * m;
-        na[m][r] = Cn[q];
-        nb[m][r] = Cp[q];
+        na[m][r] = __builtin_nontemporal_load(Cn + q);
+        nb[m][r] = __builtin_nontemporal_load(Cp + q);
       }
   };
   auto load_f = [&](int z) {
@@ -695,8 +699,8 @@ __global__ __launch_bounds__(kThreads, (L == 2 && XM == 1 && R == 4) ? 3 : 1) vo
 #pragma unroll
       for (int r = 0; r < L; ++r) {
         const int64_t q = zb + (int64_t)row_of(r) * nx + tid + 256 * m;
-        nf0[m][r] = F0[q];
-        nf2[m][r] = F2[q];
+        nf0[m][r] = __builtin_nontemporal_load(F0 + q);
+        nf2[m][r] = __builtin_nontemporal_load(F2 + q);
       }
 #pragma unroll
       for (int r = 0; r < L + 1; ++r) nf1[m][r] = F1[zb + (int64_t)row_of(r - 1) * nx + tid + 256 * m];
@@ -889,8 +893,8 @@ __global__ __launch_bounds__(kThreads, (L == 2 && XM == 1 && R == 4) ? 3 : 1) vo
       const int ak = kx + (kx >> 4), an = kk + (kk >> 4);
       const T p = pb[ak], qq = pb[pitch + ak], rr = pb[an], sv = pb[pitch + an];
       T *o = W + (line0 + 2 * b) * nx + kx;
-      o[0] = (p - qq + rr + sv) * T(0.5);
-      o[nx] = (p + qq - rr + sv) * T(0.5);
+      __builtin_nontemporal_store((p - qq + rr + sv) * T(0.5), o);
+      __builtin_nontemporal_store((p + qq - rr + sv) * T(0.5), o + nx);
     }
     }
   }
@@ -908,7 +912,8 @@ __device__ __forceinline__ void xdht_body(unsigned char *smem_raw, const T *__re
   const int tot = L << lnx;
   const int pitch = line_pitch(nx);
   const T *src = in + (int64_t)line0 * nx;
-  stage_tile(s, tot, [&](int e) { return src[e]; }, [&](int e) {
+  // (streaming reads: the input is not read again by this pass or the next one)
+  stage_tile(s, tot, [&](int e) { return __builtin_nontemporal_load(src + e); }, [&](int e) {
     const int l = e >> lnx, i = e & (nx - 1);
     return l * pitch + i + (i >> 4);
   });
