@@ -94,7 +94,7 @@ def kernel_template(name: str, shapes, es: int, nx: int) -> list:
     if name in ("ns_predict", "ns_pressure_rhs", "ns_correct"):
         return [f"k_{name}<{t}>"]
     if name == "ghost_dphi":
-        return [f"k_ghost_dphi<{t}>"]
+        return [f"k_point_phit<{t}>", f"k_ghost_dg<{t}>", f"k_patch_dq<{t}>"]
     if name == "ghost_fill_C":
         return [f"k_fill_static<{t}>"]
     if name == "ghost_fill_u":

@@ -68,6 +68,10 @@ struct PatchList {
   std::vector<int> cell;   // [NP]
   std::vector<int> ref;    // [2d+1][NP]
   std::vector<int> row;    // [rows+1]
+  // cells where dg needs phi~ (every ghost's averaging points and the ghost itself), sorted, and
+  // for every slot of every ghost (ghost-major, kGhostSlots per ghost; slot 2K the ghost) its index
+  std::vector<int> pt_cell;   // [NU]
+  std::vector<int> pt_idx;    // [G][kGhostSlots]
 };
 
 PatchList build_patch(const ch_ib_geometry &g) {
@@ -121,6 +125,18 @@ PatchList build_patch(const ch_ib_geometry &g) {
     while (e < NP && cells[e] / nx < r) ++e;
     pl.row[r] = (int)e;
   }
+  const int KK = 2 * g.n_ap;
+  std::vector<int64_t> pts(g.ap.begin(), g.ap.end());
+  pts.insert(pts.end(), g.gidx.begin(), g.gidx.end());
+  std::sort(pts.begin(), pts.end());
+  pts.erase(std::unique(pts.begin(), pts.end()), pts.end());
+  pl.pt_cell.assign(pts.begin(), pts.end());
+  pl.pt_idx.assign((size_t)G * chib::kGhostSlots, 0);
+  auto pt_of = [&](int64_t c) { return (int)(std::lower_bound(pts.begin(), pts.end(), c) - pts.begin()); };
+  for (int64_t gi = 0; gi < G; ++gi) {
+    for (int k = 0; k < KK; ++k) pl.pt_idx[(size_t)gi * chib::kGhostSlots + k] = pt_of(g.ap[(size_t)k * G + gi]);
+    pl.pt_idx[(size_t)gi * chib::kGhostSlots + KK] = pt_of(g.gidx[gi]);
+  }
   return pl;
 }
 
@@ -135,14 +151,15 @@ struct Layout {
 
 struct Offsets {
   size_t C[2], F[3], W, R, alpha, gidx, normal, dn, gamma, ap, w, apg, wg, CGn, CGnm1, CMs, CI, CGnew, UG;
-  size_t dg, pl_cell, pl_ref, pl_row, pl_dq;
+  size_t dg, pl_cell, pl_ref, pl_row, pl_dq, pt_cell, pt_idx, pt_phi;
   size_t Us[3], Ut[3], Nh[3], Af[3], P[2];
   size_t f_cell, f_axis, f_gL, f_gR, stashL, stashR;
   size_t twr[3], twi[3], dctc, dcts, lam[3], partial, red_out;
   size_t total;
 };
 
-Offsets plan_layout(const ch_ib_geometry &g, int es, int64_t NF, int64_t NP, bool explicit_ab2, bool ns) {
+Offsets plan_layout(const ch_ib_geometry &g, int es, int64_t NF, const PatchList &pl, bool explicit_ab2, bool ns) {
+  const int64_t NP = (int64_t)pl.cell.size(), NU = (int64_t)pl.pt_cell.size();
   Layout L;
   Offsets o{};
   const int64_t N = g.cells, G = g.n_ghost;
@@ -181,6 +198,9 @@ Offsets plan_layout(const ch_ib_geometry &g, int es, int64_t NF, int64_t NP, boo
   o.pl_ref = L.off((2 * d + 1) * NP * 4);
   o.pl_row = L.off((N / g.n[0] + 1) * 4);
   o.pl_dq = L.off(NP * es);
+  o.pt_cell = L.off(NU * 4);
+  o.pt_idx = L.off((int64_t)pl.pt_idx.size() * 4);
+  o.pt_phi = L.off(NU * es);
   o.f_cell = L.off(NF * 4);
   o.f_axis = L.off(NF * 4);
   o.f_gL = L.off(NF * 4);
@@ -286,7 +306,7 @@ extern "C" size_t ch_ib_workspace_bytes(const ch_ib_grid *grid, const ch_ib_geom
   const int es = params->precision == 64 ? 8 : 4;
   FaceList fl = build_faces(*geom);
   PatchList pl = build_patch(*geom);
-  return plan_layout(*geom, es, (int64_t)fl.cell.size(), (int64_t)pl.cell.size(),
+  return plan_layout(*geom, es, (int64_t)fl.cell.size(), pl,
                      (params->flags & CH_IB_FLAG_EXPLICIT) != 0, (params->flags & CH_IB_FLAG_NAVIER_STOKES) != 0)
              .total +
          256;
@@ -323,7 +343,7 @@ extern "C" int ch_ib_state_create(const ch_ib_grid *grid, const ch_ib_geometry *
   PatchList pl = build_patch(*geom);
   const int64_t NP = (int64_t)pl.cell.size();
   const bool ns = (params->flags & CH_IB_FLAG_NAVIER_STOKES) != 0;
-  st->off = plan_layout(*geom, st->es, NF, NP, (params->flags & CH_IB_FLAG_EXPLICIT) != 0, ns);
+  st->off = plan_layout(*geom, st->es, NF, pl, (params->flags & CH_IB_FLAG_EXPLICIT) != 0, ns);
   const Offsets &o = st->off;
   chib::Plan &p = st->plan;
   const int d = geom->ndim;
@@ -396,6 +416,10 @@ extern "C" int ch_ib_state_create(const ch_ib_grid *grid, const ch_ib_geometry *
   p.pl_ref = (const int *)(W0 + o.pl_ref);
   p.pl_row = (const int *)(W0 + o.pl_row);
   p.pl_dq = W0 + o.pl_dq;
+  p.NU = (int64_t)pl.pt_cell.size();
+  p.pt_cell = (const int *)(W0 + o.pt_cell);
+  p.pt_idx = (const int *)(W0 + o.pt_idx);
+  p.pt_phi = W0 + o.pt_phi;
   p.NF = NF;
   p.f_cell = (const int *)(W0 + o.f_cell);
   p.f_axis = (const int *)(W0 + o.f_axis);
@@ -485,6 +509,11 @@ extern "C" int ch_ib_state_create(const ch_ib_grid *grid, const ch_ib_geometry *
       e = hipMemcpyAsync((void *)p.pl_ref, pl.ref.data(), pl.ref.size() * 4, hipMemcpyHostToDevice, s);
     if (e == hipSuccess)
       e = hipMemcpyAsync((void *)p.pl_row, pl.row.data(), pl.row.size() * 4, hipMemcpyHostToDevice, s);
+  }
+  if (p.NU && e == hipSuccess) {
+    e = hipMemcpyAsync((void *)p.pt_cell, pl.pt_cell.data(), pl.pt_cell.size() * 4, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync((void *)p.pt_idx, pl.pt_idx.data(), pl.pt_idx.size() * 4, hipMemcpyHostToDevice, s);
   }
   if (NF && e == hipSuccess) {
     e = hipMemcpyAsync((void *)p.f_cell, fl.cell.data(), NF * 4, hipMemcpyHostToDevice, s);

@@ -55,6 +55,12 @@ struct Plan {
   // the kernels that give each ghost a lane group: one wave request then covers a few cache lines
   const int *apg = nullptr;        // [G][kGhostSlots]
   const void *wg = nullptr;        // [G][kGhostSlots]
+  // the cells where dg needs phi~ (averaging points and ghosts, sorted), each slot's index into
+  // them, and phi~ there
+  int64_t NU = 0;
+  const int *pt_cell = nullptr;    // [NU]
+  const int *pt_idx = nullptr;     // [G][kGhostSlots]
+  void *pt_phi = nullptr;          // [NU]
   void *CGn = nullptr, *CGnm1 = nullptr, *CMs = nullptr, *CI = nullptr, *CGnew = nullptr;
   void *UG = nullptr;              // [d][G]
 

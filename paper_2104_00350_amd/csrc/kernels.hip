@@ -1354,6 +1354,34 @@ __device__ __forceinline__ void ghost_dphi_body(const T *__restrict__ Cn, const 
   if (g < G && sl == 0) dg[g] = sum * inv_cn2;
 }
 
+// The same dg from phi~ evaluated once per listed point (many ghosts share averaging points):
+// k_point_phit takes one point per thread (the list is sorted by cell, so neighbouring threads read
+// neighbouring cells), k_ghost_dg gathers those values per ghost.  Each product and the lane sum are
+// those of ghost_dphi_body, in the same order, so both give the same bits.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_point_phit(const T *__restrict__ Cn, const T *__restrict__ Cp,
+                                                         const int *__restrict__ pt_cell, T *__restrict__ pt_phi,
+                                                         int64_t nu, Dims dm, int d, T cn2, T inv_h2) {
+  const int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (u < nu) pt_phi[u] = phit_at(Cn, Cp, (int64_t)pt_cell[u], dm, d, cn2, inv_h2);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_ghost_dg(const T *__restrict__ pt_phi, const int *__restrict__ pt_idx,
+                                                       const T *__restrict__ w, T *__restrict__ dg, int64_t G, int K,
+                                                       T inv_cn2) {
+  const int64_t g = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 4;
+  const int sl = threadIdx.x & 15;
+  T v = T(0);
+  if (g < G && sl <= 2 * K) {
+    const int64_t i = g * kGhostSlots + sl;
+    const T coef = sl < 2 * K ? (sl < K ? T(2) : T(-1)) * w[i] : T(-1);
+    v = coef * pt_phi[pt_idx[i]];
+  }
+  const T sum = group16_sum(v);
+  if (g < G && sl == 0) dg[g] = sum * inv_cn2;
+}
+
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_ghost_dphi(const T *__restrict__ Cn, const T *__restrict__ Cp,
                                                          const int *__restrict__ gidx, const int *__restrict__ ap,
@@ -2044,9 +2072,16 @@ template <typename T>
 hipError_t launch_ghost_patch(const Plan &p, const T *Cn, const T *Cp) {
   if (p.G == 0 || p.NP == 0 || !p.dg) return hipSuccess;
   const Dims dm = make_dims(p);
-  hipLaunchKernelGGL((k_ghost_dphi<T>), dim3(blocks_for(p.G * 16)), dim3(kThreads), 0, p.stream, Cn, Cp, p.gidx,
-                     p.apg, (const T *)p.wg, (T *)p.dg, p.G, p.K, dm, p.d, (T)(p.Cn * p.Cn), (T)(1.0 / (p.h * p.h)),
-                     (T)(1.0 / (p.Cn * p.Cn)));
+  if (p.NU && p.pt_phi) {
+    hipLaunchKernelGGL((k_point_phit<T>), dim3(blocks_for(p.NU)), dim3(kThreads), 0, p.stream, Cn, Cp, p.pt_cell,
+                       (T *)p.pt_phi, p.NU, dm, p.d, (T)(p.Cn * p.Cn), (T)(1.0 / (p.h * p.h)));
+    hipLaunchKernelGGL((k_ghost_dg<T>), dim3(blocks_for(p.G * 16)), dim3(kThreads), 0, p.stream,
+                       (const T *)p.pt_phi, p.pt_idx, (const T *)p.wg, (T *)p.dg, p.G, p.K, (T)(1.0 / (p.Cn * p.Cn)));
+  } else {
+    hipLaunchKernelGGL((k_ghost_dphi<T>), dim3(blocks_for(p.G * 16)), dim3(kThreads), 0, p.stream, Cn, Cp, p.gidx,
+                       p.apg, (const T *)p.wg, (T *)p.dg, p.G, p.K, dm, p.d, (T)(p.Cn * p.Cn), (T)(1.0 / (p.h * p.h)),
+                       (T)(1.0 / (p.Cn * p.Cn)));
+  }
   hipLaunchKernelGGL((k_patch_dq<T>), dim3(blocks_for(p.NP)), dim3(kThreads), 0, p.stream, p.pl_ref,
                      (const T *)p.dg, (T *)p.pl_dq, p.NP, 2 * p.d + 1, (T)(2 * p.d), (T)(1.0 / (p.h * p.h)));
   return hipGetLastError();
