@@ -375,6 +375,25 @@ def test_tuned_shapes_keep_parity(chib):
         st.set_shapes([[2, 4, 1]] * 4)
 
 
+def test_radix_4_outside_the_z_march_takes_radix_8(chib):
+    """Pass-0 radix 4 exists for the z-marching kernel only; the 2D rhs kernels (line-tiled and
+    y-marching) take radix 8 for it, bit for bit."""
+    case = W.small_case(128, 64, kind="sin", theta_deg=70.0)
+    faces = _random_faces(case.grid, 4, 0.3)
+    st, _, _ = _pair(chib, case, faces)
+    st.step(0)
+    blob = st.save()
+    for unroll in (1, 2, 3):
+        out = []
+        for radix in (4, 8):
+            st.load(blob)
+            st.set_shapes([[2, radix, unroll], [3, 8, 1], [3, 8, 1], [3, 8, 1]])
+            assert st.shapes()[0] == [2, radix, unroll]
+            st.step(5)
+            out.append(st.get(chib.FIELD_C))
+        assert np.array_equal(out[0], out[1]), unroll
+
+
 @pytest.mark.parametrize("n", [(256, 16, 32), (512, 8, 32)])
 def test_z_marching_rhs_variants(chib, n):
     """Every shape of the z-marching rhs kernel (3D, nx = 256 and 512: one and two columns per
