@@ -143,22 +143,14 @@ def evaluate(net: "chib.Net", make_case, angles: Sequence[float], interval: int,
             g = cases[0].grid
             dist, nrm = chib.wall_field(g.n, g.lo, g.hi, cases[0].shapes)
             net.bind(states[0], dist, nrm, BAND_CELLS)
-        # batches hold states without the momentum step: those advance one after another
-        batch = chib.Batch(states) if not cases[0].params.navier_stokes else None
+        # (members with the momentum step are advanced in turn by the batch, with their own launches)
+        batch = chib.Batch(states)
 
         def advance(k):
-            if batch is not None:
-                batch.step(k)
-            else:
-                for st in states:
-                    st.step(k)
+            batch.step(k)
 
         def wait():
-            if batch is not None:
-                batch.sync()
-            else:
-                for st in states:
-                    st.sync()
+            batch.sync()
         done, wall = 0, 0.0
         meas = [[] for _ in angles]
         meas_loc = [[] for _ in angles]
@@ -194,8 +186,7 @@ def evaluate(net: "chib.Net", make_case, angles: Sequence[float], interval: int,
             if learned:
                 recs[a][kind]["fallback_to_fine"] = fallback[a]
         log(f"[learned] {kind}: {len(angles)} cases x {done} steps in {wall:.2f} s")
-        if batch is not None:
-            batch.close()
+        batch.close()
         for st in states:
             st.close()
         for r in recs:

@@ -280,7 +280,7 @@ def test_restriction_of_a_momentum_state(chib):
 
 def test_study_driver_with_the_momentum_step(chib):
     """The learned correction binds to states that run the momentum step, and the scoring driver
-    advances such states one by one (batches hold frozen-flow states only)."""
+    advances such states in a batch (which steps them with their own launches)."""
     from paper_2104_00350_amd import learned as LR
     coarse = W.config5_flow(False)
     net = chib.Net(coarse.grid.cells, coarse.grid.cells // 256, 1, 1, 0.1, torch.cuda.current_stream())
