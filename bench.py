@@ -70,10 +70,20 @@ def algorithmic_bytes(name: str, cells: int, d: int, es: int, G: int, NF: int, d
     return 0.0
 
 
-def kernel_template(name: str, shapes, es: int, nx: int) -> list:
-    """Device kernel instantiation(s) behind a step kernel name, for the launch shapes in use."""
+def kernel_template(name: str, shapes, es: int, n) -> list:
+    """Device kernel instantiation(s) behind a step kernel name, for the launch shapes in use on a
+    grid of n cells per axis."""
     t = "double" if es == 8 else "float"
     E = 32768 // es
+    nx = n[0]
+    lines = n[1] * (n[2] if len(n) == 3 else 1)
+
+    def clamp(v, hi):
+        return 1 if v < 1 else min(v, hi)
+
+    def log2(v):
+        return v.bit_length() - 1
+
     if name == "rhs_xdht":
         lt, r, u = shapes[0]
         if u >= 3 and nx in (256, 512):
@@ -83,14 +93,22 @@ def kernel_template(name: str, shapes, es: int, nx: int) -> list:
     if name == "rhs_stencil":
         lt = shapes[0][0]
         return [f"k_rhs_xdht_zm<{t}, {2 ** min(max(lt, 1), 3 if nx == 256 else 2)}, {nx // 256}, 8, true>"]
-    if name == "xdht_fwd":
-        return [f"k_xdht<{t}, {E}, {shapes[3][1]}>"]
+    if name in ("xdht_fwd", "xdht_out"):
+        lt, r, _ = shapes[3]
+        logL = clamp(lt, log2(max(min(E // nx, lines), 2)))
+        fixed = (8, 3) if (r == 8 and nx == 256 and logL == 3) else (0, 0)
+        return [f"k_xdht<{t}, {E}, {r if r == 8 else 16}, {fixed[0]}, {fixed[1]}>"]
     if name in ("ydht_fwd", "ydht_inv"):
-        return [f"k_strided_dht<{t}, {E}, {shapes[1][1]}>"]
+        lt, r, _ = shapes[1]
+        lb = clamp(lt, log2(max(min(E // n[1], nx), 2)))
+        fixed = (8, 3) if (r == 8 and n[1] == 256 and lb == 3 and nx * 256 * es < 2 ** 32) else (0, 0)
+        return [f"k_strided_dht<{t}, {E}, {r if r == 8 else 16}, {fixed[0]}, {fixed[1]}>"]
     if name == "neumann_solve":
-        return [f"k_neumann_solve<{t}, {E}, {shapes[2][1]}>"]
-    if name == "xdht_out":
-        return [f"k_xdht<{t}, {E}, {shapes[3][1]}>"]
+        lt, r, _ = shapes[2]
+        lb = clamp(lt, log2(max(min(E // n[-1], nx), 2)))
+        stride = nx * (n[1] if len(n) == 3 else 1)
+        fixed = (8, log2(E // 256)) if (r != 8 and n[-1] == 256 and (256 << lb) == E and stride * 256 * es < 2 ** 32) else (0, 0)
+        return [f"k_neumann_solve<{t}, {E}, {r if r == 8 else 16}, {fixed[0]}, {fixed[1]}>"]
     if name in ("ns_predict", "ns_pressure_rhs", "ns_correct"):
         return [f"k_{name}<{t}>"]
     if name == "ghost_dphi":
@@ -115,7 +133,7 @@ def code_digest(path: str) -> str:
     return hashlib.sha256("".join(src.split()).encode()).hexdigest()
 
 
-def measured_traffic(name: str, shapes, es: int, nx: int):
+def measured_traffic(name: str, shapes, es: int, n):
     """HBM bytes per launch from the committed counter summary, or None when the kernel source has
     changed since the counters were taken (or the kernel was not profiled)."""
     path = os.path.join(ROOT, "profiles", "hbm_traffic_sphere256_fp64.json")
@@ -129,7 +147,7 @@ def measured_traffic(name: str, shapes, es: int, nx: int):
     by_shape = rec.get("k_rhs_xdht_zm_by_pass0_shape") or {}
     key = ",".join(str(v) for v in shapes[0])
     total = 0
-    for k in kernel_template(name, shapes, es, nx):
+    for k in kernel_template(name, shapes, es, n):
         if k.startswith("k_rhs_xdht_zm"):
             # its z-chunk (a runtime launch argument) changes the halo re-reads: take the counters of
             # the same launch shape, or none
@@ -574,7 +592,7 @@ def main() -> int:
                    "launch_shapes": shapes},
         "roofline": {"bound": "hbm", "kernel": dominant, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": measured_traffic(dominant, shapes, es, g.n[0]),
+                     "traffic": measured_traffic(dominant, shapes, es, tuple(g.n)),
                      "alg_bytes_per_launch": dom["alg_bytes"]},
         "ms_per_step_hip_events": round(event_ms / args.steps, 5),
         "kernel_ms_per_step_sum": round(gpu_ms, 5),

@@ -654,7 +654,7 @@ __global__ __launch_bounds__(kThreads, (L == 2 && XM == 1 && R == 4) ? 3 : 1) vo
                                                           RhsCoef<T> cf, int zc_log, const T *__restrict__ twr,
                                                           const T *__restrict__ twi, RhsPatch<T> rp) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  const int nx = dm.nx;
+  constexpr int nx = 256 * XM, lnx = ilog2c(nx);   // the launcher takes this kernel only for nx = 256 XM
   T *plane = reinterpret_cast<T *>(smem_raw);        // L rows x nx: C~ of plane z
   T *fxp = plane + L * nx;                             // L rows x nx: x faces of plane z
   const int pitch = line_pitch(nx);
@@ -874,19 +874,19 @@ __global__ __launch_bounds__(kThreads, (L == 2 && XM == 1 && R == 4) ? 3 : 1) vo
 #pragma unroll
       for (int k = 0; k < PF; ++k)
         if (e_lo + tid + 256 * k < e_hi) {
-          const int l = (int)((pc[k] >> dm.lnx) - line0);
+          const int l = (int)((pc[k] >> lnx) - line0);
           const int i = pc[k] & (nx - 1);
           fb[l * pitch + i + (i >> 4)] += pd[k];
         }
-      if (e_hi - e_lo > PF * 256) patch_tile(fb, rp, line0, dm.lnx, pitch, e_lo + PF * 256, e_hi);
+      if (e_hi - e_lo > PF * 256) patch_tile(fb, rp, line0, lnx, pitch, e_lo + PF * 256, e_hi);
       __syncthreads();
     }
-    lds_fft<T, L * 256 * XM, false, R>(fb, dm.lnx, ilog2c(L) - 1, 2 * pitch, 1, pitch, 1, false, tw, tw + nx);
+    lds_fft<T, L * 256 * XM, false, R>(fb, lnx, ilog2c(L) - 1, 2 * pitch, 1, pitch, 1, false, tw, tw + nx);
     // (the FFT's final barrier also protects the LDS plane buffers for the next plane's writes)
     if (more) rotate();
     const int half = (L * nx) >> 1;
     for (int e = tid; e < half; e += blockDim.x) {
-      const int b = e >> dm.lnx;
+      const int b = e >> lnx;
       const int kx = e & (nx - 1);
       const int kk = (nx - kx) & (nx - 1);
       const T *pb = fb + b * 2 * pitch;
@@ -902,9 +902,11 @@ __global__ __launch_bounds__(kThreads, (L == 2 && XM == 1 && R == 4) ? 3 : 1) vo
 
 // K5 (and the forward x pass of the SOLVE stage): Hartley transform of L consecutive
 // contiguous lines of length nx from `in` to `out`.
-template <typename T, int E, int MAXR = 16>
+template <typename T, int E, int MAXR = 16, int CLN = 0, int CLB = 0>
 __device__ __forceinline__ void xdht_body(unsigned char *smem_raw, const T *__restrict__ in, T *__restrict__ out, int lnx,
                                                    int logL, const T *__restrict__ twr, const T *__restrict__ twi, int tile) {
+  if constexpr (CLN != 0) lnx = CLN;   // compile-time line length and tile height (see neumann_body)
+  if constexpr (CLB != 0) logL = CLB;
   T *s = reinterpret_cast<T *>(smem_raw);
   const int L = 1 << logL;
   const int nx = 1 << lnx;
@@ -913,10 +915,30 @@ __device__ __forceinline__ void xdht_body(unsigned char *smem_raw, const T *__re
   const int pitch = line_pitch(nx);
   const T *src = in + (int64_t)line0 * nx;
   // (streaming reads: the input is not read again by this pass or the next one)
-  stage_tile(s, tot, [&](int e) { return __builtin_nontemporal_load(src + e); }, [&](int e) {
-    const int l = e >> lnx, i = e & (nx - 1);
-    return l * pitch + i + (i >> 4);
-  });
+  constexpr int CP = 16 / (int)sizeof(T);
+  typedef T FV __attribute__((ext_vector_type(CP)));
+  if constexpr (CLN != 0 && CLB != 0) {
+    // fixed size: 16 bytes per thread and every RS-th line, so that offsets step by constants
+    constexpr int RS = (CP * kThreads) >> CLN, KR = (1 << CLB) / RS;
+    static_assert(RS >= 1 && KR * RS == (1 << CLB), "fixed-size tile");
+    const int i = (threadIdx.x & ((1 << CLN) / CP - 1)) * CP, l0 = threadIdx.x / ((1 << CLN) / CP);
+    FV v[KR];
+#pragma unroll
+    for (int k = 0; k < KR; ++k)
+      v[k] = __builtin_nontemporal_load(reinterpret_cast<const FV *>(src + (l0 + k * RS) * (1 << CLN) + i));
+#pragma unroll
+    for (int k = 0; k < KR; ++k) {
+      T *d = s + (l0 + k * RS) * pitch + i + (i >> 4);   // CP elements of one padding group
+      const T *e = reinterpret_cast<const T *>(&v[k]);
+#pragma unroll
+      for (int c = 0; c < CP; ++c) d[c] = e[c];
+    }
+  } else {
+    stage_tile(s, tot, [&](int e) { return __builtin_nontemporal_load(src + e); }, [&](int e) {
+      const int l = e >> lnx, i = e & (nx - 1);
+      return l * pitch + i + (i >> 4);
+    });
+  }
   __syncthreads();
   lds_fft<T, E, false, MAXR>(s, lnx, logL - 1, 2 * pitch, 1, pitch, 1, false, twr, twi);
   T *dst = out + (int64_t)line0 * nx;
@@ -934,11 +956,11 @@ __device__ __forceinline__ void xdht_body(unsigned char *smem_raw, const T *__re
   }
 }
 
-template <typename T, int E, int MAXR = 16>
+template <typename T, int E, int MAXR = 16, int CLN = 0, int CLB = 0>
 __global__ __launch_bounds__(kThreads) void k_xdht(const T *__restrict__ in, T *__restrict__ out, int lnx,
                                                    int logL, const T *__restrict__ twr, const T *__restrict__ twi) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  xdht_body<T, E, MAXR>(smem_raw, in, out, lnx, logL, twr, twi, xcd_tile(blockIdx.x, gridDim.x));
+  xdht_body<T, E, MAXR, CLN, CLB>(smem_raw, in, out, lnx, logL, twr, twi, xcd_tile(blockIdx.x, gridDim.x));
 }
 
 template <typename T> struct Vec2;
@@ -949,10 +971,12 @@ template <> struct Vec2<float> { using type = float2; };
 // B = 2^logB adjacent x-columns (contiguous in memory) times N positions; tile t covers
 // base = (t >> lognxb) * outer + (t & (nxb-1)) * B, element n at base + n*stride.  Columns
 // 2b and 2b+1 form the pair b (real and imaginary parts of one complex line).
-template <typename T, int E, int MAXR = 16>
+template <typename T, int E, int MAXR = 16, int CLN = 0, int CLB = 0>
 __global__ __launch_bounds__(kThreads) void k_strided_dht(T *__restrict__ W, int logN, int64_t stride, int logB,
                                                           int lognxb, int64_t outer, const T *__restrict__ twr,
                                                           const T *__restrict__ twi) {
+  if constexpr (CLN != 0) logN = CLN;   // compile-time line length and tile width (see neumann_body)
+  if constexpr (CLB != 0) logB = CLB;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T *s = reinterpret_cast<T *>(smem_raw);
   using V2 = typename Vec2<T>::type;
@@ -960,14 +984,54 @@ __global__ __launch_bounds__(kThreads) void k_strided_dht(T *__restrict__ W, int
   const int t = xcd_tile(blockIdx.x, gridDim.x);
   const int64_t base = (int64_t)(t >> lognxb) * outer + (int64_t)(t & ((1 << lognxb) - 1)) * B;
   const int tot = N << logB;
-  stage_tile(s, tot, [&](int e) { return W[base + (e >> logB) * stride + (e & (B - 1))]; }, [&](int e) {
-    const int n = e >> logB, col = e & (B - 1);
-    return n * B + (n >> 4) * 2 + col;
-  });
+  // fixed size (as in neumann_body): 16 bytes of adjacent columns per thread, every RS-th position,
+  // unsigned 32-bit byte offsets from a uniform base (the caller bounds N * stride * sizeof(T))
+  using FV = std::conditional_t<sizeof(T) == 8, double2, float4>;
+  constexpr int CP = 16 / (int)sizeof(T);
+  constexpr int RS = CLB ? (CP * kThreads) >> CLB : 16, KR = CLN ? (1 << CLN) / RS : 1;
+  char *const gb = reinterpret_cast<char *>(W + base);
+  if constexpr (CLN != 0 && CLB != 0) {
+    static_assert(RS % 16 == 0 && KR * RS == (1 << CLN), "fixed-size tile");
+    const int fcol = (threadIdx.x & ((B / CP) - 1)) * CP, fn0 = threadIdx.x / (B / CP);
+    const unsigned foff = ((unsigned)fn0 * (unsigned)stride + (unsigned)fcol) * (unsigned)sizeof(T);
+    const unsigned fstep = (unsigned)RS * (unsigned)stride * (unsigned)sizeof(T);
+    const int fa0 = fn0 * B + (fn0 >> 4) * 2 + fcol, fda = RS * B + (RS >> 4) * 2;
+    FV v[KR];
+#pragma unroll
+    for (int k = 0; k < KR; ++k) v[k] = *reinterpret_cast<const FV *>(gb + (foff + k * fstep));
+#pragma unroll
+    for (int k = 0; k < KR; ++k) *reinterpret_cast<FV *>(s + fa0 + k * fda) = v[k];
+  } else {
+    stage_tile(s, tot, [&](int e) { return W[base + (e >> logB) * stride + (e & (B - 1))]; }, [&](int e) {
+      const int n = e >> logB, col = e & (B - 1);
+      return n * B + (n >> 4) * 2 + col;
+    });
+  }
   __syncthreads();
   lds_fft<T, E, false, MAXR, 256, true>(s, logN, logB - 1, 2, B, 1, 2, true, twr, twi);
   const int lp = logB - 1;
   const int half = tot >> 1;
+  if constexpr (CLN != 0 && CLB != 0) {
+    // one column pair per thread, every RO-th position; the offset is made opaque so that the
+    // compiler forms these addresses here rather than holding them from the staging loads
+    constexpr int RO = (2 * kThreads) >> CLB, KO = (1 << CLN) / RO;
+    const int b = threadIdx.x & ((B >> 1) - 1), n0 = threadIdx.x >> (logB - 1);
+    unsigned ooff = ((unsigned)n0 * (unsigned)stride + 2u * b) * (unsigned)sizeof(T);
+    const unsigned ostep = (unsigned)RO * (unsigned)stride * (unsigned)sizeof(T);
+    asm volatile("" : "+v"(ooff));
+#pragma unroll
+    for (int j = 0; j < KO; ++j) {
+      const int n = n0 + j * RO;
+      const int nn = (N - n) & (N - 1);
+      const V2 u0 = *reinterpret_cast<const V2 *>(s + n * B + (n >> 4) * 2 + 2 * b);
+      const V2 u1 = *reinterpret_cast<const V2 *>(s + nn * B + (nn >> 4) * 2 + 2 * b);
+      V2 v;
+      v.x = (u0.x - u0.y + u1.x + u1.y) * T(0.5);
+      v.y = (u0.x + u0.y - u1.x + u1.y) * T(0.5);
+      *reinterpret_cast<V2 *>(gb + (ooff + j * ostep)) = v;
+    }
+    return;
+  }
   for (int e = threadIdx.x; e < half; e += blockDim.x) {
     const int b = e & ((1 << lp) - 1), n = e >> lp;
     const int nn = (N - n) & (N - 1);
@@ -985,13 +1049,17 @@ __global__ __launch_bounds__(kThreads) void k_strided_dht(T *__restrict__ W, int
 // K3: along the bounded axis, per column: DCT-II (even/odd reorder + FFT + post-twiddle),
 // division by (lam - a)(lam + alpha_s) times the inverse normalisation, inverse DCT-II
 // (pre-twiddle + inverse FFT + reorder).  lam = lamx[kx] (+ lamy[ky]) + lamz[kz].
-template <typename T, int E, int MAXR = 16>
+template <typename T, int E, int MAXR = 16, int CLN = 0, int CLB = 0>
 __device__ __forceinline__ void neumann_body(unsigned char *smem_raw, T *__restrict__ W, int logN, int64_t stride, int logB,
                                                             int lognxb, int64_t outer, const T *__restrict__ lamx,
                                                             const T *__restrict__ lamy, const T *__restrict__ lamz,
                                                             T a, T alpha_s, T inv_norm, const T *__restrict__ twr,
                                                             const T *__restrict__ twi, const T *__restrict__ dctc,
                                                             const T *__restrict__ dcts, int tile, int poisson) {
+  // CLN/CLB != 0 fix the line length and the tile width at compile time, so that the FFT's
+  // LDS addresses fold into instruction offsets
+  if constexpr (CLN != 0) logN = CLN;
+  if constexpr (CLB != 0) logB = CLB;
   T *s = reinterpret_cast<T *>(smem_raw);
   const int N = 1 << logN, B = 1 << logB;
   const int t = tile;
@@ -999,17 +1067,41 @@ __device__ __forceinline__ void neumann_body(unsigned char *smem_raw, T *__restr
   const int oy = t >> lognxb;
   const int64_t base = (int64_t)oy * outer + (int64_t)xb * B;
   const int tot = N << logB;
-  stage_tile(s, tot, [&](int e) { return W[base + (e >> logB) * stride + (e & (B - 1))]; }, [&](int e) {
-    const int n = e >> logB, col = e & (B - 1);
-    const int pos = (n & 1) ? (N - 1 - (n >> 1)) : (n >> 1);
-    return pos * B + (pos >> 4) * 2 + col;
-  });
+  // fixed size: a thread keeps 16 bytes of adjacent columns and every (CP kThreads / B)-th
+  // position, so its global offsets step by a constant (unsigned 32-bit bytes from a uniform base:
+  // the caller bounds N * stride * sizeof(T)) and, the step being even, all its positions share one parity and
+  // land on reordered slots a constant LDS distance apart (16 positions, one padding group)
+  using FV = std::conditional_t<sizeof(T) == 8, double2, float4>;
+  constexpr int CP = 16 / (int)sizeof(T);
+  constexpr int RS = CLB ? (CP * kThreads) >> CLB : 2, KR = CLN ? (1 << CLN) / RS : 1;
+  const int fcol = (threadIdx.x & ((B / CP) - 1)) * CP, fn0 = threadIdx.x / (B / CP);
+  const int fp0 = (fn0 & 1) ? N - 1 - (fn0 >> 1) : fn0 >> 1;
+  const int fa0 = fp0 * B + (fp0 >> 4) * 2 + fcol;
+  const int fda = (fn0 & 1) ? -((RS / 2) * B + 2) : (RS / 2) * B + 2;
+  unsigned foff = ((unsigned)fn0 * (unsigned)stride + (unsigned)fcol) * (unsigned)sizeof(T);   // bytes
+  const unsigned fstep = (unsigned)RS * (unsigned)stride * (unsigned)sizeof(T);
+  char *const gb = reinterpret_cast<char *>(W + base);
+  if constexpr (CLN != 0 && CLB != 0) {
+    static_assert(RS == 32 && KR * RS == (1 << CLN), "fixed-size tile");
+    FV v[KR];
+#pragma unroll
+    for (int k = 0; k < KR; ++k) v[k] = *reinterpret_cast<const FV *>(gb + (foff + k * fstep));
+#pragma unroll
+    for (int k = 0; k < KR; ++k) *reinterpret_cast<FV *>(s + fa0 + k * fda) = v[k];
+  } else {
+    stage_tile(s, tot, [&](int e) { return W[base + (e >> logB) * stride + (e & (B - 1))]; }, [&](int e) {
+      const int n = e >> logB, col = e & (B - 1);
+      const int pos = (n & 1) ? (N - 1 - (n >> 1)) : (n >> 1);
+      return pos * B + (pos >> 4) * 2 + col;
+    });
+  }
   __syncthreads();
   lds_fft<T, E, false, MAXR, 256, true>(s, logN, logB - 1, 2, B, 1, 2, true, twr, twi);
   const int half = N >> 1;
   const int lpairs = logB - 1;   // B / 2 column pairs per position
   const int items = (half + 1) << lpairs;
   const T lam_y = lamy ? lamy[oy] : T(0);
+  const T hnorm = inv_norm * T(0.5);
   // the pressure (POIS) divides by lam itself and drops the mean mode (lam = 0); the order
   // parameter divides by (lam - a)(lam + alpha_s), which is never zero, so the four divisors of
   // an item share divisions: 1/d1 = d2 / (d1 d2) and so on, in FP64 even 1/(d1 d2) = d3 d4 / (d1 d2 d3 d4)
@@ -1024,18 +1116,20 @@ __device__ __forceinline__ void neumann_body(unsigned char *smem_raw, T *__restr
       T *zn = s + kk * B + (kk >> 4) * 2 + 2 * b;
       const V2 uk = *reinterpret_cast<const V2 *>(zk), un = *reinterpret_cast<const V2 *>(zn);
       const T p = uk.x, q = uk.y, r = un.x, sv = un.y;
-      const T var = (p + r) * T(0.5), vai = (q - sv) * T(0.5);
-      const T vbr = (q + sv) * T(0.5), vbi = (r - p) * T(0.5);
+      // (the spectra of the two columns are (p + r, q - sv)/2 and (q + sv, r - p)/2; the halves,
+      // the doubling below and the final halving are exact powers of two and fold into hnorm)
+      const T var = p + r, vai = q - sv;
+      const T vbr = q + sv, vbi = r - p;
       const T c = dctc[k], sn = dcts[k];
       const int kxa = xb * B + 2 * b;
       const T la = lamx[kxa] + lam_y, lb = lamx[kxa + 1] + lam_y;
       const T lk = lamz[k];
       const T lnk = k ? lamz[N - k] : T(0);
       // cosine-transform coefficients X[k], X[N-k] of both columns
-      T xa1 = T(2) * (c * var + sn * vai), xa2 = T(2) * (sn * var - c * vai);
-      T xb1 = T(2) * (c * vbr + sn * vbi), xb2 = T(2) * (sn * vbr - c * vbi);
+      T xa1 = c * var + sn * vai, xa2 = sn * var - c * vai;
+      T xb1 = c * vbr + sn * vbi, xb2 = sn * vbr - c * vbi;
       if constexpr (POIS) {
-        auto fac = [&](T l) { return l != T(0) ? inv_norm / l : T(0); };
+        auto fac = [&](T l) { return l != T(0) ? hnorm / l : T(0); };
         xa1 *= fac(la + lk);
         xb1 *= fac(lb + lk);
         xa2 = k ? xa2 * fac(la + lnk) : T(0);
@@ -1046,12 +1140,12 @@ __device__ __forceinline__ void neumann_body(unsigned char *smem_raw, T *__restr
         const T p12 = d1 * d2, p34 = d3 * d4;
         T r12, r34;
         if constexpr (sizeof(T) == 8) {   // one division (the product of four stays far inside FP64)
-          const T rr = inv_norm / (p12 * p34);
+          const T rr = hnorm / (p12 * p34);
           r12 = rr * p34;
           r34 = rr * p12;
         } else {                          // two (in FP32 the product of four can underflow the quotient)
-          r12 = inv_norm / p12;
-          r34 = inv_norm / p34;
+          r12 = hnorm / p12;
+          r34 = hnorm / p34;
         }
         xa1 *= r12 * d2;
         xb1 *= r12 * d1;
@@ -1059,8 +1153,8 @@ __device__ __forceinline__ void neumann_body(unsigned char *smem_raw, T *__restr
         xb2 = k ? xb2 * (r34 * d3) : T(0);
       }
       // back to the reordered-sequence spectrum: V'[k] = e^{i pi k/2N} (X[k] - i X[N-k]) / 2
-      const T a1 = (c * xa1 + sn * xa2) * T(0.5), a2 = (sn * xa1 - c * xa2) * T(0.5);
-      const T b1 = (c * xb1 + sn * xb2) * T(0.5), b2 = (sn * xb1 - c * xb2) * T(0.5);
+      const T a1 = c * xa1 + sn * xa2, a2 = sn * xa1 - c * xa2;
+      const T b1 = c * xb1 + sn * xb2, b2 = sn * xb1 - c * xb2;
       V2 ok;
       ok.x = a1 - b2;
       ok.y = a2 + b1;
@@ -1077,22 +1171,33 @@ __device__ __forceinline__ void neumann_body(unsigned char *smem_raw, T *__restr
   else solve(std::false_type{});
   __syncthreads();
   lds_fft<T, E, true, MAXR, 256, true>(s, logN, logB - 1, 2, B, 1, 2, true, twr, twi);
-  for (int e = threadIdx.x; e < tot; e += blockDim.x) {
-    const int n = e >> logB, col = e & (B - 1);
-    const int pos = (n & 1) ? (N - 1 - (n >> 1)) : (n >> 1);
-    W[base + n * stride + col] = s[pos * B + (pos >> 4) * 2 + col];
+  if constexpr (CLN != 0 && CLB != 0) {
+    // (an empty asm makes the offset opaque here, so the compiler forms these addresses now
+    // instead of holding the staging loads' addresses in registers through the whole solve)
+    asm volatile("" : "+v"(foff));
+#pragma unroll
+    for (int k = 0; k < KR; ++k)
+      *reinterpret_cast<FV *>(gb + (foff + k * fstep)) = *reinterpret_cast<const FV *>(s + fa0 + k * fda);
+  } else {
+    for (int e = threadIdx.x; e < tot; e += blockDim.x) {
+      const int n = e >> logB, col = e & (B - 1);
+      const int pos = (n & 1) ? (N - 1 - (n >> 1)) : (n >> 1);
+      W[base + n * stride + col] = s[pos * B + (pos >> 4) * 2 + col];
+    }
   }
 }
 
-template <typename T, int E, int MAXR = 16>
-__global__ __launch_bounds__(kThreads) void k_neumann_solve(T *__restrict__ W, int logN, int64_t stride, int logB,
+// The fixed-size instance is held to 128 VGPRs (4 waves per SIMD, as the LDS tile allows): the
+// constant addresses free the compiler to hoist more, and at 3 waves it runs no faster.
+template <typename T, int E, int MAXR = 16, int CLN = 0, int CLB = 0>
+__global__ __launch_bounds__(kThreads, CLN ? 4 : 1) void k_neumann_solve(T *__restrict__ W, int logN, int64_t stride, int logB,
                                                             int lognxb, int64_t outer, const T *__restrict__ lamx,
                                                             const T *__restrict__ lamy, const T *__restrict__ lamz,
                                                             T a, T alpha_s, T inv_norm, const T *__restrict__ twr,
                                                             const T *__restrict__ twi, const T *__restrict__ dctc,
                                                             const T *__restrict__ dcts, int poisson) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  neumann_body<T, E, MAXR>(smem_raw, W, logN, stride, logB, lognxb, outer, lamx, lamy, lamz, a, alpha_s, inv_norm, twr, twi, dctc, dcts, xcd_tile(blockIdx.x, gridDim.x), poisson);
+  neumann_body<T, E, MAXR, CLN, CLB>(smem_raw, W, logN, stride, logB, lognxb, outer, lamx, lamy, lamz, a, alpha_s, inv_norm, twr, twi, dctc, dcts, xcd_tile(blockIdx.x, gridDim.x), poisson);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -2128,7 +2233,10 @@ hipError_t launch_xdht(const Plan &p, const T *in, T *out, const Plan::Shape &sh
   const int lines = p.d == 3 ? p.n[1] * p.n[2] : p.n[1];
   const unsigned nb = (unsigned)(lines >> logL);
   const size_t lds = (size_t)(1 << logL) * line_pitch(p.n[0]) * sizeof(T);
-  if (sh.radix == 8)
+  if (sh.radix == 8 && p.logn[0] == 8 && logL == 3)   // 256-point lines, 8 per tile
+    hipLaunchKernelGGL((k_xdht<T, E, 8, 8, 3>), dim3(nb), dim3(kThreads), lds, p.stream, in, out, p.logn[0], logL,
+                       (const T *)p.twr[0], (const T *)p.twi[0]);
+  else if (sh.radix == 8)
     hipLaunchKernelGGL((k_xdht<T, E, 8>), dim3(nb), dim3(kThreads), lds, p.stream, in, out, p.logn[0], logL,
                        (const T *)p.twr[0], (const T *)p.twi[0]);
   else
@@ -2145,7 +2253,10 @@ hipError_t launch_ydht(const Plan &p, const Plan::Shape &sh) {
   const int lxb = p.logn[0] - lb;
   const unsigned nb = (unsigned)((nx >> lb) * p.n[2]);
   const size_t lds = (size_t)col_tile(p.n[1], 1 << lb) * sizeof(T);
-  if (sh.radix == 8)
+  if (sh.radix == 8 && p.logn[1] == 8 && lb == 3 && (int64_t)nx * 256 * (int64_t)sizeof(T) < (int64_t(1) << 32))   // 256-point lines, 8 columns per tile
+    hipLaunchKernelGGL((k_strided_dht<T, E, 8, 8, 3>), dim3(nb), dim3(kThreads), lds, p.stream, (T *)p.W, p.logn[1],
+                       (int64_t)nx, lb, lxb, (int64_t)nx * p.n[1], (const T *)p.twr[1], (const T *)p.twi[1]);
+  else if (sh.radix == 8)
     hipLaunchKernelGGL((k_strided_dht<T, E, 8>), dim3(nb), dim3(kThreads), lds, p.stream, (T *)p.W, p.logn[1],
                        (int64_t)nx, lb, lxb, (int64_t)nx * p.n[1], (const T *)p.twr[1], (const T *)p.twi[1]);
   else
@@ -2170,6 +2281,11 @@ hipError_t launch_neumann(const Plan &p, const Plan::Shape &sh) {
   const T *lamy = p.d == 3 ? (const T *)p.lam[1] : (const T *)nullptr;
   if (sh.radix == 8)
     hipLaunchKernelGGL((k_neumann_solve<T, E, 8>), dim3(nb), dim3(kThreads), lds, p.stream, (T *)p.W, p.logn[ax],
+                       stride, lb, lxb, outer, (const T *)p.lam[0], lamy, (const T *)p.lam[ax], (T)p.a, (T)p.alpha_s,
+                       (T)(1.0 / norm), (const T *)p.twr[ax], (const T *)p.twi[ax], (const T *)p.dctc,
+                       (const T *)p.dcts, p.poisson);
+  else if (p.logn[ax] == 8 && (1 << lb) * 256 == E && stride * 256 * (int64_t)sizeof(T) < (int64_t(1) << 32))   // 256-point lines in a full tile
+    hipLaunchKernelGGL((k_neumann_solve<T, E, 16, 8, ilog2c(E / 256)>), dim3(nb), dim3(kThreads), lds, p.stream, (T *)p.W, p.logn[ax],
                        stride, lb, lxb, outer, (const T *)p.lam[0], lamy, (const T *)p.lam[ax], (T)p.a, (T)p.alpha_s,
                        (T)(1.0 / norm), (const T *)p.twr[ax], (const T *)p.twi[ax], (const T *)p.dctc,
                        (const T *)p.dcts, p.poisson);

@@ -22,7 +22,19 @@ def test_committed_counters_match_the_kernel_code():
     """The committed HBM counter summary was taken on the kernel code in the tree, so bench.py reports
     its traffic for the dominant kernel (in the launch shape the counters were taken with)."""
     rest = [[3, 8, 1], [4, 16, 1], [3, 8, 1]]
-    t32 = bench.measured_traffic("rhs_xdht", [[2, 4, 5]] + rest, 8, 256)
-    t16 = bench.measured_traffic("rhs_xdht", [[2, 4, 4]] + rest, 8, 256)
+    t32 = bench.measured_traffic("rhs_xdht", [[2, 4, 5]] + rest, 8, (256, 256, 256))
+    t16 = bench.measured_traffic("rhs_xdht", [[2, 4, 4]] + rest, 8, (256, 256, 256))
     assert t16 is not None and t32 is not None and t16 > t32 > 0   # thinner z-chunks re-read more halo
-    assert bench.measured_traffic("rhs_xdht", [[2, 8, 4]] + rest, 8, 256) is None
+    assert bench.measured_traffic("rhs_xdht", [[2, 8, 4]] + rest, 8, (256, 256, 256)) is None
+
+
+def test_kernel_names_match_the_committed_trace():
+    """bench.py's map from step kernels to device instantiations names kernels that the committed
+    kernel trace of the 256^3 workload (taken at the shapes in its command) actually ran."""
+    path = os.path.join(os.path.dirname(bench.__file__), "profiles", "step_sphere256_fp64_kernel_trace.md")
+    text = open(path).read()
+    shapes = [[int(v) for v in grp.split(",")] for grp in text.split('--shapes "')[1].split('"')[0].split(";")]
+    names = {line.split("|")[1].strip() for line in text.splitlines() if line.startswith("| k_")}
+    for step_kernel in ("rhs_xdht", "ydht_fwd", "neumann_solve", "ydht_inv", "xdht_out", "ghost_dphi", "ghost_fills"):
+        for k in bench.kernel_template(step_kernel, shapes, 8, (256, 256, 256)):
+            assert k in names, (step_kernel, k)
