@@ -96,18 +96,18 @@ def kernel_template(name: str, shapes, es: int, n) -> list:
     if name in ("xdht_fwd", "xdht_out"):
         lt, r, _ = shapes[3]
         logL = clamp(lt, log2(max(min(E // nx, lines), 2)))
-        fixed = (8, 3) if (r == 8 and nx == 256 and logL == 3) else (0, 0)
+        fixed = (8, logL) if (nx == 256 and logL in (3, 4)) else (0, 0)
         return [f"k_xdht<{t}, {E}, {r if r == 8 else 16}, {fixed[0]}, {fixed[1]}>"]
     if name in ("ydht_fwd", "ydht_inv"):
         lt, r, _ = shapes[1]
         lb = clamp(lt, log2(max(min(E // n[1], nx), 2)))
-        fixed = (8, 3) if (r == 8 and n[1] == 256 and lb == 3 and nx * 256 * es < 2 ** 32) else (0, 0)
+        fixed = (8, lb) if (n[1] == 256 and lb in (3, 4) and nx * 256 * es < 2 ** 32) else (0, 0)
         return [f"k_strided_dht<{t}, {E}, {r if r == 8 else 16}, {fixed[0]}, {fixed[1]}>"]
     if name == "neumann_solve":
         lt, r, _ = shapes[2]
         lb = clamp(lt, log2(max(min(E // n[-1], nx), 2)))
         stride = nx * (n[1] if len(n) == 3 else 1)
-        fixed = (8, log2(E // 256)) if (r != 8 and n[-1] == 256 and (256 << lb) == E and stride * 256 * es < 2 ** 32) else (0, 0)
+        fixed = (8, lb) if (n[-1] == 256 and (256 << lb) == E and stride * 256 * es < 2 ** 32) else (0, 0)
         return [f"k_neumann_solve<{t}, {E}, {r if r == 8 else 16}, {fixed[0]}, {fixed[1]}>"]
     if name in ("ns_predict", "ns_pressure_rhs", "ns_correct"):
         return [f"k_{name}<{t}>"]

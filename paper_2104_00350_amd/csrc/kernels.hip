@@ -2226,6 +2226,8 @@ inline int max_log_cols(const Plan &p, int N, int E) {
 
 inline int clamp_log(int v, int hi) { return v < 1 ? 1 : (v > hi ? hi : v); }
 
+// The fixed-size instances (256-point lines, template constants for the line length and tile width)
+// serve the tile widths and radices below; other shapes take the runtime-size kernels.
 template <typename T>
 hipError_t launch_xdht(const Plan &p, const T *in, T *out, const Plan::Shape &sh) {
   constexpr int E = tile_elems<T>();
@@ -2233,15 +2235,22 @@ hipError_t launch_xdht(const Plan &p, const T *in, T *out, const Plan::Shape &sh
   const int lines = p.d == 3 ? p.n[1] * p.n[2] : p.n[1];
   const unsigned nb = (unsigned)(lines >> logL);
   const size_t lds = (size_t)(1 << logL) * line_pitch(p.n[0]) * sizeof(T);
-  if (sh.radix == 8 && p.logn[0] == 8 && logL == 3)   // 256-point lines, 8 per tile
-    hipLaunchKernelGGL((k_xdht<T, E, 8, 8, 3>), dim3(nb), dim3(kThreads), lds, p.stream, in, out, p.logn[0], logL,
-                       (const T *)p.twr[0], (const T *)p.twi[0]);
-  else if (sh.radix == 8)
-    hipLaunchKernelGGL((k_xdht<T, E, 8>), dim3(nb), dim3(kThreads), lds, p.stream, in, out, p.logn[0], logL,
-                       (const T *)p.twr[0], (const T *)p.twi[0]);
-  else
-    hipLaunchKernelGGL((k_xdht<T, E, 16>), dim3(nb), dim3(kThreads), lds, p.stream, in, out, p.logn[0], logL,
-                       (const T *)p.twr[0], (const T *)p.twi[0]);
+#define CHIB_XDHT(...)                                                                                         \
+  hipLaunchKernelGGL((k_xdht<__VA_ARGS__>), dim3(nb), dim3(kThreads), lds, p.stream, in, out, p.logn[0], logL, \
+                     (const T *)p.twr[0], (const T *)p.twi[0])
+  const bool r8 = sh.radix == 8, fixed = p.logn[0] == 8;
+  if (fixed && logL == 3) {
+    if (r8) CHIB_XDHT(T, E, 8, 8, 3);
+    else CHIB_XDHT(T, E, 16, 8, 3);
+  } else if (fixed && logL == 4) {
+    if (r8) CHIB_XDHT(T, E, 8, 8, 4);
+    else CHIB_XDHT(T, E, 16, 8, 4);
+  } else if (r8) {
+    CHIB_XDHT(T, E, 8);
+  } else {
+    CHIB_XDHT(T, E, 16);
+  }
+#undef CHIB_XDHT
   return hipGetLastError();
 }
 
@@ -2253,15 +2262,23 @@ hipError_t launch_ydht(const Plan &p, const Plan::Shape &sh) {
   const int lxb = p.logn[0] - lb;
   const unsigned nb = (unsigned)((nx >> lb) * p.n[2]);
   const size_t lds = (size_t)col_tile(p.n[1], 1 << lb) * sizeof(T);
-  if (sh.radix == 8 && p.logn[1] == 8 && lb == 3 && (int64_t)nx * 256 * (int64_t)sizeof(T) < (int64_t(1) << 32))   // 256-point lines, 8 columns per tile
-    hipLaunchKernelGGL((k_strided_dht<T, E, 8, 8, 3>), dim3(nb), dim3(kThreads), lds, p.stream, (T *)p.W, p.logn[1],
-                       (int64_t)nx, lb, lxb, (int64_t)nx * p.n[1], (const T *)p.twr[1], (const T *)p.twi[1]);
-  else if (sh.radix == 8)
-    hipLaunchKernelGGL((k_strided_dht<T, E, 8>), dim3(nb), dim3(kThreads), lds, p.stream, (T *)p.W, p.logn[1],
-                       (int64_t)nx, lb, lxb, (int64_t)nx * p.n[1], (const T *)p.twr[1], (const T *)p.twi[1]);
-  else
-    hipLaunchKernelGGL((k_strided_dht<T, E, 16>), dim3(nb), dim3(kThreads), lds, p.stream, (T *)p.W, p.logn[1],
-                       (int64_t)nx, lb, lxb, (int64_t)nx * p.n[1], (const T *)p.twr[1], (const T *)p.twi[1]);
+#define CHIB_YDHT(...)                                                                                          \
+  hipLaunchKernelGGL((k_strided_dht<__VA_ARGS__>), dim3(nb), dim3(kThreads), lds, p.stream, (T *)p.W, p.logn[1], \
+                     (int64_t)nx, lb, lxb, (int64_t)nx * p.n[1], (const T *)p.twr[1], (const T *)p.twi[1])
+  const bool r8 = sh.radix == 8;
+  const bool fixed = p.logn[1] == 8 && (int64_t)nx * 256 * (int64_t)sizeof(T) < (int64_t(1) << 32);
+  if (fixed && lb == 3) {
+    if (r8) CHIB_YDHT(T, E, 8, 8, 3);
+    else CHIB_YDHT(T, E, 16, 8, 3);
+  } else if (fixed && lb == 4) {
+    if (r8) CHIB_YDHT(T, E, 8, 8, 4);
+    else CHIB_YDHT(T, E, 16, 8, 4);
+  } else if (r8) {
+    CHIB_YDHT(T, E, 8);
+  } else {
+    CHIB_YDHT(T, E, 16);
+  }
+#undef CHIB_YDHT
   return hipGetLastError();
 }
 
@@ -2279,21 +2296,23 @@ hipError_t launch_neumann(const Plan &p, const Plan::Shape &sh) {
   const size_t lds = (size_t)col_tile(Nn, 1 << lb) * sizeof(T);
   const double norm = (double)p.N;  // 1/(nx [ny] n_last): inverse Hartley scales and the inverse FFT
   const T *lamy = p.d == 3 ? (const T *)p.lam[1] : (const T *)nullptr;
-  if (sh.radix == 8)
-    hipLaunchKernelGGL((k_neumann_solve<T, E, 8>), dim3(nb), dim3(kThreads), lds, p.stream, (T *)p.W, p.logn[ax],
-                       stride, lb, lxb, outer, (const T *)p.lam[0], lamy, (const T *)p.lam[ax], (T)p.a, (T)p.alpha_s,
-                       (T)(1.0 / norm), (const T *)p.twr[ax], (const T *)p.twi[ax], (const T *)p.dctc,
-                       (const T *)p.dcts, p.poisson);
-  else if (p.logn[ax] == 8 && (1 << lb) * 256 == E && stride * 256 * (int64_t)sizeof(T) < (int64_t(1) << 32))   // 256-point lines in a full tile
-    hipLaunchKernelGGL((k_neumann_solve<T, E, 16, 8, ilog2c(E / 256)>), dim3(nb), dim3(kThreads), lds, p.stream, (T *)p.W, p.logn[ax],
-                       stride, lb, lxb, outer, (const T *)p.lam[0], lamy, (const T *)p.lam[ax], (T)p.a, (T)p.alpha_s,
-                       (T)(1.0 / norm), (const T *)p.twr[ax], (const T *)p.twi[ax], (const T *)p.dctc,
-                       (const T *)p.dcts, p.poisson);
-  else
-    hipLaunchKernelGGL((k_neumann_solve<T, E, 16>), dim3(nb), dim3(kThreads), lds, p.stream, (T *)p.W, p.logn[ax],
-                       stride, lb, lxb, outer, (const T *)p.lam[0], lamy, (const T *)p.lam[ax], (T)p.a, (T)p.alpha_s,
-                       (T)(1.0 / norm), (const T *)p.twr[ax], (const T *)p.twi[ax], (const T *)p.dctc,
-                       (const T *)p.dcts, p.poisson);
+#define CHIB_NEUMANN(...)                                                                                        \
+  hipLaunchKernelGGL((k_neumann_solve<__VA_ARGS__>), dim3(nb), dim3(kThreads), lds, p.stream, (T *)p.W,          \
+                     p.logn[ax], stride, lb, lxb, outer, (const T *)p.lam[0], lamy, (const T *)p.lam[ax], (T)p.a, \
+                     (T)p.alpha_s, (T)(1.0 / norm), (const T *)p.twr[ax], (const T *)p.twi[ax],               \
+                     (const T *)p.dctc, (const T *)p.dcts, p.poisson)
+  // 256-point lines in a full tile
+  constexpr int FB = ilog2c(E / 256);
+  const bool fixed = p.logn[ax] == 8 && lb == FB && stride * 256 * (int64_t)sizeof(T) < (int64_t(1) << 32);
+  if (fixed) {
+    if (sh.radix == 8) CHIB_NEUMANN(T, E, 8, 8, FB);
+    else CHIB_NEUMANN(T, E, 16, 8, FB);
+  } else if (sh.radix == 8) {
+    CHIB_NEUMANN(T, E, 8);
+  } else {
+    CHIB_NEUMANN(T, E, 16);
+  }
+#undef CHIB_NEUMANN
   return hipGetLastError();
 }
 
@@ -2575,9 +2594,31 @@ hipError_t tune_shapes(Plan &p, int cur, int reps) {
     }
     return best;
   };
+  // the transform passes are timed where the step runs them, right after the passes before them
+  // (untimed): repeated on their own, W stays in the 256 MB Infinity Cache, which the fused rhs
+  // pass's streaming traffic flushes in a real step, and the tuner would favour other shapes
+  auto time_after = [&](auto &&pre, auto &&launch) -> float {
+    float best = 1e30f;
+    for (int w = 0; w < 2 && e == hipSuccess; ++w) {
+      e = pre();
+      if (e == hipSuccess) e = launch();
+    }
+    for (int r = 0; r < reps && e == hipSuccess; ++r) {
+      e = pre();
+      if (e == hipSuccess) e = hipEventRecord(e0, p.stream);
+      if (e == hipSuccess) e = launch();
+      if (e == hipSuccess) e = hipEventRecord(e1, p.stream);
+      if (e == hipSuccess) e = hipEventSynchronize(e1);
+      float ms = 0.f;
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+      if (ms < best) best = ms;
+    }
+    return best;
+  };
   const T *Cn = (const T *)p.C[cur];
   const T *Cp = (const T *)p.C[1 - cur];
   e = launch_ghost_patch<T>(p, Cn, Cp);   // the rhs candidates read the ghost patch
+  auto rhs = [&]() { return p.d == 2 ? launch_rhs<T, 2>(p, Cn, Cp, p.shape[0]) : launch_rhs<T, 3>(p, Cn, Cp, p.shape[0]); };
   // pass 0: fused rhs
   if (e == hipSuccess) {
     const int hi = max_log_lines(p, E);
@@ -2611,7 +2652,13 @@ hipError_t tune_shapes(Plan &p, int cur, int reps) {
     for (int lt = 1; lt <= hi; ++lt)
       for (int radix : {8, 16}) {
         Plan::Shape sh{lt, radix, 1};
-        const float t = time_it([&]() { return launch_ydht<T>(p, sh); });
+        // the shape serves the forward pass (after the rhs) and the inverse one (after the solve)
+        const float t = time_after(rhs, [&]() { return launch_ydht<T>(p, sh); }) +
+                        time_after([&]() {
+                          hipError_t r = rhs();
+                          if (r == hipSuccess) r = launch_ydht<T>(p, sh);
+                          return r == hipSuccess ? launch_neumann<T>(p, p.shape[2]) : r;
+                        }, [&]() { return launch_ydht<T>(p, sh); });
         if (e != hipSuccess) break;
         if (t < best) {
           best = t;
@@ -2627,7 +2674,10 @@ hipError_t tune_shapes(Plan &p, int cur, int reps) {
     for (int lt = 1; lt <= hi; ++lt)
       for (int radix : {8, 16}) {
         Plan::Shape sh{lt, radix, 1};
-        const float t = time_it([&]() { return launch_neumann<T>(p, sh); });
+        const float t = time_after([&]() {
+          hipError_t r = rhs();
+          return (r == hipSuccess && p.d == 3) ? launch_ydht<T>(p, p.shape[1]) : r;
+        }, [&]() { return launch_neumann<T>(p, sh); });
         if (e != hipSuccess) break;
         if (t < best) {
           best = t;
@@ -2644,7 +2694,11 @@ hipError_t tune_shapes(Plan &p, int cur, int reps) {
     for (int lt = 1; lt <= hi; ++lt)
       for (int radix : {8, 16}) {
         Plan::Shape sh{lt, radix, 1};
-        const float t = time_it([&]() { return launch_xdht<T>(p, (const T *)p.W, (T *)p.W, sh); });
+        const float t = time_after([&]() {
+          hipError_t r = rhs();
+          if (r == hipSuccess) r = launch_spectral_tail<T>(p);
+          return r;
+        }, [&]() { return launch_xdht<T>(p, (const T *)p.W, (T *)p.W, sh); });
         if (e != hipSuccess) break;
         if (t < best) {
           best = t;

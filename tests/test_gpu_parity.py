@@ -77,12 +77,14 @@ def test_spectral_solve_stage(chib, n):
     assert _linf(out, ref) <= 1e-12 * np.max(np.abs(ref))
 
 
+@pytest.mark.parametrize("tile", [3, 4])
+@pytest.mark.parametrize("radix", [8, 16])
 @pytest.mark.parametrize("precision", [64, 32])
 @pytest.mark.parametrize("n", [(256, 256, 8), (32, 8, 256), (256, 256)])
-def test_fixed_size_transform_kernels(chib, n, precision):
-    """256-point lines in the tile widths the fixed-size instances take (x pass 8 lines, y pass
-    8 columns, bounded-axis solve 4096 elements) give the same bits as the runtime-size kernels at
-    narrower tiles, whose per-line arithmetic is the same, and match the oracle."""
+def test_fixed_size_transform_kernels(chib, n, precision, radix, tile):
+    """256-point lines in the tile widths that have fixed-size instances (x pass 8 or 16 lines, y pass
+    8 or 16 columns, bounded-axis solve a full 32 KB tile) give the same bits as the runtime-size
+    kernels at narrower tiles, whose per-line arithmetic is the same, and match the oracle."""
     d = len(n)
     grid = W.Grid(n, (0.0,) * d, tuple(v / 64.0 for v in n))
     prm = W.Params(Cn=0.02, Pe=100.0, dt=1e-4)
@@ -92,10 +94,10 @@ def test_fixed_size_transform_kernels(chib, n, precision):
     st.set_initial(np.zeros(grid.shape))
     Q = np.random.default_rng(7).standard_normal(grid.shape) * 1e9
     full = 4 if precision == 64 else 5      # log2 of the columns of a full bounded-axis tile
-    _say("fixed-size transforms", n, precision)
-    st.set_shapes([[3, 8, 1], [3, 8, 1], [full, 16, 1], [3, 8, 1]])
+    _say("fixed-size transforms", n, precision, radix, tile)
+    st.set_shapes([[tile, radix, 1], [tile, radix, 1], [full, radix, 1], [tile, radix, 1]])
     fixed = st.stage(chib.STAGE_SOLVE, Q)
-    st.set_shapes([[2, 8, 1], [2, 8, 1], [full - 1, 16, 1], [2, 8, 1]])
+    st.set_shapes([[2, radix, 1], [2, radix, 1], [full - 1, radix, 1], [2, radix, 1]])
     runtime = st.stage(chib.STAGE_SOLVE, Q)
     assert np.array_equal(np.asarray(fixed), np.asarray(runtime))
     ref = spectral_solve(Q, grid, st_alpha(prm)[0], st_alpha(prm)[1])
