@@ -242,6 +242,34 @@ template <typename T> struct Pair2;
 template <> struct Pair2<double> { using type = double2; };
 template <> struct Pair2<float> { using type = float2; };
 
+// 16 bytes of a padded LDS tile at an element offset that is only a multiple of 2: the tiles put a
+// 2-element gap after every 16 positions, so a 4-float group need not be 16-byte aligned.  One
+// 16-byte access for double2, two 8-byte ones for float4.
+template <typename T, typename V>
+__device__ __forceinline__ void lds_put16(T *a, const V &v) {
+  if constexpr (sizeof(T) == 8) {
+    *reinterpret_cast<V *>(a) = v;
+  } else {
+    using H = typename Pair2<T>::type;
+    const H *h = reinterpret_cast<const H *>(&v);
+    *reinterpret_cast<H *>(a) = h[0];
+    *reinterpret_cast<H *>(a + 2) = h[1];
+  }
+}
+template <typename V, typename T>
+__device__ __forceinline__ V lds_get16(const T *a) {
+  if constexpr (sizeof(T) == 8) {
+    return *reinterpret_cast<const V *>(a);
+  } else {
+    using H = typename Pair2<T>::type;
+    V v;
+    H *h = reinterpret_cast<H *>(&v);
+    h[0] = *reinterpret_cast<const H *>(a);
+    h[1] = *reinterpret_cast<const H *>(a + 2);
+    return v;
+  }
+}
+
 // PAIRED: the imaginary part sits right after the real part (io == 1), and both move as one
 // 2-element LDS access; with the sequence index fastest across lanes (bfast) the lanes served
 // together then touch distinct bank groups, where two separate accesses would collide.
@@ -1000,7 +1028,7 @@ __global__ __launch_bounds__(kThreads) void k_strided_dht(T *__restrict__ W, int
 #pragma unroll
     for (int k = 0; k < KR; ++k) v[k] = *reinterpret_cast<const FV *>(gb + (foff + k * fstep));
 #pragma unroll
-    for (int k = 0; k < KR; ++k) *reinterpret_cast<FV *>(s + fa0 + k * fda) = v[k];
+    for (int k = 0; k < KR; ++k) lds_put16(s + fa0 + k * fda, v[k]);
   } else {
     stage_tile(s, tot, [&](int e) { return W[base + (e >> logB) * stride + (e & (B - 1))]; }, [&](int e) {
       const int n = e >> logB, col = e & (B - 1);
@@ -1087,7 +1115,7 @@ __device__ __forceinline__ void neumann_body(unsigned char *smem_raw, T *__restr
 #pragma unroll
     for (int k = 0; k < KR; ++k) v[k] = *reinterpret_cast<const FV *>(gb + (foff + k * fstep));
 #pragma unroll
-    for (int k = 0; k < KR; ++k) *reinterpret_cast<FV *>(s + fa0 + k * fda) = v[k];
+    for (int k = 0; k < KR; ++k) lds_put16(s + fa0 + k * fda, v[k]);
   } else {
     stage_tile(s, tot, [&](int e) { return W[base + (e >> logB) * stride + (e & (B - 1))]; }, [&](int e) {
       const int n = e >> logB, col = e & (B - 1);
@@ -1177,7 +1205,7 @@ __device__ __forceinline__ void neumann_body(unsigned char *smem_raw, T *__restr
     asm volatile("" : "+v"(foff));
 #pragma unroll
     for (int k = 0; k < KR; ++k)
-      *reinterpret_cast<FV *>(gb + (foff + k * fstep)) = *reinterpret_cast<const FV *>(s + fa0 + k * fda);
+      *reinterpret_cast<FV *>(gb + (foff + k * fstep)) = lds_get16<FV>(s + fa0 + k * fda);
   } else {
     for (int e = threadIdx.x; e < tot; e += blockDim.x) {
       const int n = e >> logB, col = e & (B - 1);
