@@ -402,6 +402,32 @@ def test_tuned_shapes_keep_parity(chib):
         st.set_shapes([[2, 4, 1]] * 4)
 
 
+def test_full_size_launch_shapes_agree(chib):
+    """At 256^3 the measured launch shapes (fixed-size y, bounded-axis and x passes at radix 16, 8
+    and 8), the default shapes (the radix-16 fixed-size instances, the ones the 256^3 oracle
+    comparison steps with) and shapes that take only runtime-size transform kernels give the same
+    C after 5 steps up to FFT rounding."""
+    case = W.config3(256)
+    g = case.grid
+    geo = chib.Geometry.build_device(g.n, g.lo, g.hi, case.shapes, case.params)
+    C0, faces = case.initial_fields()
+    out = {}
+    for name, shapes in (("measured", [[2, 4, 5], [4, 16, 1], [4, 8, 1], [3, 8, 1]]), ("default", None),
+                         ("runtime-size", [[2, 4, 5], [2, 8, 1], [3, 16, 1], [2, 16, 1]])):
+        st = chib.State(geo, case.params)
+        st.set_initial(C0, faces)
+        if shapes:
+            st.set_shapes(shapes)
+        _say("256^3 shapes", name)
+        st.step(5)
+        out[name] = np.asarray(st.get(chib.FIELD_C))
+        del st
+    for name in ("default", "runtime-size"):
+        err = float(np.max(np.abs(out["measured"] - out[name])))
+        _say("256^3 shapes: measured vs", name, err)
+        assert err <= 1e-11
+
+
 def test_radix_4_outside_the_z_march_takes_radix_8(chib):
     """Pass-0 radix 4 exists for the z-marching kernel only; the 2D rhs kernels (line-tiled and
     y-marching) take radix 8 for it, bit for bit."""
